@@ -1,0 +1,685 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each test compares the oracle with something other than itself: closed forms,
+an independent quadrature, brute-force dense linear algebra, library rounding
+routines (numpy binary16, torch float8_e4m3fn) or values printed in the paper.
+"""
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workload as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ------------------------------------------------------------ test helpers
+def _grad_ref(d, a, xi):
+    """Gradient of the reference d-linear shape function a at xi (unit cube)."""
+    g = np.zeros(d)
+    for k in range(d):
+        v = 1.0 if (a >> k) & 1 else -1.0
+        for m in range(d):
+            if m != k:
+                v *= xi[m] if (a >> m) & 1 else 1.0 - xi[m]
+        g[k] = v
+    return g
+
+
+def _gauss_box(d, lo, hi, npts):
+    x, w = np.polynomial.legendre.leggauss(npts)
+    pts, wts = [], []
+    for idx in np.ndindex(*([npts] * d)):
+        p = np.array([lo[m] + (hi[m] - lo[m]) * 0.5 * (x[idx[m]] + 1) for m in range(d)])
+        ww = np.prod([(hi[m] - lo[m]) * 0.5 * w[idx[m]] for m in range(d)])
+        pts.append(p)
+        wts.append(ww)
+    return pts, wts
+
+
+def _quad_matrix(d, lo, hi, npts, weight=lambda xi: 1.0):
+    nl = 1 << d
+    K = np.zeros((nl, nl))
+    for p, w in zip(*_gauss_box(d, lo, hi, npts)):
+        gs = [_grad_ref(d, a, p) for a in range(nl)]
+        e = weight(p)
+        for a in range(nl):
+            for b in range(nl):
+                K[a, b] += w * e * gs[a].dot(gs[b])
+    return K
+
+
+def _kref(d, h):
+    rows = [r for r in _golden("q1_unit_stiffness.txt") if int(r[0]) == d]
+    val = {int(r[1]): float(Fr(int(r[2]), int(r[3]))) * h ** int(r[4]) for r in rows}
+    nl = 1 << d
+    return np.array([[val[bin(a ^ b).count("1")] for b in range(nl)] for a in range(nl)])
+
+
+def _dense_global(d, n, K):
+    """Scatter-assemble the global (N+1)^d matrix from element matrices."""
+    nv = n + 1
+    A = np.zeros((nv ** d, nv ** d))
+    nl = 1 << d
+    for c in range(n ** d):
+        ci = [(c // n ** m) % n for m in range(d)]
+        ids = [sum((ci[m] + ((a >> m) & 1)) * nv ** m for m in range(d)) for a in range(nl)]
+        for a in range(nl):
+            for b in range(nl):
+                A[ids[a], ids[b]] += K[c][a, b]
+    return A
+
+
+def _stencil_to_dense(d, n, S):
+    nv = n + 1
+    A = np.zeros((nv ** d, nv ** d))
+    for v in range(nv ** d):
+        vi = [(v // nv ** m) % nv for m in range(d)]
+        for oi in range(3 ** d):
+            o = [(oi // 3 ** m) % 3 - 1 for m in range(d)]
+            wi = [vi[m] + o[m] for m in range(d)]
+            if all(0 <= x < nv for x in wi):
+                A[v, sum(wi[m] * nv ** m for m in range(d))] += S[v, oi]
+    return A
+
+
+def _prolongation(d, nf):
+    nc = nf // 2
+    nvf, nvc = nf + 1, nc + 1
+    P = np.zeros((nvf ** d, nvc ** d))
+    wt = {0: 1.0, 1: 0.5, -1: 0.5}
+    for v in range(nvf ** d):
+        vi = [(v // nvf ** m) % nvf for m in range(d)]
+        for V in range(nvc ** d):
+            Vi = [(V // nvc ** m) % nvc for m in range(d)]
+            p = 1.0
+            for m in range(d):
+                p *= wt.get(vi[m] - 2 * Vi[m], 0.0)
+            P[v, V] = p
+    return P
+
+
+def _interior(d, n):
+    return W.interior_mask(d, n)
+
+
+# ------------------------------------------------------------ sub-cell G_q
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("s", [1, 2, 4, 16])
+def test_subcell_matrix_matches_gauss_quadrature(d, s):
+    """G_q is the exact integral of grad phi_a . grad phi_b over sub-cell q:
+    two Gauss points per axis integrate these (per-axis quadratic) products
+    exactly."""
+    rng = np.random.default_rng(1)
+    h = 0.125
+    for _ in range(4):
+        q = rng.integers(0, s, size=d)
+        lo = q / s
+        hi = (q + 1) / s
+        ref = _quad_matrix(d, lo, hi, 2) * h ** (d - 2)
+        got = O.subcell_matrix(d, s, q, h)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15 * max(1.0, abs(ref).max()))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("s", [1, 2, 8])
+def test_subcell_sum_is_unit_q1_matrix(d, s):
+    h = 0.25
+    tot = np.zeros((1 << d, 1 << d))
+    for q in np.ndindex(*([s] * d)):
+        G = O.subcell_matrix(d, s, q, h)
+        np.testing.assert_allclose(G.sum(1), 0.0, atol=1e-16)  # zero row sums
+        np.testing.assert_allclose(G, G.T, atol=0)  # symmetry
+        tot += G
+    np.testing.assert_allclose(tot, _kref(d, h), rtol=1e-14, atol=1e-16)
+
+
+# ----------------------------------------------------------- element matrix
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+def test_constant_eps_gives_scaled_unit_matrix_for_every_s(d, n):
+    fld = W.const_field(d, 2.5)
+    for s in (1, 2, 4, 8, 16) if d == 2 else (1, 2, 4, 8):
+        K = O.element_matrix(fld, d, n, s, 3)
+        np.testing.assert_allclose(K, 2.5 * _kref(d, 1.0 / n), rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_aligned_interface_exact(d):
+    """eps jumps from e1 to e2 at the mid-plane x = (i+1/2)h of a cell.  With
+    even s the sub-cells resolve the jump exactly; the element matrix is
+    e1 * (left-half integral) + e2 * (right-half integral), from hand-derived
+    1D integrals over [0,1/2] and [1/2,1]."""
+    n, i = 4, 1
+    e1, e2 = 1.0, 1e3
+    xm = (i + 0.5) / n
+    row = [xm] + [-1.0] * (d - 1) + [2.0] * d + [e2]
+    fld = W.Field(W.BOXES, d, p0=e1, count=1, data=np.array(row))
+    # 1D integrals of psi_a psi_b (M) and psi_a' psi_b' (D) over the halves
+    M_left = {(0, 0): Fr(7, 24), (0, 1): Fr(1, 12), (1, 1): Fr(1, 24)}
+    M_right = {(0, 0): Fr(1, 24), (0, 1): Fr(1, 12), (1, 1): Fr(7, 24)}
+    M_full = {(0, 0): Fr(1, 3), (0, 1): Fr(1, 6), (1, 1): Fr(1, 3)}
+
+    def mm(tab, a, b):
+        return tab[(min(a, b), max(a, b))]
+
+    def half(Mx, Dx):
+        nl = 1 << d
+        G = np.zeros((nl, nl))
+        for a in range(nl):
+            for b in range(nl):
+                tot = Fr(0)
+                for k in range(d):
+                    sg = 1 if ((a >> k) & 1) == ((b >> k) & 1) else -1
+                    term = Fr(sg) * (Dx if k == 0 else 1)
+                    for m in range(d):
+                        if m == k:
+                            continue
+                        tab = Mx if m == 0 else M_full
+                        term *= mm(tab, (a >> m) & 1, (b >> m) & 1)
+                    tot += term
+                G[a, b] = float(tot)
+        return G * (1.0 / n) ** (d - 2)
+
+    ref = e1 * half(M_left, Fr(1, 2)) + e2 * half(M_right, Fr(1, 2))
+    cell = i  # cell (i, 0[, 0])
+    for s in (2, 4, 8):
+        K = O.element_matrix(fld, d, n, s, cell)
+        np.testing.assert_allclose(K, ref, rtol=1e-13, atol=1e-12)
+    # odd resolution (s = 1) cannot see the jump at the midpoint exactly
+    K1 = O.element_matrix(fld, d, n, 1, cell)
+    assert np.abs(K1 - ref).max() > 1.0
+
+
+def test_sub_sampling_converges_second_order_to_quadrature():
+    """Smooth eps: K(s) -> the exact cell integral (high-order Gauss on the
+    true eps) with error O(s^-2)."""
+    d, n = 2, 4
+    fld = W.sine_field(2, 0.9)
+    cell = 5
+    ci = [cell % n, cell // n]
+
+    def eps(xi):
+        x = [(ci[m] + xi[m]) / n for m in range(d)]
+        return 1.0 + 0.9 * math.sin(2 * math.pi * x[0]) * math.sin(2 * math.pi * x[1])
+
+    ref = _quad_matrix(d, [0, 0], [1, 1], 14, eps)
+    errs = [np.abs(O.element_matrix(fld, d, n, s, cell) - ref).max() for s in (2, 4, 8, 16)]
+    ratios = [errs[k] / errs[k + 1] for k in range(3)]
+    assert all(3.6 < r < 4.4 for r in ratios), (errs, ratios)
+
+
+def test_sample_form_matches_field_form():
+    d, n, s = 3, 4, 4
+    fld = W.lattice_field(3, 8, 7, sigma=0.7)
+    cell = 17
+    ci = [(cell // n ** m) % n for m in range(d)]
+    eps_q = []
+    for q in np.ndindex(*([s] * d)):
+        q = q[::-1]  # ndindex is last-fastest; we need x fastest
+        x = [(ci[m] + (q[m] + 0.5) / s) / n for m in range(d)]
+        eps_q.append(O.eps_at(fld, x))
+    K1 = O.element_matrix(fld, d, n, s, cell)
+    K2 = O.element_matrix_samples(d, n, s, np.array(eps_q))
+    np.testing.assert_allclose(K1, K2, rtol=1e-15, atol=0)
+
+
+def test_lattice_field_interpolates_vertex_values():
+    fld = W.lattice_field(2, 8, 3, sigma=1.0)
+    g = fld.data.reshape(9, 9)
+    for (j, i) in [(0, 0), (3, 5), (8, 8), (2, 7)]:
+        e = O.eps_at(fld, [i / 8, j / 8])
+        assert abs(e - math.exp(g[j, i])) < 1e-12 * math.exp(abs(g[j, i]))
+    # midpoint of a lattice edge is the mean of its two end values
+    e = O.eps_at(fld, [(3 + 0.5) / 8, 2 / 8])
+    assert abs(math.log(e) - 0.5 * (g[2, 3] + g[2, 4])) < 1e-12
+
+
+# -------------------------------------------------------------------- ladder
+def test_ladder_constant_field_stops_after_first_comparison():
+    K, sf, rel = O.ladder(W.const_field(2, 3.0), 2, 8, 16, 0.01)
+    assert (sf == 2).all()
+    assert np.nanmax(rel[:, 0]) < 1e-14
+
+
+def test_ladder_theta1_matches_paper_table():
+    """Table memory-footprint, theta = 1: the first comparison (two samples per
+    axis against the centre sample) already differs by less than C = 1 % in
+    every cell, so no cell ever integrates beyond it (max n stays at its
+    first value in every cycle).  Grid: h = 1/27 ~ 0.037 (the paper's h ~ 0.038
+    on a k = 3 spacetree)."""
+    rows = _golden("table_memory_footprint.txt")
+    assert all(r[1] == "1" and r[2] == "1.00" for r in rows)  # theta = 1 columns
+    K, sf, rel = O.ladder(W.theta_field(2, 1.0), 2, 27, 16, 0.01)
+    assert (sf == 2).all()
+    assert np.nanmax(rel[:, 0]) < 0.01
+
+
+def test_ladder_keeps_new_matrix_and_caps_at_smax():
+    fld = W.balls_field(2, 6, 11, r_lo=0.05, r_hi=0.2)
+    n = 8
+    K, sf, rel = O.ladder(fld, 2, n, 8, 0.01)
+    for c in range(n * n):
+        np.testing.assert_allclose(K[c], O.element_matrix(fld, 2, n, int(sf[c]), c), rtol=0, atol=0)
+        assert sf[c] in (2, 4, 8)
+        k = int(math.log2(sf[c])) - 1
+        if sf[c] < 8:
+            assert rel[c, k] < 0.01
+        for j in range(k):
+            assert rel[c, j] >= 0.01
+    assert (sf == 8).any() and (sf == 2).any()
+
+
+# ------------------------------------------------------------------ stencils
+@pytest.mark.parametrize("d,n", [(2, 4), (3, 3)])
+def test_stencils_are_rows_of_scatter_assembled_matrix(d, n):
+    fld = W.balls_field(d, 4, 5, r_lo=0.1, r_hi=0.3, eps_in=50.0)
+    K = O.assemble(fld, d, n, 4)
+    S = O.stencils(d, n, K)
+    A = _dense_global(d, n, K)
+    np.testing.assert_allclose(_stencil_to_dense(d, n, S), A, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(A, A.T, atol=1e-13)
+    inner = _interior(d, n)
+    np.testing.assert_allclose(A[inner].sum(1), 0.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_constant_eps_stencil_closed_form(d):
+    n = 6
+    S = O.stencils(d, n, O.assemble(W.const_field(d, 1.0), d, n, 1))
+    h = 1.0 / n
+    rows = [r for r in _golden("q1_stencils.txt") if int(r[0]) == d]
+    val = {int(r[1]): float(Fr(int(r[2]), int(r[3]))) * h ** int(r[4]) for r in rows}
+    v = sum(3 * (n + 1) ** m for m in range(d))  # interior vertex (3,3[,3])
+    for oi in range(3 ** d):
+        nz = sum(((oi // 3 ** m) % 3) != 1 for m in range(d))
+        assert abs(S[v, oi] - val[nz]) < 1e-14
+
+
+def test_base_coupling_is_centre_sample_stencil():
+    """The hierarchical-surplus base equals the stencil assembled from s = 1
+    element matrices (eps_c K_ref) for every stored coupling."""
+    for d, n in [(2, 5), (3, 3)]:
+        fld = W.lattice_field(d, n, 9, sigma=1.0)
+        K1 = O.assemble(fld, d, n, 1)
+        S1 = O.stencils(d, n, K1)
+        # centre samples as FP32 (the base is defined on FP32 centre samples)
+        eps_c = np.array([K1[c][0, 0] / _kref(d, 1.0 / n)[0, 0] for c in range(n ** d)], np.float32)
+        S1f = O.stencils(d, n, np.array([eps_c[c] * _kref(d, 1.0 / n) for c in range(n ** d)]))
+        for v in range(O.nvert(d, n)):
+            for oi in O.half_offsets(d):
+                b, ref = O.base_coupling(d, n, eps_c, v, oi)
+                assert abs(b - S1f[v, oi]) <= 1e-15 * max(1.0, abs(ref))
+        assert np.abs(S1f - S1).max() < 1e-6 * np.abs(S1).max()
+
+
+# ------------------------------------------------------------------ Galerkin
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+def test_galerkin_equals_dense_ptap(d, n):
+    fld = W.balls_field(d, 5, 2, r_lo=0.1, r_hi=0.3, eps_in=100.0)
+    S = O.stencils(d, n, O.assemble(fld, d, n, 2))
+    Sc = O.galerkin(d, n, S)
+    A = _stencil_to_dense(d, n, S)
+    P = _prolongation(d, n)
+    Ac = P.T @ A @ P
+    np.testing.assert_allclose(_stencil_to_dense(d, n // 2, Sc), Ac, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+def test_galerkin_of_constant_eps_is_q1_at_2h(d, n):
+    S = O.stencils(d, n, O.assemble(W.const_field(d, 1.0), d, n, 1))
+    H = O.Hierarchy(d, n, S, coarsest=2)
+    for l in range(1, H.nlev):
+        nl = H.level_n(l)
+        ref = O.stencils(d, nl, O.assemble(W.const_field(d, 1.0), d, nl, 1))
+        got = H.level_stencils(l)
+        inner = _interior(d, nl)
+        np.testing.assert_allclose(got[inner], ref[inner], rtol=1e-13, atol=1e-14 * np.abs(ref).max())
+
+
+def test_galerkin_equals_rediscretisation_with_inherited_samples():
+    """Nested Q1 spaces: P^T A(s on h) P = A(2s on 2h) when the coarse cells
+    sample eps at exactly the fine sub-cell midpoints."""
+    for d, n, s in [(2, 8, 2), (3, 4, 2)]:
+        fld = W.sine_field(d, 0.9)
+        Sf = O.stencils(d, n, O.assemble(fld, d, n, s))
+        Sc = O.galerkin(d, n, Sf)
+        Sre = O.stencils(d, n // 2, O.assemble(fld, d, n // 2, 2 * s))
+        np.testing.assert_allclose(Sc, Sre, rtol=1e-12, atol=1e-14)
+
+
+# ----------------------------------------------------------- multigrid pieces
+def test_cholesky_matches_numpy():
+    d, n = 2, 8
+    S = O.stencils(d, n, O.assemble(W.sine_field(2), d, n, 2))
+    A = O.dense_matrix(d, n, S)
+    b = np.random.default_rng(0).standard_normal(A.shape[0])
+    np.testing.assert_allclose(O.cholesky_solve(A, b), np.linalg.solve(A, b), rtol=1e-12)
+
+
+def test_restrict_is_transpose_of_prolong():
+    for d, n in [(2, 8), (3, 4)]:
+        rng = np.random.default_rng(4)
+        P = _prolongation(d, n)
+        r = rng.standard_normal(O.nvert(d, n))
+        r[~_interior(d, n)] = 0
+        fc = O.restrict(d, n, r)
+        ref = P.T @ r
+        ref[~_interior(d, n // 2)] = 0
+        np.testing.assert_allclose(fc, ref, atol=1e-14)
+        e = rng.standard_normal(O.nvert(d, n // 2))
+        e[~_interior(d, n // 2)] = 0
+        u = O.prolong_add(d, n, e, np.zeros(O.nvert(d, n)))
+        ref = P @ e
+        ref[~_interior(d, n)] = 0
+        np.testing.assert_allclose(u, ref, atol=1e-14)
+
+
+def test_jacobi_matches_dense_formula():
+    d, n = 2, 8
+    S = O.stencils(d, n, O.assemble(W.sine_field(2), d, n, 2))
+    A = _stencil_to_dense(d, n, S)
+    rng = np.random.default_rng(3)
+    inner = _interior(d, n)
+    u = rng.standard_normal(A.shape[0]) * inner
+    f = rng.standard_normal(A.shape[0]) * inner
+    ref = u + 0.6 * (f - A @ u) / np.diag(A)
+    ref[~inner] = 0
+    np.testing.assert_allclose(O.jacobi(d, n, S, u, f, 0.6), ref, atol=1e-13)
+    r = O.residual(d, n, S, u, f)
+    np.testing.assert_allclose(r, (f - A @ u) * inner, atol=1e-13)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (2, 16), (3, 4), (3, 8)])
+def test_dense_solution_is_vcycle_fixed_point(d, n):
+    fld = W.balls_field(d, 6, 8, r_lo=0.05, r_hi=0.25, eps_in=1e3)
+    S = O.stencils(d, n, O.assemble(fld, d, n, 4))
+    A = O.dense_matrix(d, n, S)
+    f = W.load_const(d, n)
+    inner = _interior(d, n)
+    u = np.zeros(O.nvert(d, n))
+    u[inner] = np.linalg.solve(A, f[inner])
+    H = O.Hierarchy(d, n, S)
+    u2 = H.vcycle(u, f)
+    np.testing.assert_allclose(u2, u, rtol=0, atol=1e-12 * np.abs(u).max())
+
+
+def test_vcycle_iteration_matrix_spectral_radius_bounds_convergence():
+    d, n = 2, 16
+    S = O.stencils(d, n, O.assemble(W.sine_field(2), d, n, 4))
+    H = O.Hierarchy(d, n, S)
+    inner = np.flatnonzero(_interior(d, n))
+    zero = np.zeros(O.nvert(d, n))
+    M = np.zeros((len(inner), len(inner)))
+    for j, v in enumerate(inner):
+        e = zero.copy()
+        e[v] = 1.0
+        M[:, j] = H.vcycle(e, zero)[inner]
+    rho = max(abs(np.linalg.eigvals(M)))
+    assert rho < 0.25
+    u = np.random.default_rng(0).standard_normal(O.nvert(d, n)) * _interior(d, n)
+    for _ in range(40):
+        u_new = H.vcycle(u, zero)
+        ratio = np.linalg.norm(u_new) / np.linalg.norm(u)
+        u = u_new
+    assert ratio <= rho * 1.02 + 1e-12
+    assert ratio >= rho * 0.7
+
+
+def test_zero_rhs_theta_setup_decays_to_zero():
+    """Setup 1 of the results section: f = 0 has the exact solution u = 0;
+    started from noise in [0, 4/3] the iterate must vanish."""
+    d, n = 2, 32
+    fld = W.theta_field(2, 8.0)
+    u0 = W.noise_guess(d, n, 12)
+    u, rep = O.solve(fld, d, n, np.zeros(O.nvert(d, n)), u0=u0, s_fixed=4, tol=1e-10)
+    assert rep["status"] == O.OK
+    assert np.abs(u).max() < 1e-8
+
+
+def _max_err_sine(d, n, fld, f, s):
+    u, rep = O.solve(fld, d, n, f, s_fixed=s, tol=1e-12, max_cycles=60)
+    assert rep["status"] == O.OK
+    xs = W._grid_coords(d, n)
+    ue = np.ones(O.nvert(d, n))
+    for x in xs:
+        ue *= np.sin(math.pi * x)
+    return np.abs(u - ue).max()
+
+
+def test_second_order_convergence_manufactured_unit_eps():
+    for d, ns in [(2, [16, 32, 64, 128]), (3, [8, 16, 32])]:
+        fld = W.const_field(d, 1.0)
+        errs = [_max_err_sine(d, n, fld, W.load_sine(d, n), 1) for n in ns]
+        orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
+        assert all(1.8 < p < 2.2 for p in orders), (d, errs, orders)
+
+
+def test_second_order_convergence_manufactured_smooth_eps():
+    a = 0.5
+    tp = 2 * math.pi
+
+    def fun(p):
+        x, y = p
+        u = np.sin(math.pi * x) * np.sin(math.pi * y)
+        eps = 1 + a * np.sin(tp * x) * np.sin(tp * y)
+        ex = a * tp * np.cos(tp * x) * np.sin(tp * y)
+        ey = a * tp * np.sin(tp * x) * np.cos(tp * y)
+        ux = math.pi * np.cos(math.pi * x) * np.sin(math.pi * y)
+        uy = math.pi * np.sin(math.pi * x) * np.cos(math.pi * y)
+        return eps * 2 * math.pi ** 2 * u - (ex * ux + ey * uy)
+
+    ns = [16, 32, 64, 128]
+    errs = [_max_err_sine(2, n, W.sine_field(2, a), W.load_quadrature(2, n, fun, 3), 4) for n in ns]
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    assert all(1.8 < p < 2.2 for p in orders), (errs, orders)
+
+
+def test_lazy_schedule_reaches_the_upfront_operator():
+    d, n = 2, 32
+    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+    f = W.load_const(d, n)
+    kw = dict(s_max=16, tol=1e-11, transfer=O.BOXMG, outer=O.PCG)
+    u1, r1 = O.solve(fld, d, n, f, lazy=False, **kw)
+    u2, r2 = O.solve(fld, d, n, f, lazy=True, **kw)
+    assert r1["status"] == O.OK and r2["status"] == O.OK
+    assert r1["cells_at_s"] == r2["cells_at_s"]
+    assert r2["cycles"] >= 4  # every rung published before termination
+    K, sf, _ = O.ladder(fld, d, n, 16, 0.01)
+    S = O.stencils(d, n, K)
+    A = O.dense_matrix(d, n, S)
+    inner = _interior(d, n)
+    ue = np.linalg.solve(A, f[inner])
+    for u in (u1, u2):
+        assert np.abs(u[inner] - ue).max() < 1e-8 * np.abs(ue).max()
+
+
+def test_boxmg_weights_reduce_to_dlinear_for_constant_eps():
+    for d, n in [(2, 8), (3, 4)]:
+        S = O.stencils(d, n, O.assemble(W.const_field(d, 3.0), d, n, 1))
+        np.testing.assert_allclose(O.transfer_weights(d, n, S, O.BOXMG),
+                                   O.transfer_weights(d, n, S, O.GEOMETRIC), rtol=0, atol=1e-14)
+
+
+def test_boxmg_weights_are_1d_harmonic_for_layered_media():
+    """eps depending on x only: the stencil collapsed over y is the 1D FE
+    operator, so a fine point between two coarse points along x takes the
+    weights eps_L/(eps_L+eps_R), eps_R/(eps_L+eps_R) of the 1D harmonic
+    interpolant; along y (eps unchanged) it takes 1/2, 1/2."""
+    n = 8
+    rng = np.random.default_rng(9)
+    eps_cols = 10.0 ** rng.uniform(-3, 3, size=n)
+    rows = [[i / n, -1.0, (i + 1) / n, 2.0, eps_cols[i]] for i in range(n)]
+    fld = W.Field(W.BOXES, 2, p0=1.0, count=n, data=np.array(rows))
+    S = O.stencils(2, n, O.assemble(fld, 2, n, 2))
+    Pw = O.transfer_weights(2, n, S, O.BOXMG)
+    nv = n + 1
+    for j in range(2, n - 1, 2):
+        for i in range(1, n, 2):
+            w = Pw[i + nv * j]
+            eL, eR = eps_cols[i - 1], eps_cols[i]
+            np.testing.assert_allclose(w[[0, 1]], [eL / (eL + eR), eR / (eL + eR)], rtol=1e-12)
+            assert abs(w[2]) + abs(w[3]) < 1e-14
+    for j in range(1, n, 2):
+        for i in range(2, n - 1, 2):
+            np.testing.assert_allclose(Pw[i + nv * j][[0, 2]], [0.5, 0.5], rtol=1e-12)
+
+
+def test_boxmg_weights_preserve_constants():
+    for d, n in [(2, 16), (3, 8)]:
+        fld = W.balls_field(d, 8, 4, r_lo=0.05, r_hi=0.25, eps_in=1e4)
+        S = O.stencils(d, n, O.assemble(fld, d, n, 2))
+        Pw = O.transfer_weights(d, n, S, O.BOXMG)
+        np.testing.assert_allclose(Pw.sum(1), 1.0, rtol=1e-12)
+        Sc = O.galerkin(d, n, S, Pw)
+        A = _stencil_to_dense(d, n // 2, Sc)
+        inner = _interior(d, n // 2)
+        np.testing.assert_allclose(A[inner].sum(1), 0.0, atol=1e-10 * np.abs(A).max())
+        np.testing.assert_allclose(A, A.T, atol=1e-12 * np.abs(A).max())
+
+
+def test_boxmg_galerkin_equals_dense_ptap_with_its_weights():
+    d, n = 2, 8
+    fld = W.balls_field(d, 5, 2, r_lo=0.1, r_hi=0.3, eps_in=100.0)
+    S = O.stencils(d, n, O.assemble(fld, d, n, 2))
+    Pw = O.transfer_weights(d, n, S, O.BOXMG)
+    nv, nvc = n + 1, n // 2 + 1
+    P = np.zeros((nv ** 2, nvc ** 2))
+    for v in range(nv ** 2):
+        vi = [v % nv, v // nv]
+        for B in range(4):
+            Vi = [(vi[m] >> 1) + ((B >> m) & 1) for m in range(2)]
+            if Pw[v, B] != 0.0:
+                P[v, Vi[0] + nvc * Vi[1]] += Pw[v, B]
+    A = _stencil_to_dense(d, n, S)
+    np.testing.assert_allclose(_stencil_to_dense(d, n // 2, O.galerkin(d, n, S, Pw)), P.T @ A @ P,
+                               atol=1e-12)
+
+
+def test_boxmg_handles_stiff_aligned_inclusion():
+    """A coarse-grid-aligned stiff inclusion (eps 1e3) stalls the d-linear
+    V-cycle but not the operator-dependent one."""
+    d, n = 2, 64
+    sq = W.Field(W.BOXES, 2, p0=1.0, count=1, data=np.array([0.25, 0.25, 0.75, 0.75, 1e3]))
+    f = W.load_sine(d, n)
+    _, rg = O.solve(sq, d, n, f, s_fixed=2, tol=1e-8, max_cycles=30, transfer=O.GEOMETRIC)
+    _, rb = O.solve(sq, d, n, f, s_fixed=2, tol=1e-8, max_cycles=30, transfer=O.BOXMG)
+    assert rg["status"] == O.ENOCONV
+    assert rb["status"] == O.OK and rb["cycles"] <= 15
+
+
+def test_pcg_outer_reaches_dense_solution_in_fewer_cycles():
+    d, n = 2, 32
+    fld = W.balls_field(2, 30, 5, r_lo=0.02, r_hi=0.08, eps_in=1e3)
+    f = W.load_sine(d, n)
+    K = O.assemble(fld, d, n, 4)
+    S = O.stencils(d, n, K)
+    inner = _interior(d, n)
+    ue = np.linalg.solve(O.dense_matrix(d, n, S), f[inner])
+    us, rs = O.solve(fld, d, n, f, s_fixed=4, tol=1e-10, transfer=O.BOXMG, outer=O.STATIONARY, max_cycles=400)
+    up, rp = O.solve(fld, d, n, f, s_fixed=4, tol=1e-10, transfer=O.BOXMG, outer=O.PCG)
+    assert rs["status"] == O.OK and rp["status"] == O.OK
+    assert rp["cycles"] < rs["cycles"]
+    for u in (us, up):
+        assert np.abs(u[inner] - ue).max() < 1e-7 * np.abs(ue).max()
+
+
+def test_divergence_guard():
+    d, n = 2, 16
+    u, rep = O.solve(W.const_field(2, 1.0), d, n, W.load_const(d, n), s_fixed=1,
+                     omega=3.0, nu1=4, nu2=4, tol=1e-10, max_cycles=100)
+    assert rep["status"] == O.EDIVERGED
+
+
+# ------------------------------------------------------------------ encoder
+def _rand_deltas(rng, k, H):
+    mag = 10.0 ** rng.uniform(-12, 3, size=(k, 1))
+    return (rng.standard_normal((k, H)) * mag).astype(np.float32)
+
+
+def test_scale_exponent_is_smallest_power_of_two():
+    rng = np.random.default_rng(5)
+    for tier, fm in [(1, 448.0), (2, 65504.0)]:
+        for m in 10.0 ** rng.uniform(-30, 30, size=200):
+            e = O.scale_exponent(m, tier)
+            if -127 < e < 127:
+                assert m <= fm * 2.0 ** e and m > fm * 2.0 ** (e - 1)
+
+
+def test_binary16_payload_matches_numpy_rounding():
+    rng = np.random.default_rng(6)
+    D = _rand_deltas(rng, 300, 13)
+    for row in D:
+        e8, words = O.encode_stencil(row, 2)
+        e = e8 - 127
+        scaled = row.astype(np.float64) * 2.0 ** (-e)
+        ref = scaled.astype(np.float16).view(np.uint16)
+        assert (words.astype(np.uint16) == ref).all()
+        dec = np.array([O.decode_entry(2, e8, w) for w in words])
+        np.testing.assert_array_equal(dec, ref.view(np.float16).astype(np.float64) * 2.0 ** e)
+
+
+def test_e4m3_payload_matches_torch_rounding():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(7)
+    D = _rand_deltas(rng, 300, 4)
+    for row in D:
+        e8, words = O.encode_stencil(row, 1)
+        e = e8 - 127
+        scaled = (row.astype(np.float64) * 2.0 ** (-e)).astype(np.float32)
+        assert np.abs(scaled).max() <= 448.0
+        ref = torch.from_numpy(scaled).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+        assert (words.astype(np.uint8) == ref).all(), (row, words, ref)
+
+
+def test_tier_choice_and_error_bound():
+    rng = np.random.default_rng(8)
+    for row in _rand_deltas(rng, 200, 4):
+        mx = float(np.abs(row).max())
+        assert O.choose_tier(row, mx, 1, 3) == 0
+        assert O.choose_tier(row, 0.0, 1, 3) == 3 or not np.any(row)
+        for tau in (mx * 0.3, mx * 1e-3, mx * 1e-6):
+            t = O.choose_tier(row, tau, 1, 3)
+            e8, words = O.encode_stencil(row, t)
+            dec = np.array([O.decode_entry(t, e8, w) for w in words])
+            assert np.abs(dec - row.astype(np.float64)).max() <= tau
+            assert t in (1, 2, 3)
+
+
+def test_level_compression_respects_tolerance():
+    d, n = 2, 16
+    fld = W.balls_field(2, 5, 3, r_lo=0.05, r_hi=0.2, eps_in=1e3)
+    K = O.assemble(fld, d, n, 8)
+    S32 = O.to_half(d, O.stencils(d, n, K)).astype(np.float32)
+    K1 = O.assemble(fld, d, n, 1)
+    eps_c = np.array([K1[c][0, 0] / (2.0 / 3.0) for c in range(n * n)], np.float32)
+    for (tmin, tmax, ta, tr) in [(2, 2, 0.0, 0.0), (1, 3, 0.0, 1e-3), (1, 3, 1e-6, 0.0)]:
+        tt, e8, words = O.compress(d, n, S32, eps_c, tmin, tmax, ta, tr)
+        NV = O.nvert(d, n)
+        for v in range(NV):
+            t = int(tt[v // 64])
+            ref = 0.0
+            for j, oi in enumerate(O.half_offsets(d)):
+                b, ref = O.base_coupling(d, n, eps_c, v, oi)
+                delta = np.float32(np.float64(S32[j, v]) - b)
+                got = O.decode_entry(t, int(e8[v]), int(words[v, j]))
+                tau = max(ta, tr * ref)
+                if t < tmax:
+                    assert abs(got - float(delta)) <= tau
+                if t == 2 and tmin == tmax:
+                    assert abs(got - float(delta)) <= abs(float(delta)) * 2.0 ** -11 + 2.0 ** (int(e8[v]) - 127 - 24)
+        if tmin == 1:
+            assert (tt == 0).any()  # cells away from the balls store nothing
