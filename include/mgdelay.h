@@ -1,0 +1,258 @@
+/*
+ * mgdelay.h -- C ABI of the MI355X (gfx950) library for delayed approximate
+ * matrix assembly in multigrid with dynamic precisions (Murray & Weinzierl,
+ * arXiv:2005.03606).
+ *
+ * Problem: -div(eps grad u) = f on the unit square / cube, homogeneous
+ * Dirichlet conditions, d-linear (Q1) finite elements on N^d equal cells
+ * (Sec. 4: nodal Ritz-Galerkin, 9- / 27-point stencils).
+ *
+ * Conventions shared by every entry point
+ *   - cell c = i + N (j + N k), vertex v = i + (N+1)(j + (N+1) k), x fastest;
+ *     NV = (N+1)^d; vectors hold every vertex, boundary entries are 0;
+ *   - local vertex a of a cell has bit m = offset along axis m;
+ *   - element matrices are stored by their off-diagonal upper triangle,
+ *     pairs (a,b), a < b, row-major: U = 6 (2D) or 28 (3D) entries per cell.
+ *     Rows sum to zero (sum_a phi_a = 1), so K[a][a] = -sum_{b != a} K[a][b];
+ *   - stencils are stored as upper-half couplings: for stencil offset index
+ *     sum_m (o_m+1) 3^m above the centre (4 in 2D, 9 in 3D is the centre),
+ *     H = 4 (2D) / 13 (3D) slots, slot-major arrays [H][NV]; the coupling
+ *     of v to v - o is slot o of vertex v - o (symmetry), and the diagonal
+ *     is minus the sum of all off-diagonal couplings of the row;
+ *   - all pointers marked (dev) are device memory owned by the caller; the
+ *     library keeps no reference to them after the call returns;
+ *   - calls are asynchronous on the given stream unless stated otherwise;
+ *   - every call returns MGD_OK (0) or a negative code; mgd_last_error()
+ *     gives a message for the context's last failure.  Argument errors are
+ *     detected before any work is enqueued.
+ */
+#ifndef MGDELAY_H
+#define MGDELAY_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MGD_OK = 0,
+    MGD_EINVAL = -1,    /* bad argument: shape, size, mode or null pointer */
+    MGD_ENOMEM = -2,    /* device allocation failed */
+    MGD_EHIP = -3,      /* a HIP runtime call failed */
+    MGD_ENOCONV = -4,   /* max_cycles reached before the tolerance */
+    MGD_EDIVERGED = -5, /* residual exceeded div_factor times its reference */
+    MGD_ESTARVED = -6   /* tolerance met but the assembly never completed */
+};
+
+enum { MGD_FP64 = 0, MGD_MIXED = 1 };          /* precision of a path */
+enum { MGD_GEOMETRIC = 0, MGD_BOXMG = 1 };     /* transfer operators */
+enum { MGD_STATIONARY = 0, MGD_PCG = 1 };      /* FP64 outer iteration */
+enum { MGD_UPFRONT = 0, MGD_LAZY = 1 };        /* assembly schedule */
+enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1 };
+
+typedef struct mgd_ctx mgd_ctx;   /* per-device context: streams, scratch */
+typedef struct mgd_hier mgd_hier; /* device-resident multigrid hierarchy */
+
+/* Context on HIP device `device`.  Owns two internal streams (assembly and
+ * copies) and a small scratch area; destroy with mgd_destroy. */
+int mgd_create(mgd_ctx **ctx, int device);
+int mgd_destroy(mgd_ctx *ctx);
+const char *mgd_last_error(const mgd_ctx *ctx);
+/* library build identification (static string) */
+const char *mgd_version(void);
+
+/* ------------------------------------------------------------------------
+ * Material description.  eps(x) is evaluated at sub-cell midpoints
+ * x_q = ((i + (q_x + 1/2)/s)/N, ...), q = q_x + s (q_y + s q_z).
+ *   MGD_EPS_CONST   eps = p0
+ *   MGD_EPS_SINE    eps = 1 + p0 prod_m sin(2 pi x_m)
+ *   MGD_EPS_THETA   eps = 1 + (0.3/d) prod_m exp(-p0 x_m) cos(pi p0 x_m)
+ *                   (results section, eq. results:theta-setup)
+ *   MGD_EPS_BALLS   eps = p1 inside any ball (|x-c|^2 <= r^2), else p0;
+ *                   data (dev) = count rows (c_0..c_{d-1}, r)
+ *   MGD_EPS_LATTICE eps = exp(p0 g(x)), g d-linear in lattice values on a
+ *                   (count+1)^d vertex lattice of spacing 1/count, x fastest
+ *   MGD_EPS_BOXES   eps = value of the last box with lo_m <= x_m < hi_m for
+ *                   all m, else p0; data (dev) = count rows (lo.., hi.., eps)
+ *   MGD_EPS_SAMPLES data (dev) = explicit samples [cells][s^d] (assemble
+ *                   only; row i belongs to the i-th listed cell)
+ * ---------------------------------------------------------------------- */
+enum {
+    MGD_EPS_CONST = 0, MGD_EPS_SINE = 1, MGD_EPS_THETA = 2, MGD_EPS_BALLS = 3,
+    MGD_EPS_LATTICE = 4, MGD_EPS_BOXES = 5, MGD_EPS_SAMPLES = 6
+};
+typedef struct {
+    int32_t kind, dim, count, pad;
+    double p0, p1;
+    const double *data;
+} mgd_eps;
+
+/* (1) Element integration, Sec. 4.2 eq. (mg:weak-form-of-assembly): eps held
+ * constant on each of the s^d equal sub-cells (s = 1: one centre sample),
+ * the gradient products integrated exactly on each sub-cell:
+ *     K_c = sum_q eps(x_q) G_q.
+ * dim 2 or 3; n >= 1 cells per axis; s in {1,2,4,8,16}.
+ * cells (dev, int64 [count]) lists the cells, or NULL for all n^d in order.
+ * mode MGD_FP64: FP64 samples and arithmetic, K_out double [count][U].
+ * mode MGD_MIXED: eps split into bf16 hi+lo, contracted with the exactly
+ *   split integer-scaled G table on MFMA with FP32 accumulation, K_out
+ *   float [count][U].
+ * Optional adaptive criterion, Sec. 5.2 eq. (termination criterion): when
+ * K_old (dev, same type and layout as K_out) is given, rel_out[i] (dev
+ * double, may be NULL) receives ||K_new - K_old||_max / ||K_old||_max over
+ * the full 2^d x 2^d matrices and done_out[i] (dev uint8, may be NULL)
+ * receives 1 if rel < C, else 0. */
+int mgd_assemble_cells(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s,
+                       const int64_t *cells, int64_t count, const mgd_eps *eps,
+                       int32_t mode, void *K_out, const void *K_old, double C,
+                       double *rel_out, uint8_t *done_out, hipStream_t stream);
+
+/* (2a) Stencil gather, Sec. 4 (a stencil is one row of A_h): for every
+ * vertex and upper slot, the coupling is the sum of K_c[loc v][loc v+o] over
+ * the cells holding both, in ascending cell order.  K (dev) holds all n^d
+ * cells in order; k_mode MGD_FP64 (double) or MGD_MIXED (float); S_out (dev)
+ * [H][NV] in s_mode's type (double / float). */
+int mgd_gather_stencils(mgd_ctx *ctx, int32_t dim, int32_t n, const void *K, int32_t k_mode,
+                        void *S_out, int32_t s_mode, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Hierarchy.  precision MGD_FP64: every level FP64 half stencils, FP64
+ * vectors.  MGD_MIXED: the finest level is the compressed store of (2b),
+ * coarse levels are FP32 half stencils, cycle vectors are FP32.
+ * Levels: n_0 = n, halved while even and n/2 >= coarsest (>= 2).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t dim, n, precision, transfer, coarsest, pad;
+} mgd_hier_desc;
+
+int mgd_hier_create(mgd_ctx *ctx, const mgd_hier_desc *desc, mgd_hier **out);
+int mgd_hier_destroy(mgd_hier *h);
+int mgd_hier_levels(const mgd_hier *h);
+int mgd_hier_level_n(const mgd_hier *h, int level);
+
+/* FP64 form: install fine half stencils S (dev double [H][NV]). */
+int mgd_hier_set_fine(mgd_ctx *ctx, mgd_hier *h, const double *S, hipStream_t stream);
+
+/* (2b) Hierarchical surplus store, Sec. 5.5.  For a MGD_MIXED hierarchy:
+ * S32 (dev float [H][NV]) are the gathered fine couplings, eps_c (dev float
+ * [n^d]) the centre samples.  Per vertex v and slot j,
+ *   base = ((sum of (double)eps_c over the cells holding v and v+o,
+ *            ascending) * k(o)) * h^{d-2}
+ * with k(o) the unit-eps Q1 coupling (2D -1/6 face, -1/3 diagonal; 3D 0
+ * face, -1/12 edge and corner), and delta = (float)((double)S32 - base).
+ * Tier per vertex: the cheapest of {0: nothing stored} u [min_tier,max_tier]
+ * (1 FP8 E4M3FN, 2 binary16, 3 binary32) whose max error over the stencil
+ * is <= tau = max(tau_abs, tau_rel * ref_v), ref_v = (sum of eps_c around v)
+ * * h^{d-2}; falling back to max_tier.  Tiles of 64 consecutive vertices take
+ * the largest tier of their vertices; each vertex is encoded at its tile's
+ * tier with an E8M0 scale 2^e, e the smallest exponent with
+ * max|delta| <= fmax(tier) 2^e (fmax 448 / 65504), round-to-nearest-even,
+ * saturating.  Tile payload (tier > 0), 64-byte aligned: 64 scale bytes
+ * (e + 127), then for each slot j the 64 entries of the tile (1/2/4 bytes
+ * each).  Tile offsets are in 64-byte units, in tile order. */
+typedef struct {
+    int32_t min_tier, max_tier;
+    double tau_abs, tau_rel;
+} mgd_tier_policy;
+
+int mgd_compress_stencils(mgd_ctx *ctx, mgd_hier *h, const float *S32, const float *eps_c,
+                          const mgd_tier_policy *policy, hipStream_t stream);
+
+/* Copy the compressed store out (dev buffers; pass NULL to skip one):
+ * tile_tier uint8 [ntile], tile_off uint32 [ntile], payload (payload_bytes).
+ * Host scalars ntile / payload_bytes are returned synchronously. */
+int mgd_store_info(mgd_ctx *ctx, const mgd_hier *h, int64_t *ntile, int64_t *payload_bytes,
+                   int64_t tier_tiles[4]);
+int mgd_store_export(mgd_ctx *ctx, const mgd_hier *h, uint8_t *tile_tier, uint32_t *tile_off,
+                     uint8_t *payload, hipStream_t stream);
+
+/* (2c) Galerkin coarse operators A_{l+1} = P^T A_l P for all levels, Sec. 4,
+ * with P d-linear (MGD_GEOMETRIC) or operator-dependent (MGD_BOXMG: coarse
+ * values injected, other fine values from their own stencil row collapsed
+ * onto the line / plane of the interpolating coarse points), R = P^T; then
+ * the dense Cholesky factor of the coarsest interior matrix (FP64). */
+int mgd_coarsen(mgd_ctx *ctx, mgd_hier *h, hipStream_t stream);
+
+/* Decoded FP64 copy of a level's half stencils (dev double [H][NV_l]) and,
+ * for levels above the coarsest, its prolongation weights (dev double
+ * [2^d][NV_l], weight of v toward coarse vertex (v_m >> 1) + B_m). */
+int mgd_level_stencils(mgd_ctx *ctx, const mgd_hier *h, int level, double *S_out, hipStream_t stream);
+int mgd_level_weights(mgd_ctx *ctx, const mgd_hier *h, int level, double *W_out, hipStream_t stream);
+
+/* (3) Multigrid pieces on one level (vectors of the hierarchy's cycle type:
+ * double for MGD_FP64, float for MGD_MIXED; [NV_l], boundary entries 0).
+ *   smooth:   sweeps x u <- u + omega D^{-1} (f - A u)  (damped Jacobi, Sec. 4.1)
+ *   residual: r = f - A u on interior vertices
+ *   restrict: fc = P^T r on interior coarse vertices  (level -> level+1)
+ *   prolong:  u += P ec on interior fine vertices     (level+1 -> level)
+ *   vcycle:   u <- V(nu1,nu2)(u; f) on the finest level: pre-smooth,
+ *             residual, restrict, recurse from zero, coarsest dense solve,
+ *             prolong, post-smooth (multiplicative correction scheme). */
+typedef struct {
+    double omega;
+    int32_t nu1, nu2;
+} mgd_cycle_opts;
+
+int mgd_smooth(mgd_ctx *ctx, mgd_hier *h, int level, void *u, const void *f, int32_t sweeps,
+               double omega, hipStream_t stream);
+int mgd_residual(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *r,
+                 hipStream_t stream);
+int mgd_restrict(mgd_ctx *ctx, mgd_hier *h, int level, const void *r, void *fc, hipStream_t stream);
+int mgd_prolong_add(mgd_ctx *ctx, mgd_hier *h, int level, const void *ec, void *u, hipStream_t stream);
+int mgd_vcycle(mgd_ctx *ctx, mgd_hier *h, void *u, const void *f, const mgd_cycle_opts *opts,
+               hipStream_t stream);
+
+/* FP64 outer residual r = f - A u of the finest operator as stored (the
+ * compressed store decoded in FP64 for MGD_MIXED); u, f, r dev double. */
+int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double *f, double *r,
+                       hipStream_t stream);
+
+/* (4) Solve.  Synchronous: returns when the run stops.
+ * Assembly: s_fixed > 0 integrates every cell once with that s; otherwise
+ * the adaptive ladder s = 1, 2, 4, .., s_max with threshold C (Sec. 5.2).
+ * MGD_UPFRONT finishes every cell's ladder before the first cycle;
+ * MGD_LAZY starts cycling on the centre-sample operator at once and runs the
+ * ladder on a second stream; completed rungs are published (stencils
+ * re-gathered, re-compressed, coarse operators recomputed) at cycle
+ * boundaries: as soon as they complete (MGD_PUBLISH_ASYNC) or rung k right
+ * before cycle k (MGD_PUBLISH_DETERMINISTIC, reproducible bit for bit).
+ * Outer FP64 iteration: MGD_STATIONARY u += V(f - A u), or MGD_PCG
+ * conjugate gradients with one V-cycle as preconditioner (Polak-Ribiere
+ * beta, restarted at every publish).  Stops when every cell's ladder is final
+ * and published and ||f - A u||_2 / ||r_0||_2 <= tol (interior vertices,
+ * r_0 at cycle 0, Sec. 6); MGD_EDIVERGED when the residual exceeds
+ * div_factor times the residual at the last operator change.
+ * f (dev double [NV]) is the load vector; u (dev double [NV]) is the initial
+ * guess on entry and the solution on return. */
+typedef struct {
+    int32_t precision, transfer, outer, schedule;
+    int32_t publish, s_fixed, s_max, nu1;
+    int32_t nu2, max_cycles, coarsest, pad;
+    double C, omega, tol, div_factor;
+    mgd_tier_policy tiers;
+} mgd_solve_opts;
+
+#define MGD_HIST 512
+typedef struct {
+    int32_t status, cycles, nlev, publishes;
+    int32_t checks, pad;     /* residual checks recorded in hist */
+    double r0, r_final;
+    int64_t cells_at_s[5];   /* cells whose final s is 1, 2, 4, 8, 16 */
+    int64_t integrations;    /* cell integrations performed */
+    int64_t tier_tiles[4];   /* fine store tiles per tier at the end */
+    double store_bytes;      /* fine operator bytes at the end */
+    double t_total_ms;       /* wall time of the call */
+    double t_first_cycle_ms; /* wall time until the first cycle was enqueued */
+    double t_cycles_ms;      /* wall time spent in the cycle loop */
+    double hist[MGD_HIST];   /* normalised residual at the start of each cycle */
+} mgd_report;
+
+int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, const double *f, double *u,
+              const mgd_solve_opts *opts, mgd_report *report, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGDELAY_H */

@@ -400,3 +400,29 @@ def compress(d, n, S32_half, eps_c, min_tier, max_tier, tau_abs, tau_rel):
                    np.ascontiguousarray(eps_c, dtype=np.float32), min_tier, max_tier,
                    tau_abs, tau_rel, tt, e8, words)
     return tt, e8, words.reshape(NV, H)
+
+
+def ladder_cells(fld, d, n, cells, s_max, C_thr):
+    """Adaptive ladder of the listed cells only: (K_final [k][2^d][2^d], s_final)."""
+    r = _FieldRef(fld)
+    nl = 1 << d
+    Ks, ss = [], []
+    for c in cells:
+        K = np.zeros(nl * nl)
+        rel = np.zeros(4)
+        s = lib().orc_ladder_cell(r.ptr, d, n, int(c), s_max, C_thr, K, rel)
+        Ks.append(K.reshape(nl, nl))
+        ss.append(s)
+    return np.array(Ks), np.array(ss)
+
+
+def pairs(d):
+    """(a, b) of the packed upper off-diagonal element-matrix entries."""
+    nl = 1 << d
+    return [(a, b) for a in range(nl) for b in range(a + 1, nl)]
+
+
+def pack_pairs(d, K):
+    """Full element matrices [k][2^d][2^d] -> packed upper pairs [k][U]."""
+    K = np.asarray(K)
+    return np.ascontiguousarray(np.stack([K[:, a, b] for a, b in pairs(d)], axis=1))

@@ -1,0 +1,13 @@
+"""MI355X (gfx950) library for delayed approximate matrix assembly in
+multigrid with dynamic precisions (Murray & Weinzierl, arXiv:2005.03606).
+
+Thin Python binding over the C ABI in ``include/mgdelay.h``: argument
+marshalling only, every step runs in the HIP kernels of ``libmgdelay.so``.
+PyTorch supplies device memory and streams.  Importing this package does not
+load the library; the first call does, and raises if it is missing.
+"""
+from .binding import (  # noqa: F401
+    FP64, MIXED, GEOMETRIC, BOXMG, STATIONARY, PCG, UPFRONT, LAZY,
+    PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, MgdError, Context, Eps, Hierarchy,
+    assemble_cells, gather_stencils, solve, n_half, n_pairs, lib, library_path,
+)

@@ -1,0 +1,323 @@
+"""ctypes binding of libmgdelay.so (same names as the C ABI, minus the prefix)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libmgdelay.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED, ESTARVED = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+GEOMETRIC, BOXMG = 0, 1
+STATIONARY, PCG = 0, 1
+UPFRONT, LAZY = 0, 1
+PUBLISH_ASYNC, PUBLISH_DETERMINISTIC = 0, 1
+EPS_SAMPLES = 6
+HIST = 512
+
+
+class MgdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mgd error {code}: {msg}")
+        self.code = code
+
+
+class _Eps(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("count", C.c_int32), ("pad", C.c_int32),
+                ("p0", C.c_double), ("p1", C.c_double), ("data", C.c_void_p)]
+
+
+class _HierDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("precision", C.c_int32),
+                ("transfer", C.c_int32), ("coarsest", C.c_int32), ("pad", C.c_int32)]
+
+
+class _Tier(C.Structure):
+    _fields_ = [("min_tier", C.c_int32), ("max_tier", C.c_int32),
+                ("tau_abs", C.c_double), ("tau_rel", C.c_double)]
+
+
+class _CycleOpts(C.Structure):
+    _fields_ = [("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32)]
+
+
+class _SolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("transfer", C.c_int32), ("outer", C.c_int32),
+                ("schedule", C.c_int32), ("publish", C.c_int32), ("s_fixed", C.c_int32),
+                ("s_max", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("max_cycles", C.c_int32), ("coarsest", C.c_int32), ("pad", C.c_int32),
+                ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
+                ("div_factor", C.c_double), ("tiers", _Tier)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("cycles", C.c_int32), ("nlev", C.c_int32),
+                ("publishes", C.c_int32), ("checks", C.c_int32), ("pad", C.c_int32),
+                ("r0", C.c_double), ("r_final", C.c_double),
+                ("cells_at_s", C.c_int64 * 5), ("integrations", C.c_int64),
+                ("tier_tiles", C.c_int64 * 4), ("store_bytes", C.c_double),
+                ("t_total_ms", C.c_double), ("t_first_cycle_ms", C.c_double),
+                ("t_cycles_ms", C.c_double), ("hist", C.c_double * HIST)]
+
+
+_lib = None
+_P = C.c_void_p
+_I = C.c_int32
+
+
+def lib():
+    """Load libmgdelay.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"{library_path} is missing: build it with paper_2005_03606_amd/build.py "
+                           "(there is no CPU fallback)")
+    L = C.CDLL(library_path)
+    sig = {
+        "mgd_create": ([C.POINTER(_P), C.c_int], C.c_int),
+        "mgd_destroy": ([_P], C.c_int),
+        "mgd_last_error": ([_P], C.c_char_p),
+        "mgd_version": ([], C.c_char_p),
+        "mgd_assemble_cells": ([_P, _I, _I, _I, _P, C.c_int64, C.POINTER(_Eps), _I, _P, _P,
+                                C.c_double, _P, _P, _P], C.c_int),
+        "mgd_gather_stencils": ([_P, _I, _I, _P, _I, _P, _I, _P], C.c_int),
+        "mgd_hier_create": ([_P, C.POINTER(_HierDesc), C.POINTER(_P)], C.c_int),
+        "mgd_hier_destroy": ([_P], C.c_int),
+        "mgd_hier_levels": ([_P], C.c_int),
+        "mgd_hier_level_n": ([_P, C.c_int], C.c_int),
+        "mgd_hier_set_fine": ([_P, _P, _P, _P], C.c_int),
+        "mgd_compress_stencils": ([_P, _P, _P, _P, C.POINTER(_Tier), _P], C.c_int),
+        "mgd_store_info": ([_P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                            C.POINTER(C.c_int64 * 4)], C.c_int),
+        "mgd_store_export": ([_P, _P, _P, _P, _P, _P], C.c_int),
+        "mgd_coarsen": ([_P, _P, _P], C.c_int),
+        "mgd_level_stencils": ([_P, _P, C.c_int, _P, _P], C.c_int),
+        "mgd_level_weights": ([_P, _P, C.c_int, _P, _P], C.c_int),
+        "mgd_smooth": ([_P, _P, C.c_int, _P, _P, _I, C.c_double, _P], C.c_int),
+        "mgd_residual": ([_P, _P, C.c_int, _P, _P, _P, _P], C.c_int),
+        "mgd_restrict": ([_P, _P, C.c_int, _P, _P, _P], C.c_int),
+        "mgd_prolong_add": ([_P, _P, C.c_int, _P, _P, _P], C.c_int),
+        "mgd_vcycle": ([_P, _P, _P, _P, C.POINTER(_CycleOpts), _P], C.c_int),
+        "mgd_outer_residual": ([_P, _P, _P, _P, _P, _P], C.c_int),
+        "mgd_solve": ([_P, _I, _I, C.POINTER(_Eps), _P, _P, C.POINTER(_SolveOpts),
+                       C.POINTER(_Report), _P], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def n_half(dim):
+    return 4 if dim == 2 else 13
+
+
+def n_pairs(dim):
+    return 6 if dim == 2 else 28
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """Per-device library context (mgd_create / mgd_destroy)."""
+
+    def __init__(self, device=0):
+        L = lib()
+        h = _P()
+        rc = L.mgd_create(C.byref(h), device)
+        if rc != OK:
+            raise MgdError(rc, f"mgd_create(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def check(self, rc):
+        if rc != OK and rc not in (ENOCONV, EDIVERGED, ESTARVED):
+            raise MgdError(rc, lib().mgd_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mgd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Eps:
+    """Material descriptor on the device (any object with kind, dim, p0, p1,
+    count and a float64 `data` array, e.g. workload.Field)."""
+
+    def __init__(self, field, device="cuda"):
+        import numpy as np
+        data = np.ascontiguousarray(getattr(field, "data", np.zeros(0)), dtype=np.float64)
+        self.data = torch.from_numpy(data if data.size else np.zeros(1)).to(device)
+        self.s = _Eps(field.kind, field.dim, field.count, 0, field.p0, field.p1, self.data.data_ptr())
+        self.dim = field.dim
+
+    @classmethod
+    def samples(cls, dim, samples):
+        obj = cls.__new__(cls)
+        obj.data = samples.contiguous()
+        obj.s = _Eps(EPS_SAMPLES, dim, 0, 0, 0.0, 0.0, obj.data.data_ptr())
+        obj.dim = dim
+        return obj
+
+
+def assemble_cells(ctx, dim, n, s, eps, mode=FP64, cells=None, K_old=None, C_thr=0.01,
+                   want_rel=False, stream=None):
+    """Element matrices [count][U] (upper off-diagonal pairs); with K_old also
+    the relative change and the below-threshold flags."""
+    dev = torch.device("cuda", ctx.device)
+    count = (n ** dim) if cells is None else int(cells.numel())
+    dt = torch.float64 if mode == FP64 else torch.float32
+    K = torch.empty((count, n_pairs(dim)), dtype=dt, device=dev)
+    rel = torch.empty(count, dtype=torch.float64, device=dev) if (K_old is not None and want_rel) else None
+    done = torch.empty(count, dtype=torch.uint8, device=dev) if K_old is not None else None
+    ctx.check(lib().mgd_assemble_cells(ctx.h, dim, n, s, _ptr(cells), count, C.byref(eps.s), mode,
+                                       _ptr(K), _ptr(K_old), C_thr, _ptr(rel), _ptr(done), _stream(stream)))
+    return K, rel, done
+
+
+def gather_stencils(ctx, dim, n, K, k_mode=FP64, s_mode=FP64, stream=None):
+    """Upper-half couplings [H][NV] from element matrices of all cells."""
+    dt = torch.float64 if s_mode == FP64 else torch.float32
+    S = torch.empty((n_half(dim), (n + 1) ** dim), dtype=dt, device=K.device)
+    ctx.check(lib().mgd_gather_stencils(ctx.h, dim, n, _ptr(K), k_mode, _ptr(S), s_mode, _stream(stream)))
+    return S
+
+
+class Hierarchy:
+    def __init__(self, ctx, dim, n, precision=FP64, transfer=GEOMETRIC, coarsest=2):
+        self.ctx, self.dim, self.n, self.precision = ctx, dim, n, precision
+        d = _HierDesc(dim, n, precision, transfer, coarsest, 0)
+        h = _P()
+        ctx.check(lib().mgd_hier_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+        self.vdtype = torch.float64 if precision == FP64 else torch.float32
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mgd_hier_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nlev(self):
+        return lib().mgd_hier_levels(self.h)
+
+    def level_n(self, l):
+        return lib().mgd_hier_level_n(self.h, l)
+
+    def nv(self, l=0):
+        return (self.level_n(l) + 1) ** self.dim
+
+    def vec(self, l=0):
+        return torch.zeros(self.nv(l), dtype=self.vdtype, device=torch.device("cuda", self.ctx.device))
+
+    def set_fine(self, S64, stream=None):
+        self.ctx.check(lib().mgd_hier_set_fine(self.ctx.h, self.h, _ptr(S64), _stream(stream)))
+
+    def compress(self, S32, eps_c, min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=0.0, stream=None):
+        pol = _Tier(min_tier, max_tier, tau_abs, tau_rel)
+        self.ctx.check(lib().mgd_compress_stencils(self.ctx.h, self.h, _ptr(S32), _ptr(eps_c),
+                                                   C.byref(pol), _stream(stream)))
+
+    def coarsen(self, stream=None):
+        self.ctx.check(lib().mgd_coarsen(self.ctx.h, self.h, _stream(stream)))
+
+    def store_info(self):
+        nt, pb, tiers = C.c_int64(), C.c_int64(), (C.c_int64 * 4)()
+        self.ctx.check(lib().mgd_store_info(self.ctx.h, self.h, C.byref(nt), C.byref(pb), C.byref(tiers)))
+        return nt.value, pb.value, list(tiers)
+
+    def store_export(self, stream=None):
+        nt, pb, _ = self.store_info()
+        dev = torch.device("cuda", self.ctx.device)
+        tt = torch.empty(nt, dtype=torch.uint8, device=dev)
+        off = torch.empty(nt, dtype=torch.int32, device=dev)
+        pay = torch.empty(max(pb, 1), dtype=torch.uint8, device=dev)
+        self.ctx.check(lib().mgd_store_export(self.ctx.h, self.h, _ptr(tt), _ptr(off), _ptr(pay),
+                                              _stream(stream)))
+        return tt, off, pay[:pb]
+
+    def level_stencils(self, l, stream=None):
+        out = torch.empty((n_half(self.dim), self.nv(l)), dtype=torch.float64,
+                          device=torch.device("cuda", self.ctx.device))
+        self.ctx.check(lib().mgd_level_stencils(self.ctx.h, self.h, l, _ptr(out), _stream(stream)))
+        return out
+
+    def level_weights(self, l, stream=None):
+        out = torch.empty((1 << self.dim, self.nv(l)), dtype=torch.float64,
+                          device=torch.device("cuda", self.ctx.device))
+        self.ctx.check(lib().mgd_level_weights(self.ctx.h, self.h, l, _ptr(out), _stream(stream)))
+        return out
+
+    def smooth(self, l, u, f, sweeps=1, omega=0.6, stream=None):
+        self.ctx.check(lib().mgd_smooth(self.ctx.h, self.h, l, _ptr(u), _ptr(f), sweeps, omega, _stream(stream)))
+
+    def residual(self, l, u, f, r, stream=None):
+        self.ctx.check(lib().mgd_residual(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))
+
+    def restrict(self, l, r, fc, stream=None):
+        self.ctx.check(lib().mgd_restrict(self.ctx.h, self.h, l, _ptr(r), _ptr(fc), _stream(stream)))
+
+    def prolong_add(self, l, ec, u, stream=None):
+        self.ctx.check(lib().mgd_prolong_add(self.ctx.h, self.h, l, _ptr(ec), _ptr(u), _stream(stream)))
+
+    def vcycle(self, u, f, omega=0.6, nu1=2, nu2=2, stream=None):
+        o = _CycleOpts(omega, nu1, nu2)
+        self.ctx.check(lib().mgd_vcycle(self.ctx.h, self.h, _ptr(u), _ptr(f), C.byref(o), _stream(stream)))
+
+    def outer_residual(self, u, f, r, stream=None):
+        self.ctx.check(lib().mgd_outer_residual(self.ctx.h, self.h, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))
+
+
+def solve(ctx, dim, n, eps, f, u=None, precision=FP64, transfer=GEOMETRIC, outer=STATIONARY,
+          schedule=UPFRONT, publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6,
+          nu1=2, nu2=2, tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0,
+          min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=0.0, stream=None):
+    """Full solve (synchronous).  f, u: device float64 [(n+1)^d]; u is the
+    initial guess (zero if None) and holds the solution on return."""
+    if u is None:
+        u = torch.zeros_like(f)
+    op = _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
+                    max_cycles, coarsest, 0, C_thr, omega, tol, div_factor,
+                    _Tier(min_tier, max_tier, tau_abs, tau_rel))
+    rep = _Report()
+    rc = ctx.check(lib().mgd_solve(ctx.h, dim, n, C.byref(eps.s), _ptr(f), _ptr(u), C.byref(op),
+                                   C.byref(rep), _stream(stream)))
+    k = rep.checks
+    report = dict(status=rc, cycles=rep.cycles, nlev=rep.nlev, publishes=rep.publishes, r0=rep.r0,
+                  r_final=rep.r_final, cells_at_s=list(rep.cells_at_s), integrations=rep.integrations,
+                  tier_tiles=list(rep.tier_tiles), store_bytes=rep.store_bytes,
+                  t_total_ms=rep.t_total_ms, t_first_cycle_ms=rep.t_first_cycle_ms,
+                  t_cycles_ms=rep.t_cycles_ms, hist=list(rep.hist[:k]))
+    return u, report

@@ -1,0 +1,242 @@
+// Shared definitions of the gfx950 library: grid geometry, half-stencil
+// layout, compressed-store decoding and the host-side objects.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <string>
+#include <vector>
+
+#include "../../include/mgdelay.h"
+
+#define MGD_MAXLEV 24
+
+// ----------------------------------------------------------------- errors
+struct mgd_ctx {
+    int device = 0;
+    int num_cu = 256;
+    hipStream_t s_asm = nullptr;  // assembly stream (default priority)
+    char err[512] = {0};
+    // small device scratch for reductions and scalars
+    double *scal = nullptr;       // [64] device scalars
+    double *partial = nullptr;    // [partial_cap] block partial sums
+    int64_t partial_cap = 0;
+    double *host_scal = nullptr;  // pinned [64]
+};
+
+int mgd_fail(mgd_ctx *ctx, int code, const char *fmt, ...);
+#define HIPCHK(ctx, x)                                                               \
+    do {                                                                             \
+        hipError_t e_ = (x);                                                         \
+        if (e_ != hipSuccess)                                                        \
+            return mgd_fail((ctx), MGD_EHIP, "%s failed: %s (%s:%d)", #x,           \
+                            hipGetErrorString(e_), __FILE__, __LINE__);              \
+    } while (0)
+
+// ------------------------------------------------------------- geometry
+__host__ __device__ constexpr int n_half(int D) { return D == 2 ? 4 : 13; }
+__host__ __device__ constexpr int n_pairs(int D) { return D == 2 ? 6 : 28; }
+
+// offset component m of half slot j (slot j = stencil index centre+1+j)
+__host__ __device__ inline int half_off(int D, int j, int m)
+{
+    int i = (D == 2 ? 5 : 14) + j;
+    for (int k = 0; k < m; ++k) i /= 3;
+    return i % 3 - 1;
+}
+
+// linear vertex offset of half slot j on a grid with nv vertices per axis
+__host__ __device__ inline int64_t half_lin(int D, int j, int64_t nv)
+{
+    int64_t s = half_off(D, j, 0) + half_off(D, j, 1) * nv;
+    if (D == 3) s += (int64_t)half_off(D, j, 2) * nv * nv;
+    return s;
+}
+
+// pair index of local vertices a < b among the upper off-diagonal entries
+__host__ __device__ inline int pair_index(int D, int a, int b)
+{
+    int nl = 1 << D;
+    if (a > b) { int t = a; a = b; b = t; }
+    // row a holds nl-1-a entries; rows before a hold sum_{r<a} (nl-1-r)
+    return a * (nl - 1) - a * (a - 1) / 2 + (b - a - 1);
+}
+
+template <int D> struct Grid {
+    int n;      // cells per axis
+    int64_t nv; // vertices per axis
+    int64_t NV;
+    __host__ __device__ Grid(int n_) : n(n_), nv(n_ + 1), NV(1)
+    {
+        for (int m = 0; m < D; ++m) NV *= nv;
+    }
+    __device__ inline void coords(int64_t v, int *x) const
+    {
+        x[0] = (int)(v % nv);
+        int64_t t = v / nv;
+        if (D == 2) { x[1] = (int)t; }
+        else { x[1] = (int)(t % nv); x[2] = (int)(t / nv); }
+    }
+    __device__ inline bool interior(const int *x) const
+    {
+        for (int m = 0; m < D; ++m)
+            if (x[m] == 0 || x[m] == n) return false;
+        return true;
+    }
+    __device__ inline int64_t vid(const int *x) const
+    {
+        return D == 2 ? x[0] + nv * x[1] : x[0] + nv * (x[1] + nv * (int64_t)x[2]);
+    }
+};
+
+// ------------------------------------------------------ compressed store
+// Tiles of 64 consecutive vertices.  Tier 0: nothing stored.  Tier t > 0:
+// [64 scale bytes][slot 0: 64 entries][slot 1] ... entries of 1/2/4 bytes.
+__host__ __device__ inline int tier_bytes(int t) { return t == 1 ? 1 : t == 2 ? 2 : t == 3 ? 4 : 0; }
+__host__ __device__ inline uint32_t tile_units(int t, int H)
+{
+    return t == 0 ? 0u : (uint32_t)((64 + 64 * H * tier_bytes(t)) / 64);
+}
+
+__device__ inline float e4m3_to_float(uint32_t b)
+{
+    uint32_t s = (b & 0x80u) << 24, e = (b >> 3) & 15u, m = b & 7u;
+    float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+    return __uint_as_float(__float_as_uint(v) | s);
+}
+
+__device__ inline float e8m0_to_float(uint32_t e8)
+{
+    return e8 ? __uint_as_float(e8 << 23) : __uint_as_float(0x00400000u);
+}
+
+struct StoreView {
+    const uint8_t *tier;
+    const uint32_t *off;
+    const uint8_t *payload;
+    const float *eps_c;
+    int n;
+    int64_t NV;
+    // decoded delta of slot j of vertex v (FP32; exact for every tier)
+    __device__ inline float delta(int64_t v, int j, int H) const
+    {
+        int64_t t = v >> 6;
+        int tt = tier[t];
+        if (tt == 0) return 0.0f;
+        const uint8_t *base = payload + (size_t)off[t] * 64;
+        int l = (int)(v & 63);
+        float sc = e8m0_to_float(base[l]);
+        const uint8_t *slot = base + 64 + (size_t)j * 64 * tier_bytes(tt);
+        if (tt == 2) {
+            uint16_t hb = ((const uint16_t *)slot)[l];
+            return (float)__builtin_bit_cast(_Float16, hb) * sc;
+        }
+        if (tt == 1) return e4m3_to_float(slot[l]) * sc;
+        return ((const float *)slot)[l];
+    }
+};
+
+// unit-eps Q1 coupling of two vertices differing in `nz` axes
+__host__ __device__ inline double kref_unit(int D, int nz)
+{
+    if (D == 2) return nz == 1 ? -1.0 / 6.0 : -1.0 / 3.0;
+    return nz == 1 ? 0.0 : -1.0 / 12.0;
+}
+
+// centre-sample base coupling of slot j at vertex v (FP64, fixed order:
+// cells holding v and v+o in ascending index, then * k(o), then * h^{d-2}).
+template <int D>
+__device__ inline double base_coupling64(const float *eps_c, int n, const int *x, int j, double *ref)
+{
+    int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
+    int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
+    double sum = 0.0, sall = 0.0;
+    for (int B = (1 << D) - 1; B >= 0; --B) {
+        bool ok = true, shared = true;
+        int64_t c = 0, stride = 1;
+        for (int m = 0; m < D; ++m) {
+            int bm = (B >> m) & 1, cm = x[m] - bm, wm = bm + o[m];
+            if (cm < 0 || cm >= n) ok = false;
+            if (wm < 0 || wm > 1) shared = false;
+            c += (int64_t)cm * stride;
+            stride *= n;
+        }
+        if (!ok) continue;
+        double e = (double)eps_c[c];
+        sall = __dadd_rn(sall, e);
+        if (shared) sum = __dadd_rn(sum, e);
+    }
+    double hp = (D == 2) ? 1.0 : 1.0 / (double)n;
+    if (ref) *ref = __dmul_rn(sall, hp);
+    return __dmul_rn(__dmul_rn(sum, kref_unit(D, nz)), hp);
+}
+
+// ------------------------------------------------------- host objects
+struct OpSet {           // operators of every level (one version)
+    double *S64[MGD_MAXLEV] = {};  // half stencils (FP64 form)
+    float *S32[MGD_MAXLEV] = {};   // half stencils (mixed: coarse levels and decoded level 0)
+    void *W[MGD_MAXLEV] = {};      // BoxMG weights [2^d][NV_l] (double / float)
+    // compressed finest store (mixed)
+    uint8_t *tier = nullptr;
+    uint32_t *toff = nullptr;
+    uint8_t *payload = nullptr;
+    float *eps_c = nullptr;
+    uint32_t *units_total = nullptr;  // device scalar: payload size in 64-byte units
+    int64_t ntile = 0, payload_cap_units = 0;
+    double *chol = nullptr;  // dense Cholesky factor of the coarsest interior matrix
+};
+
+struct mgd_hier {
+    mgd_ctx *ctx = nullptr;
+    int dim = 2, n = 0, precision = MGD_FP64, transfer = MGD_GEOMETRIC, coarsest = 2;
+    int nlev = 0, H = 4;
+    int nl[MGD_MAXLEV] = {};
+    int64_t NV[MGD_MAXLEV] = {};
+    int64_t m_coarse = 0;
+    OpSet ops;
+    // cycle vectors (double for FP64, float for mixed)
+    void *u[MGD_MAXLEV] = {}, *f[MGD_MAXLEV] = {}, *r[MGD_MAXLEV] = {}, *t[MGD_MAXLEV] = {};
+    // scratch for compression
+    float *delta = nullptr;
+    uint8_t *vtier = nullptr;
+    size_t vec_bytes() const { return precision == MGD_FP64 ? 8 : 4; }
+};
+
+// ------------------------------------------------------- launch helpers
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// host-side allocation helpers (return MGD_ENOMEM through ctx on failure)
+int dev_alloc(mgd_ctx *ctx, void **p, size_t bytes);
+void dev_free(void *p);
+
+// kernels / launchers implemented in the .hip files
+int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, int64_t count,
+                    const mgd_eps *eps, int mode, void *K_out, const void *K_old, int k_by_cell,
+                    double C, double *rel_out, uint8_t *done_out, const int64_t *count_dev,
+                    hipStream_t st);
+int launch_compact_open(mgd_ctx *ctx, const uint8_t *done, const int64_t *cells_in, const int64_t *count_dev,
+                        int64_t count_bound, int32_t *block_tmp, int64_t *cells_out, int64_t *count_out,
+                        hipStream_t st);
+int launch_gather(mgd_ctx *ctx, int dim, int n, const void *K, int k_mode, void *S, int s_mode,
+                  hipStream_t st);
+int launch_centre_eps(mgd_ctx *ctx, int dim, int n, const mgd_eps *eps, float *eps_c, hipStream_t st);
+int opset_alloc(mgd_hier *h, OpSet &o);
+void opset_free(OpSet &o);
+int compress_into(mgd_hier *h, OpSet &o, const float *S32, const float *eps_c,
+                  const mgd_tier_policy *pol, hipStream_t st);
+int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st);
+int decode_level_f64(mgd_hier *h, const OpSet &o, int level, double *out, hipStream_t st);
+int weights_f64(mgd_hier *h, const OpSet &o, int level, double *out, hipStream_t st);
+int cycle_smooth(mgd_hier *h, const OpSet &o, int level, void *u, const void *f, void *tmp,
+                 int sweeps, double omega, bool zero_guess, hipStream_t st);
+int cycle_residual(mgd_hier *h, const OpSet &o, int level, const void *u, const void *f, void *r,
+                   hipStream_t st);
+int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *fc, hipStream_t st);
+int cycle_prolong(mgd_hier *h, const OpSet &o, int level, const void *ec, void *u, hipStream_t st);
+int cycle_coarse_solve(mgd_hier *h, const OpSet &o, void *u, const void *f, hipStream_t st);
+int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega, int nu1, int nu2,
+               bool zero_guess, hipStream_t st);
+int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r,
+                   double *norm2_dev, hipStream_t st);
+int hier_alloc_levels(mgd_hier *h);
+void hier_free(mgd_hier *h);

@@ -1,0 +1,582 @@
+// Multigrid cycle kernels (paper Sec. 4 and 4.1): damped Jacobi
+// u <- u + omega D^{-1} (f - A u), residual, restriction R = P^T,
+// prolongation, on any operator view: FP64 / FP32 half stencils or the
+// compressed surplus store decoded on the fly; plus the FP64 outer residual
+// and the vector kernels of the outer iteration, with deterministic
+// (fixed-order) reductions.
+#include "common.h"
+
+// ------------------------------------------------------------ operator views
+template <typename T> struct OpHalf {
+    const T *S;
+    int64_t NV;
+    __device__ inline T c(int64_t v, int j, const int *) const { return S[(int64_t)j * NV + v]; }
+};
+
+// compressed fine store: base from the centre samples (in T) + decoded delta
+template <int D, typename T> struct OpComp {
+    StoreView sv;
+    int n;
+    T hp;
+    __device__ inline T c(int64_t v, int j, const int *x) const
+    {
+        // x: coordinates of v
+        int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
+        int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
+        T base = (T)0;
+        if (!(D == 3 && nz == 1)) {
+            T sum = (T)0;
+            for (int B = (1 << D) - 1; B >= 0; --B) {
+                bool ok = true;
+                int64_t cc = 0, stride = 1;
+                for (int m = 0; m < D; ++m) {
+                    int bm = (B >> m) & 1, cm = x[m] - bm, wm = bm + o[m];
+                    if (cm < 0 || cm >= n || wm < 0 || wm > 1) ok = false;
+                    cc += (int64_t)cm * stride;
+                    stride *= n;
+                }
+                if (ok) sum += (T)sv.eps_c[cc];
+            }
+            base = sum * (T)kref_unit(D, nz) * hp;
+        }
+        return base + (T)sv.delta(v, j, n_half(D));
+    }
+};
+
+// ------------------------------------------------------------ reductions
+template <int BS> __device__ inline double block_sum(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = BS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// (A u)_v and the diagonal D_v = -sum of the couplings of v (interior v)
+template <int D, class Op, typename T>
+__device__ inline void apply_row(const Op &A, const Grid<D> &g, int64_t v, const int *x, const T *u, T &Au, T &Dv)
+{
+    constexpr int H = n_half(D);
+    T acc = (T)0, dsum = (T)0;
+    for (int j = 0; j < H; ++j) {
+        int64_t lin = half_lin(D, j, g.nv);
+        T a = A.c(v, j, x);
+        acc += a * u[v + lin];
+        dsum += a;
+        int y[3] = {x[0] - half_off(D, j, 0), x[1] - half_off(D, j, 1), D == 3 ? x[2] - half_off(D, j, 2) : 0};
+        T b = A.c(v - lin, j, y);
+        acc += b * u[v - lin];
+        dsum += b;
+    }
+    Dv = -dsum;
+    Au = Dv * u[v] + acc;
+}
+
+// mode 0: Jacobi sweep out = u + omega (f - A u) / D; mode 1: residual out = f - A u;
+// zero_guess: u treated as 0 (first sweep from a zero start).
+template <int D, class Op, typename T>
+__global__ __launch_bounds__(256) void k_sweep(Op A, int n, const T *u, const T *f, T *out, T omega, int mode,
+                                               int zero_guess, double *partial)
+{
+    __shared__ double red[256];
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0;
+    if (v < g.NV) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) {
+            out[v] = (T)0;
+        } else {
+            T Au, Dv;
+            if (zero_guess) {
+                constexpr int H = n_half(D);
+                T dsum = (T)0;
+                for (int j = 0; j < H; ++j) {
+                    int64_t lin = half_lin(D, j, g.nv);
+                    int y[3] = {x[0] - half_off(D, j, 0), x[1] - half_off(D, j, 1), D == 3 ? x[2] - half_off(D, j, 2) : 0};
+                    dsum += A.c(v, j, x) + A.c(v - lin, j, y);
+                }
+                Dv = -dsum;
+                Au = (T)0;
+            } else {
+                apply_row<D, Op, T>(A, g, v, x, u, Au, Dv);
+            }
+            T r = f[v] - Au;
+            rr = (double)r * (double)r;
+            if (mode == 0) out[v] = (zero_guess ? (T)0 : u[v]) + omega * r / Dv;
+            else out[v] = r;
+        }
+    }
+    if (partial) {
+        double s = block_sum<256>(rr, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+__device__ inline double pw1c(int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; }
+
+template <int D, typename T, typename TW>
+__device__ inline T wt(const TW *W, int64_t NV, int64_t v, const int *x, const int *X)
+{
+    int B = 0;
+    for (int m = 0; m < D; ++m) {
+        int b = X[m] - (x[m] >> 1);
+        if (b < 0 || b > 1) return (T)0;
+        B |= b << m;
+    }
+    if (W) return (T)W[(int64_t)B * NV + v];
+    double p = 1.0;
+    for (int m = 0; m < D; ++m) p *= pw1c(x[m] - 2 * X[m]);
+    return (T)p;
+}
+
+// fc[X] = sum_v P[v][X] r[v] over the 3^d fine vertices around 2X (interior X)
+template <int D, typename T>
+__global__ void k_restrict(const T *W, int nf, const T *r, T *fc)
+{
+    Grid<D> gf(nf), gc(nf / 2);
+    int64_t V = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (V >= gc.NV) return;
+    int X[3] = {0, 0, 0};
+    gc.coords(V, X);
+    if (!gc.interior(X)) { fc[V] = (T)0; return; }
+    T s = (T)0;
+    constexpr int ns = D == 2 ? 9 : 27;
+    for (int sv = 0; sv < ns; ++sv) {
+        int x[3] = {0, 0, 0}, t = sv;
+        for (int m = 0; m < D; ++m) { x[m] = 2 * X[m] + t % 3 - 1; t /= 3; }
+        int64_t v = gf.vid(x);
+        s += wt<D, T, T>(W, gf.NV, v, x, X) * r[v];
+    }
+    fc[V] = s;
+}
+
+// u[v] += sum_B P[v][corner B] e[corner B] (interior fine v)
+template <int D, typename T>
+__global__ void k_prolong(const T *W, int nf, const T *ec, T *u)
+{
+    Grid<D> gf(nf), gc(nf / 2);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= gf.NV) return;
+    int x[3] = {0, 0, 0};
+    gf.coords(v, x);
+    if (!gf.interior(x)) return;
+    T s = (T)0;
+    for (int B = 0; B < (1 << D); ++B) {
+        int X[3] = {0, 0, 0};
+        bool ok = true;
+        for (int m = 0; m < D; ++m) {
+            X[m] = (x[m] >> 1) + ((B >> m) & 1);
+            if (X[m] > gc.n) ok = false;
+        }
+        if (!ok) continue;
+        T w = wt<D, T, T>(W, gf.NV, v, x, X);
+        if (w != (T)0) s += w * ec[gc.vid(X)];
+    }
+    u[v] += s;
+}
+
+template <typename T> __global__ void k_fill(T *a, int64_t n, T val)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = val;
+}
+
+// ------------------------------------------------------------ dispatch
+int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
+StoreView store_view(const mgd_hier *h, const OpSet &o);
+
+template <int D, typename T, class F> static int with_op(mgd_hier *h, const OpSet &o, int level, F fn)
+{
+    if (h->precision == MGD_FP64) return fn(OpHalf<double>{o.S64[level], h->NV[level]});
+    if (level > 0) return fn(OpHalf<float>{o.S32[level], h->NV[level]});
+    OpComp<D, float> c{store_view(h, o), h->n, (float)(D == 2 ? 1.0 : 1.0 / h->n)};
+    return fn(c);
+}
+
+template <int D, typename T>
+static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *f, T *out, double omega, int mode,
+                   bool zero_guess, double *partial, hipStream_t st)
+{
+    int n = h->nl[level];
+    dim3 gr(grid_for(h->NV[level], 256));
+    auto go = [&](auto A) {
+        hipLaunchKernelGGL((k_sweep<D, decltype(A), T>), gr, dim3(256), 0, st, A, n, u, f, out, (T)omega, mode,
+                           zero_guess ? 1 : 0, partial);
+        return MGD_OK;
+    };
+    if (h->precision == MGD_FP64) go(OpHalf<double>{o.S64[level], h->NV[level]});
+    else if (level > 0) go(OpHalf<float>{o.S32[level], h->NV[level]});
+    else go(OpComp<D, float>{store_view(h, o), h->n, (float)(D == 2 ? 1.0 : 1.0 / h->n)});
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+static int sweep(mgd_hier *h, const OpSet &o, int level, const void *u, const void *f, void *out, double omega,
+                 int mode, bool zero_guess, double *partial, hipStream_t st)
+{
+    if (h->precision == MGD_FP64) {
+        if (h->dim == 2) return sweep_t<2, double>(h, o, level, (const double *)u, (const double *)f, (double *)out, omega, mode, zero_guess, partial, st);
+        return sweep_t<3, double>(h, o, level, (const double *)u, (const double *)f, (double *)out, omega, mode, zero_guess, partial, st);
+    }
+    if (h->dim == 2) return sweep_t<2, float>(h, o, level, (const float *)u, (const float *)f, (float *)out, omega, mode, zero_guess, partial, st);
+    return sweep_t<3, float>(h, o, level, (const float *)u, (const float *)f, (float *)out, omega, mode, zero_guess, partial, st);
+}
+
+int cycle_smooth(mgd_hier *h, const OpSet &o, int level, void *u, const void *f, void *tmp, int sweeps,
+                 double omega, bool zero_guess, hipStream_t st)
+{
+    // ping-pong u -> tmp -> u; an odd count ends with a copy back
+    for (int k = 0; k < sweeps; ++k) {
+        const void *src = (k % 2 == 0) ? u : tmp;
+        void *dst = (k % 2 == 0) ? tmp : u;
+        int rc = sweep(h, o, level, src, f, dst, omega, 0, zero_guess && k == 0, nullptr, st);
+        if (rc) return rc;
+    }
+    if (sweeps % 2 == 1)
+        HIPCHK(h->ctx, hipMemcpyAsync(u, tmp, h->NV[level] * h->vec_bytes(), hipMemcpyDeviceToDevice, st));
+    return MGD_OK;
+}
+
+int cycle_residual(mgd_hier *h, const OpSet &o, int level, const void *u, const void *f, void *r, hipStream_t st)
+{
+    return sweep(h, o, level, u, f, r, 0.0, 1, false, nullptr, st);
+}
+
+int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *fc, hipStream_t st)
+{
+    int nf = h->nl[level];
+    dim3 gr(grid_for(h->NV[level + 1], 256));
+    bool box = h->transfer == MGD_BOXMG;
+    if (h->precision == MGD_FP64) {
+        const double *W = box ? (const double *)o.W[level] : nullptr;
+        if (h->dim == 2) hipLaunchKernelGGL((k_restrict<2, double>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+        else hipLaunchKernelGGL((k_restrict<3, double>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+    } else {
+        const float *W = box ? (const float *)o.W[level] : nullptr;
+        if (h->dim == 2) hipLaunchKernelGGL((k_restrict<2, float>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+        else hipLaunchKernelGGL((k_restrict<3, float>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+    }
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int cycle_prolong(mgd_hier *h, const OpSet &o, int level, const void *ec, void *u, hipStream_t st)
+{
+    int nf = h->nl[level];
+    dim3 gr(grid_for(h->NV[level], 256));
+    bool box = h->transfer == MGD_BOXMG;
+    if (h->precision == MGD_FP64) {
+        const double *W = box ? (const double *)o.W[level] : nullptr;
+        if (h->dim == 2) hipLaunchKernelGGL((k_prolong<2, double>), gr, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
+        else hipLaunchKernelGGL((k_prolong<3, double>), gr, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
+    } else {
+        const float *W = box ? (const float *)o.W[level] : nullptr;
+        if (h->dim == 2) hipLaunchKernelGGL((k_prolong<2, float>), gr, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
+        else hipLaunchKernelGGL((k_prolong<3, float>), gr, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
+    }
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+static int fill_zero(mgd_hier *h, void *a, int64_t n, hipStream_t st)
+{
+    if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, (double *)a, n, 0.0);
+    else hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (float *)a, n, 0.0f);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// multiplicative V(nu1,nu2) correction scheme from level l down
+static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f, double omega, int nu1, int nu2,
+                      bool zero_guess, hipStream_t st)
+{
+    int rc;
+    if (l == h->nlev - 1) return cycle_coarse_solve(h, o, u, f, st);
+    if (nu1 > 0) {
+        if ((rc = cycle_smooth(h, o, l, u, f, h->t[l], nu1, omega, zero_guess, st))) return rc;
+    } else if (zero_guess) {
+        if ((rc = fill_zero(h, u, h->NV[l], st))) return rc;
+    }
+    if ((rc = cycle_residual(h, o, l, u, f, h->r[l], st))) return rc;
+    if ((rc = cycle_restrict(h, o, l, h->r[l], h->f[l + 1], st))) return rc;
+    if ((rc = vcycle_rec(h, o, l + 1, h->u[l + 1], h->f[l + 1], omega, nu1, nu2, true, st))) return rc;
+    if ((rc = cycle_prolong(h, o, l, h->u[l + 1], u, st))) return rc;
+    if (nu2 > 0)
+        if ((rc = cycle_smooth(h, o, l, u, f, h->t[l], nu2, omega, false, st))) return rc;
+    return MGD_OK;
+}
+
+int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega, int nu1, int nu2, bool zero_guess,
+               hipStream_t st)
+{
+    return vcycle_rec(h, o, 0, u, f, omega, nu1, nu2, zero_guess, st);
+}
+
+// ------------------------------------------------------------ FP64 outer
+template <int D> struct OpComp64 {
+    StoreView sv;
+    int n;
+    __device__ inline double c(int64_t v, int j, const int *x) const
+    {
+        return base_coupling64<D>(sv.eps_c, n, x, j, nullptr) + (double)sv.delta(v, j, n_half(D));
+    }
+};
+
+template <int D, class Op>
+__global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const double *u, const double *f, double *r,
+                                                        double *partial)
+{
+    __shared__ double red[256];
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0;
+    if (v < g.NV) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) r[v] = 0.0;
+        else {
+            double Au, Dv;
+            apply_row<D, Op, double>(A, g, v, x, u, Au, Dv);
+            double rv = f[v] - Au;
+            r[v] = rv;
+            rr = rv * rv;
+        }
+    }
+    double s = block_sum<256>(rr, red);
+    if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
+}
+
+// out[k] = sum of partial[k*stride .. k*stride+cnt), fixed order, one block
+__global__ void k_reduce(const double *partial, int64_t cnt, int nvec, int64_t stride, double *out)
+{
+    __shared__ double red[1024];
+    for (int k = 0; k < nvec; ++k) {
+        double s = 0.0;
+        for (int64_t i = threadIdx.x; i < cnt; i += 1024) s += partial[k * stride + i];
+        double t = block_sum<1024>(s, red);
+        if (threadIdx.x == 0) out[k] = t;
+    }
+}
+
+template <int D>
+static int outer_residual_t(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r,
+                            double *partial, hipStream_t st)
+{
+    dim3 gr(grid_for(h->NV[0], 256));
+    if (h->precision == MGD_FP64)
+        hipLaunchKernelGGL((k_outer_residual<D, OpHalf<double>>), gr, dim3(256), 0, st,
+                           OpHalf<double>{o.S64[0], h->NV[0]}, h->n, u, f, r, partial);
+    else
+        hipLaunchKernelGGL((k_outer_residual<D, OpComp64<D>>), gr, dim3(256), 0, st,
+                           OpComp64<D>{store_view(h, o), h->n}, h->n, u, f, r, partial);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// r = f - A u (finest operator as stored, FP64); if norm2_dev: ||r||^2 there
+int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, double *norm2_dev,
+                   hipStream_t st)
+{
+    double *partial = norm2_dev ? h->ctx->partial : nullptr;
+    int rc = h->dim == 2 ? outer_residual_t<2>(h, o, u, f, r, partial, st) : outer_residual_t<3>(h, o, u, f, r, partial, st);
+    if (rc) return rc;
+    if (norm2_dev) {
+        int64_t nb = grid_for(h->NV[0], 256);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->ctx->partial, nb, 1, nb, norm2_dev);
+        HIPCHK(h->ctx, hipGetLastError());
+    }
+    return MGD_OK;
+}
+
+// ------------------------------------------------------------ outer vectors
+// convert the FP64 residual to the cycle type (rhs of the correction equation)
+template <typename T> __global__ void k_cast(const double *a, int64_t n, T *b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (T)a[i];
+}
+
+// u += e (e in the cycle type)
+template <typename T> __global__ void k_add(double *u, const T *e, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] += (double)e[i];
+}
+
+// partials of z.r and z.(r - r_old)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dots_zr(const T *z, const double *r, const double *rold, int64_t n,
+                                                 double *partial, int64_t nb)
+{
+    __shared__ double red[256];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < n) {
+        double zz = (double)z[i];
+        a = zz * r[i];
+        b = zz * (r[i] - rold[i]);
+    }
+    double sa = block_sum<256>(a, red), sb = block_sum<256>(b, red);
+    if (threadIdx.x == 0) { partial[blockIdx.x] = sa; partial[nb + blockIdx.x] = sb; }
+}
+
+// scalars: s[0] zr_old, s[1] zr, s[2] zdr, s[3] pAp, s[4] rr, s[5] beta, s[6] alpha, s[7] restart
+__global__ void k_beta(double *s)
+{
+    if (threadIdx.x == 0) {
+        s[5] = s[7] != 0.0 ? 0.0 : s[2] / s[0];
+        s[0] = s[1];
+        s[7] = 0.0;
+    }
+}
+__global__ void k_alpha(double *s)
+{
+    if (threadIdx.x == 0) s[6] = s[1] / s[3];
+}
+
+// p_new = z + beta p_old on every vertex; Ap = A p_new on the interior,
+// with partials of p_new . Ap
+template <int D, class Op, typename TZ>
+__global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, const double *pold, double *pnew,
+                                                  double *Ap, const double *s, double *partial)
+{
+    __shared__ double red[256];
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double beta = s[5], prod = 0.0;
+    if (v < g.NV) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        double pv = (double)z[v] + beta * pold[v];
+        pnew[v] = pv;
+        if (g.interior(x)) {
+            constexpr int H = n_half(D);
+            double acc = 0.0, dsum = 0.0;
+            for (int j = 0; j < H; ++j) {
+                int64_t lin = half_lin(D, j, g.nv);
+                double a = A.c(v, j, x);
+                acc += a * ((double)z[v + lin] + beta * pold[v + lin]);
+                dsum += a;
+                int y[3] = {x[0] - half_off(D, j, 0), x[1] - half_off(D, j, 1), D == 3 ? x[2] - half_off(D, j, 2) : 0};
+                double b = A.c(v - lin, j, y);
+                acc += b * ((double)z[v - lin] + beta * pold[v - lin]);
+                dsum += b;
+            }
+            double apv = -dsum * pv + acc;
+            Ap[v] = apv;
+            prod = pv * apv;
+        } else {
+            Ap[v] = 0.0;
+        }
+    }
+    double sum = block_sum<256>(prod, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
+// x += alpha p; r_old = r; r -= alpha Ap; partials of r.r
+__global__ __launch_bounds__(256) void k_cg_update(double *x, const double *p, double *r, double *rold,
+                                                   const double *Ap, int64_t n, const double *s, double *partial)
+{
+    __shared__ double red[256];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double alpha = s[6], rr = 0.0;
+    if (i < n) {
+        x[i] += alpha * p[i];
+        double ri = r[i];
+        rold[i] = ri;
+        ri -= alpha * Ap[i];
+        r[i] = ri;
+        rr = ri * ri;
+    }
+    double sum = block_sum<256>(rr, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
+struct PcgBufs {
+    double *r, *rold, *p0, *p1, *Ap;
+};
+
+// host helpers used by the solver
+int vec_cast_to_cycle(mgd_hier *h, const double *a, void *b, hipStream_t st)
+{
+    int64_t n = h->NV[0];
+    if (h->precision == MGD_FP64) HIPCHK(h->ctx, hipMemcpyAsync(b, a, n * 8, hipMemcpyDeviceToDevice, st));
+    else hipLaunchKernelGGL(k_cast<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, a, n, (float *)b);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int vec_add_cycle(mgd_hier *h, double *u, const void *e, hipStream_t st)
+{
+    int64_t n = h->NV[0];
+    if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_add<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, u, (const double *)e, n);
+    else hipLaunchKernelGGL(k_add<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, u, (const float *)e, n);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// z.r, z.(r - r_old) -> s[1], s[2]; then beta
+int pcg_beta(mgd_hier *h, const void *z, const double *r, const double *rold, double *s, hipStream_t st)
+{
+    int64_t n = h->NV[0], nb = grid_for(n, 256);
+    double *part = h->ctx->partial;
+    if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_dots_zr<double>, dim3(nb), dim3(256), 0, st, (const double *)z, r, rold, n, part, nb);
+    else hipLaunchKernelGGL(k_dots_zr<float>, dim3(nb), dim3(256), 0, st, (const float *)z, r, rold, n, part, nb);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 2, nb, s + 1);
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, st, s);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+template <int D, typename TZ>
+static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *pold, double *pnew, double *Ap,
+                        double *s, hipStream_t st)
+{
+    int64_t n = h->NV[0], nb = grid_for(n, 256);
+    double *part = h->ctx->partial;
+    if (h->precision == MGD_FP64)
+        hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(nb), dim3(256), 0, st,
+                           OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, (const double *)s, part);
+    else
+        hipLaunchKernelGGL((k_p_matvec<D, OpComp64<D>, TZ>), dim3(nb), dim3(256), 0, st,
+                           OpComp64<D>{store_view(h, o), h->n}, h->n, z, pold, pnew, Ap, (const double *)s, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 3);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, st, s);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap, double *s,
+               hipStream_t st)
+{
+    if (h->precision == MGD_FP64)
+        return h->dim == 2 ? pcg_matvec_t<2, double>(h, o, (const double *)z, pold, pnew, Ap, s, st)
+                           : pcg_matvec_t<3, double>(h, o, (const double *)z, pold, pnew, Ap, s, st);
+    return h->dim == 2 ? pcg_matvec_t<2, float>(h, o, (const float *)z, pold, pnew, Ap, s, st)
+                       : pcg_matvec_t<3, float>(h, o, (const float *)z, pold, pnew, Ap, s, st);
+}
+
+int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap, double *s,
+               hipStream_t st)
+{
+    int64_t n = h->NV[0], nb = grid_for(n, 256);
+    double *part = h->ctx->partial;
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, x, p, r, rold, Ap, n, (const double *)s, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 4);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int vec_fill_f64(mgd_ctx *ctx, double *a, int64_t n, double v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, a, n, v);
+    HIPCHK(ctx, hipGetLastError());
+    return MGD_OK;
+}

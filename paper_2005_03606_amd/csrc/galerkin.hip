@@ -1,0 +1,362 @@
+// Coarse operators (paper Sec. 4): prolongation P (d-linear, or BoxMG's
+// operator-dependent interpolation), R = P^T and the Ritz-Galerkin product
+// A_{l+1} = P^T A_l P, computed stencil-wise for every coarse vertex; plus the
+// dense FP64 Cholesky factor of the coarsest interior matrix.
+#include "common.h"
+
+// ----------------------------------------------------- half-stencil rows
+template <int D, typename T> struct HalfRow {
+    const T *S;
+    int64_t NV, nv;
+    // coupling A[v][v+o] for a full-stencil index oi != centre
+    __device__ inline T at(int64_t v, int oi) const
+    {
+        constexpr int c = D == 2 ? 4 : 13;
+        if (oi > c) return S[(int64_t)(oi - c - 1) * NV + v];
+        int mo = (D == 2 ? 8 : 26) - oi;  // index of -o
+        int64_t lin = 0, st = 1;
+        for (int m = 0; m < D; ++m) {
+            int om = oi % 3 - 1;
+            oi /= 3;
+            lin += om * st;
+            st *= nv;
+        }
+        return S[(int64_t)(mo - c - 1) * NV + v + lin];
+    }
+};
+
+__device__ inline void off_of(int D, int oi, int *o)
+{
+    for (int m = 0; m < D; ++m) { o[m] = oi % 3 - 1; oi /= 3; }
+}
+
+__device__ inline double pw1(int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; }
+
+// d-linear weights of fine vertex x toward the corners (x_m >> 1) + B_m
+template <int D, typename T> __device__ inline void geo_weights(const int *x, T *w)
+{
+    for (int B = 0; B < (1 << D); ++B) {
+        double p = 1.0;
+        for (int m = 0; m < D; ++m) p *= pw1(x[m] - 2 * ((x[m] >> 1) + ((B >> m) & 1)));
+        w[B] = (T)p;
+    }
+}
+
+// pass k: fine vertices with k odd coordinates.  k = 0 pass also sets every
+// boundary vertex (d-linear weights).  BoxMG: the row of v with offsets along
+// even axes summed (collapsed); each odd-axis neighbour u contributes its own
+// (final) weights; divided by the collapsed diagonal.
+template <int D, typename T>
+__global__ void k_weights(HalfRow<D, T> A, int n, int pass, T *W)
+{
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3] = {0, 0, 0};
+    g.coords(v, x);
+    int odd = 0;
+    for (int m = 0; m < D; ++m) odd += x[m] & 1;
+    bool bnd = !g.interior(x);
+    constexpr int nl = 1 << D, ns = D == 2 ? 9 : 27, c = ns / 2;
+    T w[nl];
+    if (pass == 0) {
+        if (!(bnd || odd == 0)) return;
+        geo_weights<D, T>(x, w);
+    } else {
+        if (bnd || odd != pass) return;
+        T acc[nl], diag = (T)0;
+        for (int B = 0; B < nl; ++B) acc[B] = (T)0;
+        // diagonal of the row: minus the sum of its couplings
+        T dsum = (T)0;
+        for (int oi = 0; oi < ns; ++oi)
+            if (oi != c) dsum += A.at(v, oi);
+        for (int oi = 0; oi < ns; ++oi) {
+            int o[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+            off_of(D, oi, o);
+            T a = oi == c ? -dsum : A.at(v, oi);
+            bool self = true;
+            for (int m = 0; m < D; ++m) {
+                int om = (x[m] & 1) ? o[m] : 0;
+                u[m] = x[m] + om;
+                if (om) self = false;
+            }
+            if (self) { diag += a; continue; }
+            int64_t uv = g.vid(u);
+            for (int Bu = 0; Bu < nl; ++Bu) {
+                T wu = W[(int64_t)Bu * g.NV + uv];
+                if (wu == (T)0) continue;
+                int B = 0;
+                for (int m = 0; m < D; ++m) B |= (((u[m] >> 1) + ((Bu >> m) & 1)) - (x[m] >> 1)) << m;
+                acc[B] -= a * wu;
+            }
+        }
+        for (int B = 0; B < nl; ++B) w[B] = acc[B] / diag;
+    }
+    for (int B = 0; B < nl; ++B) W[(int64_t)B * g.NV + v] = w[B];
+}
+
+// weight of fine vertex x toward coarse vertex X (0 unless X is a corner of x's box)
+template <int D, typename T>
+__device__ inline T weight_to(const T *W, int64_t NV, int64_t v, const int *x, const int *X)
+{
+    int B = 0;
+    for (int m = 0; m < D; ++m) {
+        int b = X[m] - (x[m] >> 1);
+        if (b < 0 || b > 1) return (T)0;
+        B |= b << m;
+    }
+    if (W) return W[(int64_t)B * NV + v];
+    double p = 1.0;
+    for (int m = 0; m < D; ++m) p *= pw1(x[m] - 2 * X[m]);
+    return (T)p;
+}
+
+// coarse coupling A_c[X][X+O_J] = sum_v sum_{w != v} P_vX A_vw (P_w,X+O - P_v,X+O),
+// valid because every row of A sums to zero and P reproduces constants.
+template <int D, typename T>
+__global__ void k_galerkin(HalfRow<D, T> A, const T *W, int nf, T *Sc)
+{
+    Grid<D> gf(nf), gc(nf / 2);
+    int64_t V = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (V >= gc.NV) return;
+    int X[3] = {0, 0, 0};
+    gc.coords(V, X);
+    constexpr int H = n_half(D), ns = D == 2 ? 9 : 27, c = ns / 2;
+    T acc[H];
+    for (int j = 0; j < H; ++j) acc[j] = (T)0;
+    for (int sv = 0; sv < ns; ++sv) {
+        int dv[3] = {0, 0, 0}, x[3] = {0, 0, 0};
+        off_of(D, sv, dv);
+        bool ok = true;
+        for (int m = 0; m < D; ++m) {
+            x[m] = 2 * X[m] + dv[m];
+            if (x[m] < 0 || x[m] > nf) ok = false;
+        }
+        if (!ok) continue;
+        int64_t v = gf.vid(x);
+        T pV = weight_to<D, T>(W, gf.NV, v, x, X);
+        if (pV == (T)0) continue;
+        T pvW[H];
+        for (int j = 0; j < H; ++j) {
+            int XW[3] = {0, 0, 0};
+            for (int m = 0; m < D; ++m) XW[m] = X[m] + half_off(D, j, m);
+            pvW[j] = weight_to<D, T>(W, gf.NV, v, x, XW);
+        }
+        for (int oi = 0; oi < ns; ++oi) {
+            if (oi == c) continue;
+            int o[3] = {0, 0, 0}, y[3] = {0, 0, 0};
+            off_of(D, oi, o);
+            bool okw = true;
+            for (int m = 0; m < D; ++m) {
+                y[m] = x[m] + o[m];
+                if (y[m] < 0 || y[m] > nf) okw = false;
+            }
+            if (!okw) continue;
+            int64_t w = gf.vid(y);
+            T a = A.at(v, oi);
+            if (a == (T)0) continue;
+            T pa = pV * a;
+            for (int j = 0; j < H; ++j) {
+                int XW[3] = {0, 0, 0};
+                for (int m = 0; m < D; ++m) XW[m] = X[m] + half_off(D, j, m);
+                T pwW = weight_to<D, T>(W, gf.NV, w, y, XW);
+                acc[j] += pa * (pwW - pvW[j]);
+            }
+        }
+    }
+    for (int j = 0; j < H; ++j) {
+        // couplings to vertices outside the coarse grid are zero
+        bool inside = true;
+        for (int m = 0; m < D; ++m) {
+            int Y = X[m] + half_off(D, j, m);
+            if (Y < 0 || Y > gc.n) inside = false;
+        }
+        Sc[(int64_t)j * gc.NV + V] = inside ? acc[j] : (T)0;
+    }
+}
+
+// ------------------------------------------------------------ coarsest solve
+// interior index of vertex x on a grid with n cells: sum (x_m - 1) (n-1)^m
+template <int D> __device__ inline int64_t interior_index(const int *x, int n)
+{
+    int64_t k = 0, st = 1;
+    for (int m = 0; m < D; ++m) { k += (int64_t)(x[m] - 1) * st; st *= (n - 1); }
+    return k;
+}
+
+template <int D, typename T>
+__global__ void k_dense_assemble(HalfRow<D, T> A, int n, int64_t m, double *M)
+{
+    Grid<D> g(n);
+    for (int64_t i = threadIdx.x; i < m * m; i += blockDim.x) M[i] = 0.0;
+    __syncthreads();
+    constexpr int ns = D == 2 ? 9 : 27, c = ns / 2;
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) continue;
+        int64_t r = interior_index<D>(x, n);
+        double dsum = 0.0;
+        for (int oi = 0; oi < ns; ++oi) {
+            if (oi == c) continue;
+            double a = (double)A.at(v, oi);
+            dsum += a;
+            int o[3] = {0, 0, 0}, y[3] = {0, 0, 0};
+            off_of(D, oi, o);
+            for (int mm = 0; mm < D; ++mm) y[mm] = x[mm] + o[mm];
+            if (g.interior(y)) M[r * m + interior_index<D>(y, n)] = a;
+        }
+        M[r * m + r] = -dsum;
+    }
+}
+
+// left-looking Cholesky in place (lower triangle), one workgroup
+__global__ void k_cholesky(double *M, int64_t m)
+{
+    __shared__ double red[256];
+    for (int64_t j = 0; j < m; ++j) {
+        double s = 0.0;
+        for (int64_t k = threadIdx.x; k < j; k += blockDim.x) s += M[j * m + k] * M[j * m + k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        double ljj = sqrt(M[j * m + j] - red[0]);
+        __syncthreads();
+        for (int64_t i = j + 1 + threadIdx.x; i < m; i += blockDim.x) {
+            double t = M[i * m + j];
+            for (int64_t k = 0; k < j; ++k) t -= M[i * m + k] * M[j * m + k];
+            M[i * m + j] = t / ljj;
+        }
+        if (threadIdx.x == 0) M[j * m + j] = ljj;
+        __syncthreads();
+    }
+}
+
+// u = A^{-1} f on the interior of the coarsest grid, FP64 triangular solves
+template <int D, typename T>
+__global__ void k_chol_solve(const double *L, int64_t m, int n, const T *f, T *u, double *work)
+{
+    Grid<D> g(n);
+    __shared__ double red[256];
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (g.interior(x)) work[interior_index<D>(x, n)] = (double)f[v];
+    }
+    __syncthreads();
+    for (int64_t i = 0; i < m; ++i) {  // L y = b
+        double s = 0.0;
+        for (int64_t k = threadIdx.x; k < i; k += blockDim.x) s += L[i * m + k] * work[k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) work[i] = (work[i] - red[0]) / L[i * m + i];
+        __syncthreads();
+    }
+    for (int64_t i = m - 1; i >= 0; --i) {  // L^T x = y
+        double s = 0.0;
+        for (int64_t k = i + 1 + threadIdx.x; k < m; k += blockDim.x) s += L[k * m + i] * work[k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) work[i] = (work[i] - red[0]) / L[i * m + i];
+        __syncthreads();
+    }
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        u[v] = g.interior(x) ? (T)work[interior_index<D>(x, n)] : (T)0;
+    }
+}
+
+// ------------------------------------------------------------ host side
+int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st);
+
+template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *const *S, hipStream_t st)
+{
+    mgd_ctx *ctx = h->ctx;
+    for (int l = 0; l + 1 < h->nlev; ++l) {
+        HalfRow<D, T> A{S[l], h->NV[l], (int64_t)h->nl[l] + 1};
+        T *W = (T *)o.W[l];
+        dim3 gv(grid_for(h->NV[l], 256));
+        if (h->transfer == MGD_BOXMG)
+            for (int pass = 0; pass <= D; ++pass)
+                hipLaunchKernelGGL((k_weights<D, T>), gv, dim3(256), 0, st, A, h->nl[l], pass, W);
+        hipLaunchKernelGGL((k_galerkin<D, T>), dim3(grid_for(h->NV[l + 1], 128)), dim3(128), 0, st, A,
+                           (const T *)(h->transfer == MGD_BOXMG ? W : nullptr), h->nl[l], S[l + 1]);
+    }
+    int lc = h->nlev - 1;
+    HalfRow<D, T> Ac{S[lc], h->NV[lc], (int64_t)h->nl[lc] + 1};
+    hipLaunchKernelGGL((k_dense_assemble<D, T>), dim3(1), dim3(256), 0, st, Ac, h->nl[lc], h->m_coarse, o.chol);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, st, o.chol, h->m_coarse);
+    HIPCHK(ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st)
+{
+    if (h->precision == MGD_FP64)
+        return h->dim == 2 ? coarsen_t<2, double>(h, o, o.S64, st) : coarsen_t<3, double>(h, o, o.S64, st);
+    int rc = decode_store_f32(h, o, st);
+    if (rc) return rc;
+    return h->dim == 2 ? coarsen_t<2, float>(h, o, o.S32, st) : coarsen_t<3, float>(h, o, o.S32, st);
+}
+
+int cycle_coarse_solve(mgd_hier *h, const OpSet &o, void *u, const void *f, hipStream_t st)
+{
+    int lc = h->nlev - 1;
+    double *work = h->ctx->partial;  // m_coarse <= partial_cap (checked at creation)
+    if (h->precision == MGD_FP64) {
+        if (h->dim == 2) hipLaunchKernelGGL((k_chol_solve<2, double>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const double *)f, (double *)u, work);
+        else hipLaunchKernelGGL((k_chol_solve<3, double>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const double *)f, (double *)u, work);
+    } else {
+        if (h->dim == 2) hipLaunchKernelGGL((k_chol_solve<2, float>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const float *)f, (float *)u, work);
+        else hipLaunchKernelGGL((k_chol_solve<3, float>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const float *)f, (float *)u, work);
+    }
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+template <typename TI> __global__ void k_w_to_f64(const TI *in, int64_t cnt, double *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = (double)in[i];
+}
+
+template <int D> __global__ void k_geo_weights_all(int n, double *W)
+{
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3] = {0, 0, 0};
+    g.coords(v, x);
+    double w[1 << D];
+    geo_weights<D, double>(x, w);
+    for (int B = 0; B < (1 << D); ++B) W[(int64_t)B * g.NV + v] = w[B];
+}
+
+int weights_f64(mgd_hier *h, const OpSet &o, int level, double *out, hipStream_t st)
+{
+    int64_t NV = h->NV[level];
+    int64_t cnt = NV << h->dim;
+    if (h->transfer == MGD_BOXMG) {
+        if (h->precision == MGD_FP64)
+            HIPCHK(h->ctx, hipMemcpyAsync(out, o.W[level], cnt * 8, hipMemcpyDeviceToDevice, st));
+        else
+            hipLaunchKernelGGL((k_w_to_f64<float>), dim3(grid_for(cnt, 256)), dim3(256), 0, st, (const float *)o.W[level], cnt, out);
+    } else {
+        if (h->dim == 2) hipLaunchKernelGGL(k_geo_weights_all<2>, dim3(grid_for(NV, 256)), dim3(256), 0, st, h->nl[level], out);
+        else hipLaunchKernelGGL(k_geo_weights_all<3>, dim3(grid_for(NV, 256)), dim3(256), 0, st, h->nl[level], out);
+    }
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}

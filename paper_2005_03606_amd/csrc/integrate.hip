@@ -1,0 +1,697 @@
+// Element integration on gfx950 (paper Sec. 4.2, eq. mg:weak-form-of-assembly;
+// adaptive criterion Sec. 5.2): eps is held constant on each of the s^d equal
+// sub-cells of a cell and the gradient products are integrated exactly, so
+//     K_c = sum_q eps(x_q) G_q,
+//     G_q[a][b] = h^{d-2} sum_k (sigma_a sigma_b / s)_k prod_{m != k} M_{q_m}(a_m, b_m),
+// M_q(a,b) the integral of psi_a psi_b over [q/s, (q+1)/s] (psi_0 = 1 - xi,
+// psi_1 = xi).  Two device paths:
+//   FP64: VALU, sum-factorised along x-lines, G lanes per cell;
+//   mixed: eps split into bf16 hi + lo, contracted on MFMA (16x16x32 bf16)
+//          against the integer-scaled G table split exactly into bf16 terms,
+//          FP32 accumulation; the [cells x s^d] x [s^d x pairs] contraction.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "common.h"
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+// ------------------------------------------------------------ eps on device
+struct EpsDev {
+    int kind, dim, count;
+    double p0, p1;
+    const double *data;
+};
+
+// eps at x; geometric membership decisions in FP64 for every path,
+// transcendental laws in T (float for the mixed path).
+template <int D, typename T> __device__ inline T eps_eval(const EpsDev &e, const double *x)
+{
+    switch (e.kind) {
+    case MGD_EPS_CONST:
+        return (T)e.p0;
+    case MGD_EPS_SINE: {
+        T p = (T)1;
+        for (int m = 0; m < D; ++m) p *= sin((T)(2.0 * M_PI) * (T)x[m]);
+        return (T)1 + (T)e.p0 * p;
+    }
+    case MGD_EPS_THETA: {
+        T p = (T)1, th = (T)e.p0;
+        for (int m = 0; m < D; ++m) p *= exp(-th * (T)x[m]) * cos((T)M_PI * th * (T)x[m]);
+        return (T)1 + ((T)0.3 / (T)D) * p;
+    }
+    case MGD_EPS_BALLS: {
+        for (int b = 0; b < e.count; ++b) {
+            const double *row = e.data + (size_t)b * (D + 1);
+            double r2 = 0.0;
+            for (int m = 0; m < D; ++m) {
+                double dx = x[m] - row[m];
+                r2 = __dadd_rn(r2, __dmul_rn(dx, dx));
+            }
+            if (r2 <= __dmul_rn(row[D], row[D])) return (T)e.p1;
+        }
+        return (T)e.p0;
+    }
+    case MGD_EPS_LATTICE: {
+        int L = e.count, base[3];
+        T t[3];
+        for (int m = 0; m < D; ++m) {
+            double y = x[m] * L;
+            int i = (int)floor(y);
+            i = i < 0 ? 0 : (i > L - 1 ? L - 1 : i);
+            base[m] = i;
+            t[m] = (T)(y - i);
+        }
+        T g = (T)0;
+        for (int a = 0; a < (1 << D); ++a) {
+            T w = (T)1;
+            int64_t idx = 0, stride = 1;
+            for (int m = 0; m < D; ++m) {
+                int bit = (a >> m) & 1;
+                w *= bit ? t[m] : (T)1 - t[m];
+                idx += (int64_t)(base[m] + bit) * stride;
+                stride *= (L + 1);
+            }
+            g += w * (T)e.data[idx];
+        }
+        return exp((T)e.p0 * g);
+    }
+    case MGD_EPS_BOXES: {
+        double v = e.p0;
+        for (int b = 0; b < e.count; ++b) {
+            const double *row = e.data + (size_t)b * (2 * D + 1);
+            bool in = true;
+            for (int m = 0; m < D; ++m) in = in && x[m] >= row[m] && x[m] < row[D + m];
+            if (in) v = row[2 * D];
+        }
+        return (T)v;
+    }
+    }
+    return (T)NAN;
+}
+
+// ------------------------------------------------------ shared argument pack
+struct AsmArgs {
+    int n, s;
+    int64_t count;
+    const int64_t *count_dev;  // if set, overrides count (device-side active count)
+    const int64_t *cells;      // null: cell = i
+    EpsDev eps;
+    const double *samples;     // MGD_EPS_SAMPLES: [count][s^d]
+    void *K_out;
+    const void *K_old;
+    int k_by_cell;             // K_out / K_old rows indexed by cell id (in-place ladder)
+    double C;
+    double *rel_out;
+    uint8_t *done_out;
+};
+
+__device__ inline int64_t asm_count(const AsmArgs &a) { return a.count_dev ? *a.count_dev : a.count; }
+
+template <int D> __device__ inline void cell_coords(int64_t c, int n, int *ci)
+{
+    ci[0] = (int)(c % n);
+    int64_t t = c / n;
+    if (D == 2) ci[1] = (int)t;
+    else { ci[1] = (int)(t % n); ci[2] = (int)(t / n); }
+}
+
+__device__ inline double sample_coord(int ci, int q, int s, int n)
+{
+    return ((double)ci + ((double)q + 0.5) / (double)s) / (double)n;
+}
+
+// M_q(a,b) over the q-th of s sub-intervals: index 0 = (0,0), 1 = (0,1), 2 = (1,1)
+__device__ inline void moments64(int s, int q, double *M)
+{
+    double S3 = (double)s * s * s;
+    int qb = s - 1 - q;
+    M[2] = (3.0 * q * q + 3.0 * q + 1.0) / (3.0 * S3);
+    M[0] = (3.0 * qb * qb + 3.0 * qb + 1.0) / (3.0 * S3);
+    M[1] = (6.0 * q * (s - q) + 3.0 * (s - 2.0 * q) - 2.0) / (6.0 * S3);
+}
+
+__device__ inline int mtype(int a, int b) { return a + b; }  // 0: 00, 1: 01/10, 2: 11
+
+// adaptive criterion: max-norm of the change over the full 2^d x 2^d matrices
+template <int D, typename T>
+__device__ inline double ladder_rel(const T *Knew, const T *Kold)
+{
+    constexpr int nl = 1 << D, U = n_pairs(D);
+    double dnew[nl], dold[nl];
+    for (int a = 0; a < nl; ++a) dnew[a] = dold[a] = 0.0;
+    double mdiff = 0.0, mold = 0.0;
+    for (int a = 0; a < nl; ++a)
+        for (int b = a + 1; b < nl; ++b) {
+            int p = pair_index(D, a, b);
+            double kn = (double)Knew[p], ko = (double)Kold[p];
+            dnew[a] -= kn; dnew[b] -= kn;
+            dold[a] -= ko; dold[b] -= ko;
+            mdiff = fmax(mdiff, fabs(kn - ko));
+            mold = fmax(mold, fabs(ko));
+        }
+    for (int a = 0; a < nl; ++a) {
+        mdiff = fmax(mdiff, fabs(dnew[a] - dold[a]));
+        mold = fmax(mold, fabs(dold[a]));
+    }
+    (void)U;
+    return mdiff / mold;
+}
+
+template <int D, typename T>
+__device__ inline void store_and_check(const AsmArgs &a, int64_t i, int64_t cell, const T *K)
+{
+    constexpr int U = n_pairs(D);
+    int64_t row = a.k_by_cell ? cell : i;
+    if (a.K_old) {
+        int64_t orow = a.k_by_cell ? cell : i;
+        const T *Ko = (const T *)a.K_old + orow * U;
+        T old[U];
+        for (int p = 0; p < U; ++p) old[p] = Ko[p];
+        double rel = ladder_rel<D, T>(K, old);
+        if (a.rel_out) a.rel_out[i] = rel;
+        if (a.done_out) a.done_out[i] = rel < a.C ? 1 : 0;
+    }
+    T *Ko = (T *)a.K_out + row * U;
+    for (int p = 0; p < U; ++p) Ko[p] = K[p];
+}
+
+// ------------------------------------------------------------ FP64 (VALU)
+// G lanes cooperate on one cell; lane g takes x-lines g, g+G, ...
+template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
+{
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = gid / G;
+    int g = (int)(gid % G);
+    int64_t cnt = asm_count(a);
+    bool valid = i < cnt;
+    int s = a.s, n = a.n;
+    int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
+    int ci[3] = {0, 0, 0};
+    cell_coords<D>(cell, n, ci);
+    int nlines = (D == 2) ? s : s * s;
+    int64_t nq = (int64_t)nlines * s;
+    // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
+    // T3[tx][ty] = sum eps Mx My (2D: T1[ty], T2[tx])
+    double T1[9], T2[9], T3[9];
+    for (int k = 0; k < 9; ++k) T1[k] = T2[k] = T3[k] = 0.0;
+    if (valid) {
+        for (int line = g; line < nlines; line += G) {
+            int qy = line % s, qz = line / s;
+            double My[3], Mz[3] = {1.0, 1.0, 1.0};
+            moments64(s, qy, My);
+            if (D == 3) moments64(s, qz, Mz);
+            double L0 = 0.0, L[3] = {0.0, 0.0, 0.0};
+            double x[3];
+            x[1] = sample_coord(ci[1], qy, s, n);
+            if (D == 3) x[2] = sample_coord(ci[2], qz, s, n);
+            for (int qx = 0; qx < s; ++qx) {
+                double e;
+                if (a.eps.kind == MGD_EPS_SAMPLES) {
+                    int64_t q = qx + (int64_t)s * line;
+                    e = a.samples[i * nq + q];
+                } else {
+                    x[0] = sample_coord(ci[0], qx, s, n);
+                    e = eps_eval<D, double>(a.eps, x);
+                }
+                double Mx[3];
+                moments64(s, qx, Mx);
+                L0 += e;
+                for (int t = 0; t < 3; ++t) L[t] += e * Mx[t];
+            }
+            if (D == 2) {
+                for (int t = 0; t < 3; ++t) { T1[t] += L0 * My[t]; T2[t] += L[t]; }
+            } else {
+                for (int ty = 0; ty < 3; ++ty)
+                    for (int tz = 0; tz < 3; ++tz) T1[ty * 3 + tz] += L0 * My[ty] * Mz[tz];
+                for (int tx = 0; tx < 3; ++tx)
+                    for (int tz = 0; tz < 3; ++tz) T2[tx * 3 + tz] += L[tx] * Mz[tz];
+                for (int tx = 0; tx < 3; ++tx)
+                    for (int ty = 0; ty < 3; ++ty) T3[tx * 3 + ty] += L[tx] * My[ty];
+            }
+        }
+    }
+    // reduce over the G lanes of the cell (fixed butterfly order)
+    for (int off = G / 2; off > 0; off >>= 1)
+        for (int k = 0; k < 9; ++k) {
+            T1[k] += __shfl_xor(T1[k], off, 64);
+            T2[k] += __shfl_xor(T2[k], off, 64);
+            T3[k] += __shfl_xor(T3[k], off, 64);
+        }
+    if (!valid || g != 0) return;
+    constexpr int nl = 1 << D, U = n_pairs(D);
+    double K[U];
+    double inv_s = 1.0 / s, hp = (D == 2) ? 1.0 : 1.0 / n;
+    for (int aa = 0; aa < nl; ++aa)
+        for (int bb = aa + 1; bb < nl; ++bb) {
+            int ax = aa & 1, bx = bb & 1, ay = (aa >> 1) & 1, by = (bb >> 1) & 1;
+            double sx = ax == bx ? inv_s : -inv_s, sy = ay == by ? inv_s : -inv_s;
+            double v;
+            if (D == 2) {
+                v = sx * T1[mtype(ay, by)] + sy * T2[mtype(ax, bx)];
+            } else {
+                int az = (aa >> 2) & 1, bz = (bb >> 2) & 1;
+                double sz = az == bz ? inv_s : -inv_s;
+                int tx = mtype(ax, bx), ty = mtype(ay, by), tz = mtype(az, bz);
+                v = hp * (sx * T1[ty * 3 + tz] + sy * T2[tx * 3 + tz] + sz * T3[tx * 3 + ty]);
+            }
+            K[pair_index(D, aa, bb)] = v;
+        }
+    store_and_check<D, double>(a, i, cell, K);
+}
+
+// ------------------------------------------------------------ mixed (MFMA)
+__device__ inline uint16_t bf16_bits_rne(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+union BF8 {
+    bf16x8 v;
+    uint16_t u[8];
+};
+
+// One wave handles 16 cells; lane l owns cell row l & 15 and samples
+// 8 (l >> 4) .. +7 of every 32-sample chunk (the A-operand layout of
+// v_mfma_f32_16x16x32_bf16); the B operand (G terms) is pre-laid out per lane.
+template <int D, int NT, int NTERM>
+__global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *Gtab, int nchunks,
+                                                        float inv_den)
+{
+    __shared__ float sm[4][16][NT * 16 + 1];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int row = lane & 15, kg = lane >> 4;
+    int64_t cnt = asm_count(a);
+    int64_t tile = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    int64_t i = tile + row;
+    bool valid = i < cnt;
+    int s = a.s, n = a.n;
+    int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
+    int ci[3] = {0, 0, 0};
+    cell_coords<D>(cell, n, ci);
+    int64_t nq = 1;
+    for (int m = 0; m < D; ++m) nq *= s;
+    floatx4 acc[NT];
+    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int nch = tile < cnt ? nchunks : 0;  // idle waves still reach the barrier
+    for (int ch = 0; ch < nch; ++ch) {
+        BF8 ahi, alo;
+        int64_t q0 = (int64_t)ch * 32 + kg * 8;
+        for (int e = 0; e < 8; ++e) {
+            int64_t q = q0 + e;
+            float ev = 0.0f;
+            if (valid && q < nq) {
+                if (a.eps.kind == MGD_EPS_SAMPLES) {
+                    ev = (float)a.samples[i * nq + q];
+                } else {
+                    int qx = (int)(q % s), qr = (int)(q / s);
+                    double x[3];
+                    x[0] = sample_coord(ci[0], qx, s, n);
+                    x[1] = sample_coord(ci[1], qr % s, s, n);
+                    if (D == 3) x[2] = sample_coord(ci[2], qr / s, s, n);
+                    ev = eps_eval<D, float>(a.eps, x);
+                }
+            }
+            uint16_t h = bf16_bits_rne(ev);
+            ahi.u[e] = h;
+            alo.u[e] = bf16_bits_rne(ev - bf16_value(h));
+        }
+        for (int t = 0; t < NT; ++t) {
+            const uint4 *gp = Gtab + ((size_t)(ch * NT + t) * NTERM) * 64 + lane;
+            BF8 g0, g1;
+            *(uint4 *)&g0 = gp[0];
+            *(uint4 *)&g1 = gp[64];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g0.v, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g1.v, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo.v, g0.v, acc[t], 0, 0, 0);
+            if (NTERM == 3) {
+                BF8 g2;
+                *(uint4 *)&g2 = gp[128];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g2.v, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // C layout: lane holds column lane & 15, rows 4 (lane >> 4) + r
+    for (int t = 0; t < NT; ++t)
+        for (int r = 0; r < 4; ++r) sm[wave][4 * kg + r][t * 16 + (lane & 15)] = acc[t][r] * inv_den;
+    __syncthreads();
+    if (lane < 16 && valid) {
+        constexpr int U = n_pairs(D);
+        float K[U];
+        for (int p = 0; p < U; ++p) K[p] = sm[wave][lane][p];
+        store_and_check<D, float>(a, i, cell, K);
+    }
+}
+
+// ------------------------------------------------------------ G tables
+// Exact integer-scaled sub-cell matrices: 2D G = G_int / (6 s^4),
+// 3D G = h G_int / (36 s^7); G_int split into bf16 terms exactly.
+static inline uint16_t host_bf16_rne(float f)
+{
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+static inline float host_bf16_val(uint16_t h)
+{
+    uint32_t b = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+struct GTable {
+    int dim = 0, s = 0, nterm = 0, nchunks = 0, nt = 0;
+    uint4 *dev = nullptr;
+};
+static GTable g_tables[2][5];  // [dim-2][log2 s]
+static int g_tables_device = -1;
+
+static int build_gtable(mgd_ctx *ctx, int D, int s, GTable &T)
+{
+    int nl = 1 << D, U = n_pairs(D);
+    int64_t nq = 1;
+    for (int m = 0; m < D; ++m) nq *= s;
+    // integer moments m_t(q) = 6 s^3 M_t(q)
+    auto mint = [&](int q, int t) -> int64_t {
+        int64_t qb = s - 1 - q;
+        if (t == 2) return 2 * (3LL * q * q + 3LL * q + 1);
+        if (t == 0) return 2 * (3 * qb * qb + 3 * qb + 1);
+        return 6LL * q * (s - q) + 3LL * (s - 2 * q) - 2;
+    };
+    std::vector<int64_t> Gint((size_t)nq * U);
+    int64_t gmax = 0;
+    for (int64_t q = 0; q < nq; ++q) {
+        int qq[3] = {(int)(q % s), (int)((q / s) % s), (int)(q / ((int64_t)s * s))};
+        for (int a = 0; a < nl; ++a)
+            for (int b = a + 1; b < nl; ++b) {
+                int64_t sum = 0;
+                for (int k = 0; k < D; ++k) {
+                    int64_t term = (((a >> k) & 1) == ((b >> k) & 1)) ? 1 : -1;
+                    for (int m = 0; m < D; ++m)
+                        if (m != k) term *= mint(qq[m], ((a >> m) & 1) + ((b >> m) & 1));
+                    sum += term;
+                }
+                Gint[(size_t)q * U + pair_index(D, a, b)] = sum;
+                gmax = sum > gmax ? sum : (-sum > gmax ? -sum : gmax);
+            }
+    }
+    if (gmax >= (1LL << 24))
+        return mgd_fail(ctx, MGD_EINVAL, "G table entries exceed 24 bits (d=%d s=%d)", D, s);
+    // number of exact bf16 terms
+    int nterm = 2;
+    for (size_t k = 0; k < Gint.size(); ++k) {
+        float g = (float)Gint[k];
+        uint16_t h0 = host_bf16_rne(g);
+        float r1 = g - host_bf16_val(h0);
+        uint16_t h1 = host_bf16_rne(r1);
+        float r2 = r1 - host_bf16_val(h1);
+        if (r2 != 0.0f) {
+            uint16_t h2 = host_bf16_rne(r2);
+            if (r2 - host_bf16_val(h2) != 0.0f)
+                return mgd_fail(ctx, MGD_EINVAL, "G table not exact in 3 bf16 terms");
+            nterm = 3;
+        }
+    }
+    int NT = (U + 15) / 16;
+    int nchunks = (int)((nq + 31) / 32);
+    size_t nvec = (size_t)nchunks * NT * nterm * 64;
+    std::vector<uint16_t> host(nvec * 8, 0);
+    for (int ch = 0; ch < nchunks; ++ch)
+        for (int t = 0; t < NT; ++t)
+            for (int lane = 0; lane < 64; ++lane) {
+                int col = t * 16 + (lane & 15);
+                for (int e = 0; e < 8; ++e) {
+                    int64_t q = (int64_t)ch * 32 + (lane >> 4) * 8 + e;
+                    float g = (col < U && q < nq) ? (float)Gint[(size_t)q * U + col] : 0.0f;
+                    uint16_t terms[3];
+                    terms[0] = host_bf16_rne(g);
+                    float r1 = g - host_bf16_val(terms[0]);
+                    terms[1] = host_bf16_rne(r1);
+                    terms[2] = host_bf16_rne(r1 - host_bf16_val(terms[1]));
+                    for (int k = 0; k < nterm; ++k) {
+                        size_t vec = ((size_t)(ch * NT + t) * nterm + k) * 64 + lane;
+                        host[vec * 8 + e] = terms[k];
+                    }
+                }
+            }
+    void *p = nullptr;
+    int rc = dev_alloc(ctx, &p, nvec * 16);
+    if (rc) return rc;
+    HIPCHK(ctx, hipMemcpy(p, host.data(), nvec * 16, hipMemcpyHostToDevice));
+    T.dim = D; T.s = s; T.nterm = nterm; T.nchunks = nchunks; T.nt = NT;
+    T.dev = (uint4 *)p;
+    return MGD_OK;
+}
+
+static int get_gtable(mgd_ctx *ctx, int D, int s, GTable **out)
+{
+    int ls = 0;
+    while ((1 << ls) < s) ++ls;
+    if (g_tables_device != ctx->device) {
+        for (auto &row : g_tables)
+            for (auto &t : row) t = GTable();
+        g_tables_device = ctx->device;
+    }
+    GTable &T = g_tables[D - 2][ls];
+    if (!T.dev) {
+        int rc = build_gtable(ctx, D, s, T);
+        if (rc) return rc;
+    }
+    *out = &T;
+    return MGD_OK;
+}
+
+// ------------------------------------------------------------ launchers
+int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, int64_t count,
+                    const mgd_eps *eps, int mode, void *K_out, const void *K_old, int k_by_cell,
+                    double C, double *rel_out, uint8_t *done_out, const int64_t *count_dev,
+                    hipStream_t st)
+{
+    if (count <= 0) return MGD_OK;
+    AsmArgs a;
+    a.n = n; a.s = s; a.count = count; a.count_dev = count_dev; a.cells = cells;
+    a.eps.kind = eps->kind; a.eps.dim = eps->dim; a.eps.count = eps->count;
+    a.eps.p0 = eps->p0; a.eps.p1 = eps->p1; a.eps.data = eps->data;
+    a.samples = eps->kind == MGD_EPS_SAMPLES ? eps->data : nullptr;
+    a.K_out = K_out; a.K_old = K_old;
+    a.k_by_cell = k_by_cell; a.C = C; a.rel_out = rel_out; a.done_out = done_out;
+    if (mode == MGD_FP64) {
+        int lines = dim == 2 ? s : s * s;
+        int G = lines >= 16 ? 16 : lines >= 4 ? 4 : 1;
+        unsigned grid = grid_for(count * G, 256);
+#define L64(DD, GG) hipLaunchKernelGGL((k_integrate64<DD, GG>), dim3(grid), dim3(256), 0, st, a)
+        if (dim == 2) { if (G == 16) L64(2, 16); else if (G == 4) L64(2, 4); else L64(2, 1); }
+        else { if (G == 16) L64(3, 16); else if (G == 4) L64(3, 4); else L64(3, 1); }
+#undef L64
+    } else {
+        GTable *T = nullptr;
+        int rc = get_gtable(ctx, dim, s, &T);
+        if (rc) return rc;
+        double inv_den = dim == 2 ? 1.0 / (6.0 * pow((double)s, 4)) : (1.0 / n) / (36.0 * pow((double)s, 7));
+        unsigned grid = grid_for(count, 64);
+        if (dim == 2) {
+            if (T->nterm == 2)
+                hipLaunchKernelGGL((k_integrate_mfma<2, 1, 2>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
+            else
+                hipLaunchKernelGGL((k_integrate_mfma<2, 1, 3>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
+        } else {
+            if (T->nterm == 2)
+                hipLaunchKernelGGL((k_integrate_mfma<3, 2, 2>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
+            else
+                hipLaunchKernelGGL((k_integrate_mfma<3, 2, 3>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
+        }
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// centre samples eps(x_c) as FP32 (the base of the hierarchical surplus)
+template <int D> __global__ void k_centre_eps(EpsDev e, int n, int64_t ncell, float *out)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int ci[3] = {0, 0, 0};
+    cell_coords<D>(c, n, ci);
+    double x[3];
+    for (int m = 0; m < D; ++m) x[m] = sample_coord(ci[m], 0, 1, n);
+    out[c] = eps_eval<D, float>(e, x);
+}
+
+int launch_centre_eps(mgd_ctx *ctx, int dim, int n, const mgd_eps *eps, float *eps_c, hipStream_t st)
+{
+    EpsDev e{eps->kind, eps->dim, eps->count, eps->p0, eps->p1, eps->data};
+    int64_t nc = 1;
+    for (int m = 0; m < dim; ++m) nc *= n;
+    if (dim == 2) hipLaunchKernelGGL(k_centre_eps<2>, dim3(grid_for(nc, 256)), dim3(256), 0, st, e, n, nc, eps_c);
+    else hipLaunchKernelGGL(k_centre_eps<3>, dim3(grid_for(nc, 256)), dim3(256), 0, st, e, n, nc, eps_c);
+    HIPCHK(ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// ------------------------------------------------------------ stencil gather
+// coupling of vertex v to v+o: sum over the cells holding both, ascending
+template <int D, typename TK, typename TS>
+__global__ void k_gather(const TK *K, int n, TS *S)
+{
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3] = {0, 0, 0};
+    g.coords(v, x);
+    constexpr int H = n_half(D), U = n_pairs(D);
+    for (int j = 0; j < H; ++j) {
+        int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
+        TK acc = 0;
+        bool first = true;
+        for (int B = (1 << D) - 1; B >= 0; --B) {
+            bool ok = true;
+            int lv = 0, lw = 0;
+            int64_t c = 0, stride = 1;
+            for (int m = 0; m < D; ++m) {
+                int bm = (B >> m) & 1, cm = x[m] - bm, wm = bm + o[m];
+                if (cm < 0 || cm >= n || wm < 0 || wm > 1) ok = false;
+                lv |= bm << m;
+                lw |= wm << m;
+                c += (int64_t)cm * stride;
+                stride *= n;
+            }
+            if (!ok) continue;
+            TK k = K[c * U + pair_index(D, lv, lw)];
+            acc = first ? k : acc + k;
+            first = false;
+        }
+        S[(int64_t)j * g.NV + v] = (TS)acc;
+    }
+}
+
+int launch_gather(mgd_ctx *ctx, int dim, int n, const void *K, int k_mode, void *S, int s_mode,
+                  hipStream_t st)
+{
+    int64_t NV = 1;
+    for (int m = 0; m < dim; ++m) NV *= (n + 1);
+    dim3 gr(grid_for(NV, 256)), bl(256);
+#define LG(DD, TK, TS) hipLaunchKernelGGL((k_gather<DD, TK, TS>), gr, bl, 0, st, (const TK *)K, n, (TS *)S)
+    if (dim == 2) {
+        if (k_mode == MGD_FP64) { if (s_mode == MGD_FP64) LG(2, double, double); else LG(2, double, float); }
+        else { if (s_mode == MGD_FP64) LG(2, float, double); else LG(2, float, float); }
+    } else {
+        if (k_mode == MGD_FP64) { if (s_mode == MGD_FP64) LG(3, double, double); else LG(3, double, float); }
+        else { if (s_mode == MGD_FP64) LG(3, float, double); else LG(3, float, float); }
+    }
+#undef LG
+    HIPCHK(ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// ------------------------------------------------------------ compaction
+// stable compaction of the entries with flag == 0 (cells still climbing):
+// out_cells[k] = cells[i], with a device-side count
+__global__ void k_count_open(const uint8_t *done, const int64_t *count_dev, int64_t count, int32_t *block_cnt)
+{
+    __shared__ int32_t red[256];
+    int64_t cnt = count_dev ? *count_dev : count;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    red[threadIdx.x] = (i < cnt && !done[i]) ? 1 : 0;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_cnt[blockIdx.x] = red[0];
+}
+
+__global__ void k_scan_blocks(int32_t *block_cnt, int64_t nblocks, int64_t *total)
+{
+    // single block: exclusive scan in place, chunked
+    __shared__ int64_t carry;
+    __shared__ int32_t buf[1024];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblocks; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        int32_t v = i < nblocks ? block_cnt[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int32_t t = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nblocks) block_cnt[i] = (int32_t)(carry + buf[threadIdx.x] - v);
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scatter_open(const uint8_t *done, const int64_t *cells_in, const int64_t *count_dev,
+                               int64_t count, const int32_t *block_off, int64_t *cells_out)
+{
+    __shared__ int32_t buf[256];
+    int64_t cnt = count_dev ? *count_dev : count;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t f = (i < cnt && !done[i]) ? 1 : 0;
+    buf[threadIdx.x] = f;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        int32_t t = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (f) cells_out[block_off[blockIdx.x] + buf[threadIdx.x] - 1] = cells_in ? cells_in[i] : i;
+}
+
+int launch_compact_open(mgd_ctx *ctx, const uint8_t *done, const int64_t *cells_in, const int64_t *count_dev,
+                        int64_t count_bound, int32_t *block_tmp, int64_t *cells_out, int64_t *count_out,
+                        hipStream_t st)
+{
+    if (count_bound <= 0) {
+        HIPCHK(ctx, hipMemsetAsync(count_out, 0, sizeof(int64_t), st));
+        return MGD_OK;
+    }
+    int64_t nb = (count_bound + 255) / 256;
+    hipLaunchKernelGGL(k_count_open, dim3(nb), dim3(256), 0, st, done, count_dev, count_bound, block_tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_tmp, nb, count_out);
+    hipLaunchKernelGGL(k_scatter_open, dim3(nb), dim3(256), 0, st, done, cells_in, count_dev, count_bound,
+                       block_tmp, cells_out);
+    HIPCHK(ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// ------------------------------------------------------------ misc
+int mgd_fail(mgd_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+int dev_alloc(mgd_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return mgd_fail(ctx, MGD_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return MGD_OK;
+}
+
+void dev_free(void *p)
+{
+    if (p) (void)hipFree(p);
+}

@@ -1,0 +1,433 @@
+"""HIP path vs the CPU oracle, through the C ABI, on seeded inputs.
+
+Bars: indexing, stencil layout and the reduced-precision payload bit-exact;
+FP64 kernels within 1e-12 relative (1e-11 after several V-cycles); the mixed
+path's error against FP64 is asserted against the number stated beside it.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workload as W
+from _gpu_util import half_mask, rel_err
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2005_03606_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+FIELDS_2D = {
+    "sine": lambda: W.sine_field(2, 0.9),
+    "theta": lambda: W.theta_field(2, 8.0),
+    "balls": lambda: W.balls_field(2, 12, 3, r_lo=0.05, r_hi=0.3, eps_in=1e3),
+    "lattice": lambda: W.lattice_field(2, 12, 4, sigma=1.0),
+    "boxes": lambda: W.boxes_field(2, 10, 5),
+}
+FIELDS_3D = {
+    "sine": lambda: W.sine_field(3, 0.9),
+    "balls": lambda: W.balls_field(3, 8, 3, r_lo=0.1, r_hi=0.4, eps_in=1e3),
+    "lattice": lambda: W.lattice_field(3, 5, 6, sigma=1.0),
+    "boxes": lambda: W.boxes_field(3, 12, 7),
+}
+
+
+# ------------------------------------------------------------ integration
+@pytest.mark.parametrize("name", sorted(FIELDS_2D))
+@pytest.mark.parametrize("s", [1, 2, 4, 8, 16])
+def test_assemble_fp64_2d(ctx, name, s):
+    fld = FIELDS_2D[name]()
+    n = 12  # 144 cells: several 64-cell blocks and a ragged tail
+    K, _, _ = P.assemble_cells(ctx, 2, n, s, P.Eps(fld), P.FP64)
+    ref = O.pack_pairs(2, O.assemble(fld, 2, n, s))
+    assert rel_err(host(K), ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(FIELDS_3D))
+@pytest.mark.parametrize("s", [1, 2, 4, 8])
+def test_assemble_fp64_3d(ctx, name, s):
+    fld = FIELDS_3D[name]()
+    n = 5
+    K, _, _ = P.assemble_cells(ctx, 3, n, s, P.Eps(fld), P.FP64)
+    ref = O.pack_pairs(3, O.assemble(fld, 3, n, s))
+    assert rel_err(host(K), ref) < 1e-12
+
+
+def test_assemble_3d_s16_cell_list(ctx):
+    fld = FIELDS_3D["balls"]()
+    n = 6
+    cells = np.array([0, 7, 100, 101, 150, 215], np.int64)
+    K, _, _ = P.assemble_cells(ctx, 3, n, 16, P.Eps(fld), P.FP64, cells=dev(cells, torch.int64))
+    ref = O.pack_pairs(3, O.assemble(fld, 3, n, 16, cells))
+    assert rel_err(host(K), ref) < 1e-12
+    Km, _, _ = P.assemble_cells(ctx, 3, n, 16, P.Eps(fld), P.MIXED, cells=dev(cells, torch.int64))
+    assert rel_err(host(Km), ref) < 2e-4
+
+
+def test_assemble_explicit_samples(ctx):
+    d, n, s = 2, 6, 4
+    rng = np.random.default_rng(0)
+    cells = np.array([3, 8, 35], np.int64)
+    samp = rng.uniform(0.5, 2.0, size=(3, s * s))
+    K, _, _ = P.assemble_cells(ctx, d, n, s, P.Eps.samples(d, dev(samp)), P.FP64, cells=dev(cells, torch.int64))
+    ref = O.pack_pairs(d, np.array([O.element_matrix_samples(d, n, s, samp[i]) for i in range(3)]))
+    assert rel_err(host(K), ref) < 1e-13
+
+
+@pytest.mark.parametrize("d,name", [(2, "sine"), (2, "balls"), (2, "lattice"), (3, "lattice"), (3, "balls")])
+@pytest.mark.parametrize("s", [2, 8, 16])
+def test_assemble_mixed_error_bound(ctx, d, name, s):
+    """bf16 hi+lo eps on MFMA with FP32 accumulation: stated error against the
+    FP64 oracle <= 2e-4 of the cell's largest entry (bf16 hi+lo keeps 16
+    significand bits of eps: ~2^-17 per sample, plus FP32 sums)."""
+    if d == 3 and s == 16:
+        pytest.skip("3D s=16 covered by the cell-list test")
+    fld = (FIELDS_2D if d == 2 else FIELDS_3D)[name]()
+    n = 12 if d == 2 else 5
+    K, _, _ = P.assemble_cells(ctx, d, n, s, P.Eps(fld), P.MIXED)
+    ref = O.pack_pairs(d, O.assemble(fld, d, n, s))
+    got = host(K).astype(np.float64)
+    per_cell = np.abs(got - ref).max(1) / np.abs(ref).max(1)
+    assert per_cell.max() < 2e-4, per_cell.max()
+
+
+def test_assemble_mixed_constant_eps_is_exact_table(ctx):
+    """Constant eps (exact in bf16) isolates the MFMA lane layout and the G
+    split: the result must be eps K_ref to FP32 rounding."""
+    for d, n, s in [(2, 8, 4), (2, 8, 16), (3, 4, 4), (3, 4, 8)]:
+        fld = W.const_field(d, 2.5)
+        K, _, _ = P.assemble_cells(ctx, d, n, s, P.Eps(fld), P.MIXED)
+        ref = O.pack_pairs(d, O.assemble(fld, d, n, 1))
+        assert rel_err(host(K), ref) < 2e-6
+
+
+def test_ladder_criterion_matches_oracle(ctx):
+    d, n = 2, 16
+    fld = W.balls_field(2, 6, 11, r_lo=0.05, r_hi=0.2, eps_in=1e3)
+    Ke = P.Eps(fld)
+    for s in (2, 4, 8, 16):
+        Kold, _, _ = P.assemble_cells(ctx, d, n, s // 2, Ke, P.FP64)
+        K, rel, done = P.assemble_cells(ctx, d, n, s, Ke, P.FP64, K_old=Kold, C_thr=0.01, want_rel=True)
+        A = O.assemble(fld, d, n, s)
+        B = O.assemble(fld, d, n, s // 2)
+        rref = np.abs(A - B).reshape(len(A), -1).max(1) / np.abs(B).reshape(len(B), -1).max(1)
+        r = host(rel)
+        np.testing.assert_allclose(r, rref, rtol=1e-10, atol=1e-15)
+        clear = np.abs(rref - 0.01) > 1e-9
+        assert (host(done)[clear] == (rref[clear] < 0.01)).all()
+
+
+# ------------------------------------------------------------ stencils
+@pytest.mark.parametrize("d,n", [(2, 9), (3, 4)])
+def test_gather_fp64_bit_exact(ctx, d, n):
+    rng = np.random.default_rng(2)
+    nl = 1 << d
+    Kfull = rng.standard_normal((n ** d, nl, nl))
+    Kfull = Kfull + Kfull.transpose(0, 2, 1)
+    S = P.gather_stencils(ctx, d, n, dev(O.pack_pairs(d, Kfull)), P.FP64, P.FP64)
+    ref = O.to_half(d, O.stencils(d, n, Kfull))
+    assert np.array_equal(host(S).view(np.uint64), ref.view(np.uint64))
+
+
+def test_gather_fp32_within_rounding(ctx):
+    d, n = 3, 4
+    fld = FIELDS_3D["balls"]()
+    Kf = O.assemble(fld, d, n, 4)
+    S = P.gather_stencils(ctx, d, n, dev(O.pack_pairs(d, Kf), torch.float32), P.MIXED, P.MIXED)
+    ref = O.to_half(d, O.stencils(d, n, Kf))
+    assert rel_err(host(S), ref) < 1e-6
+
+
+# ------------------------------------------------------------ compressed store
+def _parse_store(d, n, tt, off, pay):
+    """Decode the GPU store by its documented byte layout."""
+    NV = (n + 1) ** d
+    H = 4 if d == 2 else 13
+    e8 = np.zeros(NV, np.int64)
+    words = np.zeros((NV, H), np.int64)
+    for t in range(len(tt)):
+        tier = int(tt[t])
+        if tier == 0:
+            continue
+        eb = {1: 1, 2: 2, 3: 4}[tier]
+        base = int(off[t]) * 64
+        for l in range(64):
+            v = t * 64 + l
+            if v >= NV:
+                continue
+            e8[v] = pay[base + l]
+            for j in range(H):
+                p = base + 64 + (j * 64 + l) * eb
+                words[v, j] = int.from_bytes(bytes(pay[p:p + eb]), "little")
+    return e8, words
+
+
+@pytest.mark.parametrize("d,n", [(2, 10), (3, 5)])
+@pytest.mark.parametrize("policy", [(2, 2, 0.0, 0.0), (1, 1, 0.0, 0.0), (3, 3, 0.0, 0.0),
+                                    (1, 3, 0.0, 1e-3), (1, 3, 1e-7, 0.0)])
+def test_compress_payload_bit_exact(ctx, d, n, policy):
+    rng = np.random.default_rng(31 + d)
+    NV = (n + 1) ** d
+    H = 4 if d == 2 else 13
+    eps_c = rng.uniform(0.5, 2.0, size=n ** d).astype(np.float32)
+    # base couplings plus deltas of widely spread size so that every tier occurs
+    S = np.zeros((H, NV))
+    for v in range(NV):
+        for j, oi in enumerate(O.half_offsets(d)):
+            S[j, v] = O.base_coupling(d, n, eps_c, v, oi)[0]
+    scale = 10.0 ** rng.uniform(-9, -1, size=(1, NV))
+    S32 = (S + rng.standard_normal((H, NV)) * scale).astype(np.float32)
+    S32[:, ::7] = S[:, ::7].astype(np.float32)
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED)
+    h.compress(dev(S32, torch.float32), dev(eps_c, torch.float32), *policy)
+    tt, off, pay = h.store_export()
+    tt, off, pay = host(tt), host(off).astype(np.int64), host(pay)
+    ott, oe8, owords = O.compress(d, n, S32, eps_c, *policy)
+    assert np.array_equal(tt, ott)
+    units = np.array([0 if t == 0 else (64 + 64 * H * {1: 1, 2: 2, 3: 4}[t]) // 64 for t in ott])
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(units)[:-1]]))
+    e8, words = _parse_store(d, n, tt, off, pay)
+    stored = np.repeat(ott > 0, 64)[:NV]
+    assert np.array_equal(e8[stored], oe8[stored].astype(np.int64))
+    assert np.array_equal(words[stored], owords[stored].astype(np.int64))
+    if policy[0] == 1 and policy[1] == 3:
+        assert len(set(ott.tolist())) >= 2
+
+
+# ------------------------------------------------------------ Galerkin
+def _fine_stencils(d, n, s=4, seed=8):
+    fld = W.balls_field(d, 6, seed, r_lo=0.05, r_hi=0.3, eps_in=1e3)
+    return O.stencils(d, n, O.assemble(fld, d, n, s))
+
+
+@pytest.mark.parametrize("transfer", [0, 1])
+@pytest.mark.parametrize("d,n", [(2, 16), (2, 12), (3, 8)])
+def test_galerkin_and_weights_fp64(ctx, transfer, d, n):
+    S = _fine_stencils(d, n)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=transfer)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    ref = O.Hierarchy(d, n, S, coarsest=2, transfer=transfer)
+    assert h.nlev == ref.nlev
+    for l in range(1, h.nlev):
+        nl = h.level_n(l)
+        got = host(h.level_stencils(l))
+        want = O.to_half(d, ref.level_stencils(l))
+        m = half_mask(d, nl)
+        assert np.abs(got - want)[m].max() <= 1e-12 * np.abs(want[m]).max()
+    for l in range(h.nlev - 1):
+        np.testing.assert_allclose(host(h.level_weights(l)).T, ref.level_weights(l), rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------ cycle pieces
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+def test_cycle_pieces_fp64(ctx, d, n):
+    S = _fine_stencils(d, n)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=P.BOXMG)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    ref = O.Hierarchy(d, n, S, coarsest=2, transfer=1)
+    rng = np.random.default_rng(5)
+    inner = W.interior_mask(d, n)
+    u = rng.standard_normal(inner.size) * inner
+    f = rng.standard_normal(inner.size) * inner
+    ut = dev(u)
+    h.smooth(0, ut, dev(f), sweeps=1, omega=0.6)
+    assert rel_err(host(ut), O.jacobi(d, n, S, u, f, 0.6)) < 1e-12
+    r = torch.zeros_like(ut)
+    h.residual(0, dev(u), dev(f), r)
+    rr = O.residual(d, n, S, u, f)
+    assert rel_err(host(r), rr) < 1e-12
+    fc = torch.zeros(h.nv(1), dtype=torch.float64, device="cuda")
+    h.restrict(0, dev(rr), fc)
+    Pw = ref.level_weights(0)
+    assert rel_err(host(fc), O.restrict(d, n, rr, Pw)) < 1e-12
+    ec = rng.standard_normal(h.nv(1)) * W.interior_mask(d, n // 2)
+    uu = dev(u)
+    h.prolong_add(0, dev(ec), uu)
+    assert rel_err(host(uu), O.prolong_add(d, n, ec, u, Pw)) < 1e-12
+
+
+@pytest.mark.parametrize("transfer", [0, 1])
+@pytest.mark.parametrize("d,n", [(2, 32), (2, 24), (3, 8)])
+def test_vcycles_fp64_match_oracle(ctx, transfer, d, n):
+    S = _fine_stencils(d, n)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=transfer)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    ref = O.Hierarchy(d, n, S, coarsest=2, transfer=transfer)
+    f = W.load_sine(d, n)
+    u_ref = np.zeros_like(f)
+    ut = dev(u_ref)
+    ft = dev(f)
+    for _ in range(3):
+        h.vcycle(ut, ft, 0.6, 2, 2)
+        u_ref = ref.vcycle(u_ref, f, 0.6, 2, 2)
+        assert rel_err(host(ut), u_ref) < 1e-11
+
+
+def test_mixed_vcycle_contracts(ctx):
+    """FP32 cycle on the compressed store: a preconditioner for the FP64
+    outer residual; its contraction must be close to the FP64 cycle's."""
+    d, n = 2, 32
+    fld = W.sine_field(2, 0.9)
+    K = O.assemble(fld, d, n, 4)
+    S = O.stencils(d, n, K)
+    eps_c = np.array([O.element_matrix(fld, d, n, 1, c)[0, 0] / (2.0 / 3.0) for c in range(n * n)], np.float32)
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED)
+    h.compress(dev(O.to_half(d, S), torch.float32), dev(eps_c, torch.float32), 2, 2, 0.0, 0.0)
+    h.coarsen()
+    f = W.load_const(d, n)
+    u = torch.zeros(h.nv(), dtype=torch.float32, device="cuda")
+    ft = dev(f, torch.float32)
+    r = torch.zeros_like(u)
+    norms = []
+    for _ in range(6):
+        h.vcycle(u, ft)
+        h.residual(0, u, ft, r)
+        norms.append(float(torch.linalg.norm(r.double())))
+    assert norms[-1] / norms[0] < 1e-4
+
+
+# ------------------------------------------------------------ solves
+def test_solve_c1_fp64_matches_oracle(ctx):
+    """2D sine eps on 64x64 cells, s = 4, FP64 geometric V(2,2), omega 0.6,
+    down to 3x3 vertices, residual reduced by 1e-10."""
+    d, n = 2, 64
+    fld = W.sine_field(2, 0.9)
+    f = W.load_const(d, n)
+    u_ref, rep_ref = O.solve(fld, d, n, f, s_fixed=4, tol=1e-10)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), s_fixed=4, tol=1e-10)
+    assert rep["status"] == 0 and rep_ref["status"] == 0
+    assert rep["cycles"] == rep_ref["cycles"]
+    np.testing.assert_allclose(rep["hist"], rep_ref["hist"], rtol=1e-8, atol=1e-18)
+    assert rel_err(host(u), u_ref) < 1e-10
+
+
+def test_solve_lazy_deterministic_matches_oracle_schedule(ctx):
+    d, n = 2, 32
+    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+    f = W.load_const(d, n)
+    kw = dict(s_max=16, tol=1e-11)
+    u_ref, rr = O.solve(fld, d, n, f, lazy=True, transfer=O.BOXMG, outer=O.PCG, **kw)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, publish=P.PUBLISH_DETERMINISTIC,
+                     transfer=P.BOXMG, outer=P.PCG, **kw)
+    assert rep["status"] == 0 and rr["status"] == 0
+    assert rep["cycles"] == rr["cycles"]
+    assert rep["cells_at_s"] == rr["cells_at_s"]
+    np.testing.assert_allclose(rep["hist"], rr["hist"], rtol=1e-7, atol=1e-16)
+    assert rel_err(host(u), u_ref) < 1e-9
+
+
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
+def test_solve_async_lazy_equals_upfront(ctx, d, n):
+    fld = W.balls_field(d, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=8, tol=1e-10, transfer=P.BOXMG, outer=P.PCG)
+    u1, r1 = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.UPFRONT, **kw)
+    u2, r2 = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, **kw)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r1["cells_at_s"] == r2["cells_at_s"]
+    assert rel_err(host(u2), host(u1)) < 1e-8
+
+
+def test_solve_mixed_error_against_fp64_oracle(ctx):
+    """Mixed form (bf16x2 MFMA integration, FP16 surplus store, FP32 cycle,
+    FP64 outer PCG) against the FP64 oracle solution of the same problem:
+    stated bound 2e-3 relative (operator perturbation from the bf16 hi+lo
+    integration and the FP16 deltas)."""
+    d, n = 2, 64
+    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    f = W.load_sine(d, n)
+    u_ref, rr = O.solve(fld, d, n, f, s_max=8, tol=1e-11, transfer=O.BOXMG, outer=O.PCG)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), precision=P.MIXED, schedule=P.LAZY, s_max=8,
+                     tol=1e-10, transfer=P.BOXMG, outer=P.PCG)
+    assert rep["status"] == 0
+    assert rep["hist"][-1] <= 1e-10
+    err = rel_err(host(u), u_ref)
+    assert err < 2e-3, err
+
+
+def test_solve_single_level_and_odd_sizes(ctx):
+    d = 2
+    for n in (7, 12):
+        fld = W.sine_field(2, 0.5)
+        f = W.load_const(d, n)
+        u_ref, rr = O.solve(fld, d, n, f, s_fixed=2, tol=1e-12)
+        u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), s_fixed=2, tol=1e-12)
+        assert rep["status"] == 0
+        assert rel_err(host(u), u_ref) < 1e-10
+
+
+def test_invalid_arguments_raise(ctx):
+    fld = W.sine_field(2)
+    with pytest.raises(P.MgdError):
+        P.assemble_cells(ctx, 2, 8, 3, P.Eps(fld), P.FP64)
+    with pytest.raises(P.MgdError):
+        P.Hierarchy(ctx, 4, 8)
+    with pytest.raises(P.MgdError):
+        P.Hierarchy(ctx, 2, 1)
+
+
+def test_empty_cell_list_is_a_no_op(ctx):
+    fld = W.sine_field(2)
+    K, _, _ = P.assemble_cells(ctx, 2, 8, 4, P.Eps(fld), P.FP64, cells=torch.zeros(0, dtype=torch.int64, device="cuda"))
+    assert K.shape == (0, 6)
+
+
+# ------------------------------------------------------------ full size
+def test_full_size_balls_1024_sampled_rows(ctx):
+    """2D 1024^2 cells, 200 balls (r 0.005-0.05, eps 1e3), manufactured load,
+    FP64 up-front ladder s = 2..16, BoxMG + PCG to 1e-8: at sampled interior
+    vertices the oracle rebuilds the row of A from its own ladder on the four
+    adjacent cells and checks the GPU solution's residual there."""
+    d, n = 2, 1024
+    fld = W.config_field(1)
+    f = W.load_sine(d, n)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), s_max=16, tol=1e-8, transfer=P.BOXMG, outer=P.PCG,
+                     max_cycles=200)
+    assert rep["status"] == 0
+    ug = host(u)
+    fn = float(np.linalg.norm(f))
+    rng = np.random.default_rng(1)
+    nv = n + 1
+    # sample vertices, biased towards the balls
+    balls = fld.data.reshape(-1, 3)
+    pts = []
+    for b in rng.choice(len(balls), 40, replace=False):
+        cx, cy, r = balls[b]
+        pts.append((int((cx + r) * n), int(cy * n)))
+    pts += [tuple(rng.integers(1, n, size=2)) for _ in range(40)]
+    pts = [(min(max(i, 1), n - 1), min(max(j, 1), n - 1)) for i, j in pts]
+    for (i, j) in pts:
+        cells = [(i - 1) + n * (j - 1), i + n * (j - 1), (i - 1) + n * j, i + n * j]
+        Ks, _ = O.ladder_cells(fld, d, n, cells, 16, 0.01)
+        # row of vertex (i,j): local index of (i,j) in cell k is 3 - k
+        row = {}
+        for k, c in enumerate(cells):
+            cx, cy = c % n, c // n
+            a = 3 - k
+            for b in range(4):
+                w = (cx + (b & 1)) + nv * (cy + (b >> 1))
+                row[w] = row.get(w, 0.0) + Ks[k][a, b]
+        v = i + nv * j
+        rv = f[v] - sum(a * ug[w] for w, a in row.items())
+        assert abs(rv) <= 1e-8 * fn + 1e-12 * sum(abs(a * ug[w]) for w, a in row.items())
