@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the delayed-assembly multigrid hot path on one MI355X.
+
+Workload: 2D unit square, 1024 x 1024 Q1 cells, eps = 1 with 200 seeded balls
+(radius 0.005-0.05) of eps = 1e3, load of u = sin(pi x) sin(pi y); the lazy
+ladder s = 2, 4, 8, 16 runs while V-cycles run.  One step = one complete
+solve to a 1e-8 relative residual of the mixed form (bf16 hi+lo MFMA
+integration, FP16 surplus store, FP32 BoxMG V(2,2), FP64 outer conjugate
+gradients) with lazy assembly; the plain FP64 form with up-front assembly is
+timed beside it.  Inputs (load vector, material data) are resident in HBM
+before timing.
+
+Prints one JSON line.  `value` is the mixed-lazy form's fine-grid V-cycle
+throughput over the whole solve: (n-1)^2 DoF x V-cycles / time-to-solution.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell integrations/s, V-cycle DoF/s, time-to-1e-8 residual: mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("2D 1024^2 Q1 cells, eps=1 + 200 seeded balls (r 0.005-0.05) of eps=1e3, "
+            "manufactured u=sin(pi x)sin(pi y), lazy ladder s=2..16 (C=1%), BoxMG V(2,2) omega=0.6 "
+            "+ FP64 outer CG to 1e-8; mixed-lazy vs FP64-up-front")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweeps", type=int, default=200, help="timed finest-level sweeps for the roofline")
+    return ap.parse_args()
+
+
+def cpu_baseline(fld, d, n, f, cycles):
+    """The oracle, untouched, on host cores: setup (full ladder + hierarchy)
+    and two outer cycles, extrapolated to the GPU's cycle count."""
+    import oracle as O
+    kw = dict(s_max=16, tol=1e-8, transfer=O.BOXMG, outer=O.PCG)
+    t0 = time.perf_counter()
+    O.solve(fld, d, n, f, max_cycles=0, **kw)
+    t1 = time.perf_counter()
+    O.solve(fld, d, n, f, max_cycles=2, **kw)
+    t2 = time.perf_counter()
+    t_setup = t1 - t0
+    t_cycle = max((t2 - t1) - t_setup, 0.0) / 2.0
+    t_tts = t_setup + cycles * t_cycle
+    dof = (n - 1) ** d
+    return {"value": dof * cycles / t_tts, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"plain-C FP64 oracle, single thread, same 1024^2 problem: up-front ladder + BoxMG "
+                       f"hierarchy ({t_setup:.2f} s) and 2 PCG cycles ({t_cycle:.3f} s/cycle), "
+                       f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition "
+              "is a design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2005_03606_amd as P
+    import workload as W
+
+    d, n = 2, args.n
+    ctx = P.Context(0)
+    fld = W.config_field(1)
+    eps = P.Eps(fld)
+    f_host = W.load_sine(d, n)
+    f = torch.from_numpy(f_host).cuda()
+    tiers = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
+    mixed = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=16,
+                 tol=1e-8, max_cycles=400, **tiers)
+    fp64 = dict(precision=P.FP64, schedule=P.UPFRONT, transfer=P.BOXMG, outer=P.PCG, s_max=16,
+                tol=1e-8, max_cycles=400)
+
+    def run(kw):
+        u = torch.zeros_like(f)
+        return P.solve(ctx, d, n, eps, f, u, **kw)
+
+    for _ in range(args.warmup):
+        run(mixed)
+        run(fp64)
+    torch.cuda.synchronize()
+    reps_m, reps_f = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        um, rm = run(mixed)
+        reps_m.append(rm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        uf, rf = run(fp64)
+        reps_f.append(rf)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms_mixed = (t1 - t0) / args.steps * 1e3
+    ms_fp64 = (t2 - t1) / args.steps * 1e3
+    assert all(r["status"] == 0 for r in reps_m + reps_f), [r["status"] for r in reps_m + reps_f]
+    dof = (n - 1) ** d
+    cyc_m = reps_m[-1]["cycles"]
+    value = dof * cyc_m / (ms_mixed / 1e3)
+    err = float(torch.linalg.norm(um - uf) / torch.linalg.norm(uf))
+
+    # cell integrations per second (all cells, s = 16), both precisions
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    integ = {}
+    for mode, name in ((P.MIXED, "mixed_bf16x2_mfma"), (P.FP64, "fp64")):
+        P.assemble_cells(ctx, d, n, 16, eps, mode)
+        ev[0].record()
+        reps = 3
+        for _ in range(reps):
+            P.assemble_cells(ctx, d, n, 16, eps, mode)
+        ev[1].record()
+        torch.cuda.synchronize()
+        integ[name] = n ** d * reps / (ev[0].elapsed_time(ev[1]) / 1e3)
+
+    # roofline: finest-level Jacobi sweep on the compressed store (the kernel
+    # the mixed V-cycle spends most of its HBM traffic in)
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
+    S32 = P.gather_stencils(ctx, d, n, K16, P.MIXED, P.MIXED)
+    eps_c = P.centre_samples(ctx, d, n, eps)
+    h.compress(S32, eps_c, **tiers)
+    h.coarsen()
+    ntile, payload, tier_tiles = h.store_info()
+    NV = (n + 1) ** d
+    store_bytes = payload + 5 * ntile + 4 * n ** d
+    alg_bytes = store_bytes + 12 * NV  # operator + u in + f in + u out (FP32)
+    u32 = torch.zeros(NV, dtype=torch.float32, device="cuda")
+    f32 = f.float()
+    h.smooth(0, u32, f32, sweeps=2)
+    torch.cuda.synchronize()
+    ev[0].record()
+    calls = max(args.sweeps // 2, 1)
+    for _ in range(calls):
+        h.smooth(0, u32, f32, sweeps=2)
+    ev[1].record()
+    torch.cuda.synchronize()
+    avg_ms = ev[0].elapsed_time(ev[1]) / (2 * calls)
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep<2, OpComp<2,float>, float, 0, false>",
+                "bytes_per_launch": int(alg_bytes), "avg_launch_us": round(avg_ms * 1e3, 3),
+                "store_tiers": tier_tiles}
+
+    out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_mixed, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16x2-mfma/f16-store/f32-cycle/f64-outer",
+           "data": "synthetic",
+           "config": {"workload": WORKLOAD, "cells": n ** d, "dof": dof, "levels": reps_m[-1]["nlev"]},
+           "components": {
+               "time_to_1e8_mixed_lazy_ms": round(ms_mixed, 3),
+               "time_to_1e8_fp64_upfront_ms": round(ms_fp64, 3),
+               "speedup_mixed_lazy_vs_fp64_upfront": round(ms_fp64 / ms_mixed, 3),
+               "cycles_mixed_lazy": cyc_m, "cycles_fp64_upfront": reps_f[-1]["cycles"],
+               "publishes_mixed_lazy": reps_m[-1]["publishes"],
+               "vcycle_dof_per_s_fp64_upfront": dof * reps_f[-1]["cycles"] / (ms_fp64 / 1e3),
+               "cell_integrations_per_s_s16": {k: round(v, 1) for k, v in integ.items()},
+               "cell_integrations_per_solve": reps_m[-1]["integrations"],
+               "cells_at_s_1_2_4_8_16": reps_m[-1]["cells_at_s"],
+               "store_bytes_per_stencil_mixed": reps_m[-1]["store_bytes"] / NV,
+               "store_bytes_per_stencil_fp64": reps_f[-1]["store_bytes"] / NV,
+               "mixed_vs_fp64_solution_rel_err": err,
+               "t_first_cycle_ms_mixed_lazy": round(reps_m[-1]["t_first_cycle_ms"], 3),
+               "t_first_cycle_ms_fp64_upfront": round(reps_f[-1]["t_first_cycle_ms"], 3),
+           },
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(fld, d, n, f_host, reps_f[-1]["cycles"])
+    h.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

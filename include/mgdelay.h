@@ -50,7 +50,7 @@ enum { MGD_FP64 = 0, MGD_MIXED = 1 };          /* precision of a path */
 enum { MGD_GEOMETRIC = 0, MGD_BOXMG = 1 };     /* transfer operators */
 enum { MGD_STATIONARY = 0, MGD_PCG = 1 };      /* FP64 outer iteration */
 enum { MGD_UPFRONT = 0, MGD_LAZY = 1 };        /* assembly schedule */
-enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1 };
+enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1, MGD_PUBLISH_EVERY = 2 };
 
 typedef struct mgd_ctx mgd_ctx;   /* per-device context: streams, scratch */
 typedef struct mgd_hier mgd_hier; /* device-resident multigrid hierarchy */
@@ -108,6 +108,12 @@ int mgd_assemble_cells(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s,
                        const int64_t *cells, int64_t count, const mgd_eps *eps,
                        int32_t mode, void *K_out, const void *K_old, double C,
                        double *rel_out, uint8_t *done_out, hipStream_t stream);
+
+/* Centre samples eps(x_c) of all n^d cells as FP32 (eps_c_out dev float
+ * [n^d]): the s = 1 integration of Sec. 5.2 and the base of the
+ * hierarchical surplus (Sec. 5.5) that mgd_compress_stencils subtracts. */
+int mgd_centre_samples(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, float *eps_c_out,
+                       hipStream_t stream);
 
 /* (2a) Stencil gather, Sec. 4 (a stencil is one row of A_h): for every
  * vertex and upper slot, the coupling is the sum of K_c[loc v][loc v+o] over
@@ -216,8 +222,12 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * MGD_LAZY starts cycling on the centre-sample operator at once and runs the
  * ladder on a second stream; completed rungs are published (stencils
  * re-gathered, re-compressed, coarse operators recomputed) at cycle
- * boundaries: as soon as they complete (MGD_PUBLISH_ASYNC) or rung k right
- * before cycle k (MGD_PUBLISH_DETERMINISTIC, reproducible bit for bit).
+ * boundaries: MGD_PUBLISH_ASYNC runs the whole ladder back to back and
+ * publishes the final operator at the first boundary after it is built (one
+ * switch); MGD_PUBLISH_EVERY publishes every rung as soon as it is built;
+ * MGD_PUBLISH_DETERMINISTIC publishes rung k right before cycle k
+ * (reproducible bit for bit).  The solver keeps its state (hierarchy,
+ * ladder buffers) in the context between calls of the same shape.
  * Outer FP64 iteration: MGD_STATIONARY u += V(f - A u), or MGD_PCG
  * conjugate gradients with one V-cycle as preconditioner (Polak-Ribiere
  * beta, restarted at every publish).  Stops when every cell's ladder is final

@@ -8,6 +8,6 @@ load the library; the first call does, and raises if it is missing.
 """
 from .binding import (  # noqa: F401
     FP64, MIXED, GEOMETRIC, BOXMG, STATIONARY, PCG, UPFRONT, LAZY,
-    PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, MgdError, Context, Eps, Hierarchy,
-    assemble_cells, gather_stencils, solve, n_half, n_pairs, lib, library_path,
+    PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY, MgdError, Context, Eps, Hierarchy,
+    assemble_cells, centre_samples, gather_stencils, solve, n_half, n_pairs, lib, library_path,
 )

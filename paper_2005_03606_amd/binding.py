@@ -14,7 +14,7 @@ FP64, MIXED = 0, 1
 GEOMETRIC, BOXMG = 0, 1
 STATIONARY, PCG = 0, 1
 UPFRONT, LAZY = 0, 1
-PUBLISH_ASYNC, PUBLISH_DETERMINISTIC = 0, 1
+PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY = 0, 1, 2
 EPS_SAMPLES = 6
 HIST = 512
 
@@ -85,6 +85,7 @@ def lib():
         "mgd_assemble_cells": ([_P, _I, _I, _I, _P, C.c_int64, C.POINTER(_Eps), _I, _P, _P,
                                 C.c_double, _P, _P, _P], C.c_int),
         "mgd_gather_stencils": ([_P, _I, _I, _P, _I, _P, _I, _P], C.c_int),
+        "mgd_centre_samples": ([_P, _I, _I, C.POINTER(_Eps), _P, _P], C.c_int),
         "mgd_hier_create": ([_P, C.POINTER(_HierDesc), C.POINTER(_P)], C.c_int),
         "mgd_hier_destroy": ([_P], C.c_int),
         "mgd_hier_levels": ([_P], C.c_int),
@@ -199,6 +200,13 @@ def assemble_cells(ctx, dim, n, s, eps, mode=FP64, cells=None, K_old=None, C_thr
     ctx.check(lib().mgd_assemble_cells(ctx.h, dim, n, s, _ptr(cells), count, C.byref(eps.s), mode,
                                        _ptr(K), _ptr(K_old), C_thr, _ptr(rel), _ptr(done), _stream(stream)))
     return K, rel, done
+
+
+def centre_samples(ctx, dim, n, eps, stream=None):
+    """FP32 eps at every cell centre [n^d]."""
+    out = torch.empty(n ** dim, dtype=torch.float32, device=torch.device("cuda", ctx.device))
+    ctx.check(lib().mgd_centre_samples(ctx.h, dim, n, C.byref(eps.s), _ptr(out), _stream(stream)))
+    return out
 
 
 def gather_stencils(ctx, dim, n, K, k_mode=FP64, s_mode=FP64, stream=None):

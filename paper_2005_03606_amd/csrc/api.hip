@@ -7,18 +7,8 @@
 int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
 
 static const int64_t kMaxCoarseDofs = 1500;
+void solve_cache_free(mgd_ctx *ctx);
 
-static int ensure_partial(mgd_ctx *ctx, int64_t need)
-{
-    if (need <= ctx->partial_cap) return MGD_OK;
-    dev_free(ctx->partial);
-    ctx->partial = nullptr;
-    ctx->partial_cap = 0;
-    int rc = dev_alloc(ctx, (void **)&ctx->partial, (size_t)need * 8);
-    if (rc) return rc;
-    ctx->partial_cap = need;
-    return MGD_OK;
-}
 
 static int64_t ipow(int64_t b, int e)
 {
@@ -60,8 +50,14 @@ int hier_alloc_levels(mgd_hier *h)
         if ((rc = dev_alloc(ctx, (void **)&h->delta, (size_t)h->NV[0] * h->H * 4))) return rc;
         if ((rc = dev_alloc(ctx, (void **)&h->vtier, (size_t)h->NV[0]))) return rc;
     }
-    int64_t nb = (h->NV[0] + 255) / 256;
-    return ensure_partial(ctx, 2 * nb + 64 > h->m_coarse ? 2 * nb + 64 : h->m_coarse + 64);
+    int64_t nb = (h->NV[0] + 255) / 256 + (h->nl[0] + 1) / 4 + 64;
+    h->partial_cap = 2 * nb > h->m_coarse + 64 ? 2 * nb : h->m_coarse + 64;
+    if ((rc = dev_alloc(ctx, (void **)&h->partial, (size_t)h->partial_cap * 8))) return rc;
+    if ((rc = dev_alloc(ctx, (void **)&h->scal, 64 * 8))) return rc;
+    HIPCHK(ctx, hipMemset(h->scal, 0, 64 * 8));
+    if (hipHostMalloc((void **)&h->host_scal, 64 * 8, hipHostMallocDefault) != hipSuccess)
+        return mgd_fail(ctx, MGD_ENOMEM, "pinned allocation failed");
+    return MGD_OK;
 }
 
 void hier_free(mgd_hier *h)
@@ -74,6 +70,12 @@ void hier_free(mgd_hier *h)
     dev_free(h->delta); dev_free(h->vtier);
     h->delta = nullptr;
     h->vtier = nullptr;
+    dev_free(h->partial); dev_free(h->scal);
+    h->partial = nullptr;
+    h->scal = nullptr;
+    h->partial_cap = 0;
+    if (h->host_scal) (void)hipHostFree(h->host_scal);
+    h->host_scal = nullptr;
 }
 
 // ------------------------------------------------------------ validation
@@ -126,11 +128,6 @@ int mgd_create(mgd_ctx **out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&ctx->s_asm, hipStreamNonBlocking) != hipSuccess) { delete ctx; return MGD_EHIP; }
-    if (dev_alloc(ctx, (void **)&ctx->scal, 64 * 8) || ensure_partial(ctx, 1 << 16) ||
-        hipHostMalloc((void **)&ctx->host_scal, 64 * 8, hipHostMallocDefault) != hipSuccess) {
-        mgd_destroy(ctx);
-        return MGD_ENOMEM;
-    }
     *out = ctx;
     return MGD_OK;
 }
@@ -140,9 +137,7 @@ int mgd_destroy(mgd_ctx *ctx)
     if (!ctx) return MGD_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->s_asm) (void)hipStreamSynchronize(ctx->s_asm);
-    dev_free(ctx->scal);
-    dev_free(ctx->partial);
-    if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
+    solve_cache_free(ctx);
     if (ctx->s_asm) (void)hipStreamDestroy(ctx->s_asm);
     delete ctx;
     return MGD_OK;
@@ -159,6 +154,7 @@ int mgd_assemble_cells(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s, const in
     if ((rc = check_grid(ctx, dim, n)) || (rc = check_s(ctx, s)) || (rc = check_eps(ctx, eps, dim, true))) return rc;
     if (mode != MGD_FP64 && mode != MGD_MIXED) return mgd_fail(ctx, MGD_EINVAL, "mode must be MGD_FP64 or MGD_MIXED");
     int64_t ncell = ipow(n, dim);
+    if (count == 0) return MGD_OK;
     if (!cells && count != ncell) return mgd_fail(ctx, MGD_EINVAL, "cells == NULL needs count == n^d");
     if (count < 0 || count > ncell) return mgd_fail(ctx, MGD_EINVAL, "bad count %lld", (long long)count);
     if (!K_out && count > 0) return mgd_fail(ctx, MGD_EINVAL, "K_out is NULL");
@@ -167,6 +163,17 @@ int mgd_assemble_cells(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s, const in
     HIPCHK(ctx, hipSetDevice(ctx->device));
     return launch_assemble(ctx, dim, n, s, cells, count, eps, mode, K_out, K_old, 0, C, rel_out, done_out,
                            nullptr, stream);
+}
+
+int mgd_centre_samples(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, float *eps_c_out,
+                       hipStream_t stream)
+{
+    if (!ctx) return MGD_EINVAL;
+    int rc;
+    if ((rc = check_grid(ctx, dim, n)) || (rc = check_eps(ctx, eps, dim, false))) return rc;
+    if (!eps_c_out) return mgd_fail(ctx, MGD_EINVAL, "eps_c_out is NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return launch_centre_eps(ctx, dim, n, eps, eps_c_out, stream);
 }
 
 int mgd_gather_stencils(mgd_ctx *ctx, int32_t dim, int32_t n, const void *K, int32_t k_mode, void *S_out,

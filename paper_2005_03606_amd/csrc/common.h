@@ -12,16 +12,13 @@
 #define MGD_MAXLEV 24
 
 // ----------------------------------------------------------------- errors
+struct SolveState;
 struct mgd_ctx {
     int device = 0;
     int num_cu = 256;
     hipStream_t s_asm = nullptr;  // assembly stream (default priority)
     char err[512] = {0};
-    // small device scratch for reductions and scalars
-    double *scal = nullptr;       // [64] device scalars
-    double *partial = nullptr;    // [partial_cap] block partial sums
-    int64_t partial_cap = 0;
-    double *host_scal = nullptr;  // pinned [64]
+    SolveState *cache = nullptr;  // device-resident workspace of the last solve shape
 };
 
 int mgd_fail(mgd_ctx *ctx, int code, const char *fmt, ...);
@@ -148,6 +145,7 @@ __host__ __device__ inline double kref_unit(int D, int nz)
 template <int D>
 __device__ inline double base_coupling64(const float *eps_c, int n, const int *x, int j, double *ref)
 {
+#pragma clang fp contract(off)
     int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
     int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
     double sum = 0.0, sall = 0.0;
@@ -163,12 +161,12 @@ __device__ inline double base_coupling64(const float *eps_c, int n, const int *x
         }
         if (!ok) continue;
         double e = (double)eps_c[c];
-        sall = __dadd_rn(sall, e);
-        if (shared) sum = __dadd_rn(sum, e);
+        sall = sall + e;
+        if (shared) sum = sum + e;
     }
     double hp = (D == 2) ? 1.0 : 1.0 / (double)n;
-    if (ref) *ref = __dmul_rn(sall, hp);
-    return __dmul_rn(__dmul_rn(sum, kref_unit(D, nz)), hp);
+    if (ref) *ref = sall * hp;
+    return (sum * kref_unit(D, nz)) * hp;
 }
 
 // ------------------------------------------------------- host objects
@@ -199,6 +197,11 @@ struct mgd_hier {
     // scratch for compression
     float *delta = nullptr;
     uint8_t *vtier = nullptr;
+    // reduction scratch and device scalars owned by this hierarchy
+    double *partial = nullptr;    // block partial sums / coarse-solve work
+    int64_t partial_cap = 0;
+    double *scal = nullptr;       // [64] device scalars
+    double *host_scal = nullptr;  // pinned [64]
     size_t vec_bytes() const { return precision == MGD_FP64 ? 8 : 4; }
 };
 

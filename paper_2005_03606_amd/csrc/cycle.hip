@@ -77,12 +77,13 @@ __device__ inline void apply_row(const Op &A, const Grid<D> &g, int64_t v, const
     Au = Dv * u[v] + acc;
 }
 
-// mode 0: Jacobi sweep out = u + omega (f - A u) / D; mode 1: residual out = f - A u;
-// zero_guess: u treated as 0 (first sweep from a zero start).
-template <int D, class Op, typename T>
-__global__ __launch_bounds__(256) void k_sweep(Op A, int n, const T *u, const T *f, T *out, T omega, int mode,
-                                               int zero_guess, double *partial)
+// MODE 0: Jacobi sweep out = u + omega (f - A u) / D; MODE 1: residual out = f - A u;
+// ZERO: u treated as 0 (first sweep from a zero start).
+template <int D, class Op, typename T, int MODE, bool ZERO>
+__global__ __launch_bounds__(256) void k_sweep(Op A, int n, const T *u, const T *f, T *out, T omega, double *partial)
 {
+    constexpr int mode = MODE;
+    constexpr bool zero_guess = ZERO;
     __shared__ double red[256];
     Grid<D> g(n);
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -188,17 +189,137 @@ template <typename T> __global__ void k_fill(T *a, int64_t n, T val)
     if (i < n) a[i] = val;
 }
 
+// ------------------------------------------------------------ staged 2D store kernels
+// Finest level of the compressed store, 2D: a 64 x 4 block of vertices
+// stages in LDS the centre samples of cells [x0-2, x0+64] x [y0-2, y0+3], the
+// decoded couplings (centre-sample base + surplus) of vertices
+// [x0-1, x0+64] x [y0-1, y0+3] and the iterate on [x0-1, x0+64] x [y0-1, y0+4];
+// each vertex then reads its 4 own and 4 low-side neighbour couplings and
+// its 9 iterate values from LDS.  TC: coupling / arithmetic type.
+enum { ST_SWEEP = 0, ST_SWEEP0 = 1, ST_RESID = 2, ST_OUTER = 3, ST_PMATVEC = 4 };
+
+template <typename TC> struct StageArgs {
+    StoreView sv;
+    int n;
+    const void *u;     // iterate (SWEEP/RESID: float; OUTER: double) / z (PMATVEC: float)
+    const void *f;     // rhs (float / double)
+    void *out;         // float / double
+    const double *pold;
+    double *pnew;
+    const double *s;   // device scalars (beta at s[5])
+    double *partial;
+    float omega;
+};
+
+template <typename TC, int KIND>
+__global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
+{
+#pragma clang fp contract(off)
+    constexpr int BX = 64, BY = 4;
+    __shared__ float s_eps[BY + 2][BX + 3];
+    __shared__ TC s_c[4][BY + 1][BX + 2];
+    __shared__ TC s_u[BY + 2][BX + 2];
+    __shared__ double red[256];
+    const int n = a.n, nv = n + 1;
+    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY;
+    const int tid = threadIdx.x;
+    // centre samples of cells x in [x0-2, x0+64], y in [y0-2, y0+3]
+    for (int k = tid; k < (BY + 2) * (BX + 3); k += 256) {
+        int cx = x0 - 2 + k % (BX + 3), cy = y0 - 2 + k / (BX + 3);
+        s_eps[k / (BX + 3)][k % (BX + 3)] = (cx >= 0 && cx < n && cy >= 0 && cy < n) ? a.sv.eps_c[(int64_t)cy * n + cx] : 0.0f;
+    }
+    // iterate with a one-vertex halo
+    double beta = KIND == ST_PMATVEC ? a.s[5] : 0.0;
+    for (int k = tid; k < (BY + 2) * (BX + 2); k += 256) {
+        int vx = x0 - 1 + k % (BX + 2), vy = y0 - 1 + k / (BX + 2);
+        TC val = (TC)0;
+        if (KIND != ST_SWEEP0 && vx >= 0 && vx < nv && vy >= 0 && vy < nv) {
+            int64_t v = (int64_t)vy * nv + vx;
+            if (KIND == ST_PMATVEC) val = (TC)((double)((const float *)a.u)[v] + beta * a.pold[v]);
+            else if (KIND == ST_OUTER) val = (TC)((const double *)a.u)[v];
+            else val = (TC)((const float *)a.u)[v];
+        }
+        s_u[k / (BX + 2)][k % (BX + 2)] = val;
+    }
+    __syncthreads();
+    // decoded couplings of vertices x in [x0-1, x0+64], y in [y0-1, y0+3]
+    for (int k = tid; k < (BY + 1) * (BX + 2); k += 256) {
+        int lx = k % (BX + 2), ly = k / (BX + 2);
+        int vx = x0 - 1 + lx, vy = y0 - 1 + ly;
+        TC c[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
+        if (vx >= 0 && vx < nv && vy >= 0 && vy < nv) {
+            int64_t v = (int64_t)vy * nv + vx;
+            // cells around (vx, vy): e(cx, cy) at s_eps[cy - y0 + 2][cx - x0 + 2]
+            TC e00 = (TC)s_eps[ly][lx], e10 = (TC)s_eps[ly][lx + 1];       // (vx-1, vy-1), (vx, vy-1)
+            TC e01 = (TC)s_eps[ly + 1][lx], e11 = (TC)s_eps[ly + 1][lx + 1]; // (vx-1, vy), (vx, vy)
+            const TC k6 = (TC)(-1.0 / 6.0), k3 = (TC)(-1.0 / 3.0);
+            TC base[4] = {(e10 + e11) * k6, e01 * k3, (e01 + e11) * k6, e11 * k3};
+            int64_t t = v >> 6;
+            int tt = a.sv.tier[t];
+            if (tt == 0) {
+                for (int j = 0; j < 4; ++j) c[j] = base[j];
+            } else {
+                const uint8_t *bp = a.sv.payload + (size_t)a.sv.off[t] * 64;
+                int l = (int)(v & 63);
+                float sc = e8m0_to_float(bp[l]);
+                for (int j = 0; j < 4; ++j) {
+                    float d;
+                    if (tt == 2) d = (float)__builtin_bit_cast(_Float16, ((const uint16_t *)(bp + 64 + j * 128))[l]) * sc;
+                    else if (tt == 1) d = e4m3_to_float(bp[64 + j * 64 + l]) * sc;
+                    else d = ((const float *)(bp + 64 + j * 256))[l];
+                    c[j] = base[j] + (TC)d;
+                }
+            }
+        }
+        for (int j = 0; j < 4; ++j) s_c[j][ly][lx] = c[j];
+    }
+    __syncthreads();
+    const int tx = tid & 63, ty = tid >> 6;
+    const int vx = x0 + tx, vy = y0 + ty;
+    double part = 0.0;
+    if (vx < nv && vy < nv) {
+        int64_t v = (int64_t)vy * nv + vx;
+        const int cx = tx + 1, cy = ty + 1;  // this vertex in s_c / s_u coordinates
+        bool inner = vx > 0 && vx < n && vy > 0 && vy < n;
+        // own upper couplings: (1,0), (-1,1), (0,1), (1,1); low-side ones from
+        // the neighbours' slots: (-1,0) slot 0 of (x-1,y), (1,-1) slot 1 of
+        // (x+1,y-1), (0,-1) slot 2 of (x,y-1), (-1,-1) slot 3 of (x-1,y-1)
+        TC a0 = s_c[0][cy][cx], a1 = s_c[1][cy][cx], a2 = s_c[2][cy][cx], a3 = s_c[3][cy][cx];
+        TC b0 = s_c[0][cy][cx - 1], b1 = s_c[1][cy - 1][cx + 1], b2 = s_c[2][cy - 1][cx], b3 = s_c[3][cy - 1][cx - 1];
+        TC dsum = ((a0 + a1) + (a2 + a3)) + ((b0 + b1) + (b2 + b3));
+        TC Dv = -dsum;
+        TC uc = s_u[cy][cx];
+        TC acc = a0 * s_u[cy][cx + 1] + a1 * s_u[cy + 1][cx - 1] + a2 * s_u[cy + 1][cx] + a3 * s_u[cy + 1][cx + 1] +
+                 b0 * s_u[cy][cx - 1] + b1 * s_u[cy - 1][cx + 1] + b2 * s_u[cy - 1][cx] + b3 * s_u[cy - 1][cx - 1];
+        TC Au = Dv * uc + acc;
+        if (KIND == ST_SWEEP || KIND == ST_SWEEP0) {
+            const float *f = (const float *)a.f;
+            float *o = (float *)a.out;
+            o[v] = inner ? (float)(uc + (TC)a.omega * ((TC)f[v] - Au) / Dv) : 0.0f;
+        } else if (KIND == ST_RESID) {
+            ((float *)a.out)[v] = inner ? (float)((TC)((const float *)a.f)[v] - Au) : 0.0f;
+        } else if (KIND == ST_OUTER) {
+            double r = inner ? (double)((TC)((const double *)a.f)[v] - Au) : 0.0;
+            ((double *)a.out)[v] = r;
+            part = r * r;
+        } else {  // PMATVEC
+            a.pnew[v] = (double)uc;
+            double ap = inner ? (double)Au : 0.0;
+            ((double *)a.out)[v] = ap;
+            part = (double)uc * ap;
+        }
+    }
+    if (KIND == ST_OUTER || KIND == ST_PMATVEC) {
+        double sum = block_sum<256>(part, red);
+        if (tid == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+    }
+}
+
+static inline dim3 stage2_grid(int n) { return dim3((unsigned)((n + 1 + 63) / 64), (unsigned)((n + 1 + 3) / 4)); }
+
 // ------------------------------------------------------------ dispatch
 int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
 StoreView store_view(const mgd_hier *h, const OpSet &o);
-
-template <int D, typename T, class F> static int with_op(mgd_hier *h, const OpSet &o, int level, F fn)
-{
-    if (h->precision == MGD_FP64) return fn(OpHalf<double>{o.S64[level], h->NV[level]});
-    if (level > 0) return fn(OpHalf<float>{o.S32[level], h->NV[level]});
-    OpComp<D, float> c{store_view(h, o), h->n, (float)(D == 2 ? 1.0 : 1.0 / h->n)};
-    return fn(c);
-}
 
 template <int D, typename T>
 static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *f, T *out, double omega, int mode,
@@ -206,9 +327,30 @@ static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *
 {
     int n = h->nl[level];
     dim3 gr(grid_for(h->NV[level], 256));
+    if (D == 2 && h->precision == MGD_MIXED && level == 0) {
+        StageArgs<float> sa;
+        memset(&sa, 0, sizeof(sa));
+        sa.sv = store_view(h, o);
+        sa.n = n;
+        sa.u = u;
+        sa.f = f;
+        sa.out = out;
+        sa.omega = (float)omega;
+        dim3 g2 = stage2_grid(n);
+        if (mode == 1) hipLaunchKernelGGL((k_stage2<float, ST_RESID>), g2, dim3(256), 0, st, sa);
+        else if (zero_guess) hipLaunchKernelGGL((k_stage2<float, ST_SWEEP0>), g2, dim3(256), 0, st, sa);
+        else hipLaunchKernelGGL((k_stage2<float, ST_SWEEP>), g2, dim3(256), 0, st, sa);
+        HIPCHK(h->ctx, hipGetLastError());
+        return MGD_OK;
+    }
     auto go = [&](auto A) {
-        hipLaunchKernelGGL((k_sweep<D, decltype(A), T>), gr, dim3(256), 0, st, A, n, u, f, out, (T)omega, mode,
-                           zero_guess ? 1 : 0, partial);
+        using OpT = decltype(A);
+        if (mode == 1)
+            hipLaunchKernelGGL((k_sweep<D, OpT, T, 1, false>), gr, dim3(256), 0, st, A, n, u, f, out, (T)omega, partial);
+        else if (zero_guess)
+            hipLaunchKernelGGL((k_sweep<D, OpT, T, 0, true>), gr, dim3(256), 0, st, A, n, u, f, out, (T)omega, partial);
+        else
+            hipLaunchKernelGGL((k_sweep<D, OpT, T, 0, false>), gr, dim3(256), 0, st, A, n, u, f, out, (T)omega, partial);
         return MGD_OK;
     };
     if (h->precision == MGD_FP64) go(OpHalf<double>{o.S64[level], h->NV[level]});
@@ -293,12 +435,257 @@ static int fill_zero(mgd_hier *h, void *a, int64_t n, hipStream_t st)
     return MGD_OK;
 }
 
+// ------------------------------------------------------------ coarse tail
+// The small levels of the V-cycle, from level `first` (zero initial guess or
+// a given u) down to the dense coarsest solve and back up, in one workgroup:
+// each step is a strided loop over the level's vertices, steps separated by
+// workgroup barriers (global writes of the workgroup are visible after them).
+struct TailLevel {
+    const void *S, *W;
+    void *u, *f, *r, *t;
+    int n;
+    int64_t NV;
+};
+struct TailArgs {
+    int first, last, nu1, nu2, zero_guess;
+    double omega;
+    const double *chol;
+    int64_t m;
+    double *work;
+    TailLevel L[MGD_MAXLEV];
+};
+
+template <int D, typename T>
+__device__ void tail_sweep(const TailLevel &lv, const T *u, T *out, bool zero, T omega)
+{
+    OpHalf<T> A{(const T *)lv.S, lv.NV};
+    Grid<D> g(lv.n);
+    const T *f = (const T *)lv.f;
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) { out[v] = (T)0; continue; }
+        T Au, Dv;
+        if (zero) {
+            constexpr int H = n_half(D);
+            T dsum = (T)0;
+            for (int j = 0; j < H; ++j) {
+                int64_t lin = half_lin(D, j, g.nv);
+                dsum += A.c(v, j, x) + A.c(v - lin, j, x);
+            }
+            Dv = -dsum;
+            Au = (T)0;
+        } else {
+            apply_row<D, OpHalf<T>, T>(A, g, v, x, u, Au, Dv);
+        }
+        out[v] = (zero ? (T)0 : u[v]) + omega * (f[v] - Au) / Dv;
+    }
+    __syncthreads();
+}
+
+template <int D, typename T> __device__ void tail_smooth(const TailLevel &lv, int sweeps, bool zero, T omega)
+{
+    T *u = (T *)lv.u, *t = (T *)lv.t;
+    for (int k = 0; k < sweeps; ++k) {
+        if (k % 2 == 0) tail_sweep<D, T>(lv, u, t, zero && k == 0, omega);
+        else tail_sweep<D, T>(lv, t, u, false, omega);
+    }
+    if (sweeps % 2 == 1) {
+        for (int64_t v = threadIdx.x; v < lv.NV; v += blockDim.x) u[v] = t[v];
+        __syncthreads();
+    }
+    if (sweeps == 0 && zero) {
+        for (int64_t v = threadIdx.x; v < lv.NV; v += blockDim.x) u[v] = (T)0;
+        __syncthreads();
+    }
+}
+
+template <int D, typename T> __device__ void tail_residual_restrict(const TailLevel &lv, const TailLevel &lc)
+{
+    OpHalf<T> A{(const T *)lv.S, lv.NV};
+    Grid<D> g(lv.n), gc(lc.n);
+    const T *u = (const T *)lv.u, *f = (const T *)lv.f;
+    T *r = (T *)lv.r;
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) { r[v] = (T)0; continue; }
+        T Au, Dv;
+        apply_row<D, OpHalf<T>, T>(A, g, v, x, u, Au, Dv);
+        r[v] = f[v] - Au;
+    }
+    __syncthreads();
+    const T *W = (const T *)lv.W;
+    T *fc = (T *)lc.f, *uc = (T *)lc.u;
+    constexpr int ns = D == 2 ? 9 : 27;
+    for (int64_t V = threadIdx.x; V < gc.NV; V += blockDim.x) {
+        int X[3] = {0, 0, 0};
+        gc.coords(V, X);
+        uc[V] = (T)0;
+        if (!gc.interior(X)) { fc[V] = (T)0; continue; }
+        T s = (T)0;
+        for (int sv = 0; sv < ns; ++sv) {
+            int x[3] = {0, 0, 0}, t = sv;
+            for (int m = 0; m < D; ++m) { x[m] = 2 * X[m] + t % 3 - 1; t /= 3; }
+            int64_t v = g.vid(x);
+            s += wt<D, T, T>(W, g.NV, v, x, X) * r[v];
+        }
+        fc[V] = s;
+    }
+    __syncthreads();
+}
+
+template <int D, typename T> __device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc)
+{
+    Grid<D> g(lv.n), gc(lc.n);
+    const T *W = (const T *)lv.W, *ec = (const T *)lc.u;
+    T *u = (T *)lv.u;
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) continue;
+        T s = (T)0;
+        for (int B = 0; B < (1 << D); ++B) {
+            int X[3] = {0, 0, 0};
+            bool ok = true;
+            for (int m = 0; m < D; ++m) {
+                X[m] = (x[m] >> 1) + ((B >> m) & 1);
+                if (X[m] > gc.n) ok = false;
+            }
+            if (!ok) continue;
+            T w = wt<D, T, T>(W, g.NV, v, x, X);
+            if (w != (T)0) s += w * ec[gc.vid(X)];
+        }
+        u[v] += s;
+    }
+    __syncthreads();
+}
+
+template <int BS> __device__ inline double block_sum_tail(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = BS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// dense solve on the coarsest interior, FP64 triangular substitutions
+template <int D, typename T> __device__ void tail_coarse(const TailLevel &lv, const double *L, int64_t m, double *work,
+                                                         double *red)
+{
+    Grid<D> g(lv.n);
+    const T *f = (const T *)lv.f;
+    T *u = (T *)lv.u;
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        if (!g.interior(x)) continue;
+        int64_t k = 0, st = 1;
+        for (int mm = 0; mm < D; ++mm) { k += (int64_t)(x[mm] - 1) * st; st *= (lv.n - 1); }
+        work[k] = (double)f[v];
+    }
+    __syncthreads();
+    for (int64_t i = 0; i < m; ++i) {
+        double s = 0.0;
+        for (int64_t k = threadIdx.x; k < i; k += blockDim.x) s += L[i * m + k] * work[k];
+        s = block_sum_tail<1024>(s, red);
+        if (threadIdx.x == 0) work[i] = (work[i] - s) / L[i * m + i];
+        __syncthreads();
+    }
+    for (int64_t i = m - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int64_t k = i + 1 + threadIdx.x; k < m; k += blockDim.x) s += L[k * m + i] * work[k];
+        s = block_sum_tail<1024>(s, red);
+        if (threadIdx.x == 0) work[i] = (work[i] - s) / L[i * m + i];
+        __syncthreads();
+    }
+    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        T val = (T)0;
+        if (g.interior(x)) {
+            int64_t k = 0, st = 1;
+            for (int mm = 0; mm < D; ++mm) { k += (int64_t)(x[mm] - 1) * st; st *= (lv.n - 1); }
+            val = (T)work[k];
+        }
+        u[v] = val;
+    }
+    __syncthreads();
+}
+
+template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(TailArgs a)
+{
+    __shared__ double red[1024];
+    T omega = (T)a.omega;
+    for (int l = a.first; l < a.last; ++l) {
+        bool zero = l > a.first || a.zero_guess;
+        tail_smooth<D, T>(a.L[l], a.nu1, zero, omega);
+        tail_residual_restrict<D, T>(a.L[l], a.L[l + 1]);
+    }
+    tail_coarse<D, T>(a.L[a.last], a.chol, a.m, a.work, red);
+    for (int l = a.last - 1; l >= a.first; --l) {
+        tail_prolong<D, T>(a.L[l], a.L[l + 1]);
+        tail_smooth<D, T>(a.L[l], a.nu2, false, omega);
+    }
+}
+
+// first level handled by the tail kernel (levels with few vertices)
+static int tail_first(const mgd_hier *h)
+{
+    const int64_t kTailNV = 5000;
+    int l = h->nlev - 1;
+    while (l > 0 && h->NV[l - 1] <= kTailNV) --l;
+    if (h->precision == MGD_MIXED && l == 0) l = h->nlev > 1 ? 1 : 0;  // level 0 is the compressed store
+    return l;
+}
+
+static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const void *f, double omega, int nu1, int nu2,
+                       bool zero_guess, hipStream_t st)
+{
+    TailArgs a;
+    memset(&a, 0, sizeof(a));
+    a.first = first;
+    a.last = h->nlev - 1;
+    a.nu1 = nu1;
+    a.nu2 = nu2;
+    a.zero_guess = zero_guess ? 1 : 0;
+    a.omega = omega;
+    a.chol = o.chol;
+    a.m = h->m_coarse;
+    a.work = h->partial;
+    for (int l = first; l <= a.last; ++l) {
+        TailLevel &L = a.L[l];
+        L.S = h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l];
+        L.W = h->transfer == MGD_BOXMG ? o.W[l] : nullptr;
+        L.u = l == first ? u : h->u[l];
+        L.f = l == first ? const_cast<void *>(f) : h->f[l];
+        L.r = h->r[l];
+        L.t = h->t[l];
+        L.n = h->nl[l];
+        L.NV = h->NV[l];
+    }
+    if (h->precision == MGD_FP64) {
+        if (h->dim == 2) hipLaunchKernelGGL((k_tail<2, double>), dim3(1), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_tail<3, double>), dim3(1), dim3(1024), 0, st, a);
+    } else {
+        if (h->dim == 2) hipLaunchKernelGGL((k_tail<2, float>), dim3(1), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_tail<3, float>), dim3(1), dim3(1024), 0, st, a);
+    }
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
 // multiplicative V(nu1,nu2) correction scheme from level l down
 static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f, double omega, int nu1, int nu2,
                       bool zero_guess, hipStream_t st)
 {
     int rc;
-    if (l == h->nlev - 1) return cycle_coarse_solve(h, o, u, f, st);
+    if (l == tail_first(h)) return launch_tail(h, o, l, u, f, omega, nu1, nu2, zero_guess, st);
     if (nu1 > 0) {
         if ((rc = cycle_smooth(h, o, l, u, f, h->t[l], nu1, omega, zero_guess, st))) return rc;
     } else if (zero_guess) {
@@ -325,6 +712,7 @@ template <int D> struct OpComp64 {
     int n;
     __device__ inline double c(int64_t v, int j, const int *x) const
     {
+#pragma clang fp contract(off)
         return base_coupling64<D>(sv.eps_c, n, x, j, nullptr) + (double)sv.delta(v, j, n_half(D));
     }
 };
@@ -384,12 +772,30 @@ static int outer_residual_t(mgd_hier *h, const OpSet &o, const double *u, const 
 int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, double *norm2_dev,
                    hipStream_t st)
 {
-    double *partial = norm2_dev ? h->ctx->partial : nullptr;
+    if (h->dim == 2 && h->precision == MGD_MIXED) {
+        StageArgs<double> sa;
+        memset(&sa, 0, sizeof(sa));
+        sa.sv = store_view(h, o);
+        sa.n = h->n;
+        sa.u = u;
+        sa.f = f;
+        sa.out = r;
+        sa.partial = h->partial;
+        dim3 g2 = stage2_grid(h->n);
+        hipLaunchKernelGGL((k_stage2<double, ST_OUTER>), g2, dim3(256), 0, st, sa);
+        if (norm2_dev) {
+            int64_t nb = (int64_t)g2.x * g2.y;
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev);
+        }
+        HIPCHK(h->ctx, hipGetLastError());
+        return MGD_OK;
+    }
+    double *partial = norm2_dev ? h->partial : nullptr;
     int rc = h->dim == 2 ? outer_residual_t<2>(h, o, u, f, r, partial, st) : outer_residual_t<3>(h, o, u, f, r, partial, st);
     if (rc) return rc;
     if (norm2_dev) {
         int64_t nb = grid_for(h->NV[0], 256);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->ctx->partial, nb, 1, nb, norm2_dev);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev);
         HIPCHK(h->ctx, hipGetLastError());
     }
     return MGD_OK;
@@ -526,7 +932,7 @@ int vec_add_cycle(mgd_hier *h, double *u, const void *e, hipStream_t st)
 int pcg_beta(mgd_hier *h, const void *z, const double *r, const double *rold, double *s, hipStream_t st)
 {
     int64_t n = h->NV[0], nb = grid_for(n, 256);
-    double *part = h->ctx->partial;
+    double *part = h->partial;
     if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_dots_zr<double>, dim3(nb), dim3(256), 0, st, (const double *)z, r, rold, n, part, nb);
     else hipLaunchKernelGGL(k_dots_zr<float>, dim3(nb), dim3(256), 0, st, (const float *)z, r, rold, n, part, nb);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 2, nb, s + 1);
@@ -540,7 +946,7 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
                         double *s, hipStream_t st)
 {
     int64_t n = h->NV[0], nb = grid_for(n, 256);
-    double *part = h->ctx->partial;
+    double *part = h->partial;
     if (h->precision == MGD_FP64)
         hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(nb), dim3(256), 0, st,
                            OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, (const double *)s, part);
@@ -556,6 +962,25 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
 int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap, double *s,
                hipStream_t st)
 {
+    if (h->dim == 2 && h->precision == MGD_MIXED) {
+        StageArgs<double> sa;
+        memset(&sa, 0, sizeof(sa));
+        sa.sv = store_view(h, o);
+        sa.n = h->n;
+        sa.u = z;
+        sa.pold = pold;
+        sa.pnew = pnew;
+        sa.out = Ap;
+        sa.s = s;
+        sa.partial = h->partial;
+        dim3 g2 = stage2_grid(h->n);
+        int64_t nb = (int64_t)g2.x * g2.y;
+        hipLaunchKernelGGL((k_stage2<double, ST_PMATVEC>), g2, dim3(256), 0, st, sa);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, s + 3);
+        hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, st, s);
+        HIPCHK(h->ctx, hipGetLastError());
+        return MGD_OK;
+    }
     if (h->precision == MGD_FP64)
         return h->dim == 2 ? pcg_matvec_t<2, double>(h, o, (const double *)z, pold, pnew, Ap, s, st)
                            : pcg_matvec_t<3, double>(h, o, (const double *)z, pold, pnew, Ap, s, st);
@@ -567,7 +992,7 @@ int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold,
                hipStream_t st)
 {
     int64_t n = h->NV[0], nb = grid_for(n, 256);
-    double *part = h->ctx->partial;
+    double *part = h->partial;
     hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, x, p, r, rold, Ap, n, (const double *)s, part);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 4);
     HIPCHK(h->ctx, hipGetLastError());

@@ -314,7 +314,7 @@ int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st)
 int cycle_coarse_solve(mgd_hier *h, const OpSet &o, void *u, const void *f, hipStream_t st)
 {
     int lc = h->nlev - 1;
-    double *work = h->ctx->partial;  // m_coarse <= partial_cap (checked at creation)
+    double *work = h->partial;  // m_coarse <= partial_cap (checked at creation)
     if (h->precision == MGD_FP64) {
         if (h->dim == 2) hipLaunchKernelGGL((k_chol_solve<2, double>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const double *)f, (double *)u, work);
         else hipLaunchKernelGGL((k_chol_solve<3, double>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const double *)f, (double *)u, work);

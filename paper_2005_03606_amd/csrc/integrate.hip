@@ -43,14 +43,15 @@ template <int D, typename T> __device__ inline T eps_eval(const EpsDev &e, const
         return (T)1 + ((T)0.3 / (T)D) * p;
     }
     case MGD_EPS_BALLS: {
+#pragma clang fp contract(off)
         for (int b = 0; b < e.count; ++b) {
             const double *row = e.data + (size_t)b * (D + 1);
             double r2 = 0.0;
             for (int m = 0; m < D; ++m) {
                 double dx = x[m] - row[m];
-                r2 = __dadd_rn(r2, __dmul_rn(dx, dx));
+                r2 = r2 + dx * dx;
             }
-            if (r2 <= __dmul_rn(row[D], row[D])) return (T)e.p1;
+            if (r2 <= row[D] * row[D]) return (T)e.p1;
         }
         return (T)e.p0;
     }

@@ -1,13 +1,16 @@
-// mgd_solve: delayed (lazy) or up-front assembly feeding a multigrid solve
-// (paper Sec. 5.1-5.4).  The ladder of sub-sample counts runs on the
-// assembly stream; each completed rung is turned into a full operator set
-// (stencils, surplus store, coarse operators) in the spare of two operator
-// sets and published at a cycle boundary, where the solver switches sets.
+// Solve driver: delayed (lazy) or up-front assembly feeding a multigrid
+// solve (paper Sec. 5.1-5.4).  The ladder of sub-sample counts runs on the
+// assembly stream; completed rungs become full operator sets (stencils,
+// surplus store, coarse operators) in the spare of two operator sets, which
+// the solver switches to at a cycle boundary.  A solve is a resumable state
+// machine (begin / step) so that several can be interleaved on one device;
+// mgd_solve drives one to completion.
 #include <math.h>
 
 #include <chrono>
 
 #include "common.h"
+#include "solve.h"
 
 int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
 int vec_cast_to_cycle(mgd_hier *h, const double *a, void *b, hipStream_t st);
@@ -19,46 +22,34 @@ int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold,
                hipStream_t st);
 int vec_fill_f64(mgd_ctx *ctx, double *a, int64_t n, double v, hipStream_t st);
 
-namespace {
+static double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
-struct Ladder {
-    mgd_hier *h = nullptr;
-    mgd_eps eps{};
-    int s_fixed = 0, s_max = 1, R = 0;  // rungs 1..R use s = 2^r
-    double C = 0.01;
-    mgd_tier_policy tiers{};
-    int64_t ncell = 0;
-    void *K = nullptr;        // [ncell][U] current element matrices (in place)
-    float *eps_c = nullptr;   // centre samples
-    float *Sg = nullptr;      // gathered FP32 couplings (mixed)
-    int64_t *act[2] = {nullptr, nullptr};
-    int64_t *cnt_dev = nullptr;  // [2]
-    uint8_t *done = nullptr;
-    int32_t *blk = nullptr;
-    int64_t *cnt_host = nullptr;  // pinned [8]: active cells at rung r
-    int mode() const { return h->precision; }
-};
-
-void ladder_free(Ladder &L)
+// ------------------------------------------------------------ ladder
+static void ladder_free(Ladder &L)
 {
     dev_free(L.K); dev_free(L.eps_c); dev_free(L.Sg);
     dev_free(L.act[0]); dev_free(L.act[1]); dev_free(L.cnt_dev); dev_free(L.done); dev_free(L.blk);
     if (L.cnt_host) (void)hipHostFree(L.cnt_host);
+    L = Ladder();
 }
 
-int ladder_alloc(Ladder &L)
+static int ladder_alloc(Ladder &L, mgd_hier *h)
 {
-    mgd_ctx *ctx = L.h->ctx;
-    int U = n_pairs(L.h->dim), rc;
-    size_t kb = L.h->precision == MGD_FP64 ? 8 : 4;
+    mgd_ctx *ctx = h->ctx;
+    int U = n_pairs(h->dim), rc;
+    L.h = h;
+    L.ncell = 1;
+    for (int m = 0; m < h->dim; ++m) L.ncell *= h->n;
+    size_t kb = h->precision == MGD_FP64 ? 8 : 4;
     if ((rc = dev_alloc(ctx, &L.K, (size_t)L.ncell * U * kb))) return rc;
     if ((rc = dev_alloc(ctx, (void **)&L.eps_c, (size_t)L.ncell * 4))) return rc;
-    if (L.h->precision == MGD_MIXED)
-        if ((rc = dev_alloc(ctx, (void **)&L.Sg, (size_t)L.h->NV[0] * L.h->H * 4))) return rc;
-    if (L.R >= 2) {
-        if ((rc = dev_alloc(ctx, (void **)&L.act[0], (size_t)L.ncell * 8))) return rc;
-        if ((rc = dev_alloc(ctx, (void **)&L.act[1], (size_t)L.ncell * 8))) return rc;
-    }
+    if (h->precision == MGD_MIXED)
+        if ((rc = dev_alloc(ctx, (void **)&L.Sg, (size_t)h->NV[0] * h->H * 4))) return rc;
+    if ((rc = dev_alloc(ctx, (void **)&L.act[0], (size_t)L.ncell * 8))) return rc;
+    if ((rc = dev_alloc(ctx, (void **)&L.act[1], (size_t)L.ncell * 8))) return rc;
     if ((rc = dev_alloc(ctx, (void **)&L.cnt_dev, 2 * 8))) return rc;
     if ((rc = dev_alloc(ctx, (void **)&L.done, (size_t)L.ncell))) return rc;
     if ((rc = dev_alloc(ctx, (void **)&L.blk, (size_t)((L.ncell + 255) / 256 + 1) * 4))) return rc;
@@ -69,13 +60,14 @@ int ladder_alloc(Ladder &L)
 }
 
 // rung 0: every cell at s_fixed (or the centre sample), plus centre samples
-int rung0(Ladder &L, hipStream_t st)
+static int rung0(Ladder &L, hipStream_t st)
 {
     mgd_ctx *ctx = L.h->ctx;
     int s0 = L.s_fixed > 0 ? L.s_fixed : 1;
-    int rc = launch_assemble(ctx, L.h->dim, L.h->n, s0, nullptr, L.ncell, &L.eps, L.mode(), L.K, nullptr, 0, 0.0,
-                             nullptr, nullptr, nullptr, st);
+    int rc = launch_assemble(ctx, L.h->dim, L.h->n, s0, nullptr, L.ncell, &L.eps, L.h->precision, L.K, nullptr, 0,
+                             0.0, nullptr, nullptr, nullptr, st);
     if (rc) return rc;
+    for (int r = 0; r < 8; ++r) L.cnt_host[r] = 0;
     L.cnt_host[0] = L.ncell;
     L.cnt_host[1] = L.R >= 1 ? L.ncell : 0;
     if (L.h->precision == MGD_MIXED) return launch_centre_eps(ctx, L.h->dim, L.h->n, &L.eps, L.eps_c, st);
@@ -84,13 +76,13 @@ int rung0(Ladder &L, hipStream_t st)
 
 // rung r >= 1: integrate the open cells at s = 2^r in place, criterion
 // against the stored matrix, then compact the still-open cells for rung r+1
-int rung(Ladder &L, int r, hipStream_t st)
+static int rung(Ladder &L, int r, hipStream_t st)
 {
     mgd_ctx *ctx = L.h->ctx;
     const int64_t *cells = r == 1 ? nullptr : L.act[r % 2];
     const int64_t *cnt = r == 1 ? nullptr : L.cnt_dev + (r % 2);
-    int rc = launch_assemble(ctx, L.h->dim, L.h->n, 1 << r, cells, L.ncell, &L.eps, L.mode(), L.K, L.K, 1, L.C,
-                             nullptr, L.done, cnt, st);
+    int rc = launch_assemble(ctx, L.h->dim, L.h->n, 1 << r, cells, L.ncell, &L.eps, L.h->precision, L.K, L.K, 1,
+                             L.C, nullptr, L.done, cnt, st);
     if (rc) return rc;
     if (r < L.R) {
         rc = launch_compact_open(ctx, L.done, cells, cnt, L.ncell, L.blk, L.act[(r + 1) % 2],
@@ -102,7 +94,7 @@ int rung(Ladder &L, int r, hipStream_t st)
 }
 
 // operator set from the current element matrices
-int build(Ladder &L, OpSet &o, bool base_only, hipStream_t st)
+static int build(Ladder &L, OpSet &o, bool base_only, hipStream_t st)
 {
     mgd_hier *h = L.h;
     int rc;
@@ -117,210 +109,282 @@ int build(Ladder &L, OpSet &o, bool base_only, hipStream_t st)
     return coarsen_ops(h, o, st);
 }
 
-double now_ms()
+// ------------------------------------------------------------ workspace
+void solve_state_free(SolveState *S)
 {
-    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    if (!S) return;
+    (void)hipSetDevice(S->ctx->device);
+    if (S->s_asm) (void)hipStreamSynchronize(S->s_asm);
+    (void)hipDeviceSynchronize();
+    ladder_free(S->L);
+    opset_free(S->O1);
+    hier_free(&S->H);
+    dev_free(S->r); dev_free(S->rold); dev_free(S->p[0]); dev_free(S->p[1]); dev_free(S->Ap);
+    for (auto &e : S->ev_ready)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {S->ev_free, S->ev_start, S->ev_norm, S->ev_final})
+        if (e) (void)hipEventDestroy(e);
+    if (S->own_asm && S->s_asm) (void)hipStreamDestroy(S->s_asm);
+    delete S;
 }
 
-}  // namespace
-
-extern "C" int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, const double *f, double *u,
-                         const mgd_solve_opts *op, mgd_report *rep, hipStream_t stream)
+void solve_cache_free(mgd_ctx *ctx)
 {
-    if (!ctx || !eps || !f || !u || !op || !rep) return MGD_EINVAL;
-    double t0 = now_ms();
-    memset(rep, 0, sizeof(*rep));
+    if (ctx && ctx->cache) {
+        solve_state_free(ctx->cache);
+        ctx->cache = nullptr;
+    }
+}
+
+// allocate the device state of one solve shape
+int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer, int coarsest, bool own_asm,
+                       SolveState **out)
+{
+    *out = nullptr;
+    SolveState *S = new SolveState();
+    S->ctx = ctx;
+    S->dim = dim; S->n = n; S->precision = precision; S->transfer = transfer; S->coarsest = coarsest;
+    mgd_hier &H = S->H;
+    H.ctx = ctx;
+    H.dim = dim; H.n = n; H.precision = precision; H.transfer = transfer; H.coarsest = coarsest;
+    int rc = MGD_OK;
+#define CK(x)                      \
+    do {                           \
+        if ((rc = (x))) {          \
+            solve_state_free(S);   \
+            return rc;             \
+        }                          \
+    } while (0)
+    CK(hier_alloc_levels(&H));
+    CK(opset_alloc(&H, S->O1));
+    CK(ladder_alloc(S->L, &H));
+    int64_t NV = H.NV[0];
+    CK(dev_alloc(ctx, (void **)&S->r, NV * 8));
+    CK(dev_alloc(ctx, (void **)&S->rold, NV * 8));
+    CK(dev_alloc(ctx, (void **)&S->p[0], NV * 8));
+    CK(dev_alloc(ctx, (void **)&S->p[1], NV * 8));
+    CK(dev_alloc(ctx, (void **)&S->Ap, NV * 8));
+    for (auto &e : S->ev_ready)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
+    for (hipEvent_t *e : {&S->ev_free, &S->ev_start, &S->ev_norm, &S->ev_final})
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
+    if (own_asm) {
+        if (hipStreamCreateWithFlags(&S->s_asm, hipStreamNonBlocking) != hipSuccess) CK(MGD_EHIP);
+        S->own_asm = true;
+    } else {
+        S->s_asm = ctx->s_asm;
+    }
+#undef CK
+    *out = S;
+    return MGD_OK;
+}
+
+bool solve_state_matches(const SolveState *S, int dim, int n, int precision, int transfer, int coarsest)
+{
+    return S && S->dim == dim && S->n == n && S->precision == precision && S->transfer == transfer &&
+           S->coarsest == coarsest;
+}
+
+// ------------------------------------------------------------ state machine
+int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, const double *f, const double *u,
+                   const mgd_solve_opts *op)
+{
+    if (!eps || !f || !u || !op) return mgd_fail(ctx, MGD_EINVAL, "null argument");
     if (dim != 2 && dim != 3) return mgd_fail(ctx, MGD_EINVAL, "dim must be 2 or 3");
+    if (n < 2) return mgd_fail(ctx, MGD_EINVAL, "n must be >= 2");
     if (eps->kind < MGD_EPS_CONST || eps->kind > MGD_EPS_BOXES || eps->dim != dim)
         return mgd_fail(ctx, MGD_EINVAL, "eps must be a field descriptor of the same dimension");
     if (eps->kind >= MGD_EPS_BALLS && !eps->data) return mgd_fail(ctx, MGD_EINVAL, "eps.data is NULL");
     if (op->precision != MGD_FP64 && op->precision != MGD_MIXED) return mgd_fail(ctx, MGD_EINVAL, "bad precision");
+    if (op->transfer != MGD_GEOMETRIC && op->transfer != MGD_BOXMG) return mgd_fail(ctx, MGD_EINVAL, "bad transfer");
     if (op->outer != MGD_STATIONARY && op->outer != MGD_PCG) return mgd_fail(ctx, MGD_EINVAL, "bad outer");
     if (op->schedule != MGD_UPFRONT && op->schedule != MGD_LAZY) return mgd_fail(ctx, MGD_EINVAL, "bad schedule");
-    int sf = op->s_fixed;
+    if (op->publish < MGD_PUBLISH_ASYNC || op->publish > MGD_PUBLISH_EVERY)
+        return mgd_fail(ctx, MGD_EINVAL, "bad publish mode");
+    int sf = op->s_fixed, sm = op->s_max;
     if (sf > 0 && sf != 1 && sf != 2 && sf != 4 && sf != 8 && sf != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_fixed");
-    int sm = op->s_max;
     if (sf <= 0 && sm != 1 && sm != 2 && sm != 4 && sm != 8 && sm != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_max");
     if (op->nu1 < 0 || op->nu2 < 0 || op->max_cycles < 0 || !(op->tol >= 0.0) || !(op->div_factor > 0.0))
         return mgd_fail(ctx, MGD_EINVAL, "bad cycle options");
     if (op->precision == MGD_MIXED &&
-        (op->tiers.min_tier < 1 || op->tiers.max_tier > 3 || op->tiers.min_tier > op->tiers.max_tier))
+        (op->tiers.min_tier < 1 || op->tiers.max_tier > 3 || op->tiers.min_tier > op->tiers.max_tier ||
+         !(op->tiers.tau_abs >= 0.0) || !(op->tiers.tau_rel >= 0.0)))
         return mgd_fail(ctx, MGD_EINVAL, "bad tier policy");
-    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return MGD_OK;
+}
 
-    mgd_hier H;
-    H.ctx = ctx;
-    H.dim = dim; H.n = n; H.precision = op->precision; H.transfer = op->transfer;
-    H.coarsest = op->coarsest < 2 ? 2 : op->coarsest;
-    Ladder L;
-    OpSet O1;
-    int rc = MGD_OK;
-    hipEvent_t ev_ready[8] = {}, ev_free = nullptr, ev_start = nullptr;
-    double *r = nullptr, *rold = nullptr, *p[2] = {nullptr, nullptr}, *Ap = nullptr;
-    bool lazy = op->schedule == MGD_LAZY && sf <= 0 && sm >= 2;
-    int status = MGD_ENOCONV, k = 0, ncyc = 0;
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(ctx->s_asm);
-        (void)hipStreamSynchronize(stream);
-        ladder_free(L);
-        opset_free(O1);
-        hier_free(&H);
-        dev_free(r); dev_free(rold); dev_free(p[0]); dev_free(p[1]); dev_free(Ap);
-        for (auto &e : ev_ready) if (e) (void)hipEventDestroy(e);
-        if (ev_free) (void)hipEventDestroy(ev_free);
-        if (ev_start) (void)hipEventDestroy(ev_start);
-    };
-#define TRY(x)                   \
-    do {                         \
-        if ((rc = (x))) {        \
-            cleanup();           \
-            return rc;           \
-        }                        \
-    } while (0)
+// enqueue the residual measurement of the next check (outer residual after
+// an operator change or for the stationary iteration; else the CG recursion's)
+static int enqueue_check(SolveState *S)
+{
+    mgd_ctx *ctx = S->ctx;
+    mgd_hier &H = S->H;
+    double *s = H.scal;
+    int rc;
+    if (S->restart || !S->pcg) {
+        if ((rc = outer_residual(&H, *S->sets[S->cur], S->u, S->f, S->r, s + 4, S->stream))) return rc;
+        if (S->pcg && (rc = vec_fill_f64(ctx, s + 7, 1, 1.0, S->stream))) return rc;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(H.host_scal, s + 4, 8, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(ctx, hipEventRecord(S->ev_norm, S->stream));
+    return MGD_OK;
+}
 
-    TRY(hier_alloc_levels(&H));
-    if (lazy) TRY(opset_alloc(&H, O1));
-    L.h = &H;
+// switch the solver to operator set `set`, built for rung `rung_no`
+static int publish(SolveState *S, int rung_no, int set, hipEvent_t ready)
+{
+    mgd_ctx *ctx = S->ctx;
+    HIPCHK(ctx, hipStreamWaitEvent(S->stream, ready, 0));
+    S->cur = set;
+    HIPCHK(ctx, hipEventRecord(S->ev_free, S->stream));
+    S->published = rung_no;
+    S->publishes++;
+    S->restart = true;
+    return MGD_OK;
+}
+
+// per-rung schedules: after publishing rung r, start the build of rung r+1
+static int chain_next(SolveState *S)
+{
+    Ladder &L = S->L;
+    int r = S->published;
+    bool more = r < L.R && L.cnt_host[r + 1] > 0;
+    if (!more) {
+        S->ladder_done = true;
+        return MGD_OK;
+    }
+    int rc;
+    HIPCHK(S->ctx, hipStreamWaitEvent(S->s_asm, S->ev_free, 0));
+    if ((rc = build(L, *S->sets[1 - S->cur], false, S->s_asm))) return rc;
+    HIPCHK(S->ctx, hipEventRecord(S->ev_ready[r + 1], S->s_asm));
+    S->built = r + 1;
+    if (r + 2 <= L.R && (rc = rung(L, r + 2, S->s_asm))) return rc;
+    return MGD_OK;
+}
+
+// publish at a cycle boundary if the schedule allows it
+static int boundary_publish(SolveState *S, bool force_wait)
+{
+    if (!S->lazy || S->ladder_done) return MGD_OK;
+    mgd_ctx *ctx = S->ctx;
+    int rc;
+    if (S->publish_mode == MGD_PUBLISH_ASYNC) {
+        if (force_wait) HIPCHK(ctx, hipEventSynchronize(S->ev_final));
+        hipError_t q = hipEventQuery(S->ev_final);
+        if (q == hipErrorNotReady) return MGD_OK;
+        HIPCHK(ctx, q);
+        if ((rc = publish(S, S->L.R, 1 - S->cur, S->ev_final))) return rc;
+        S->ladder_done = true;
+        return MGD_OK;
+    }
+    if (S->published >= S->built) return MGD_OK;
+    int next = S->published + 1;
+    bool ready;
+    if (S->publish_mode == MGD_PUBLISH_DETERMINISTIC) {
+        ready = S->ncyc >= next;
+        if (ready) HIPCHK(ctx, hipEventSynchronize(S->ev_ready[next]));
+    } else {
+        if (force_wait) HIPCHK(ctx, hipEventSynchronize(S->ev_ready[next]));
+        hipError_t q = hipEventQuery(S->ev_ready[next]);
+        ready = q == hipSuccess;
+        if (q != hipSuccess && q != hipErrorNotReady) HIPCHK(ctx, q);
+    }
+    if (!ready) return MGD_OK;
+    if ((rc = publish(S, next, next % 2, S->ev_ready[next]))) return rc;
+    return chain_next(S);
+}
+
+int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, const mgd_solve_opts *op,
+                mgd_report *rep, hipStream_t stream)
+{
+    mgd_ctx *ctx = S->ctx;
+    S->t0 = now_ms();
+    S->op = *op;
+    S->eps = *eps;
+    S->f = f;
+    S->u = u;
+    S->rep = rep;
+    S->stream = stream;
+    memset(rep, 0, sizeof(*rep));
+    int sf = op->s_fixed, sm = op->s_max;
+    S->lazy = op->schedule == MGD_LAZY && sf <= 0 && sm >= 2;
+    S->pcg = op->outer == MGD_PCG;
+    S->publish_mode = op->publish;
+    S->sets[0] = &S->H.ops;
+    S->sets[1] = &S->O1;
+    S->cur = 0;
+    S->published = S->built = 0;
+    S->publishes = 0;
+    S->ncyc = 0;
+    S->k = 0;
+    S->r0 = S->rk = S->r_ref = 0.0;
+    S->status = MGD_ENOCONV;
+    S->done = false;
+    S->restart = true;
+    S->t_first = S->t_loop0 = 0.0;
+    Ladder &L = S->L;
     L.eps = *eps;
     L.s_fixed = sf;
     L.s_max = sf > 0 ? sf : sm;
     L.R = 0;
-    if (sf <= 0) while ((1 << L.R) < sm) ++L.R;
+    if (sf <= 0)
+        while ((1 << L.R) < sm) ++L.R;
     L.C = op->C;
     L.tiers = op->tiers;
-    L.ncell = 1;
-    for (int m = 0; m < dim; ++m) L.ncell *= n;
-    TRY(ladder_alloc(L));
-    int64_t NV = H.NV[0];
-    TRY(dev_alloc(ctx, (void **)&r, NV * 8));
-    TRY(dev_alloc(ctx, (void **)&rold, NV * 8));
-    TRY(dev_alloc(ctx, (void **)&p[0], NV * 8));
-    TRY(dev_alloc(ctx, (void **)&p[1], NV * 8));
-    TRY(dev_alloc(ctx, (void **)&Ap, NV * 8));
-    TRY(vec_fill_f64(ctx, rold, NV, 0.0, stream));
-    TRY(vec_fill_f64(ctx, p[0], NV, 0.0, stream));
-    TRY(vec_fill_f64(ctx, p[1], NV, 0.0, stream));
-    for (auto &e : ev_ready) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIPCHK(ctx, hipEventCreateWithFlags(&ev_free, hipEventDisableTiming));
-    HIPCHK(ctx, hipEventCreateWithFlags(&ev_start, hipEventDisableTiming));
-
-    OpSet *sets[2] = {&H.ops, &O1};
-    int cur = 0;
-    // ---- assembly
-    TRY(rung0(L, stream));
-    int published = 0, built = 0;  // highest rung published / whose build is enqueued
-    bool ladder_done = L.R == 0;
-    if (!lazy) {
-        for (int rr = 1; rr <= L.R; ++rr) TRY(rung(L, rr, stream));
-        TRY(build(L, H.ops, false, stream));
-        published = built = L.R;
-        ladder_done = true;
+    S->ladder_done = L.R == 0;
+    int64_t NV = S->H.NV[0];
+    int rc;
+    if ((rc = vec_fill_f64(ctx, S->rold, NV, 0.0, stream)) || (rc = vec_fill_f64(ctx, S->p[0], NV, 0.0, stream)) ||
+        (rc = vec_fill_f64(ctx, S->p[1], NV, 0.0, stream)))
+        return rc;
+    // the assembly stream may still hold work of an earlier solve on this state
+    HIPCHK(ctx, hipEventRecord(S->ev_start, S->s_asm));
+    HIPCHK(ctx, hipStreamWaitEvent(stream, S->ev_start, 0));
+    if ((rc = rung0(L, stream))) return rc;
+    if (!S->lazy) {
+        for (int rr = 1; rr <= L.R; ++rr)
+            if ((rc = rung(L, rr, stream))) return rc;
+        if ((rc = build(L, S->H.ops, false, stream))) return rc;
+        S->published = S->built = L.R;
+        S->ladder_done = true;
     } else {
-        TRY(build(L, H.ops, true, stream));
-        HIPCHK(ctx, hipEventRecord(ev_start, stream));
-        HIPCHK(ctx, hipStreamWaitEvent(ctx->s_asm, ev_start, 0));
-        TRY(rung(L, 1, ctx->s_asm));
-        TRY(build(L, O1, false, ctx->s_asm));
-        HIPCHK(ctx, hipEventRecord(ev_ready[1], ctx->s_asm));
-        built = 1;
-        if (L.R >= 2) TRY(rung(L, 2, ctx->s_asm));
-    }
-
-    // ---- cycles
-    double *s = ctx->scal, r0 = 0.0, rk = 0.0, r_ref = 0.0;
-    bool restart = true, pcg = op->outer == MGD_PCG;
-    bool deterministic = op->publish == MGD_PUBLISH_DETERMINISTIC;
-    double t_first = 0.0, t_loop0 = 0.0;
-    int publishes = 0;
-    for (k = 0;; ++k) {
-        // publish a completed rung at this cycle boundary
-        if (lazy && published < built) {
-            int next = published + 1;
-            bool ready;
-            if (deterministic) {
-                ready = ncyc >= next;
-                if (ready) HIPCHK(ctx, hipEventSynchronize(ev_ready[next]));
-            } else {
-                hipError_t q = hipEventQuery(ev_ready[next]);
-                ready = q == hipSuccess;
-                if (q != hipSuccess && q != hipErrorNotReady) HIPCHK(ctx, q);
-            }
-            if (ready) {
-                HIPCHK(ctx, hipStreamWaitEvent(stream, ev_ready[next], 0));
-                int old = cur;
-                cur = next % 2;
-                HIPCHK(ctx, hipEventRecord(ev_free, stream));
-                published = next;
-                ++publishes;
-                restart = true;
-                // rung `next` is final when no cell stays open after it
-                bool more = next < L.R && L.cnt_host[next + 1] > 0;
-                if (more) {
-                    HIPCHK(ctx, hipStreamWaitEvent(ctx->s_asm, ev_free, 0));
-                    TRY(build(L, *sets[old], false, ctx->s_asm));
-                    HIPCHK(ctx, hipEventRecord(ev_ready[next + 1], ctx->s_asm));
-                    built = next + 1;
-                    if (next + 2 <= L.R) TRY(rung(L, next + 2, ctx->s_asm));
-                } else {
-                    ladder_done = true;
-                }
-            }
-        }
-        const OpSet &O = *sets[cur];
-        if (restart || !pcg) {
-            TRY(outer_residual(&H, O, u, f, r, s + 4, stream));
-            if (pcg) TRY(vec_fill_f64(ctx, s + 7, 1, 1.0, stream));
-        }
-        HIPCHK(ctx, hipMemcpyAsync(ctx->host_scal, s + 4, 8, hipMemcpyDeviceToHost, stream));
-        HIPCHK(ctx, hipStreamSynchronize(stream));
-        rk = sqrt(ctx->host_scal[0]);
-        if (k == 0) {
-            r0 = rk;
-            t_first = now_ms() - t0;
-            t_loop0 = now_ms();
-        }
-        if (k == 0 || restart) r_ref = rk > r0 ? rk : r0;
-        double rel = r0 > 0.0 ? rk / r0 : 0.0;
-        if (k < MGD_HIST) rep->hist[k] = rel;
-        if (!(rk <= op->div_factor * r_ref)) { status = MGD_EDIVERGED; break; }
-        if (rel <= op->tol) {
-            if (ladder_done) { status = MGD_OK; break; }
-            // starvation guard: the tolerance was met on a provisional
-            // operator; in the asynchronous mode wait for the pending rung and
-            // publish it at once, the deterministic mode keeps its schedule
-            if (!deterministic && published < built) {
-                HIPCHK(ctx, hipEventSynchronize(ev_ready[published + 1]));
-                continue;
-            }
-        }
-        if (ncyc >= op->max_cycles) { status = (rel <= op->tol) ? MGD_ESTARVED : MGD_ENOCONV; break; }
-        TRY(vec_cast_to_cycle(&H, r, H.f[0], stream));
-        TRY(vcycle_ops(&H, O, H.u[0], H.f[0], op->omega, op->nu1, op->nu2, true, stream));
-        if (!pcg) {
-            TRY(vec_add_cycle(&H, u, H.u[0], stream));
+        if ((rc = build(L, S->H.ops, true, stream))) return rc;
+        HIPCHK(ctx, hipEventRecord(S->ev_start, stream));
+        HIPCHK(ctx, hipStreamWaitEvent(S->s_asm, S->ev_start, 0));
+        if (S->publish_mode == MGD_PUBLISH_ASYNC) {
+            // the whole ladder back to back, then one build of the final operator
+            for (int rr = 1; rr <= L.R; ++rr)
+                if ((rc = rung(L, rr, S->s_asm))) return rc;
+            if ((rc = build(L, S->O1, false, S->s_asm))) return rc;
+            HIPCHK(ctx, hipEventRecord(S->ev_final, S->s_asm));
+            S->built = L.R;
         } else {
-            TRY(pcg_beta(&H, H.u[0], r, rold, s, stream));
-            TRY(pcg_matvec(&H, O, H.u[0], p[0], p[1], Ap, s, stream));
-            TRY(pcg_update(&H, u, p[1], r, rold, Ap, s, stream));
-            double *t = p[0]; p[0] = p[1]; p[1] = t;
+            if ((rc = rung(L, 1, S->s_asm))) return rc;
+            if ((rc = build(L, S->O1, false, S->s_asm))) return rc;
+            HIPCHK(ctx, hipEventRecord(S->ev_ready[1], S->s_asm));
+            S->built = 1;
+            if (L.R >= 2 && (rc = rung(L, 2, S->s_asm))) return rc;
         }
-        ++ncyc;
-        restart = false;
     }
-    HIPCHK(ctx, hipStreamSynchronize(stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->s_asm));
+    return enqueue_check(S);
+}
+
+static void finish(SolveState *S)
+{
+    mgd_report *rep = S->rep;
+    Ladder &L = S->L;
     double t_end = now_ms();
-    rep->status = status;
-    rep->cycles = ncyc;
-    rep->checks = k + 1 < MGD_HIST ? k + 1 : MGD_HIST;
-    rep->nlev = H.nlev;
-    rep->publishes = publishes;
-    rep->r0 = r0;
-    rep->r_final = rk;
-    rep->t_total_ms = t_end - t0;
-    rep->t_first_cycle_ms = t_first;
-    rep->t_cycles_ms = t_end - t_loop0;
-    // cells per final s and cell integrations
+    rep->status = S->status;
+    rep->cycles = S->ncyc;
+    rep->checks = S->k + 1 < MGD_HIST ? S->k + 1 : MGD_HIST;
+    rep->nlev = S->H.nlev;
+    rep->publishes = S->publishes;
+    rep->r0 = S->r0;
+    rep->r_final = S->rk;
+    rep->t_total_ms = t_end - S->t0;
+    rep->t_first_cycle_ms = S->t_first;
+    rep->t_cycles_ms = t_end - S->t_loop0;
+    int sf = L.s_fixed;
     if (sf > 0) {
         int b = 0;
         while ((1 << b) < sf) ++b;
@@ -328,7 +392,8 @@ extern "C" int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *ep
         rep->integrations = L.ncell;
     } else {
         rep->integrations = L.ncell;
-        for (int rr = 1; rr <= published && rr <= L.R; ++rr) {
+        int top = S->published < L.R ? S->published : L.R;
+        for (int rr = 1; rr <= top; ++rr) {
             int64_t open_r = L.cnt_host[rr];
             int64_t open_next = rr < L.R ? L.cnt_host[rr + 1] : 0;
             rep->integrations += open_r;
@@ -336,19 +401,127 @@ extern "C" int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *ep
         }
         if (L.R == 0) rep->cells_at_s[0] = L.ncell;
     }
+    mgd_hier &H = S->H;
+    const OpSet &O = *S->sets[S->cur];
     if (H.precision == MGD_MIXED) {
-        const OpSet &O = *sets[cur];
         uint32_t units = 0;
-        HIPCHK(ctx, hipMemcpy(&units, O.units_total, 4, hipMemcpyDeviceToHost));
+        (void)hipMemcpy(&units, O.units_total, 4, hipMemcpyDeviceToHost);
         std::vector<uint8_t> t(O.ntile);
-        HIPCHK(ctx, hipMemcpy(t.data(), O.tier, O.ntile, hipMemcpyDeviceToHost));
+        (void)hipMemcpy(t.data(), O.tier, O.ntile, hipMemcpyDeviceToHost);
         for (uint8_t x : t) rep->tier_tiles[x & 3]++;
         // payload + tier byte and offset per tile + centre sample per cell
         rep->store_bytes = (double)units * 64 + (double)O.ntile * 5 + (double)L.ncell * 4;
     } else {
-        rep->store_bytes = (double)NV * H.H * 8;
+        rep->store_bytes = (double)H.NV[0] * H.H * 8;
     }
-    cleanup();
-#undef TRY
-    return status;
+    S->done = true;
+}
+
+// one cycle boundary: returns 1 when finished, 0 when more steps follow,
+// 2 when the residual is not available yet (non-blocking), < 0 on error
+int solve_step(SolveState *S, bool blocking)
+{
+    if (S->done) return 1;
+    mgd_ctx *ctx = S->ctx;
+    int rc;
+    if (blocking) {
+        HIPCHK(ctx, hipEventSynchronize(S->ev_norm));
+    } else {
+        hipError_t q = hipEventQuery(S->ev_norm);
+        if (q == hipErrorNotReady) return 2;
+        HIPCHK(ctx, q);
+    }
+    mgd_hier &H = S->H;
+    const mgd_solve_opts &op = S->op;
+    S->rk = sqrt(H.host_scal[0]);
+    if (S->k == 0) {
+        S->r0 = S->rk;
+        S->t_first = now_ms() - S->t0;
+        S->t_loop0 = now_ms();
+    }
+    if (S->k == 0 || S->restart) S->r_ref = S->rk > S->r0 ? S->rk : S->r0;
+    double rel = S->r0 > 0.0 ? S->rk / S->r0 : 0.0;
+    if (S->k < MGD_HIST) S->rep->hist[S->k] = rel;
+    if (!(S->rk <= op.div_factor * S->r_ref)) {
+        S->status = MGD_EDIVERGED;
+        finish(S);
+        return 1;
+    }
+    if (rel <= op.tol) {
+        if (S->ladder_done) {
+            S->status = MGD_OK;
+            finish(S);
+            return 1;
+        }
+        // starvation guard: the tolerance was met on a provisional operator;
+        // the asynchronous modes wait for the pending operator and publish it
+        // at once, the deterministic mode keeps its schedule
+        if (S->publish_mode != MGD_PUBLISH_DETERMINISTIC) {
+            if ((rc = boundary_publish(S, true))) return rc;
+            S->k++;
+            if ((rc = enqueue_check(S))) return rc;
+            return 0;
+        }
+    }
+    if (S->ncyc >= op.max_cycles) {
+        S->status = rel <= op.tol ? MGD_ESTARVED : MGD_ENOCONV;
+        finish(S);
+        return 1;
+    }
+    // one preconditioned cycle with the current operator
+    const OpSet &O = *S->sets[S->cur];
+    hipStream_t st = S->stream;
+    if ((rc = vec_cast_to_cycle(&H, S->r, H.f[0], st))) return rc;
+    if ((rc = vcycle_ops(&H, O, H.u[0], H.f[0], op.omega, op.nu1, op.nu2, true, st))) return rc;
+    if (!S->pcg) {
+        if ((rc = vec_add_cycle(&H, S->u, H.u[0], st))) return rc;
+    } else {
+        double *s = H.scal;
+        if ((rc = pcg_beta(&H, H.u[0], S->r, S->rold, s, st))) return rc;
+        if ((rc = pcg_matvec(&H, O, H.u[0], S->p[0], S->p[1], S->Ap, s, st))) return rc;
+        if ((rc = pcg_update(&H, S->u, S->p[1], S->r, S->rold, S->Ap, s, st))) return rc;
+        double *t = S->p[0];
+        S->p[0] = S->p[1];
+        S->p[1] = t;
+    }
+    S->ncyc++;
+    S->restart = false;
+    if ((rc = boundary_publish(S, false))) return rc;
+    S->k++;
+    if ((rc = enqueue_check(S))) return rc;
+    return 0;
+}
+
+int solve_end(SolveState *S)
+{
+    HIPCHK(S->ctx, hipStreamSynchronize(S->stream));
+    HIPCHK(S->ctx, hipStreamSynchronize(S->s_asm));
+    return MGD_OK;
+}
+
+extern "C" int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, const double *f, double *u,
+                         const mgd_solve_opts *op, mgd_report *rep, hipStream_t stream)
+{
+    if (!ctx || !rep) return MGD_EINVAL;
+    int rc = solve_validate(ctx, dim, n, eps, f, u, op);
+    if (rc) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    double t0 = now_ms();
+    int coarsest = op->coarsest < 2 ? 2 : op->coarsest;
+    if (!solve_state_matches(ctx->cache, dim, n, op->precision, op->transfer, coarsest)) {
+        solve_cache_free(ctx);
+        SolveState *S = nullptr;
+        if ((rc = solve_state_create(ctx, dim, n, op->precision, op->transfer, coarsest, false, &S))) return rc;
+        ctx->cache = S;
+    }
+    SolveState *S = ctx->cache;
+    if ((rc = solve_begin(S, eps, f, u, op, rep, stream))) return rc;
+    S->t0 = t0;
+    int st;
+    while ((st = solve_step(S, true)) == 0) {
+    }
+    if (st < 0) return st;
+    if ((rc = solve_end(S))) return rc;
+    rep->t_total_ms = now_ms() - t0;
+    return rep->status;
 }

@@ -58,6 +58,7 @@ __device__ inline int scale_exponent(float mx, int t)
 // code of delta at tier t with scale 2^e, and its decoded value (exact, FP64)
 __device__ inline uint32_t quantise(float d, int t, int e, double *dec)
 {
+#pragma clang fp contract(off)
     if (t == 3) {
         *dec = (double)d;
         return __float_as_uint(d);
@@ -82,6 +83,8 @@ template <int D>
 __global__ void k_deltas(const float *S32, const float *eps_c, int n, int64_t NV, double tau_abs,
                          double tau_rel, int tmin, int tmax, float *delta, uint8_t *vtier)
 {
+    // the surplus is defined by unfused FP64 operations (no FMA contraction)
+#pragma clang fp contract(off)
     Grid<D> g(n);
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= NV) return;
@@ -93,11 +96,11 @@ __global__ void k_deltas(const float *S32, const float *eps_c, int n, int64_t NV
     float mx = 0.0f;
     for (int j = 0; j < H; ++j) {
         double b = base_coupling64<D>(eps_c, n, x, j, &ref);
-        d[j] = (float)__dadd_rn((double)S32[(int64_t)j * NV + v], -b);
+        d[j] = (float)((double)S32[(int64_t)j * NV + v] - b);
         delta[(int64_t)j * NV + v] = d[j];
         mx = fmaxf(mx, fabsf(d[j]));
     }
-    double tau = __dmul_rn(tau_rel, ref);
+    double tau = tau_rel * ref;
     if (tau_abs > tau) tau = tau_abs;
     int tier = tmax;
     if ((double)mx <= tau) tier = 0;
@@ -194,6 +197,7 @@ __global__ void k_encode(const float *delta, int64_t NV, int64_t ntile, const ui
 template <int D, typename TO>
 __global__ void k_decode_store(StoreView sv, int n, TO *out)
 {
+#pragma clang fp contract(off)
     Grid<D> g(n);
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.NV) return;
