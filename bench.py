@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweeps", type=int, default=200, help="timed finest-level sweeps for the roofline")
+    ap.add_argument("--serve-requests", type=int, default=96,
+                    help="requests in the serving replay (0 skips it)")
+    ap.add_argument("--serve-slots", type=int, default=8)
     return ap.parse_args()
 
 
@@ -58,6 +61,56 @@ def cpu_baseline(fld, d, n, f, cycles):
             "sample": (f"plain-C FP64 oracle, single thread, same 1024^2 problem: up-front ladder + BoxMG "
                        f"hierarchy ({t_setup:.2f} s) and 2 PCG cycles ({t_cycle:.3f} s/cycle), "
                        f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
+
+
+def serving_bench(ctx, P, W, count, slots):
+    """Serving replay: mixed 2D/3D requests with Gaussian-field materials,
+    Poisson arrivals at 0.8x the measured single-stream capacity."""
+    import numpy as np
+    import torch
+    from paper_2005_03606_amd import serving
+
+    opts = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=16, tol=1e-8,
+                max_cycles=400, min_tier=2, max_tier=2, tau_rel=1e-7)
+    loads = {}
+    reqs = []
+    for i in range(count):
+        d, n, fld = W.serving_request(i)
+        if (d, n) not in loads:
+            loads[(d, n)] = torch.from_numpy(W.load_sine(d, n)).cuda()
+        reqs.append((d, n, P.Eps(fld), loads[(d, n)]))
+    srv = P.Server(ctx, max_slots=slots, budget_bytes=96e9)
+    try:
+        # resident state for every shape, then single-stream service times
+        warm = {}
+        for r in reqs:
+            warm.setdefault((r[0], r[1]), r)
+        serving.replay(ctx, list(warm.values()), None, server=srv, **opts)
+        calib = reqs[:min(len(reqs), 24)]
+        t_alone = []
+        for d, n, eps, f in calib:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = serving.replay(ctx, [(d, n, eps, f)], None, server=srv, **opts)
+            t_alone.append(time.perf_counter() - t0)
+            assert res["status"][0] == P.OK
+        mean_service = float(np.mean(t_alone))
+        rate = 0.8 / mean_service
+        arr = W.poisson_arrivals(len(reqs), rate, 4242)
+        res = serving.replay(ctx, reqs, arr, server=srv, **opts)
+    finally:
+        srv.close()
+    ok = res["status"] == P.OK
+    lat = res["latency_ms"][ok]
+    dof_cyc = sum((n - 1) ** d * c for (d, n, _, _), c in zip(reqs, res["cycles"]))
+    out = {"requests": len(reqs), "ok": int(ok.sum()), "slots": slots,
+           "single_stream_service_ms": round(mean_service * 1e3, 3),
+           "arrival_rate_per_s": round(rate, 2),
+           "throughput_req_per_s": round(len(reqs) / res["wall_s"], 2),
+           "throughput_dof_cycles_per_s": dof_cyc / res["wall_s"],
+           "queue_ms_mean": round(float(np.mean(res["queue_ms"])), 3)}
+    out.update({k: round(v, 3) for k, v in serving.percentiles(lat).items()})
+    return out
 
 
 def main():
@@ -177,6 +230,8 @@ def main():
                "t_first_cycle_ms_fp64_upfront": round(reps_f[-1]["t_first_cycle_ms"], 3),
            },
            "roofline": roofline}
+    if args.serve_requests > 0:
+        out["components"]["serving"] = serving_bench(ctx, P, W, args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fld, d, n, f_host, reps_f[-1]["cycles"])
     h.close()

@@ -262,6 +262,47 @@ typedef struct {
 int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, const double *f, double *u,
               const mgd_solve_opts *opts, mgd_report *report, hipStream_t stream);
 
+/* Device bytes that mgd_solve keeps resident for a problem of this shape
+ * (hierarchy, both operator sets, ladder buffers, outer vectors). */
+int mgd_solve_footprint(int32_t dim, int32_t n, const mgd_solve_opts *opts, double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving (continuous batching).  Requests of any shape and material are
+ * admitted in arrival order whenever one of max_slots slots is free and the
+ * device bytes of all resident solve states stay within hbm_budget_bytes;
+ * each admitted request runs as an mgd_solve on its own streams and all
+ * active ones advance on every mgd_server_poll, so their kernels overlap on
+ * the device.  Solve states stay resident after completion and are reused
+ * by later requests of the same shape (evicted oldest-first when the budget
+ * needs room).  f and u are owned by the caller and must stay valid until
+ * mgd_server_result reports the request finished.  Not thread-safe: one host
+ * thread drives a server.
+ * ---------------------------------------------------------------------- */
+typedef struct mgd_server mgd_server;
+typedef struct {
+    int32_t max_slots, pad;
+    double hbm_budget_bytes;
+} mgd_server_opts;
+
+int mgd_server_create(mgd_ctx *ctx, const mgd_server_opts *opts, mgd_server **out);
+int mgd_server_destroy(mgd_server *srv);
+/* Queue a solve (validated now; the descriptors are copied); *ticket
+ * identifies it.  The solve runs on a server stream after everything queued
+ * on `producer` so far (the writes of f, u and the eps data), so the caller
+ * need not synchronise before submitting. */
+int mgd_server_submit(mgd_server *srv, int32_t dim, int32_t n, const mgd_eps *eps, const double *f, double *u,
+                      const mgd_solve_opts *opts, hipStream_t producer, int64_t *ticket);
+/* advance every active solve without blocking, then admit waiting ones;
+ * returns the number of solves that finished in this call (or < 0) */
+int mgd_server_poll(mgd_server *srv, int32_t *n_active, int32_t *n_waiting);
+/* 1 once finished: the report (report->status is the solve's outcome, an
+ * MGD_* code such as MGD_ENOMEM for a request larger than the whole budget)
+ * and times_ms[3] = submit, admit, done on the host's steady clock in ms;
+ * the ticket is then forgotten.  0 while still queued or running; MGD_EINVAL
+ * for an unknown ticket. */
+int mgd_server_result(mgd_server *srv, int64_t ticket, mgd_report *report, double *times_ms);
+int mgd_server_stats(const mgd_server *srv, int64_t *completed, double *resident_bytes, int32_t *idle_states);
+
 #ifdef __cplusplus
 }
 #endif

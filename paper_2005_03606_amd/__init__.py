@@ -7,7 +7,9 @@ PyTorch supplies device memory and streams.  Importing this package does not
 load the library; the first call does, and raises if it is missing.
 """
 from .binding import (  # noqa: F401
+    OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED, ESTARVED,
     FP64, MIXED, GEOMETRIC, BOXMG, STATIONARY, PCG, UPFRONT, LAZY,
     PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY, MgdError, Context, Eps, Hierarchy,
-    assemble_cells, centre_samples, gather_stencils, solve, n_half, n_pairs, lib, library_path,
+    assemble_cells, centre_samples, gather_stencils, solve, solve_opts, solve_footprint, Server,
+    n_half, n_pairs, lib, library_path,
 )

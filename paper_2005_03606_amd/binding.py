@@ -63,6 +63,10 @@ class _Report(C.Structure):
                 ("t_cycles_ms", C.c_double), ("hist", C.c_double * HIST)]
 
 
+class _ServerOpts(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("pad", C.c_int32), ("hbm_budget_bytes", C.c_double)]
+
+
 _lib = None
 _P = C.c_void_p
 _I = C.c_int32
@@ -106,6 +110,14 @@ def lib():
         "mgd_outer_residual": ([_P, _P, _P, _P, _P, _P], C.c_int),
         "mgd_solve": ([_P, _I, _I, C.POINTER(_Eps), _P, _P, C.POINTER(_SolveOpts),
                        C.POINTER(_Report), _P], C.c_int),
+        "mgd_solve_footprint": ([_I, _I, C.POINTER(_SolveOpts), C.POINTER(C.c_double)], C.c_int),
+        "mgd_server_create": ([_P, C.POINTER(_ServerOpts), C.POINTER(_P)], C.c_int),
+        "mgd_server_destroy": ([_P], C.c_int),
+        "mgd_server_submit": ([_P, _I, _I, C.POINTER(_Eps), _P, _P, C.POINTER(_SolveOpts), _P,
+                               C.POINTER(C.c_int64)], C.c_int),
+        "mgd_server_poll": ([_P, C.POINTER(_I), C.POINTER(_I)], C.c_int),
+        "mgd_server_result": ([_P, C.c_int64, C.POINTER(_Report), C.POINTER(C.c_double * 3)], C.c_int),
+        "mgd_server_stats": ([_P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(_I)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -308,24 +320,95 @@ class Hierarchy:
         self.ctx.check(lib().mgd_outer_residual(self.ctx.h, self.h, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))
 
 
-def solve(ctx, dim, n, eps, f, u=None, precision=FP64, transfer=GEOMETRIC, outer=STATIONARY,
-          schedule=UPFRONT, publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6,
-          nu1=2, nu2=2, tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0,
-          min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=0.0, stream=None):
+def solve_opts(precision=FP64, transfer=GEOMETRIC, outer=STATIONARY, schedule=UPFRONT,
+               publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6, nu1=2, nu2=2,
+               tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0, min_tier=2, max_tier=2,
+               tau_abs=0.0, tau_rel=0.0):
+    return _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
+                      max_cycles, coarsest, 0, C_thr, omega, tol, div_factor,
+                      _Tier(min_tier, max_tier, tau_abs, tau_rel))
+
+
+def _report_dict(rc, rep):
+    k = rep.checks
+    return dict(status=rc, cycles=rep.cycles, nlev=rep.nlev, publishes=rep.publishes, r0=rep.r0,
+                r_final=rep.r_final, cells_at_s=list(rep.cells_at_s), integrations=rep.integrations,
+                tier_tiles=list(rep.tier_tiles), store_bytes=rep.store_bytes,
+                t_total_ms=rep.t_total_ms, t_first_cycle_ms=rep.t_first_cycle_ms,
+                t_cycles_ms=rep.t_cycles_ms, hist=list(rep.hist[:k]))
+
+
+def solve(ctx, dim, n, eps, f, u=None, stream=None, **kw):
     """Full solve (synchronous).  f, u: device float64 [(n+1)^d]; u is the
-    initial guess (zero if None) and holds the solution on return."""
+    initial guess (zero if None) and holds the solution on return.  Keyword
+    options as in solve_opts."""
     if u is None:
         u = torch.zeros_like(f)
-    op = _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
-                    max_cycles, coarsest, 0, C_thr, omega, tol, div_factor,
-                    _Tier(min_tier, max_tier, tau_abs, tau_rel))
+    op = solve_opts(**kw)
     rep = _Report()
     rc = ctx.check(lib().mgd_solve(ctx.h, dim, n, C.byref(eps.s), _ptr(f), _ptr(u), C.byref(op),
                                    C.byref(rep), _stream(stream)))
-    k = rep.checks
-    report = dict(status=rc, cycles=rep.cycles, nlev=rep.nlev, publishes=rep.publishes, r0=rep.r0,
-                  r_final=rep.r_final, cells_at_s=list(rep.cells_at_s), integrations=rep.integrations,
-                  tier_tiles=list(rep.tier_tiles), store_bytes=rep.store_bytes,
-                  t_total_ms=rep.t_total_ms, t_first_cycle_ms=rep.t_first_cycle_ms,
-                  t_cycles_ms=rep.t_cycles_ms, hist=list(rep.hist[:k]))
-    return u, report
+    return u, _report_dict(rc, rep)
+
+
+def solve_footprint(dim, n, **kw):
+    b = C.c_double()
+    rc = lib().mgd_solve_footprint(dim, n, C.byref(solve_opts(**kw)), C.byref(b))
+    if rc != OK:
+        raise MgdError(rc, "bad footprint arguments")
+    return b.value
+
+
+class Server:
+    """Continuous-batching solve server (mgd_server_*)."""
+
+    def __init__(self, ctx, max_slots=8, budget_bytes=64e9):
+        self.ctx = ctx
+        h = _P()
+        ctx.check(lib().mgd_server_create(ctx.h, C.byref(_ServerOpts(max_slots, 0, budget_bytes)), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, dim, n, eps, f, u, stream=None, **kw):
+        """Queue a solve; it starts after the work queued so far on `stream`
+        (default: the current torch stream), where f and u were written."""
+        t = C.c_int64()
+        op = solve_opts(**kw)
+        self.ctx.check(lib().mgd_server_submit(self.h, dim, n, C.byref(eps.s), _ptr(f), _ptr(u),
+                                               C.byref(op), _stream(stream), C.byref(t)))
+        self._keep[t.value] = (eps, f, u)
+        return t.value
+
+    def poll(self):
+        a, w = _I(), _I()
+        rc = lib().mgd_server_poll(self.h, C.byref(a), C.byref(w))
+        if rc < 0:
+            raise MgdError(rc, lib().mgd_last_error(self.ctx.h).decode())
+        return rc, a.value, w.value
+
+    def result(self, ticket):
+        rep = _Report()
+        times = (C.c_double * 3)()
+        rc = lib().mgd_server_result(self.h, ticket, C.byref(rep), C.byref(times))
+        if rc < 0:
+            raise MgdError(rc, lib().mgd_last_error(self.ctx.h).decode())
+        if rc == 0:
+            return None
+        keep = self._keep.pop(ticket, None)
+        return rep.status, _report_dict(rep.status, rep), tuple(times), keep
+
+    def stats(self):
+        c, b, i = C.c_int64(), C.c_double(), _I()
+        lib().mgd_server_stats(self.h, C.byref(c), C.byref(b), C.byref(i))
+        return dict(completed=c.value, resident_bytes=b.value, idle_states=i.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mgd_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

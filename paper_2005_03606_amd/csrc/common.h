@@ -210,6 +210,7 @@ static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + b
 
 // host-side allocation helpers (return MGD_ENOMEM through ctx on failure)
 int dev_alloc(mgd_ctx *ctx, void **p, size_t bytes);
+extern thread_local size_t g_dev_alloc_bytes;
 void dev_free(void *p);
 
 // kernels / launchers implemented in the .hip files

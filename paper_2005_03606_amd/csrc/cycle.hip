@@ -208,6 +208,7 @@ template <typename TC> struct StageArgs {
     double *pnew;
     const double *s;   // device scalars (beta at s[5])
     double *partial;
+    float *rf;         // OUTER: FP32 copy of the residual (rhs of the FP32 cycle)
     float omega;
 };
 
@@ -301,6 +302,7 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
         } else if (KIND == ST_OUTER) {
             double r = inner ? (double)((TC)((const double *)a.f)[v] - Au) : 0.0;
             ((double *)a.out)[v] = r;
+            if (a.rf) a.rf[v] = (float)r;
             part = r * r;
         } else {  // PMATVEC
             a.pnew[v] = (double)uc;
@@ -719,7 +721,7 @@ template <int D> struct OpComp64 {
 
 template <int D, class Op>
 __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const double *u, const double *f, double *r,
-                                                        double *partial)
+                                                        double *partial, float *rf)
 {
     __shared__ double red[256];
     Grid<D> g(n);
@@ -728,21 +730,25 @@ __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const doubl
     if (v < g.NV) {
         int x[3] = {0, 0, 0};
         g.coords(v, x);
-        if (!g.interior(x)) r[v] = 0.0;
-        else {
+        double rv = 0.0;
+        if (g.interior(x)) {
             double Au, Dv;
             apply_row<D, Op, double>(A, g, v, x, u, Au, Dv);
-            double rv = f[v] - Au;
-            r[v] = rv;
+            rv = f[v] - Au;
             rr = rv * rv;
         }
+        r[v] = rv;
+        if (rf) rf[v] = (float)rv;
     }
     double s = block_sum<256>(rr, red);
     if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
 }
 
-// out[k] = sum of partial[k*stride .. k*stride+cnt), fixed order, one block
-__global__ void k_reduce(const double *partial, int64_t cnt, int nvec, int64_t stride, double *out)
+// out[k] = sum of partial[k*stride .. k*stride+cnt), fixed order, one block;
+// post 1: CG beta from the scalars (see k_beta), post 2: CG alpha
+enum { RED_PLAIN = 0, RED_BETA = 1, RED_ALPHA = 2 };
+__global__ void k_reduce(const double *partial, int64_t cnt, int nvec, int64_t stride, double *out, double *sc,
+                         int post)
 {
     __shared__ double red[1024];
     for (int k = 0; k < nvec; ++k) {
@@ -751,6 +757,13 @@ __global__ void k_reduce(const double *partial, int64_t cnt, int nvec, int64_t s
         double t = block_sum<1024>(s, red);
         if (threadIdx.x == 0) out[k] = t;
     }
+    if (threadIdx.x == 0 && post == RED_BETA) {
+        // sc: [0] zr_old, [1] zr, [2] zdr, [3] pAp, [4] rr, [5] beta, [6] alpha, [7] restart
+        sc[5] = sc[7] != 0.0 ? 0.0 : sc[2] / sc[0];
+        sc[0] = sc[1];
+        sc[7] = 0.0;
+    }
+    if (threadIdx.x == 0 && post == RED_ALPHA) sc[6] = sc[1] / sc[3];
 }
 
 template <int D>
@@ -760,10 +773,10 @@ static int outer_residual_t(mgd_hier *h, const OpSet &o, const double *u, const 
     dim3 gr(grid_for(h->NV[0], 256));
     if (h->precision == MGD_FP64)
         hipLaunchKernelGGL((k_outer_residual<D, OpHalf<double>>), gr, dim3(256), 0, st,
-                           OpHalf<double>{o.S64[0], h->NV[0]}, h->n, u, f, r, partial);
+                           OpHalf<double>{o.S64[0], h->NV[0]}, h->n, u, f, r, partial, (float *)nullptr);
     else
         hipLaunchKernelGGL((k_outer_residual<D, OpComp64<D>>), gr, dim3(256), 0, st,
-                           OpComp64<D>{store_view(h, o), h->n}, h->n, u, f, r, partial);
+                           OpComp64<D>{store_view(h, o), h->n}, h->n, u, f, r, partial, (float *)h->f[0]);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
@@ -781,11 +794,12 @@ int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f
         sa.f = f;
         sa.out = r;
         sa.partial = h->partial;
+        sa.rf = (float *)h->f[0];
         dim3 g2 = stage2_grid(h->n);
         hipLaunchKernelGGL((k_stage2<double, ST_OUTER>), g2, dim3(256), 0, st, sa);
         if (norm2_dev) {
             int64_t nb = (int64_t)g2.x * g2.y;
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev);
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev, nullptr, 0);
         }
         HIPCHK(h->ctx, hipGetLastError());
         return MGD_OK;
@@ -795,7 +809,7 @@ int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f
     if (rc) return rc;
     if (norm2_dev) {
         int64_t nb = grid_for(h->NV[0], 256);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev, nullptr, 0);
         HIPCHK(h->ctx, hipGetLastError());
     }
     return MGD_OK;
@@ -833,19 +847,6 @@ __global__ __launch_bounds__(256) void k_dots_zr(const T *z, const double *r, co
     if (threadIdx.x == 0) { partial[blockIdx.x] = sa; partial[nb + blockIdx.x] = sb; }
 }
 
-// scalars: s[0] zr_old, s[1] zr, s[2] zdr, s[3] pAp, s[4] rr, s[5] beta, s[6] alpha, s[7] restart
-__global__ void k_beta(double *s)
-{
-    if (threadIdx.x == 0) {
-        s[5] = s[7] != 0.0 ? 0.0 : s[2] / s[0];
-        s[0] = s[1];
-        s[7] = 0.0;
-    }
-}
-__global__ void k_alpha(double *s)
-{
-    if (threadIdx.x == 0) s[6] = s[1] / s[3];
-}
 
 // p_new = z + beta p_old on every vertex; Ap = A p_new on the interior,
 // with partials of p_new . Ap
@@ -888,7 +889,8 @@ __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, cons
 
 // x += alpha p; r_old = r; r -= alpha Ap; partials of r.r
 __global__ __launch_bounds__(256) void k_cg_update(double *x, const double *p, double *r, double *rold,
-                                                   const double *Ap, int64_t n, const double *s, double *partial)
+                                                   const double *Ap, int64_t n, const double *s, double *partial,
+                                                   float *rf)
 {
     __shared__ double red[256];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -899,6 +901,7 @@ __global__ __launch_bounds__(256) void k_cg_update(double *x, const double *p, d
         rold[i] = ri;
         ri -= alpha * Ap[i];
         r[i] = ri;
+        if (rf) rf[i] = (float)ri;
         rr = ri * ri;
     }
     double sum = block_sum<256>(rr, red);
@@ -935,8 +938,7 @@ int pcg_beta(mgd_hier *h, const void *z, const double *r, const double *rold, do
     double *part = h->partial;
     if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_dots_zr<double>, dim3(nb), dim3(256), 0, st, (const double *)z, r, rold, n, part, nb);
     else hipLaunchKernelGGL(k_dots_zr<float>, dim3(nb), dim3(256), 0, st, (const float *)z, r, rold, n, part, nb);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 2, nb, s + 1);
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 2, nb, s + 1, s, (int)RED_BETA);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
@@ -953,8 +955,7 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
     else
         hipLaunchKernelGGL((k_p_matvec<D, OpComp64<D>, TZ>), dim3(nb), dim3(256), 0, st,
                            OpComp64<D>{store_view(h, o), h->n}, h->n, z, pold, pnew, Ap, (const double *)s, part);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 3);
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 3, s, (int)RED_ALPHA);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
@@ -976,8 +977,7 @@ int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, d
         dim3 g2 = stage2_grid(h->n);
         int64_t nb = (int64_t)g2.x * g2.y;
         hipLaunchKernelGGL((k_stage2<double, ST_PMATVEC>), g2, dim3(256), 0, st, sa);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, s + 3);
-        hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, st, s);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, s + 3, s, (int)RED_ALPHA);
         HIPCHK(h->ctx, hipGetLastError());
         return MGD_OK;
     }
@@ -993,8 +993,9 @@ int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold,
 {
     int64_t n = h->NV[0], nb = grid_for(n, 256);
     double *part = h->partial;
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, x, p, r, rold, Ap, n, (const double *)s, part);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 4);
+    float *rf = h->precision == MGD_MIXED ? (float *)h->f[0] : nullptr;
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, x, p, r, rold, Ap, n, (const double *)s, part, rf);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 4, nullptr, 0);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }

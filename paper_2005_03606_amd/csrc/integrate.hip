@@ -26,8 +26,11 @@ struct EpsDev {
 };
 
 // eps at x; geometric membership decisions in FP64 for every path,
-// transcendental laws in T (float for the mixed path).
-template <int D, typename T> __device__ inline T eps_eval(const EpsDev &e, const double *x)
+// transcendental laws in T (float for the mixed path).  Balls and boxes are
+// taken from `rows` / `count`: the block's candidate list (same row layout,
+// same order as the descriptor) or the descriptor's own data.
+template <int D, typename T>
+__device__ inline T eps_eval(const EpsDev &e, const double *x, const double *rows, int count)
 {
     switch (e.kind) {
     case MGD_EPS_CONST:
@@ -44,8 +47,8 @@ template <int D, typename T> __device__ inline T eps_eval(const EpsDev &e, const
     }
     case MGD_EPS_BALLS: {
 #pragma clang fp contract(off)
-        for (int b = 0; b < e.count; ++b) {
-            const double *row = e.data + (size_t)b * (D + 1);
+        for (int b = 0; b < count; ++b) {
+            const double *row = rows + (size_t)b * (D + 1);
             double r2 = 0.0;
             for (int m = 0; m < D; ++m) {
                 double dx = x[m] - row[m];
@@ -81,8 +84,8 @@ template <int D, typename T> __device__ inline T eps_eval(const EpsDev &e, const
     }
     case MGD_EPS_BOXES: {
         double v = e.p0;
-        for (int b = 0; b < e.count; ++b) {
-            const double *row = e.data + (size_t)b * (2 * D + 1);
+        for (int b = 0; b < count; ++b) {
+            const double *row = rows + (size_t)b * (2 * D + 1);
             bool in = true;
             for (int m = 0; m < D; ++m) in = in && x[m] >= row[m] && x[m] < row[D + m];
             if (in) v = row[2 * D];
@@ -91,6 +94,89 @@ template <int D, typename T> __device__ inline T eps_eval(const EpsDev &e, const
     }
     }
     return (T)NAN;
+}
+
+// ------------------------------------------------------ candidate culling
+// A workgroup evaluates eps only inside the bounding box of its cells; balls
+// and boxes that cannot reach the box are dropped once per workgroup.  The
+// kept rows are copied to LDS in descriptor order (boxes paint in order).
+#define MGD_MAX_CAND 192
+struct CandLDS {
+    double rows[MGD_MAX_CAND * 7];
+    int lo[3], hi[3];
+    int count, overflow;
+    int wave_cnt[16];
+};
+
+template <int D>
+__device__ inline void build_candidates(const EpsDev &e, int n, bool valid, const int *ci, CandLDS &L,
+                                        const double **rows, int *count)
+{
+    *rows = e.data;
+    *count = e.count;
+    if (e.kind != MGD_EPS_BALLS && e.kind != MGD_EPS_BOXES) return;  // uniform branch
+    int tid = threadIdx.x;
+    if (tid == 0) {
+        for (int m = 0; m < 3; ++m) { L.lo[m] = 0x7fffffff; L.hi[m] = -1; }
+        L.count = 0;
+        L.overflow = 0;
+    }
+    __syncthreads();
+    if (valid)
+        for (int m = 0; m < D; ++m) {
+            atomicMin(&L.lo[m], ci[m]);
+            atomicMax(&L.hi[m], ci[m]);
+        }
+    __syncthreads();
+    if (L.hi[0] < 0) return;  // no valid cell in this workgroup
+    double blo[3], bhi[3];
+    for (int m = 0; m < D; ++m) {
+        blo[m] = (double)L.lo[m] / n;
+        bhi[m] = (double)(L.hi[m] + 1) / n;
+    }
+    const int stride = e.kind == MGD_EPS_BALLS ? D + 1 : 2 * D + 1;
+    const int lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int base = 0; base < e.count; base += blockDim.x) {
+        int b = base + tid;
+        bool keep = false;
+        if (b < e.count) {
+            const double *row = e.data + (size_t)b * stride;
+            if (e.kind == MGD_EPS_BALLS) {
+                double d2 = 0.0;
+                for (int m = 0; m < D; ++m) {
+                    double c = row[m], q = c < blo[m] ? blo[m] : (c > bhi[m] ? bhi[m] : c);
+                    d2 += (c - q) * (c - q);
+                }
+                keep = d2 <= row[D] * row[D] * (1.0 + 1e-12) + 1e-300;
+            } else {
+                keep = true;
+                for (int m = 0; m < D; ++m) keep = keep && row[m] < bhi[m] && row[D + m] > blo[m];
+            }
+        }
+        unsigned long long mask = __ballot(keep);
+        if (lane == 0) L.wave_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < nw; ++w) {
+            if (w < wave) before += L.wave_cnt[w];
+            total += L.wave_cnt[w];
+        }
+        int pos = L.count + before + __popcll(mask & ((1ull << lane) - 1ull));
+        if (keep && pos < MGD_MAX_CAND) {
+            const double *row = e.data + (size_t)b * stride;
+            for (int k = 0; k < stride; ++k) L.rows[pos * stride + k] = row[k];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            L.count += total;
+            if (L.count > MGD_MAX_CAND) L.overflow = 1;
+        }
+        __syncthreads();
+    }
+    if (!L.overflow) {
+        *rows = L.rows;
+        *count = L.count;
+    }
 }
 
 // ------------------------------------------------------ shared argument pack
@@ -192,6 +278,10 @@ template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(Asm
     int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
     int ci[3] = {0, 0, 0};
     cell_coords<D>(cell, n, ci);
+    __shared__ CandLDS cand;
+    const double *rows;
+    int nrows;
+    build_candidates<D>(a.eps, n, valid, ci, cand, &rows, &nrows);
     int nlines = (D == 2) ? s : s * s;
     int64_t nq = (int64_t)nlines * s;
     // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
@@ -215,7 +305,7 @@ template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(Asm
                     e = a.samples[i * nq + q];
                 } else {
                     x[0] = sample_coord(ci[0], qx, s, n);
-                    e = eps_eval<D, double>(a.eps, x);
+                    e = eps_eval<D, double>(a.eps, x, rows, nrows);
                 }
                 double Mx[3];
                 moments64(s, qx, Mx);
@@ -294,6 +384,10 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
     int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
     int ci[3] = {0, 0, 0};
     cell_coords<D>(cell, n, ci);
+    __shared__ CandLDS cand;
+    const double *rows;
+    int nrows;
+    build_candidates<D>(a.eps, n, valid, ci, cand, &rows, &nrows);
     int64_t nq = 1;
     for (int m = 0; m < D; ++m) nq *= s;
     floatx4 acc[NT];
@@ -314,7 +408,7 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
                     x[0] = sample_coord(ci[0], qx, s, n);
                     x[1] = sample_coord(ci[1], qr % s, s, n);
                     if (D == 3) x[2] = sample_coord(ci[2], qr / s, s, n);
-                    ev = eps_eval<D, float>(a.eps, x);
+                    ev = eps_eval<D, float>(a.eps, x, rows, nrows);
                 }
             }
             uint16_t h = bf16_bits_rne(ev);
@@ -515,12 +609,17 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
 template <int D> __global__ void k_centre_eps(EpsDev e, int n, int64_t ncell, float *out)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
+    bool valid = c < ncell;
     int ci[3] = {0, 0, 0};
-    cell_coords<D>(c, n, ci);
+    cell_coords<D>(valid ? c : 0, n, ci);
+    __shared__ CandLDS cand;
+    const double *rows;
+    int nrows;
+    build_candidates<D>(e, n, valid, ci, cand, &rows, &nrows);
+    if (!valid) return;
     double x[3];
     for (int m = 0; m < D; ++m) x[m] = sample_coord(ci[m], 0, 1, n);
-    out[c] = eps_eval<D, float>(e, x);
+    out[c] = eps_eval<D, float>(e, x, rows, nrows);
 }
 
 int launch_centre_eps(mgd_ctx *ctx, int dim, int n, const mgd_eps *eps, float *eps_c, hipStream_t st)
@@ -679,10 +778,14 @@ int mgd_fail(mgd_ctx *ctx, int code, const char *fmt, ...)
     return code;
 }
 
+// bytes handed out by dev_alloc on this host thread (footprint accounting)
+thread_local size_t g_dev_alloc_bytes = 0;
+
 int dev_alloc(mgd_ctx *ctx, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
+    g_dev_alloc_bytes += bytes;
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();

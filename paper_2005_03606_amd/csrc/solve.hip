@@ -141,6 +141,7 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
                        SolveState **out)
 {
     *out = nullptr;
+    size_t bytes0 = g_dev_alloc_bytes;
     SolveState *S = new SolveState();
     S->ctx = ctx;
     S->dim = dim; S->n = n; S->precision = precision; S->transfer = transfer; S->coarsest = coarsest;
@@ -175,6 +176,7 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
         S->s_asm = ctx->s_asm;
     }
 #undef CK
+    S->bytes = g_dev_alloc_bytes - bytes0;
     *out = S;
     return MGD_OK;
 }
@@ -471,8 +473,10 @@ int solve_step(SolveState *S, bool blocking)
     // one preconditioned cycle with the current operator
     const OpSet &O = *S->sets[S->cur];
     hipStream_t st = S->stream;
-    if ((rc = vec_cast_to_cycle(&H, S->r, H.f[0], st))) return rc;
-    if ((rc = vcycle_ops(&H, O, H.u[0], H.f[0], op.omega, op.nu1, op.nu2, true, st))) return rc;
+    // rhs of the correction cycle: the FP64 residual itself, or the FP32 copy
+    // that the kernels producing r write beside it
+    const void *rhs = H.precision == MGD_FP64 ? (const void *)S->r : (const void *)H.f[0];
+    if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st))) return rc;
     if (!S->pcg) {
         if ((rc = vec_add_cycle(&H, S->u, H.u[0], st))) return rc;
     } else {
@@ -524,4 +528,41 @@ extern "C" int mgd_solve(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *ep
     if ((rc = solve_end(S))) return rc;
     rep->t_total_ms = now_ms() - t0;
     return rep->status;
+}
+
+// device bytes a solve state of this shape allocates (mirrors the
+// allocations of hier_alloc_levels, opset_alloc, ladder_alloc and the CG
+// vectors), used for admission before anything is allocated
+size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest)
+{
+    auto ipow = [](int64_t b, int e) { int64_t r = 1; for (int i = 0; i < e; ++i) r *= b; return r; };
+    int H = n_half(dim), U = n_pairs(dim), nlw = 1 << dim;
+    size_t vb = precision == MGD_FP64 ? 8 : 4;
+    int nl[MGD_MAXLEV], nlev = 0, nn = n;
+    nl[nlev++] = nn;
+    while (nn % 2 == 0 && nn / 2 >= coarsest && nlev < MGD_MAXLEV) {
+        nn /= 2;
+        nl[nlev++] = nn;
+    }
+    int64_t NV0 = ipow(n + 1, dim), ncell = ipow(n, dim), m = ipow(nl[nlev - 1] - 1, dim);
+    size_t ops = 0, vec = 0;
+    for (int l = 0; l < nlev; ++l) {
+        int64_t NV = ipow(nl[l] + 1, dim);
+        ops += (size_t)NV * H * vb;
+        if (transfer == MGD_BOXMG && l + 1 < nlev) ops += (size_t)NV * nlw * vb;
+        vec += 4 * (size_t)NV * vb;
+    }
+    if (precision == MGD_MIXED) {
+        int64_t ntile = (NV0 + 63) / 64;
+        ops += (size_t)ntile * 5 + (size_t)ntile * (64 + 256 * H) + (size_t)ncell * 4 + 64;
+    }
+    ops += (size_t)(m > 0 ? m * m : 1) * 8;
+    size_t hier = ops + vec + (precision == MGD_MIXED ? (size_t)NV0 * H * 4 + NV0 : 0);
+    int64_t nb = (NV0 + 255) / 256 + (n + 1) / 4 + 64;
+    int64_t pcap = 2 * nb > m + 64 ? 2 * nb : m + 64;
+    hier += (size_t)pcap * 8 + 64 * 8;
+    size_t ladder = (size_t)ncell * U * vb + (size_t)ncell * 4 + (precision == MGD_MIXED ? (size_t)NV0 * H * 4 : 0) +
+                    2 * (size_t)ncell * 8 + 16 + (size_t)ncell + ((size_t)(ncell + 255) / 256 + 1) * 4;
+    size_t cg = 5 * (size_t)NV0 * 8;
+    return hier + ops + ladder + cg;
 }

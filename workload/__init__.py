@@ -125,6 +125,33 @@ def config_field(index, dim=None, n=None):
     raise ValueError(index)
 
 
+# ---------------------------------------------------------------- serving
+SERVE_SEED_BASE = 1_000_000
+SERVE_N = {2: (128, 256, 512, 768, 1024), 3: (64, 96, 128, 160, 192)}
+
+
+def serving_request(i, sizes=None, lattice=None):
+    """Request `i` of the serving workload: dimension 2 or 3 with equal odds,
+    grid size uniform over `sizes[dim]`, eps = exp(sigma g) with sigma
+    uniform in [0.5, 2] and g a Gaussian field of correlation length 1/32 on
+    an L^d lattice (L = `lattice[dim]`, default 128 in 2D and 64 in 3D,
+    which resolves the correlation length with 2-4 lattice steps)."""
+    sizes = sizes or SERVE_N
+    lattice = lattice or {2: 128, 3: 64}
+    rng = np.random.Generator(np.random.PCG64(SERVE_SEED_BASE + i))
+    dim = 2 if rng.uniform() < 0.5 else 3
+    n = int(sizes[dim][rng.integers(len(sizes[dim]))])
+    sigma = float(rng.uniform(0.5, 2.0))
+    fseed = int(rng.integers(1 << 62))
+    return dim, n, lattice_field(dim, lattice[dim], fseed, sigma=sigma)
+
+
+def poisson_arrivals(count, rate, seed):
+    """Arrival times (s) of a Poisson process of `rate` per second."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
 # ------------------------------------------------------------- load vectors
 def n_vertices(dim, n):
     return (n + 1) ** dim
