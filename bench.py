@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests in the serving replay (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--big-n", type=int, default=4096,
+                    help="also time the sweep at this size, beyond the Infinity Cache (0 skips)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the roofline sweep and a calibration copy (for counter runs)")
     return ap.parse_args()
 
 
@@ -61,6 +65,72 @@ def cpu_baseline(fld, d, n, f, cycles):
             "sample": (f"plain-C FP64 oracle, single thread, same 1024^2 problem: up-front ladder + BoxMG "
                        f"hierarchy ({t_setup:.2f} s) and 2 PCG cycles ({t_cycle:.3f} s/cycle), "
                        f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
+
+
+SWEEP_KERNEL = "k_stage2<float, 0>"  # staged 2D compressed-store Jacobi sweep
+# Memory traffic per launch of SWEEP_KERNEL at n (bytes), from FETCH_SIZE and
+# WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
+# copy; valid only for the kernel version they were taken on.
+SWEEP_TRAFFIC = {1024: 43.44e6}
+
+
+def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
+    """Finest-level damped-Jacobi sweep on the compressed store (the kernel
+    the mixed V-cycle spends most of its finest-level time in), timed with
+    HIP events on the stream it runs on, same kernel and launch shape as in
+    the solve.  Algorithmic bytes per launch: store payload + tier byte and
+    offset per tile + FP32 centre sample per cell + FP32 u in, f in, u out."""
+    import torch
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
+    S32 = P.gather_stencils(ctx, d, n, K16, P.MIXED, P.MIXED)
+    eps_c = P.centre_samples(ctx, d, n, eps)
+    h.compress(S32, eps_c, **tiers)
+    h.coarsen()
+    del K16, S32
+    ntile, payload, tier_tiles = h.store_info()
+    NV = (n + 1) ** d
+    store_bytes = payload + 5 * ntile + 4 * n ** d
+    alg_bytes = store_bytes + 12 * NV
+    u32 = torch.zeros(NV, dtype=torch.float32, device="cuda")
+    f32 = torch.ones(NV, dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    st = torch.cuda.current_stream()
+    h.smooth(0, u32, f32, sweeps=2)
+    torch.cuda.synchronize()
+    calls = max(sweeps // 2, 1)
+    ev[0].record(st)
+    for _ in range(calls):
+        h.smooth(0, u32, f32, sweeps=2)
+    ev[1].record(st)
+    torch.cuda.synchronize()
+    avg_ms = ev[0].elapsed_time(ev[1]) / (2 * calls)
+    h.close()
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": SWEEP_TRAFFIC.get(n),
+            "kernel": SWEEP_KERNEL,
+            "bytes_per_launch": int(alg_bytes), "avg_launch_us": round(avg_ms * 1e3, 3),
+            "store_tiers": tier_tiles}
+
+
+def kernels_only(args):
+    """Counter runs: the roofline sweep at the workload size, then a plain
+    device copy of known size (calibration of the traffic counters)."""
+    import torch
+    import paper_2005_03606_amd as P
+    import workload as W
+    ctx = P.Context(0)
+    tiers = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
+    r = sweep_roofline(ctx, P, 2, args.n, P.Eps(W.config_field(1)), tiers, args.sweeps)
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"sweep": r, "copy_bytes_each_way": nbytes, "copies": 4}), flush=True)
 
 
 def serving_bench(ctx, P, W, count, slots):
@@ -115,6 +185,8 @@ def serving_bench(ctx, P, W, count, slots):
 
 def main():
     args = parse()
+    if args.kernels_only:
+        return kernels_only(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition "
               "is a design note, not a measured path", file=sys.stderr)
@@ -178,35 +250,14 @@ def main():
         torch.cuda.synchronize()
         integ[name] = n ** d * reps / (ev[0].elapsed_time(ev[1]) / 1e3)
 
-    # roofline: finest-level Jacobi sweep on the compressed store (the kernel
-    # the mixed V-cycle spends most of its HBM traffic in)
-    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
-    K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
-    S32 = P.gather_stencils(ctx, d, n, K16, P.MIXED, P.MIXED)
-    eps_c = P.centre_samples(ctx, d, n, eps)
-    h.compress(S32, eps_c, **tiers)
-    h.coarsen()
-    ntile, payload, tier_tiles = h.store_info()
+    roofline = sweep_roofline(ctx, P, d, n, eps, tiers, args.sweeps)
+    big = None
+    if args.big_n > 0:
+        big_eps = P.Eps(W.config_field(1))
+        big = sweep_roofline(ctx, P, d, args.big_n, big_eps, tiers, args.sweeps)
+        big = {k: big[k] for k in ("achieved", "frac", "bytes_per_launch", "avg_launch_us", "store_tiers")}
+        big["workload"] = f"same material, {args.big_n}^2 cells (store and vectors beyond the 256 MB Infinity Cache)"
     NV = (n + 1) ** d
-    store_bytes = payload + 5 * ntile + 4 * n ** d
-    alg_bytes = store_bytes + 12 * NV  # operator + u in + f in + u out (FP32)
-    u32 = torch.zeros(NV, dtype=torch.float32, device="cuda")
-    f32 = f.float()
-    h.smooth(0, u32, f32, sweeps=2)
-    torch.cuda.synchronize()
-    ev[0].record()
-    calls = max(args.sweeps // 2, 1)
-    for _ in range(calls):
-        h.smooth(0, u32, f32, sweeps=2)
-    ev[1].record()
-    torch.cuda.synchronize()
-    avg_ms = ev[0].elapsed_time(ev[1]) / (2 * calls)
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep<2, OpComp<2,float>, float, 0, false>",
-                "bytes_per_launch": int(alg_bytes), "avg_launch_us": round(avg_ms * 1e3, 3),
-                "store_tiers": tier_tiles}
 
     out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_mixed, "higher_is_better": True, "scaling": "weak",
@@ -230,11 +281,12 @@ def main():
                "t_first_cycle_ms_fp64_upfront": round(reps_f[-1]["t_first_cycle_ms"], 3),
            },
            "roofline": roofline}
+    if big is not None:
+        out["components"]["sweep_roofline_beyond_cache"] = big
     if args.serve_requests > 0:
         out["components"]["serving"] = serving_bench(ctx, P, W, args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fld, d, n, f_host, reps_f[-1]["cycles"])
-    h.close()
     ctx.close()
     print(json.dumps(out), flush=True)
 

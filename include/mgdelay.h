@@ -55,8 +55,9 @@ enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1, MGD_PUBLISH_EVERY =
 typedef struct mgd_ctx mgd_ctx;   /* per-device context: streams, scratch */
 typedef struct mgd_hier mgd_hier; /* device-resident multigrid hierarchy */
 
-/* Context on HIP device `device`.  Owns two internal streams (assembly and
- * copies) and a small scratch area; destroy with mgd_destroy. */
+/* Context on HIP device `device`.  Owns the assembly stream of mgd_solve
+ * and the cached workspace of the last mgd_solve shape; destroy with
+ * mgd_destroy. */
 int mgd_create(mgd_ctx **ctx, int device);
 int mgd_destroy(mgd_ctx *ctx);
 const char *mgd_last_error(const mgd_ctx *ctx);
