@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sweeps", type=int, default=200, help="timed finest-level sweeps for the roofline")
+    ap.add_argument("--sweeps", type=int, default=200, help="timed launches of the roofline kernel")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests in the serving replay (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -67,19 +67,21 @@ def cpu_baseline(fld, d, n, f, cycles):
                        f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
 
 
-SWEEP_KERNEL = "k_stage2<float, 0>"  # staged 2D compressed-store Jacobi sweep
+SWEEP_KERNEL = "k_lev2<float, 16, 0, true, true, false>"  # fused pre half: 2 sweeps + residual, store
 # Memory traffic per launch of SWEEP_KERNEL at n (bytes), from FETCH_SIZE and
 # WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
 # copy; valid only for the kernel version they were taken on.
-SWEEP_TRAFFIC = {1024: 43.44e6}
+SWEEP_TRAFFIC = {}
 
 
 def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
-    """Finest-level damped-Jacobi sweep on the compressed store (the kernel
-    the mixed V-cycle spends most of its finest-level time in), timed with
-    HIP events on the stream it runs on, same kernel and launch shape as in
-    the solve.  Algorithmic bytes per launch: store payload + tier byte and
-    offset per tile + FP32 centre sample per cell + FP32 u in, f in, u out."""
+    """Pre-smoothing half of the finest level of the mixed V-cycle (two
+    damped-Jacobi sweeps from zero and the residual, one pass over the
+    compressed store): the kernel the mixed cycle moves most of its bytes in.
+    Timed with HIP events on the stream it runs on, same kernel and launch
+    shape as in the solve.  Algorithmic bytes per launch: store payload +
+    tier byte and offset per tile + FP32 centre sample per cell + FP32 f in,
+    u out, r out."""
     import torch
     h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
     K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
@@ -92,19 +94,20 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     NV = (n + 1) ** d
     store_bytes = payload + 5 * ntile + 4 * n ** d
     alg_bytes = store_bytes + 12 * NV
-    u32 = torch.zeros(NV, dtype=torch.float32, device="cuda")
     f32 = torch.ones(NV, dtype=torch.float32, device="cuda")
+    u32 = torch.zeros_like(f32)
+    r32 = torch.zeros_like(f32)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     st = torch.cuda.current_stream()
-    h.smooth(0, u32, f32, sweeps=2)
+    h.presmooth(0, None, f32, u32, r32)
     torch.cuda.synchronize()
-    calls = max(sweeps // 2, 1)
+    calls = max(sweeps, 1)
     ev[0].record(st)
     for _ in range(calls):
-        h.smooth(0, u32, f32, sweeps=2)
+        h.presmooth(0, None, f32, u32, r32)
     ev[1].record(st)
     torch.cuda.synchronize()
-    avg_ms = ev[0].elapsed_time(ev[1]) / (2 * calls)
+    avg_ms = ev[0].elapsed_time(ev[1]) / calls
     h.close()
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -173,7 +176,8 @@ def serving_bench(ctx, P, W, count, slots):
     ok = res["status"] == P.OK
     lat = res["latency_ms"][ok]
     dof_cyc = sum((n - 1) ** d * c for (d, n, _, _), c in zip(reqs, res["cycles"]))
-    out = {"requests": len(reqs), "ok": int(ok.sum()), "slots": slots,
+    failed = [[i, reqs[i][0], reqs[i][1], int(res["status"][i])] for i in range(len(reqs)) if not ok[i]]
+    out = {"requests": len(reqs), "ok": int(ok.sum()), "failed_i_dim_n_status": failed, "slots": slots,
            "single_stream_service_ms": round(mean_service * 1e3, 3),
            "arrival_rate_per_s": round(rate, 2),
            "throughput_req_per_s": round(len(reqs) / res["wall_s"], 2),

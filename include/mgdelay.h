@@ -210,6 +210,13 @@ int mgd_restrict(mgd_ctx *ctx, mgd_hier *h, int level, const void *r, void *fc, 
 int mgd_prolong_add(mgd_ctx *ctx, mgd_hier *h, int level, const void *ec, void *u, hipStream_t stream);
 int mgd_vcycle(mgd_ctx *ctx, mgd_hier *h, void *u, const void *f, const mgd_cycle_opts *opts,
                hipStream_t stream);
+/* Pre-smoothing half of a V(2,.) level in one pass (Sec. 4.1): two damped
+ * Jacobi sweeps from u (u = NULL: from zero) into u_out, then the residual
+ * r_out = f - A u_out.  u_out must not alias u.  In 2D the level's operator,
+ * rhs and iterate cross HBM once (halo-tiled in LDS); in 3D the separate
+ * kernels run. */
+int mgd_presmooth(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *u_out, void *r_out,
+                  double omega, hipStream_t stream);
 
 /* FP64 outer residual r = f - A u of the finest operator as stored (the
  * compressed store decoded in FP64 for MGD_MIXED); u, f, r dev double. */

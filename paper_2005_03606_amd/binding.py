@@ -103,6 +103,7 @@ def lib():
         "mgd_level_stencils": ([_P, _P, C.c_int, _P, _P], C.c_int),
         "mgd_level_weights": ([_P, _P, C.c_int, _P, _P], C.c_int),
         "mgd_smooth": ([_P, _P, C.c_int, _P, _P, _I, C.c_double, _P], C.c_int),
+        "mgd_presmooth": ([_P, _P, _I, _P, _P, _P, _P, C.c_double, _P], C.c_int),
         "mgd_residual": ([_P, _P, C.c_int, _P, _P, _P, _P], C.c_int),
         "mgd_restrict": ([_P, _P, C.c_int, _P, _P, _P], C.c_int),
         "mgd_prolong_add": ([_P, _P, C.c_int, _P, _P, _P], C.c_int),
@@ -302,6 +303,11 @@ class Hierarchy:
 
     def smooth(self, l, u, f, sweeps=1, omega=0.6, stream=None):
         self.ctx.check(lib().mgd_smooth(self.ctx.h, self.h, l, _ptr(u), _ptr(f), sweeps, omega, _stream(stream)))
+
+    def presmooth(self, l, u, f, u_out, r_out, omega=0.6, stream=None):
+        """Two sweeps from u (None: zero) into u_out, then r_out = f - A u_out."""
+        self.ctx.check(lib().mgd_presmooth(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(u_out), _ptr(r_out),
+                                           omega, _stream(stream)))
 
     def residual(self, l, u, f, r, stream=None):
         self.ctx.check(lib().mgd_residual(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))

@@ -55,8 +55,12 @@ int hier_alloc_levels(mgd_hier *h)
     if ((rc = dev_alloc(ctx, (void **)&h->partial, (size_t)h->partial_cap * 8))) return rc;
     if ((rc = dev_alloc(ctx, (void **)&h->scal, 64 * 8))) return rc;
     HIPCHK(ctx, hipMemset(h->scal, 0, 64 * 8));
+    if ((rc = dev_alloc(ctx, (void **)&h->partial2, (size_t)h->partial_cap * 8))) return rc;
     if (hipHostMalloc((void **)&h->host_scal, 64 * 8, hipHostMallocDefault) != hipSuccess)
         return mgd_fail(ctx, MGD_ENOMEM, "pinned allocation failed");
+    if (hipHostMalloc((void **)&h->host_part, kHostParts * 8, hipHostMallocDefault) != hipSuccess)
+        return mgd_fail(ctx, MGD_ENOMEM, "pinned allocation failed");
+    HIPCHK(ctx, hipHostGetDevicePointer((void **)&h->host_part_dev, h->host_part, 0));
     return MGD_OK;
 }
 
@@ -76,6 +80,10 @@ void hier_free(mgd_hier *h)
     h->partial_cap = 0;
     if (h->host_scal) (void)hipHostFree(h->host_scal);
     h->host_scal = nullptr;
+    dev_free(h->partial2);
+    h->partial2 = nullptr;
+    if (h->host_part) (void)hipHostFree(h->host_part);
+    h->host_part = h->host_part_dev = nullptr;
 }
 
 // ------------------------------------------------------------ validation
@@ -317,6 +325,21 @@ int mgd_smooth(mgd_ctx *ctx, mgd_hier *h, int level, void *u, const void *f, int
     if ((rc = check_level(ctx, h, level, false))) return rc;
     if (!u || !f || sweeps < 0) return mgd_fail(ctx, MGD_EINVAL, "bad smooth arguments");
     return cycle_smooth(h, h->ops, level, u, f, h->t[level], sweeps, omega, false, stream);
+}
+
+int mgd_presmooth(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *u_out, void *r_out,
+                  double omega, hipStream_t stream)
+{
+    if (!ctx) return MGD_EINVAL;
+    int rc;
+    if ((rc = check_level(ctx, h, level, false))) return rc;
+    if (!f || !u_out || !r_out || u_out == u || u_out == r_out || r_out == f)
+        return mgd_fail(ctx, MGD_EINVAL, "bad presmooth arguments (null or aliased buffers)");
+    if (h->dim == 2) return lev2_pre(h, h->ops, level, u, f, u_out, r_out, omega, stream);
+    size_t b = h->NV[level] * h->vec_bytes();
+    if (u) HIPCHK(ctx, hipMemcpyAsync(u_out, u, b, hipMemcpyDeviceToDevice, stream));
+    if ((rc = cycle_smooth(h, h->ops, level, u_out, f, h->t[level], 2, omega, u == nullptr, stream))) return rc;
+    return cycle_residual(h, h->ops, level, u_out, f, r_out, stream);
 }
 
 int mgd_residual(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *r, hipStream_t stream)

@@ -67,8 +67,17 @@ template <int D> struct Grid {
     {
         for (int m = 0; m < D; ++m) NV *= nv;
     }
+    // 32-bit unsigned division whenever the grid allows it (64-bit integer
+    // division is a long software sequence on the GPU)
     __device__ inline void coords(int64_t v, int *x) const
     {
+        if (NV <= 0xffffffffLL) {
+            const uint32_t vv = (uint32_t)v, m = (uint32_t)nv, t = vv / m;
+            x[0] = (int)(vv - t * m);
+            if (D == 2) x[1] = (int)t;
+            else { const uint32_t t2 = t / m; x[1] = (int)(t - t2 * m); x[2] = (int)t2; }
+            return;
+        }
         x[0] = (int)(v % nv);
         int64_t t = v / nv;
         if (D == 2) { x[1] = (int)t; }
@@ -182,7 +191,9 @@ struct OpSet {           // operators of every level (one version)
     uint32_t *units_total = nullptr;  // device scalar: payload size in 64-byte units
     int64_t ntile = 0, payload_cap_units = 0;
     double *chol = nullptr;  // dense Cholesky factor of the coarsest interior matrix
+    double *cinv = nullptr;  // its inverse, for coarse grids of at most kCinvMax unknowns
 };
+constexpr int64_t kCinvMax = 128;
 
 struct mgd_hier {
     mgd_ctx *ctx = nullptr;
@@ -202,6 +213,11 @@ struct mgd_hier {
     int64_t partial_cap = 0;
     double *scal = nullptr;       // [64] device scalars
     double *host_scal = nullptr;  // pinned [64]
+    double *partial2 = nullptr;   // second partial list (matrix-vector product of CG), partial_cap
+    const double *p1 = nullptr;   // CG dot partials (z.r then z.(r - r_old)), p1_n each
+    int64_t p1_n = 0, p2_n = 0;
+    double *host_part = nullptr;      // pinned [kHostParts]: partials of the residual norm
+    double *host_part_dev = nullptr;  // its device address
     size_t vec_bytes() const { return precision == MGD_FP64 ? 8 : 4; }
 };
 
@@ -237,10 +253,43 @@ int cycle_residual(mgd_hier *h, const OpSet &o, int level, const void *u, const 
                    hipStream_t st);
 int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *fc, hipStream_t st);
 int cycle_prolong(mgd_hier *h, const OpSet &o, int level, const void *ec, void *u, hipStream_t st);
-int cycle_coarse_solve(mgd_hier *h, const OpSet &o, void *u, const void *f, hipStream_t st);
+// CG scalars: s[7] restart flag (beta = 0), s[zr_old] / s[zr_new] the
+// alternating slots of z.r; p1: partials of z.r and z.(r - r_old), n1 each
+struct CgScalars {
+    double *s;
+    const double *p1;
+    int64_t n1;
+    int zr_old, zr_new;
+};
+constexpr int kHostParts = 1024;
+int pcg_dots(mgd_hier *h, const void *z, const double *r, const double *rold, hipStream_t st);
+int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap,
+               const CgScalars &c, hipStream_t st);
+int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap,
+               const CgScalars &c, int *nparts, hipStream_t st);
+int compress_partials(mgd_hier *h, const double *partial, int64_t cnt, int nvec, double *out, hipStream_t st);
+int lev2_pmv(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap,
+             const CgScalars &c, hipStream_t st);
+
+// CG dot products z.r and z.(r - r_old) fused into the last kernel of a
+// V-cycle whose result is z; s: the CG scalars (beta is formed there too)
+struct Lev2Dots {
+    const double *r, *rold;
+    double *s;
+};
+// V(nu1,nu2) correction cycle on u.  With `result`, the cycle's result may be
+// left in another level buffer, whose address is returned there; without it
+// the result is always in u.  With `dots`, *dots_done tells whether the dot
+// products were formed inside the cycle.
 int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega, int nu1, int nu2,
-               bool zero_guess, hipStream_t st);
-int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r,
-                   double *norm2_dev, hipStream_t st);
+               bool zero_guess, hipStream_t st, const Lev2Dots *dots = nullptr, void **result = nullptr,
+               bool *dots_done = nullptr);
+bool lev2_ok(const mgd_hier *h, int l, int nu1, int nu2);
+int lev2_pre(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *r_out,
+             double omega, hipStream_t st);
+int lev2_post(mgd_hier *h, const OpSet &o, int l, const void *u, const void *ec, const void *f, void *u_out,
+              double omega, const Lev2Dots *dots, hipStream_t st);
+int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, int *nparts,
+                   hipStream_t st);
 int hier_alloc_levels(mgd_hier *h);
 void hier_free(mgd_hier *h);

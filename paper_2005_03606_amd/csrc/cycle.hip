@@ -4,6 +4,8 @@
 // compressed surplus store decoded on the fly; plus the FP64 outer residual
 // and the vector kernels of the outer iteration, with deterministic
 // (fixed-order) reductions.
+#include <algorithm>
+
 #include "common.h"
 
 // ------------------------------------------------------------ operator views
@@ -189,6 +191,23 @@ template <typename T> __global__ void k_fill(T *a, int64_t n, T val)
     if (i < n) a[i] = val;
 }
 
+// ------------------------------------------------------------ reductions across blocks
+// Kernels that produce a global sum leave one partial per block; kernels
+// that need the sum add those partials themselves, every block in the same
+// fixed order (so the result is deterministic and identical in all blocks);
+// the residual norm's partials go straight to pinned host memory and the host
+// adds them.  Reducing kernels therefore run at most kRedBlocks persistent
+// blocks, which keeps the partial lists short.
+constexpr int kRedBlocks = 512;
+static inline unsigned red_grid(int64_t items) { return (unsigned)std::min<int64_t>(grid_for(items, 256), kRedBlocks); }
+
+__device__ inline double sum_partials(const double *p, int64_t cnt, double *red)
+{
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < cnt; i += 256) s += p[i];
+    return block_sum<256>(s, red);
+}
+
 // ------------------------------------------------------------ staged 2D store kernels
 // Finest level of the compressed store, 2D: a 64 x 4 block of vertices
 // stages in LDS the centre samples of cells [x0-2, x0+64] x [y0-2, y0+3], the
@@ -200,14 +219,17 @@ enum { ST_SWEEP = 0, ST_SWEEP0 = 1, ST_RESID = 2, ST_OUTER = 3, ST_PMATVEC = 4 }
 
 template <typename TC> struct StageArgs {
     StoreView sv;
-    int n;
+    int n, ntx, nt;    // cells per axis; tiles along x and in all
     const void *u;     // iterate (SWEEP/RESID: float; OUTER: double) / z (PMATVEC: float)
     const void *f;     // rhs (float / double)
     void *out;         // float / double
     const double *pold;
     double *pnew;
-    const double *s;   // device scalars (beta at s[5])
-    double *partial;
+    double *s;         // CG scalars: [7] restart flag, zr slots
+    const double *p1;  // PMATVEC: partials of z.r and z.(r - r_old), n1 each
+    int64_t n1;
+    int zr_old, zr_new;
+    double *partial;   // one partial per block (OUTER: r.r, PMATVEC: p.Ap)
     float *rf;         // OUTER: FP32 copy of the residual (rhs of the FP32 cycle)
     float omega;
 };
@@ -222,15 +244,22 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
     __shared__ TC s_u[BY + 2][BX + 2];
     __shared__ double red[256];
     const int n = a.n, nv = n + 1;
-    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY;
     const int tid = threadIdx.x;
+    double beta = 0.0, part = 0.0;
+    if (KIND == ST_PMATVEC) {
+        // Polak-Ribiere coefficient from the dot partials (every block sums them in the same order)
+        const double zr = sum_partials(a.p1, a.n1, red), zdr = sum_partials(a.p1 + a.n1, a.n1, red);
+        beta = a.s[7] != 0.0 ? 0.0 : zdr / a.s[a.zr_old];
+        if (blockIdx.x == 0 && tid == 0) a.s[a.zr_new] = zr;
+    }
+    for (int tile = blockIdx.x; tile < a.nt; tile += gridDim.x) {
+    const int x0 = (tile % a.ntx) * BX, y0 = (tile / a.ntx) * BY;
     // centre samples of cells x in [x0-2, x0+64], y in [y0-2, y0+3]
     for (int k = tid; k < (BY + 2) * (BX + 3); k += 256) {
         int cx = x0 - 2 + k % (BX + 3), cy = y0 - 2 + k / (BX + 3);
         s_eps[k / (BX + 3)][k % (BX + 3)] = (cx >= 0 && cx < n && cy >= 0 && cy < n) ? a.sv.eps_c[(int64_t)cy * n + cx] : 0.0f;
     }
     // iterate with a one-vertex halo
-    double beta = KIND == ST_PMATVEC ? a.s[5] : 0.0;
     for (int k = tid; k < (BY + 2) * (BX + 2); k += 256) {
         int vx = x0 - 1 + k % (BX + 2), vy = y0 - 1 + k / (BX + 2);
         TC val = (TC)0;
@@ -277,7 +306,6 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
     __syncthreads();
     const int tx = tid & 63, ty = tid >> 6;
     const int vx = x0 + tx, vy = y0 + ty;
-    double part = 0.0;
     if (vx < nv && vy < nv) {
         int64_t v = (int64_t)vy * nv + vx;
         const int cx = tx + 1, cy = ty + 1;  // this vertex in s_c / s_u coordinates
@@ -303,21 +331,28 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
             double r = inner ? (double)((TC)((const double *)a.f)[v] - Au) : 0.0;
             ((double *)a.out)[v] = r;
             if (a.rf) a.rf[v] = (float)r;
-            part = r * r;
+            part += r * r;
         } else {  // PMATVEC
             a.pnew[v] = (double)uc;
             double ap = inner ? (double)Au : 0.0;
             ((double *)a.out)[v] = ap;
-            part = (double)uc * ap;
+            part += (double)uc * ap;
         }
+    }
+    __syncthreads();  // the next tile overwrites the staged data
     }
     if (KIND == ST_OUTER || KIND == ST_PMATVEC) {
         double sum = block_sum<256>(part, red);
-        if (tid == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+        if (tid == 0) a.partial[blockIdx.x] = sum;
     }
 }
 
-static inline dim3 stage2_grid(int n) { return dim3((unsigned)((n + 1 + 63) / 64), (unsigned)((n + 1 + 3) / 4)); }
+// 64 x 4 tiles; the reducing modes run persistent blocks (at most kRedBlocks)
+static inline void stage2_tiles(int n, int &ntx, int &nt)
+{
+    ntx = (n + 1 + 63) / 64;
+    nt = ntx * ((n + 1 + 3) / 4);
+}
 
 // ------------------------------------------------------------ dispatch
 int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
@@ -338,7 +373,8 @@ static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *
         sa.f = f;
         sa.out = out;
         sa.omega = (float)omega;
-        dim3 g2 = stage2_grid(n);
+        stage2_tiles(n, sa.ntx, sa.nt);
+        dim3 g2((unsigned)sa.nt);
         if (mode == 1) hipLaunchKernelGGL((k_stage2<float, ST_RESID>), g2, dim3(256), 0, st, sa);
         else if (zero_guess) hipLaunchKernelGGL((k_stage2<float, ST_SWEEP0>), g2, dim3(256), 0, st, sa);
         else hipLaunchKernelGGL((k_stage2<float, ST_SWEEP>), g2, dim3(256), 0, st, sa);
@@ -439,211 +475,342 @@ static int fill_zero(mgd_hier *h, void *a, int64_t n, hipStream_t st)
 
 // ------------------------------------------------------------ coarse tail
 // The small levels of the V-cycle, from level `first` (zero initial guess or
-// a given u) down to the dense coarsest solve and back up, in one workgroup:
-// each step is a strided loop over the level's vertices, steps separated by
-// workgroup barriers (global writes of the workgroup are visible after them).
+// a given u) down to the dense coarsest solve and back up, in one workgroup
+// of 1024 threads.  The vectors of every tail level (iterate, right-hand
+// side, scratch) live in LDS for the whole tail; stencils and transfer
+// weights are read from memory (they stay in L2), each phase issuing all its
+// loads before its LDS arithmetic.  Phases are separated by workgroup
+// barriers.  The coarsest solve multiplies by the precomputed FP64 inverse
+// (small coarse grids) or runs FP64 forward and backward substitution with
+// the Cholesky factor.
+constexpr int kTailThreads = 1024;
 struct TailLevel {
     const void *S, *W;
-    void *u, *f, *r, *t;
-    int n;
-    int64_t NV;
+    int n, NV;
+    int off;         // element offset of this level's vectors in LDS: u | f | t
+    int s_off, w_off;  // element offsets of its stencils / weights copied into LDS, or -1
 };
 struct TailArgs {
-    int first, last, nu1, nu2, zero_guess;
+    int first, last, nu1, nu2, zero_guess, m, work_off;
     double omega;
-    const double *chol;
-    int64_t m;
-    double *work;
+    void *u;
+    const void *f;
+    const double *chol, *cinv;
     TailLevel L[MGD_MAXLEV];
 };
 
+// vertices handled per thread and phase with their loads in flight together
+template <int D> constexpr int tail_chunk() { return D == 2 ? 5 : 1; }
+
 template <int D, typename T>
-__device__ void tail_sweep(const TailLevel &lv, const T *u, T *out, bool zero, T omega)
+__device__ void tail_sweep(const TailLevel &lv, const T *S, const T *uin, T *uout, const T *f, bool zero, T omega)
 {
-    OpHalf<T> A{(const T *)lv.S, lv.NV};
-    Grid<D> g(lv.n);
-    const T *f = (const T *)lv.f;
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
-        int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        if (!g.interior(x)) { out[v] = (T)0; continue; }
-        T Au, Dv;
-        if (zero) {
-            constexpr int H = n_half(D);
-            T dsum = (T)0;
+    constexpr int H = n_half(D), CK = tail_chunk<D>();
+    const Grid<D> g(lv.n);
+    const int64_t NV = lv.NV, safe = D == 2 ? 1 + g.nv : 1 + g.nv + g.nv * g.nv;  // an interior vertex
+    for (int v0 = threadIdx.x; v0 < lv.NV; v0 += CK * kTailThreads) {
+        T c[CK][2 * H];
+        bool in[CK];
+#pragma unroll
+        for (int q = 0; q < CK; ++q) {
+            const int v = v0 + q * kTailThreads;
+            int x[3] = {0, 0, 0};
+            g.coords(v < lv.NV ? v : 0, x);
+            in[q] = v < lv.NV && g.interior(x);
+            const int64_t vs = in[q] ? v : safe;
+#pragma unroll
             for (int j = 0; j < H; ++j) {
-                int64_t lin = half_lin(D, j, g.nv);
-                dsum += A.c(v, j, x) + A.c(v - lin, j, x);
+                c[q][j] = S[(int64_t)j * NV + vs];
+                c[q][H + j] = S[(int64_t)j * NV + vs - half_lin(D, j, g.nv)];
             }
-            Dv = -dsum;
-            Au = (T)0;
-        } else {
-            apply_row<D, OpHalf<T>, T>(A, g, v, x, u, Au, Dv);
         }
-        out[v] = (zero ? (T)0 : u[v]) + omega * (f[v] - Au) / Dv;
+#pragma unroll
+        for (int q = 0; q < CK; ++q) {
+            const int v = v0 + q * kTailThreads;
+            if (v >= lv.NV) continue;
+            if (!in[q]) {
+                uout[v] = (T)0;
+                continue;
+            }
+            T acc = (T)0, dsum = (T)0;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int64_t lin = half_lin(D, j, g.nv);
+                if (!zero) acc += c[q][j] * uin[v + lin] + c[q][H + j] * uin[v - lin];
+                dsum += c[q][j] + c[q][H + j];
+            }
+            const T Dv = -dsum;
+            uout[v] = zero ? omega * f[v] / Dv : uin[v] + omega * (f[v] - (Dv * uin[v] + acc)) / Dv;
+        }
     }
     __syncthreads();
 }
 
-template <int D, typename T> __device__ void tail_smooth(const TailLevel &lv, int sweeps, bool zero, T omega)
+template <int D, typename T>
+__device__ void tail_residual(const TailLevel &lv, const T *S, const T *u, const T *f, T *r)
 {
-    T *u = (T *)lv.u, *t = (T *)lv.t;
+    constexpr int H = n_half(D), CK = tail_chunk<D>();
+    const Grid<D> g(lv.n);
+    const int64_t NV = lv.NV, safe = D == 2 ? 1 + g.nv : 1 + g.nv + g.nv * g.nv;
+    for (int v0 = threadIdx.x; v0 < lv.NV; v0 += CK * kTailThreads) {
+        T c[CK][2 * H];
+        bool in[CK];
+#pragma unroll
+        for (int q = 0; q < CK; ++q) {
+            const int v = v0 + q * kTailThreads;
+            int x[3] = {0, 0, 0};
+            g.coords(v < lv.NV ? v : 0, x);
+            in[q] = v < lv.NV && g.interior(x);
+            const int64_t vs = in[q] ? v : safe;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                c[q][j] = S[(int64_t)j * NV + vs];
+                c[q][H + j] = S[(int64_t)j * NV + vs - half_lin(D, j, g.nv)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CK; ++q) {
+            const int v = v0 + q * kTailThreads;
+            if (v >= lv.NV) continue;
+            T rv = (T)0;
+            if (in[q]) {
+                T acc = (T)0, dsum = (T)0;
+#pragma unroll
+                for (int j = 0; j < H; ++j) {
+                    const int64_t lin = half_lin(D, j, g.nv);
+                    acc += c[q][j] * u[v + lin] + c[q][H + j] * u[v - lin];
+                    dsum += c[q][j] + c[q][H + j];
+                }
+                rv = f[v] - (-dsum * u[v] + acc);
+            }
+            r[v] = rv;
+        }
+    }
+    __syncthreads();
+}
+
+template <int D, typename T>
+__device__ void tail_smooth(const TailLevel &lv, const T *S, T *u, const T *f, T *t, int sweeps, bool zero, T omega)
+{
     for (int k = 0; k < sweeps; ++k) {
-        if (k % 2 == 0) tail_sweep<D, T>(lv, u, t, zero && k == 0, omega);
-        else tail_sweep<D, T>(lv, t, u, false, omega);
+        if (k % 2 == 0) tail_sweep<D, T>(lv, S, u, t, f, zero && k == 0, omega);
+        else tail_sweep<D, T>(lv, S, t, u, f, false, omega);
     }
     if (sweeps % 2 == 1) {
-        for (int64_t v = threadIdx.x; v < lv.NV; v += blockDim.x) u[v] = t[v];
+        for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = t[v];
         __syncthreads();
     }
     if (sweeps == 0 && zero) {
-        for (int64_t v = threadIdx.x; v < lv.NV; v += blockDim.x) u[v] = (T)0;
+        for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = (T)0;
         __syncthreads();
     }
 }
 
-template <int D, typename T> __device__ void tail_residual_restrict(const TailLevel &lv, const TailLevel &lc)
+// fc = P^T r on the interior coarse vertices, uc = 0
+template <int D, typename T>
+__device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T *W, const T *r, T *fc, T *uc)
 {
-    OpHalf<T> A{(const T *)lv.S, lv.NV};
-    Grid<D> g(lv.n), gc(lc.n);
-    const T *u = (const T *)lv.u, *f = (const T *)lv.f;
-    T *r = (T *)lv.r;
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
-        int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        if (!g.interior(x)) { r[v] = (T)0; continue; }
-        T Au, Dv;
-        apply_row<D, OpHalf<T>, T>(A, g, v, x, u, Au, Dv);
-        r[v] = f[v] - Au;
-    }
-    __syncthreads();
-    const T *W = (const T *)lv.W;
-    T *fc = (T *)lc.f, *uc = (T *)lc.u;
     constexpr int ns = D == 2 ? 9 : 27;
-    for (int64_t V = threadIdx.x; V < gc.NV; V += blockDim.x) {
+    const Grid<D> g(lv.n), gc(lc.n);
+    for (int V = threadIdx.x; V < lc.NV; V += kTailThreads) {
         int X[3] = {0, 0, 0};
         gc.coords(V, X);
         uc[V] = (T)0;
-        if (!gc.interior(X)) { fc[V] = (T)0; continue; }
-        T s = (T)0;
-        for (int sv = 0; sv < ns; ++sv) {
-            int x[3] = {0, 0, 0}, t = sv;
-            for (int m = 0; m < D; ++m) { x[m] = 2 * X[m] + t % 3 - 1; t /= 3; }
-            int64_t v = g.vid(x);
-            s += wt<D, T, T>(W, g.NV, v, x, X) * r[v];
+        if (!gc.interior(X)) {
+            fc[V] = (T)0;
+            continue;
         }
+        T w[ns];
+        int64_t vv[ns];
+#pragma unroll
+        for (int sv = 0; sv < ns; ++sv) {
+            int x[3] = {0, 0, 0}, t = sv, B = 0;
+            for (int m = 0; m < D; ++m) {
+                const int o = t % 3 - 1;
+                t /= 3;
+                x[m] = 2 * X[m] + o;
+                B |= (o < 0 ? 1 : 0) << m;  // X - (x >> 1) is 1 exactly when o = -1
+            }
+            vv[sv] = g.vid(x);
+            if (W) {
+                w[sv] = W[(int64_t)B * lv.NV + vv[sv]];
+            } else {
+                double p = 1.0;
+                for (int m = 0; m < D; ++m) p *= x[m] == 2 * X[m] ? 1.0 : 0.5;
+                w[sv] = (T)p;
+            }
+        }
+        T s = (T)0;
+#pragma unroll
+        for (int sv = 0; sv < ns; ++sv) s += w[sv] * r[vv[sv]];
         fc[V] = s;
     }
     __syncthreads();
 }
 
-template <int D, typename T> __device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc)
+// u += P ec on the interior fine vertices
+template <int D, typename T>
+__device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, const T *W, T *u, const T *ec)
 {
-    Grid<D> g(lv.n), gc(lc.n);
-    const T *W = (const T *)lv.W, *ec = (const T *)lc.u;
-    T *u = (T *)lv.u;
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
+    constexpr int nl = 1 << D;
+    const Grid<D> g(lv.n), gc(lc.n);
+    for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) {
         int x[3] = {0, 0, 0};
         g.coords(v, x);
         if (!g.interior(x)) continue;
-        T s = (T)0;
-        for (int B = 0; B < (1 << D); ++B) {
+        T w[nl];
+        int64_t ic[nl];
+#pragma unroll
+        for (int B = 0; B < nl; ++B) {
+            bool use = true;
             int X[3] = {0, 0, 0};
-            bool ok = true;
+            double p = 1.0;
             for (int m = 0; m < D; ++m) {
-                X[m] = (x[m] >> 1) + ((B >> m) & 1);
-                if (X[m] > gc.n) ok = false;
+                const int b = (B >> m) & 1;
+                if (b && !(x[m] & 1)) use = false;  // only odd axes reach the upper corner
+                X[m] = (x[m] >> 1) + b;
+                p *= (x[m] & 1) ? 0.5 : 1.0;
             }
-            if (!ok) continue;
-            T w = wt<D, T, T>(W, g.NV, v, x, X);
-            if (w != (T)0) s += w * ec[gc.vid(X)];
+            ic[B] = use ? gc.vid(X) : 0;
+            w[B] = use ? (W ? W[(int64_t)B * lv.NV + v] : (T)p) : (T)0;
         }
+        T s = (T)0;
+#pragma unroll
+        for (int B = 0; B < nl; ++B)
+            if (w[B] != (T)0) s += w[B] * ec[ic[B]];
         u[v] += s;
     }
     __syncthreads();
 }
 
-template <int BS> __device__ inline double block_sum_tail(double v, double *red)
+// dense FP64 solve on the interior of the coarsest level: u = A^{-1} f
+template <int D, typename T>
+__device__ void tail_coarse(const TailArgs &a, const TailLevel &lv, T *u, const T *f, double *work)
 {
-    red[threadIdx.x] = v;
+    const Grid<D> g(lv.n);
+    const int m = a.m, nin = lv.n - 1;
+    auto vof = [&](int k) {  // interior index -> vertex
+        int x[3] = {0, 0, 0}, t = k;
+        for (int mm = 0; mm < D; ++mm) { x[mm] = 1 + t % nin; t /= nin; }
+        return g.vid(x);
+    };
+    for (int k = threadIdx.x; k < m; k += kTailThreads) work[k] = (double)f[vof(k)];
+    for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = (T)0;
     __syncthreads();
-    for (int o = BS / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
-}
-
-// dense solve on the coarsest interior, FP64 triangular substitutions
-template <int D, typename T> __device__ void tail_coarse(const TailLevel &lv, const double *L, int64_t m, double *work,
-                                                         double *red)
-{
-    Grid<D> g(lv.n);
-    const T *f = (const T *)lv.f;
-    T *u = (T *)lv.u;
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
-        int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        if (!g.interior(x)) continue;
-        int64_t k = 0, st = 1;
-        for (int mm = 0; mm < D; ++mm) { k += (int64_t)(x[mm] - 1) * st; st *= (lv.n - 1); }
-        work[k] = (double)f[v];
-    }
-    __syncthreads();
-    for (int64_t i = 0; i < m; ++i) {
-        double s = 0.0;
-        for (int64_t k = threadIdx.x; k < i; k += blockDim.x) s += L[i * m + k] * work[k];
-        s = block_sum_tail<1024>(s, red);
-        if (threadIdx.x == 0) work[i] = (work[i] - s) / L[i * m + i];
-        __syncthreads();
-    }
-    for (int64_t i = m - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int64_t k = i + 1 + threadIdx.x; k < m; k += blockDim.x) s += L[k * m + i] * work[k];
-        s = block_sum_tail<1024>(s, red);
-        if (threadIdx.x == 0) work[i] = (work[i] - s) / L[i * m + i];
-        __syncthreads();
-    }
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
-        int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        T val = (T)0;
-        if (g.interior(x)) {
-            int64_t k = 0, st = 1;
-            for (int mm = 0; mm < D; ++mm) { k += (int64_t)(x[mm] - 1) * st; st *= (lv.n - 1); }
-            val = (T)work[k];
+    if (a.cinv) {
+        for (int i = threadIdx.x; i < m; i += kTailThreads) {
+            double s = 0.0;
+            for (int k = 0; k < m; ++k) s += a.cinv[(int64_t)i * m + k] * work[k];
+            u[vof(i)] = (T)s;
         }
-        u[v] = val;
+        __syncthreads();
+        return;
     }
+    const double *L = a.chol;
+    // forward: L y = b, column by column
+    for (int i = 0; i < m; ++i) {
+        const double yi = work[i] / L[(int64_t)i * m + i];
+        __syncthreads();
+        if (threadIdx.x == 0) work[i] = yi;
+        for (int k = i + 1 + threadIdx.x; k < m; k += kTailThreads) work[k] -= L[(int64_t)k * m + i] * yi;
+        __syncthreads();
+    }
+    // backward: L^T x = y, row i needs x_k for k > i
+    for (int i = m - 1; i >= 0; --i) {
+        const double xi = work[i] / L[(int64_t)i * m + i];
+        __syncthreads();
+        if (threadIdx.x == 0) work[i] = xi;
+        for (int k = threadIdx.x; k < i; k += kTailThreads) work[k] -= L[(int64_t)i * m + k] * xi;
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < m; k += kTailThreads) u[vof(k)] = (T)work[k];
     __syncthreads();
 }
 
 template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(TailArgs a)
 {
-    __shared__ double red[1024];
-    T omega = (T)a.omega;
-    for (int l = a.first; l < a.last; ++l) {
-        bool zero = l > a.first || a.zero_guess;
-        tail_smooth<D, T>(a.L[l], a.nu1, zero, omega);
-        tail_residual_restrict<D, T>(a.L[l], a.L[l + 1]);
+    extern __shared__ __align__(16) unsigned char tail_lds[];
+    T *base = (T *)tail_lds;
+    double *work = (double *)(tail_lds + a.work_off);
+    const T omega = (T)a.omega;
+    auto U = [&](int l) { return base + a.L[l].off; };
+    auto F = [&](int l) { return base + a.L[l].off + a.L[l].NV; };
+    auto Tt = [&](int l) { return base + a.L[l].off + 2 * a.L[l].NV; };
+    // stencils and weights: the LDS copy where one was made
+    auto Sp = [&](int l) { return a.L[l].s_off >= 0 ? (const T *)(base + a.L[l].s_off) : (const T *)a.L[l].S; };
+    auto Wp = [&](int l) {
+        return a.L[l].W == nullptr ? (const T *)nullptr
+                                   : a.L[l].w_off >= 0 ? (const T *)(base + a.L[l].w_off) : (const T *)a.L[l].W;
+    };
+    {
+        // copies into LDS, four loads in flight per thread
+        auto copy = [&](T *dst, const T *src, int cnt) {
+            for (int i0 = threadIdx.x; i0 < cnt; i0 += 4 * kTailThreads) {
+                T r[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = i0 + q * kTailThreads;
+                    r[q] = src[i < cnt ? i : 0];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = i0 + q * kTailThreads;
+                    if (i < cnt) dst[i] = r[q];
+                }
+            }
+        };
+        for (int l = a.first; l <= a.last; ++l) {
+            const TailLevel &L = a.L[l];
+            if (L.s_off >= 0) copy(base + L.s_off, (const T *)L.S, n_half(D) * L.NV);
+            if (L.w_off >= 0) copy(base + L.w_off, (const T *)L.W, (1 << D) * L.NV);
+        }
+        const TailLevel &l0 = a.L[a.first];
+        const T *fg = (const T *)a.f, *ug = (const T *)a.u;
+        T *u0 = U(a.first), *f0 = F(a.first);
+        for (int v = threadIdx.x; v < l0.NV; v += kTailThreads) {
+            f0[v] = fg[v];
+            u0[v] = a.zero_guess ? (T)0 : ug[v];
+        }
+        __syncthreads();
     }
-    tail_coarse<D, T>(a.L[a.last], a.chol, a.m, a.work, red);
+    for (int l = a.first; l < a.last; ++l) {
+        const bool zero = l > a.first || a.zero_guess;
+        tail_smooth<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l), a.nu1, zero, omega);
+        tail_residual<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l));
+        tail_restrict<D, T>(a.L[l], a.L[l + 1], Wp(l), Tt(l), F(l + 1), U(l + 1));
+    }
+    tail_coarse<D, T>(a, a.L[a.last], U(a.last), F(a.last), work);
     for (int l = a.last - 1; l >= a.first; --l) {
-        tail_prolong<D, T>(a.L[l], a.L[l + 1]);
-        tail_smooth<D, T>(a.L[l], a.nu2, false, omega);
+        tail_prolong<D, T>(a.L[l], a.L[l + 1], Wp(l), U(l), U(l + 1));
+        tail_smooth<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l), a.nu2, false, omega);
+    }
+    {
+        T *ug = (T *)a.u;
+        const T *u0 = U(a.first);
+        for (int v = threadIdx.x; v < a.L[a.first].NV; v += kTailThreads) ug[v] = u0[v];
     }
 }
 
-// first level handled by the tail kernel (levels with few vertices)
+// first level handled by the single-workgroup tail: in 2D the levels up to
+// 33 x 33 vertices (larger ones run faster as fused multi-block passes), in
+// 3D up to 17^3 (their vectors still fit in LDS)
 static int tail_first(const mgd_hier *h)
 {
-    const int64_t kTailNV = 5000;
+    const int64_t kTailNV = h->dim == 2 ? 1100 : 5000;
     int l = h->nlev - 1;
     while (l > 0 && h->NV[l - 1] <= kTailNV) --l;
     if (h->precision == MGD_MIXED && l == 0) l = h->nlev > 1 ? 1 : 0;  // level 0 is the compressed store
     return l;
+}
+
+template <int D, typename T> static void tail_launch_t(const TailArgs &a, size_t lds, hipStream_t st)
+{
+    static bool attr = false;  // once per instantiation: allow more than 64 KB of dynamic LDS
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_tail<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_tail<D, T>), dim3(1), dim3(kTailThreads), lds, st, a);
 }
 
 static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const void *f, double omega, int nu1, int nu2,
@@ -657,37 +824,75 @@ static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const vo
     a.nu2 = nu2;
     a.zero_guess = zero_guess ? 1 : 0;
     a.omega = omega;
+    a.u = u;
+    a.f = f;
     a.chol = o.chol;
-    a.m = h->m_coarse;
-    a.work = h->partial;
+    a.cinv = o.cinv;
+    a.m = (int)h->m_coarse;
+    const size_t vb = h->vec_bytes(), cap = 160 * 1024;
+    int64_t off = 0;
     for (int l = first; l <= a.last; ++l) {
         TailLevel &L = a.L[l];
         L.S = h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l];
-        L.W = h->transfer == MGD_BOXMG ? o.W[l] : nullptr;
-        L.u = l == first ? u : h->u[l];
-        L.f = l == first ? const_cast<void *>(f) : h->f[l];
-        L.r = h->r[l];
-        L.t = h->t[l];
+        L.W = h->transfer == MGD_BOXMG && l < a.last ? o.W[l] : nullptr;
         L.n = h->nl[l];
-        L.NV = h->NV[l];
+        L.NV = (int)h->NV[l];
+        L.off = (int)off;
+        L.s_off = L.w_off = -1;
+        off += 3 * h->NV[l];
     }
+    const size_t work = (size_t)(a.m > 0 ? a.m : 1) * 8 + 16;
+    if ((size_t)off * vb + work > cap)
+        return mgd_fail(h->ctx, MGD_EINVAL, "coarse levels need %zu bytes of LDS", (size_t)off * vb + work);
+    // copy stencils and weights into LDS too, coarsest level first, while they fit
+    for (int l = a.last; l >= first; --l) {
+        TailLevel &L = a.L[l];
+        const int64_t ns = (int64_t)h->H * L.NV, nw = L.W ? ((int64_t)1 << h->dim) * L.NV : 0;
+        if ((size_t)(off + ns + nw) * vb + work > cap) break;
+        L.s_off = (int)off;
+        off += ns;
+        if (nw) {
+            L.w_off = (int)off;
+            off += nw;
+        }
+    }
+    size_t bytes = ((size_t)off * vb + 15) / 16 * 16;
+    a.work_off = (int)bytes;
+    bytes += work;
     if (h->precision == MGD_FP64) {
-        if (h->dim == 2) hipLaunchKernelGGL((k_tail<2, double>), dim3(1), dim3(1024), 0, st, a);
-        else hipLaunchKernelGGL((k_tail<3, double>), dim3(1), dim3(1024), 0, st, a);
+        if (h->dim == 2) tail_launch_t<2, double>(a, bytes, st);
+        else tail_launch_t<3, double>(a, bytes, st);
     } else {
-        if (h->dim == 2) hipLaunchKernelGGL((k_tail<2, float>), dim3(1), dim3(1024), 0, st, a);
-        else hipLaunchKernelGGL((k_tail<3, float>), dim3(1), dim3(1024), 0, st, a);
+        if (h->dim == 2) tail_launch_t<2, float>(a, bytes, st);
+        else tail_launch_t<3, float>(a, bytes, st);
     }
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
 
-// multiplicative V(nu1,nu2) correction scheme from level l down
+// multiplicative V(nu1,nu2) correction scheme from level l down; *res: the
+// buffer holding the level's result (u, or the level's spare buffer when the
+// fused 2D kernels ran from a zero start)
 static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f, double omega, int nu1, int nu2,
-                      bool zero_guess, hipStream_t st)
+                      bool zero_guess, const Lev2Dots *dots, bool *dots_done, void **res, hipStream_t st)
 {
     int rc;
+    *res = u;
     if (l == tail_first(h)) return launch_tail(h, o, l, u, f, omega, nu1, nu2, zero_guess, st);
+    if (lev2_ok(h, l, nu1, nu2)) {
+        // pre half: u (or its spare) <- S^2 u, r <- f - A u; post half into the other buffer
+        void *us = zero_guess ? u : h->t[l];
+        if ((rc = lev2_pre(h, o, l, zero_guess ? nullptr : u, f, us, h->r[l], omega, st))) return rc;
+        if ((rc = cycle_restrict(h, o, l, h->r[l], h->f[l + 1], st))) return rc;
+        void *ec = nullptr;
+        if ((rc = vcycle_rec(h, o, l + 1, h->u[l + 1], h->f[l + 1], omega, nu1, nu2, true, nullptr, nullptr, &ec, st)))
+            return rc;
+        void *dst = us == u ? h->t[l] : u;
+        if ((rc = lev2_post(h, o, l, us, ec, f, dst, omega, dots, st))) return rc;
+        if (dots && dots_done) *dots_done = true;
+        *res = dst;
+        return MGD_OK;
+    }
     if (nu1 > 0) {
         if ((rc = cycle_smooth(h, o, l, u, f, h->t[l], nu1, omega, zero_guess, st))) return rc;
     } else if (zero_guess) {
@@ -695,17 +900,26 @@ static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f
     }
     if ((rc = cycle_residual(h, o, l, u, f, h->r[l], st))) return rc;
     if ((rc = cycle_restrict(h, o, l, h->r[l], h->f[l + 1], st))) return rc;
-    if ((rc = vcycle_rec(h, o, l + 1, h->u[l + 1], h->f[l + 1], omega, nu1, nu2, true, st))) return rc;
-    if ((rc = cycle_prolong(h, o, l, h->u[l + 1], u, st))) return rc;
+    void *ec = nullptr;
+    if ((rc = vcycle_rec(h, o, l + 1, h->u[l + 1], h->f[l + 1], omega, nu1, nu2, true, nullptr, nullptr, &ec, st)))
+        return rc;
+    if ((rc = cycle_prolong(h, o, l, ec, u, st))) return rc;
     if (nu2 > 0)
         if ((rc = cycle_smooth(h, o, l, u, f, h->t[l], nu2, omega, false, st))) return rc;
     return MGD_OK;
 }
 
 int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega, int nu1, int nu2, bool zero_guess,
-               hipStream_t st)
+               hipStream_t st, const Lev2Dots *dots, void **result, bool *dots_done)
 {
-    return vcycle_rec(h, o, 0, u, f, omega, nu1, nu2, zero_guess, st);
+    if (dots_done) *dots_done = false;
+    void *res = nullptr;
+    int rc = vcycle_rec(h, o, 0, u, f, omega, nu1, nu2, zero_guess, dots, dots_done, &res, st);
+    if (rc) return rc;
+    if (result) *result = res;
+    else if (res != u)
+        HIPCHK(h->ctx, hipMemcpyAsync(u, res, h->NV[0] * h->vec_bytes(), hipMemcpyDeviceToDevice, st));
+    return MGD_OK;
 }
 
 // ------------------------------------------------------------ FP64 outer
@@ -725,9 +939,8 @@ __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const doubl
 {
     __shared__ double red[256];
     Grid<D> g(n);
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0;
-    if (v < g.NV) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
         int x[3] = {0, 0, 0};
         g.coords(v, x);
         double rv = 0.0;
@@ -735,7 +948,7 @@ __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const doubl
             double Au, Dv;
             apply_row<D, Op, double>(A, g, v, x, u, Au, Dv);
             rv = f[v] - Au;
-            rr = rv * rv;
+            rr += rv * rv;
         }
         r[v] = rv;
         if (rf) rf[v] = (float)rv;
@@ -744,47 +957,46 @@ __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const doubl
     if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
 }
 
-// out[k] = sum of partial[k*stride .. k*stride+cnt), fixed order, one block;
-// post 1: CG beta from the scalars (see k_beta), post 2: CG alpha
-enum { RED_PLAIN = 0, RED_BETA = 1, RED_ALPHA = 2 };
-__global__ void k_reduce(const double *partial, int64_t cnt, int nvec, int64_t stride, double *out, double *sc,
-                         int post)
+// fixed-order sum of nvec runs of cnt block partials by one block
+__global__ void k_reduce(const double *partial, int64_t cnt, int nvec, double *out)
 {
     __shared__ double red[1024];
     for (int k = 0; k < nvec; ++k) {
         double s = 0.0;
-        for (int64_t i = threadIdx.x; i < cnt; i += 1024) s += partial[k * stride + i];
+        for (int64_t i = threadIdx.x; i < cnt; i += 1024) s += partial[k * cnt + i];
         double t = block_sum<1024>(s, red);
         if (threadIdx.x == 0) out[k] = t;
     }
-    if (threadIdx.x == 0 && post == RED_BETA) {
-        // sc: [0] zr_old, [1] zr, [2] zdr, [3] pAp, [4] rr, [5] beta, [6] alpha, [7] restart
-        sc[5] = sc[7] != 0.0 ? 0.0 : sc[2] / sc[0];
-        sc[0] = sc[1];
-        sc[7] = 0.0;
-    }
-    if (threadIdx.x == 0 && post == RED_ALPHA) sc[6] = sc[1] / sc[3];
+}
+
+// long partial lists (fused kernels on large grids) are first summed to one
+int compress_partials(mgd_hier *h, const double *partial, int64_t cnt, int nvec, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, cnt, nvec, out);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
 }
 
 template <int D>
 static int outer_residual_t(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r,
-                            double *partial, hipStream_t st)
+                            double *partial, unsigned grid, hipStream_t st)
 {
-    dim3 gr(grid_for(h->NV[0], 256));
     if (h->precision == MGD_FP64)
-        hipLaunchKernelGGL((k_outer_residual<D, OpHalf<double>>), gr, dim3(256), 0, st,
+        hipLaunchKernelGGL((k_outer_residual<D, OpHalf<double>>), dim3(grid), dim3(256), 0, st,
                            OpHalf<double>{o.S64[0], h->NV[0]}, h->n, u, f, r, partial, (float *)nullptr);
     else
-        hipLaunchKernelGGL((k_outer_residual<D, OpComp64<D>>), gr, dim3(256), 0, st,
+        hipLaunchKernelGGL((k_outer_residual<D, OpComp64<D>>), dim3(grid), dim3(256), 0, st,
                            OpComp64<D>{store_view(h, o), h->n}, h->n, u, f, r, partial, (float *)h->f[0]);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
 
-// r = f - A u (finest operator as stored, FP64); if norm2_dev: ||r||^2 there
-int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, double *norm2_dev,
+// r = f - A u (finest operator as stored, FP64); with nparts: the partials of
+// ||r||^2 go to the pinned host array h->host_part (*nparts of them)
+int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, int *nparts,
                    hipStream_t st)
 {
+    double *partial = nparts ? h->host_part_dev : nullptr;
     if (h->dim == 2 && h->precision == MGD_MIXED) {
         StageArgs<double> sa;
         memset(&sa, 0, sizeof(sa));
@@ -793,26 +1005,19 @@ int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f
         sa.u = u;
         sa.f = f;
         sa.out = r;
-        sa.partial = h->partial;
+        sa.partial = partial ? partial : h->partial;
         sa.rf = (float *)h->f[0];
-        dim3 g2 = stage2_grid(h->n);
-        hipLaunchKernelGGL((k_stage2<double, ST_OUTER>), g2, dim3(256), 0, st, sa);
-        if (norm2_dev) {
-            int64_t nb = (int64_t)g2.x * g2.y;
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev, nullptr, 0);
-        }
+        stage2_tiles(h->n, sa.ntx, sa.nt);
+        const unsigned grid = (unsigned)std::min(sa.nt, kRedBlocks);
+        hipLaunchKernelGGL((k_stage2<double, ST_OUTER>), dim3(grid), dim3(256), 0, st, sa);
         HIPCHK(h->ctx, hipGetLastError());
+        if (nparts) *nparts = (int)grid;
         return MGD_OK;
     }
-    double *partial = norm2_dev ? h->partial : nullptr;
-    int rc = h->dim == 2 ? outer_residual_t<2>(h, o, u, f, r, partial, st) : outer_residual_t<3>(h, o, u, f, r, partial, st);
-    if (rc) return rc;
-    if (norm2_dev) {
-        int64_t nb = grid_for(h->NV[0], 256);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, norm2_dev, nullptr, 0);
-        HIPCHK(h->ctx, hipGetLastError());
-    }
-    return MGD_OK;
+    const unsigned grid = red_grid(h->NV[0]);
+    if (nparts) *nparts = (int)grid;
+    return h->dim == 2 ? outer_residual_t<2>(h, o, u, f, r, partial, grid, st)
+                       : outer_residual_t<3>(h, o, u, f, r, partial, grid, st);
 }
 
 // ------------------------------------------------------------ outer vectors
@@ -830,35 +1035,35 @@ template <typename T> __global__ void k_add(double *u, const T *e, int64_t n)
     if (i < n) u[i] += (double)e[i];
 }
 
-// partials of z.r and z.(r - r_old)
+// partials of z.r and z.(r - r_old): [blocks] then [blocks]
 template <typename T>
 __global__ __launch_bounds__(256) void k_dots_zr(const T *z, const double *r, const double *rold, int64_t n,
-                                                 double *partial, int64_t nb)
+                                                 double *partial)
 {
     __shared__ double red[256];
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double a = 0.0, b = 0.0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double zz = (double)z[i];
-        a = zz * r[i];
-        b = zz * (r[i] - rold[i]);
+        a += zz * r[i];
+        b += zz * (r[i] - rold[i]);
     }
     double sa = block_sum<256>(a, red), sb = block_sum<256>(b, red);
-    if (threadIdx.x == 0) { partial[blockIdx.x] = sa; partial[nb + blockIdx.x] = sb; }
+    if (threadIdx.x == 0) { partial[blockIdx.x] = sa; partial[gridDim.x + blockIdx.x] = sb; }
 }
 
-
 // p_new = z + beta p_old on every vertex; Ap = A p_new on the interior,
-// with partials of p_new . Ap
+// with partials of p_new . Ap; beta from the dot partials
 template <int D, class Op, typename TZ>
 __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, const double *pold, double *pnew,
-                                                  double *Ap, const double *s, double *partial)
+                                                  double *Ap, CgScalars c, double *partial)
 {
     __shared__ double red[256];
     Grid<D> g(n);
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double beta = s[5], prod = 0.0;
-    if (v < g.NV) {
+    const double zr = sum_partials(c.p1, c.n1, red), zdr = sum_partials(c.p1 + c.n1, c.n1, red);
+    const double beta = c.s[7] != 0.0 ? 0.0 : zdr / c.s[c.zr_old];
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[c.zr_new] = zr;
+    double prod = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
         int x[3] = {0, 0, 0};
         g.coords(v, x);
         double pv = (double)z[v] + beta * pold[v];
@@ -878,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, cons
             }
             double apv = -dsum * pv + acc;
             Ap[v] = apv;
-            prod = pv * apv;
+            prod += pv * apv;
         } else {
             Ap[v] = 0.0;
         }
@@ -887,30 +1092,29 @@ __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, cons
     if (threadIdx.x == 0) partial[blockIdx.x] = sum;
 }
 
-// x += alpha p; r_old = r; r -= alpha Ap; partials of r.r
+// x += alpha p; r_old = r; r -= alpha Ap (and its FP32 copy); partials of
+// r.r to pinned host memory; alpha = zr / p.Ap from the matvec's partials
 __global__ __launch_bounds__(256) void k_cg_update(double *x, const double *p, double *r, double *rold,
-                                                   const double *Ap, int64_t n, const double *s, double *partial,
-                                                   float *rf)
+                                                   const double *Ap, int64_t n, CgScalars c, const double *p2,
+                                                   int64_t n2, double *partial, float *rf)
 {
     __shared__ double red[256];
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double alpha = s[6], rr = 0.0;
-    if (i < n) {
+    const double pAp = sum_partials(p2, n2, red);
+    const double alpha = c.s[c.zr_new] / pAp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[7] = 0.0;  // restart consumed
+    double rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += alpha * p[i];
         double ri = r[i];
         rold[i] = ri;
         ri -= alpha * Ap[i];
         r[i] = ri;
         if (rf) rf[i] = (float)ri;
-        rr = ri * ri;
+        rr += ri * ri;
     }
     double sum = block_sum<256>(rr, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = sum;
 }
-
-struct PcgBufs {
-    double *r, *rold, *p0, *p1, *Ap;
-};
 
 // host helpers used by the solver
 int vec_cast_to_cycle(mgd_hier *h, const double *a, void *b, hipStream_t st)
@@ -931,72 +1135,58 @@ int vec_add_cycle(mgd_hier *h, double *u, const void *e, hipStream_t st)
     return MGD_OK;
 }
 
-// z.r, z.(r - r_old) -> s[1], s[2]; then beta
-int pcg_beta(mgd_hier *h, const void *z, const double *r, const double *rold, double *s, hipStream_t st)
+// partials of z.r and z.(r - r_old) into h->partial (h->p1_n each)
+int pcg_dots(mgd_hier *h, const void *z, const double *r, const double *rold, hipStream_t st)
 {
-    int64_t n = h->NV[0], nb = grid_for(n, 256);
-    double *part = h->partial;
-    if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_dots_zr<double>, dim3(nb), dim3(256), 0, st, (const double *)z, r, rold, n, part, nb);
-    else hipLaunchKernelGGL(k_dots_zr<float>, dim3(nb), dim3(256), 0, st, (const float *)z, r, rold, n, part, nb);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 2, nb, s + 1, s, (int)RED_BETA);
+    int64_t n = h->NV[0];
+    const unsigned grid = red_grid(n);
+    if (h->precision == MGD_FP64) hipLaunchKernelGGL(k_dots_zr<double>, dim3(grid), dim3(256), 0, st, (const double *)z, r, rold, n, h->partial);
+    else hipLaunchKernelGGL(k_dots_zr<float>, dim3(grid), dim3(256), 0, st, (const float *)z, r, rold, n, h->partial);
     HIPCHK(h->ctx, hipGetLastError());
+    h->p1 = h->partial;
+    h->p1_n = grid;
     return MGD_OK;
 }
 
 template <int D, typename TZ>
 static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *pold, double *pnew, double *Ap,
-                        double *s, hipStream_t st)
+                        const CgScalars &c, hipStream_t st)
 {
-    int64_t n = h->NV[0], nb = grid_for(n, 256);
-    double *part = h->partial;
+    const unsigned grid = red_grid(h->NV[0]);
     if (h->precision == MGD_FP64)
-        hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(nb), dim3(256), 0, st,
-                           OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, (const double *)s, part);
+        hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
+                           OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
     else
-        hipLaunchKernelGGL((k_p_matvec<D, OpComp64<D>, TZ>), dim3(nb), dim3(256), 0, st,
-                           OpComp64<D>{store_view(h, o), h->n}, h->n, z, pold, pnew, Ap, (const double *)s, part);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 3, s, (int)RED_ALPHA);
+        hipLaunchKernelGGL((k_p_matvec<D, OpComp64<D>, TZ>), dim3(grid), dim3(256), 0, st,
+                           OpComp64<D>{store_view(h, o), h->n}, h->n, z, pold, pnew, Ap, c, h->partial2);
     HIPCHK(h->ctx, hipGetLastError());
+    h->p2_n = grid;
     return MGD_OK;
 }
 
-int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap, double *s,
-               hipStream_t st)
+// p_new = z + beta p_old, Ap = A p_new, partials of p.Ap into h->partial2
+int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap,
+               const CgScalars &c, hipStream_t st)
 {
-    if (h->dim == 2 && h->precision == MGD_MIXED) {
-        StageArgs<double> sa;
-        memset(&sa, 0, sizeof(sa));
-        sa.sv = store_view(h, o);
-        sa.n = h->n;
-        sa.u = z;
-        sa.pold = pold;
-        sa.pnew = pnew;
-        sa.out = Ap;
-        sa.s = s;
-        sa.partial = h->partial;
-        dim3 g2 = stage2_grid(h->n);
-        int64_t nb = (int64_t)g2.x * g2.y;
-        hipLaunchKernelGGL((k_stage2<double, ST_PMATVEC>), g2, dim3(256), 0, st, sa);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nb, 1, nb, s + 3, s, (int)RED_ALPHA);
-        HIPCHK(h->ctx, hipGetLastError());
-        return MGD_OK;
-    }
+    if (h->dim == 2 && h->NV[0] * 4 < ((int64_t)1 << 31)) return lev2_pmv(h, o, z, pold, pnew, Ap, c, st);
     if (h->precision == MGD_FP64)
-        return h->dim == 2 ? pcg_matvec_t<2, double>(h, o, (const double *)z, pold, pnew, Ap, s, st)
-                           : pcg_matvec_t<3, double>(h, o, (const double *)z, pold, pnew, Ap, s, st);
-    return h->dim == 2 ? pcg_matvec_t<2, float>(h, o, (const float *)z, pold, pnew, Ap, s, st)
-                       : pcg_matvec_t<3, float>(h, o, (const float *)z, pold, pnew, Ap, s, st);
+        return h->dim == 2 ? pcg_matvec_t<2, double>(h, o, (const double *)z, pold, pnew, Ap, c, st)
+                           : pcg_matvec_t<3, double>(h, o, (const double *)z, pold, pnew, Ap, c, st);
+    return h->dim == 2 ? pcg_matvec_t<2, float>(h, o, (const float *)z, pold, pnew, Ap, c, st)
+                       : pcg_matvec_t<3, float>(h, o, (const float *)z, pold, pnew, Ap, c, st);
 }
 
-int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap, double *s,
-               hipStream_t st)
+// x += alpha p, r -= alpha Ap; the partials of r.r to the pinned host array
+int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap,
+               const CgScalars &c, int *nparts, hipStream_t st)
 {
-    int64_t n = h->NV[0], nb = grid_for(n, 256);
-    double *part = h->partial;
+    int64_t n = h->NV[0];
+    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(n, 256), kHostParts);
     float *rf = h->precision == MGD_MIXED ? (float *)h->f[0] : nullptr;
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, x, p, r, rold, Ap, n, (const double *)s, part, rf);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, (const double *)part, nb, 1, nb, s + 4, nullptr, 0);
+    hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(256), 0, st, x, p, r, rold, Ap, n, c, (const double *)h->partial2,
+                       h->p2_n, h->host_part_dev, rf);
     HIPCHK(h->ctx, hipGetLastError());
+    *nparts = (int)grid;
     return MGD_OK;
 }
 

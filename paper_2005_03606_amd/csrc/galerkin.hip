@@ -235,50 +235,24 @@ __global__ void k_cholesky(double *M, int64_t m)
     }
 }
 
-// u = A^{-1} f on the interior of the coarsest grid, FP64 triangular solves
-template <int D, typename T>
-__global__ void k_chol_solve(const double *L, int64_t m, int n, const T *f, T *u, double *work)
+// inverse of L L^T, one thread per column j: L y = e_j, then L^T x = y,
+// both in place in column j of Ainv (m <= kCinvMax)
+__global__ void k_chol_inverse(const double *L, int64_t m, double *Ainv)
 {
-    Grid<D> g(n);
-    __shared__ double red[256];
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
-        int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        if (g.interior(x)) work[interior_index<D>(x, n)] = (double)f[v];
+    const int64_t j = threadIdx.x;
+    if (j >= m) return;
+    for (int64_t i = 0; i < m; ++i) {
+        double s = i == j ? 1.0 : 0.0;
+        for (int64_t k = j; k < i; ++k) s -= L[i * m + k] * Ainv[k * m + j];
+        Ainv[i * m + j] = i < j ? 0.0 : s / L[i * m + i];
     }
-    __syncthreads();
-    for (int64_t i = 0; i < m; ++i) {  // L y = b
-        double s = 0.0;
-        for (int64_t k = threadIdx.x; k < i; k += blockDim.x) s += L[i * m + k] * work[k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) work[i] = (work[i] - red[0]) / L[i * m + i];
-        __syncthreads();
-    }
-    for (int64_t i = m - 1; i >= 0; --i) {  // L^T x = y
-        double s = 0.0;
-        for (int64_t k = i + 1 + threadIdx.x; k < m; k += blockDim.x) s += L[k * m + i] * work[k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) work[i] = (work[i] - red[0]) / L[i * m + i];
-        __syncthreads();
-    }
-    for (int64_t v = threadIdx.x; v < g.NV; v += blockDim.x) {
-        int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        u[v] = g.interior(x) ? (T)work[interior_index<D>(x, n)] : (T)0;
+    for (int64_t i = m - 1; i >= 0; --i) {
+        double s = Ainv[i * m + j];
+        for (int64_t k = i + 1; k < m; ++k) s -= L[k * m + i] * Ainv[k * m + j];
+        Ainv[i * m + j] = s / L[i * m + i];
     }
 }
 
-// ------------------------------------------------------------ host side
 int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st);
 
 template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *const *S, hipStream_t st)
@@ -298,6 +272,7 @@ template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *cons
     HalfRow<D, T> Ac{S[lc], h->NV[lc], (int64_t)h->nl[lc] + 1};
     hipLaunchKernelGGL((k_dense_assemble<D, T>), dim3(1), dim3(256), 0, st, Ac, h->nl[lc], h->m_coarse, o.chol);
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, st, o.chol, h->m_coarse);
+    if (o.cinv) hipLaunchKernelGGL(k_chol_inverse, dim3(1), dim3((unsigned)kCinvMax), 0, st, o.chol, h->m_coarse, o.cinv);
     HIPCHK(ctx, hipGetLastError());
     return MGD_OK;
 }
@@ -309,21 +284,6 @@ int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st)
     int rc = decode_store_f32(h, o, st);
     if (rc) return rc;
     return h->dim == 2 ? coarsen_t<2, float>(h, o, o.S32, st) : coarsen_t<3, float>(h, o, o.S32, st);
-}
-
-int cycle_coarse_solve(mgd_hier *h, const OpSet &o, void *u, const void *f, hipStream_t st)
-{
-    int lc = h->nlev - 1;
-    double *work = h->partial;  // m_coarse <= partial_cap (checked at creation)
-    if (h->precision == MGD_FP64) {
-        if (h->dim == 2) hipLaunchKernelGGL((k_chol_solve<2, double>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const double *)f, (double *)u, work);
-        else hipLaunchKernelGGL((k_chol_solve<3, double>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const double *)f, (double *)u, work);
-    } else {
-        if (h->dim == 2) hipLaunchKernelGGL((k_chol_solve<2, float>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const float *)f, (float *)u, work);
-        else hipLaunchKernelGGL((k_chol_solve<3, float>), dim3(1), dim3(256), 0, st, o.chol, h->m_coarse, h->nl[lc], (const float *)f, (float *)u, work);
-    }
-    HIPCHK(h->ctx, hipGetLastError());
-    return MGD_OK;
 }
 
 template <typename TI> __global__ void k_w_to_f64(const TI *in, int64_t cnt, double *out)

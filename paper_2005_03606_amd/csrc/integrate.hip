@@ -199,6 +199,13 @@ __device__ inline int64_t asm_count(const AsmArgs &a) { return a.count_dev ? *a.
 
 template <int D> __device__ inline void cell_coords(int64_t c, int n, int *ci)
 {
+    if (c <= 0xffffffffLL) {  // 32-bit division (the 64-bit one is a long software sequence)
+        const uint32_t cc = (uint32_t)c, m = (uint32_t)n, t = cc / m;
+        ci[0] = (int)(cc - t * m);
+        if (D == 2) ci[1] = (int)t;
+        else { const uint32_t t2 = t / m; ci[1] = (int)(t - t2 * m); ci[2] = (int)t2; }
+        return;
+    }
     ci[0] = (int)(c % n);
     int64_t t = c / n;
     if (D == 2) ci[1] = (int)t;

@@ -38,7 +38,7 @@ struct SolveState {
     double *u = nullptr;
     mgd_report *rep = nullptr;
     OpSet *sets[2] = {nullptr, nullptr};
-    int cur = 0, published = 0, built = 0, publishes = 0, ncyc = 0, k = 0, status = 0, publish_mode = 0;
+    int cur = 0, published = 0, built = 0, publishes = 0, ncyc = 0, k = 0, status = 0, publish_mode = 0, nparts = 0;
     bool lazy = false, pcg = false, ladder_done = false, restart = true, done = false;
     double r0 = 0, rk = 0, r_ref = 0, t0 = 0, t_first = 0, t_loop0 = 0;
 };

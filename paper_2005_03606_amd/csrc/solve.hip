@@ -15,11 +15,6 @@
 int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
 int vec_cast_to_cycle(mgd_hier *h, const double *a, void *b, hipStream_t st);
 int vec_add_cycle(mgd_hier *h, double *u, const void *e, hipStream_t st);
-int pcg_beta(mgd_hier *h, const void *z, const double *r, const double *rold, double *s, hipStream_t st);
-int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap, double *s,
-               hipStream_t st);
-int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap, double *s,
-               hipStream_t st);
 int vec_fill_f64(mgd_ctx *ctx, double *a, int64_t n, double v, hipStream_t st);
 
 static double now_ms()
@@ -216,18 +211,19 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
 }
 
 // enqueue the residual measurement of the next check (outer residual after
-// an operator change or for the stationary iteration; else the CG recursion's)
-static int enqueue_check(SolveState *S)
+// an operator change or for the stationary iteration, else the CG
+// recursion's, whose partials the update kernel already left in pinned host
+// memory); the host adds the partials when the event has completed
+static int enqueue_check(SolveState *S, int nparts)
 {
     mgd_ctx *ctx = S->ctx;
     mgd_hier &H = S->H;
-    double *s = H.scal;
     int rc;
-    if (S->restart || !S->pcg) {
-        if ((rc = outer_residual(&H, *S->sets[S->cur], S->u, S->f, S->r, s + 4, S->stream))) return rc;
-        if (S->pcg && (rc = vec_fill_f64(ctx, s + 7, 1, 1.0, S->stream))) return rc;
+    if (S->restart || !S->pcg || nparts == 0) {
+        if ((rc = outer_residual(&H, *S->sets[S->cur], S->u, S->f, S->r, &nparts, S->stream))) return rc;
+        if (S->pcg && S->restart && (rc = vec_fill_f64(ctx, H.scal + 7, 1, 1.0, S->stream))) return rc;
     }
-    HIPCHK(ctx, hipMemcpyAsync(H.host_scal, s + 4, 8, hipMemcpyDeviceToHost, S->stream));
+    S->nparts = nparts;
     HIPCHK(ctx, hipEventRecord(S->ev_norm, S->stream));
     return MGD_OK;
 }
@@ -368,7 +364,7 @@ int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, c
             if (L.R >= 2 && (rc = rung(L, 2, S->s_asm))) return rc;
         }
     }
-    return enqueue_check(S);
+    return enqueue_check(S, 0);
 }
 
 static void finish(SolveState *S)
@@ -435,7 +431,9 @@ int solve_step(SolveState *S, bool blocking)
     }
     mgd_hier &H = S->H;
     const mgd_solve_opts &op = S->op;
-    S->rk = sqrt(H.host_scal[0]);
+    double rr = 0.0;
+    for (int i = 0; i < S->nparts; ++i) rr += H.host_part[i];
+    S->rk = sqrt(rr);
     if (S->k == 0) {
         S->r0 = S->rk;
         S->t_first = now_ms() - S->t0;
@@ -461,7 +459,7 @@ int solve_step(SolveState *S, bool blocking)
         if (S->publish_mode != MGD_PUBLISH_DETERMINISTIC) {
             if ((rc = boundary_publish(S, true))) return rc;
             S->k++;
-            if ((rc = enqueue_check(S))) return rc;
+            if ((rc = enqueue_check(S, 0))) return rc;
             return 0;
         }
     }
@@ -476,14 +474,20 @@ int solve_step(SolveState *S, bool blocking)
     // rhs of the correction cycle: the FP64 residual itself, or the FP32 copy
     // that the kernels producing r write beside it
     const void *rhs = H.precision == MGD_FP64 ? (const void *)S->r : (const void *)H.f[0];
-    if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st))) return rc;
+    void *z = nullptr;
+    bool dots_done = false;
+    int nparts = 0;
+    Lev2Dots dots{S->r, S->rold, H.scal};
+    if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st, S->pcg ? &dots : nullptr, &z,
+                         &dots_done)))
+        return rc;
     if (!S->pcg) {
-        if ((rc = vec_add_cycle(&H, S->u, H.u[0], st))) return rc;
+        if ((rc = vec_add_cycle(&H, S->u, z, st))) return rc;
     } else {
-        double *s = H.scal;
-        if ((rc = pcg_beta(&H, H.u[0], S->r, S->rold, s, st))) return rc;
-        if ((rc = pcg_matvec(&H, O, H.u[0], S->p[0], S->p[1], S->Ap, s, st))) return rc;
-        if ((rc = pcg_update(&H, S->u, S->p[1], S->r, S->rold, S->Ap, s, st))) return rc;
+        if (!dots_done && (rc = pcg_dots(&H, z, S->r, S->rold, st))) return rc;
+        CgScalars c{H.scal, H.p1, H.p1_n, 8 + (S->ncyc & 1), 8 + ((S->ncyc + 1) & 1)};
+        if ((rc = pcg_matvec(&H, O, z, S->p[0], S->p[1], S->Ap, c, st))) return rc;
+        if ((rc = pcg_update(&H, S->u, S->p[1], S->r, S->rold, S->Ap, c, &nparts, st))) return rc;
         double *t = S->p[0];
         S->p[0] = S->p[1];
         S->p[1] = t;
@@ -492,7 +496,7 @@ int solve_step(SolveState *S, bool blocking)
     S->restart = false;
     if ((rc = boundary_publish(S, false))) return rc;
     S->k++;
-    if ((rc = enqueue_check(S))) return rc;
+    if ((rc = enqueue_check(S, nparts))) return rc;
     return 0;
 }
 
@@ -557,10 +561,11 @@ size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest
         ops += (size_t)ntile * 5 + (size_t)ntile * (64 + 256 * H) + (size_t)ncell * 4 + 64;
     }
     ops += (size_t)(m > 0 ? m * m : 1) * 8;
+    if (m <= kCinvMax) ops += (size_t)(m > 0 ? m * m : 1) * 8;
     size_t hier = ops + vec + (precision == MGD_MIXED ? (size_t)NV0 * H * 4 + NV0 : 0);
     int64_t nb = (NV0 + 255) / 256 + (n + 1) / 4 + 64;
     int64_t pcap = 2 * nb > m + 64 ? 2 * nb : m + 64;
-    hier += (size_t)pcap * 8 + 64 * 8;
+    hier += 2 * (size_t)pcap * 8 + 64 * 8;  // two partial lists, device scalars
     size_t ladder = (size_t)ncell * U * vb + (size_t)ncell * 4 + (precision == MGD_MIXED ? (size_t)NV0 * H * 4 : 0) +
                     2 * (size_t)ncell * 8 + 16 + (size_t)ncell + ((size_t)(ncell + 255) / 256 + 1) * 4;
     size_t cg = 5 * (size_t)NV0 * 8;

@@ -327,6 +327,7 @@ int opset_alloc(mgd_hier *h, OpSet &o)
     }
     int64_t m = h->m_coarse;
     if ((rc = dev_alloc(ctx, (void **)&o.chol, (size_t)(m > 0 ? m * m : 1) * 8))) return rc;
+    if (m <= kCinvMax && (rc = dev_alloc(ctx, (void **)&o.cinv, (size_t)(m > 0 ? m * m : 1) * 8))) return rc;
     return MGD_OK;
 }
 
@@ -337,6 +338,6 @@ void opset_free(OpSet &o)
         o.S64[l] = nullptr; o.S32[l] = nullptr; o.W[l] = nullptr;
     }
     dev_free(o.tier); dev_free(o.toff); dev_free(o.payload); dev_free(o.eps_c);
-    dev_free(o.units_total); dev_free(o.chol);
+    dev_free(o.units_total); dev_free(o.chol); dev_free(o.cinv);
     o = OpSet();
 }

@@ -286,6 +286,144 @@ def test_vcycles_fp64_match_oracle(ctx, transfer, d, n):
         assert rel_err(host(ut), u_ref) < 1e-11
 
 
+# fused 2D level kernels: grids above the single-workgroup tail, ragged tiles
+@pytest.mark.parametrize("zero", [True, False])
+@pytest.mark.parametrize("d,n", [(2, 6), (2, 40), (2, 70), (2, 136), (3, 8)])
+def test_presmooth_fp64_matches_oracle_pieces(ctx, d, n, zero):
+    S = _fine_stencils(d, n)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=P.BOXMG)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    rng = np.random.default_rng(11)
+    inner = W.interior_mask(d, n)
+    u = np.zeros(inner.size) if zero else rng.standard_normal(inner.size) * inner
+    f = rng.standard_normal(inner.size) * inner
+    uo = torch.full((inner.size,), 7.0, dtype=torch.float64, device="cuda")
+    ro = torch.full_like(uo, 7.0)
+    h.presmooth(0, None if zero else dev(u), dev(f), uo, ro, omega=0.6)
+    u2 = O.jacobi(d, n, S, O.jacobi(d, n, S, u, f, 0.6), f, 0.6)
+    assert rel_err(host(uo), u2) < 1e-12
+    assert rel_err(host(ro), O.residual(d, n, S, u2, f)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [40, 136, 256])
+def test_presmooth_mixed_matches_separate_sweeps(ctx, n):
+    """Compressed finest level and FP32 coarse levels: the fused pass equals
+    two sweeps plus a residual of the separate kernels up to FP32 rounding."""
+    d = 2
+    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    K, _, _ = P.assemble_cells(ctx, d, n, 4, P.Eps(fld), P.MIXED)
+    S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    h.compress(S32, P.centre_samples(ctx, d, n, P.Eps(fld)), 1, 3, 0.0, 1e-4)
+    h.coarsen()
+    rng = np.random.default_rng(12)
+    for level in range(min(h.nlev, 3)):
+        nl = h.level_n(level)
+        inner = W.interior_mask(d, nl)
+        f = dev(rng.standard_normal(inner.size) * inner, torch.float32)
+        u = dev(rng.standard_normal(inner.size) * inner, torch.float32)
+        for start in (None, u):
+            uo = torch.zeros_like(f)
+            ro = torch.zeros_like(f)
+            h.presmooth(level, start, f, uo, ro)
+            ref = torch.zeros_like(f) if start is None else start.clone()
+            for _ in range(2):
+                h.smooth(level, ref, f, sweeps=1)
+            rr = torch.zeros_like(f)
+            h.residual(level, ref, f, rr)
+            assert rel_err(host(uo).astype(np.float64), host(ref).astype(np.float64)) < 1e-5, level
+            assert rel_err(host(ro).astype(np.float64), host(rr).astype(np.float64)) < 1e-4, level
+
+
+@pytest.mark.parametrize("d,n", [(2, 52), (2, 22), (3, 10), (3, 12)])
+def test_vcycles_fp64_coarse_solves_match_oracle(ctx, d, n):
+    """Coarsest grids solved by the dense inverse (up to 128 unknowns: 2D
+    n=22 -> 11, 3D 10 -> 5, 12 -> 3) and by Cholesky substitution (2D
+    52 -> 13: 144 unknowns)."""
+    S = _fine_stencils(d, n)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=P.BOXMG)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    ref = O.Hierarchy(d, n, S, coarsest=2, transfer=1)
+    f = W.load_sine(d, n)
+    u_ref = np.zeros_like(f)
+    ut = dev(u_ref)
+    ft = dev(f)
+    for _ in range(3):
+        h.vcycle(ut, ft, 0.6, 2, 2)
+        u_ref = ref.vcycle(u_ref, f, 0.6, 2, 2)
+        assert rel_err(host(ut), u_ref) < 1e-11
+
+
+@pytest.mark.parametrize("transfer", [0, 1])
+@pytest.mark.parametrize("n", [128, 256])
+def test_vcycles_fp64_fused_levels_match_oracle(ctx, transfer, n):
+    d = 2
+    S = _fine_stencils(d, n, s=2)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=transfer)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    ref = O.Hierarchy(d, n, S, coarsest=2, transfer=transfer)
+    f = W.load_sine(d, n)
+    u_ref = np.zeros_like(f)
+    ut = dev(u_ref)
+    ft = dev(f)
+    for _ in range(3):
+        h.vcycle(ut, ft, 0.6, 2, 2)
+        u_ref = ref.vcycle(u_ref, f, 0.6, 2, 2)
+        assert rel_err(host(ut), u_ref) < 1e-11
+
+
+def test_solve_fp64_pcg_fused_levels_matches_oracle(ctx):
+    """PCG outer iteration whose V-cycle runs the fused finest-level kernels
+    (dot products formed inside the post-smoothing pass)."""
+    d, n = 2, 256
+    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_fixed=2, tol=1e-10)
+    u_ref, rr = O.solve(fld, d, n, f, transfer=O.BOXMG, outer=O.PCG, **kw)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), transfer=P.BOXMG, outer=P.PCG, **kw)
+    assert rep["status"] == 0 and rr["status"] == 0
+    assert rep["cycles"] == rr["cycles"]
+    np.testing.assert_allclose(rep["hist"], rr["hist"], rtol=1e-7, atol=1e-13)
+    assert rel_err(host(u), u_ref) < 1e-9
+
+
+def _vcycle_rate(h, f, dtype):
+    ft = dev(f, dtype)
+    u = torch.zeros_like(ft)
+    r = torch.zeros_like(u)
+    norms = []
+    for _ in range(6):
+        h.vcycle(u, ft)
+        h.residual(0, u, ft, r)
+        norms.append(float(torch.linalg.norm(r.double())))
+    return (norms[-1] / norms[0]) ** (1.0 / 5)
+
+
+def test_mixed_vcycle_contracts_fused(ctx):
+    """Fused finest and middle levels in the mixed form (compressed store,
+    FP32 cycle): per-cycle contraction as a stationary iteration within 0.02
+    of the FP64 cycle on the oracle's stencils of the same material."""
+    d, n = 2, 256
+    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    f = W.load_sine(d, n)
+    S = O.stencils(d, n, O.assemble(fld, d, n, 8))
+    h64 = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=P.BOXMG)
+    h64.set_fine(dev(O.to_half(d, S)))
+    h64.coarsen()
+    rate64 = _vcycle_rate(h64, f, torch.float64)
+    K, _, _ = P.assemble_cells(ctx, d, n, 8, P.Eps(fld), P.MIXED)
+    S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    h.compress(S32, P.centre_samples(ctx, d, n, P.Eps(fld)), 2, 2, 0.0, 1e-7)
+    h.coarsen()
+    rate32 = _vcycle_rate(h, f, torch.float32)
+    assert rate64 < 1.0
+    assert rate32 <= rate64 + 0.02, (rate32, rate64)
+
+
 def test_mixed_vcycle_contracts(ctx):
     """FP32 cycle on the compressed store: a preconditioner for the FP64
     outer residual; its contraction must be close to the FP64 cycle's."""
