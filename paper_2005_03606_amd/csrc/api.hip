@@ -58,9 +58,14 @@ int hier_alloc_levels(mgd_hier *h)
     if ((rc = dev_alloc(ctx, (void **)&h->partial2, (size_t)h->partial_cap * 8))) return rc;
     if (hipHostMalloc((void **)&h->host_scal, 64 * 8, hipHostMallocDefault) != hipSuccess)
         return mgd_fail(ctx, MGD_ENOMEM, "pinned allocation failed");
-    if (hipHostMalloc((void **)&h->host_part, kHostParts * 8, hipHostMallocDefault) != hipSuccess)
+    // coherent: kernel stores bypass the GPU caches on their way to the host
+    if (hipHostMalloc((void **)&h->host_part, kHostParts * 8, hipHostMallocCoherent) != hipSuccess)
         return mgd_fail(ctx, MGD_ENOMEM, "pinned allocation failed");
+    for (int i = 0; i < kHostParts; ++i) h->host_part[i] = 0.0;
     HIPCHK(ctx, hipHostGetDevicePointer((void **)&h->host_part_dev, h->host_part, 0));
+    // the clears above run on the null stream, which work on the caller's
+    // non-blocking streams does not wait for: finish them before returning
+    HIPCHK(ctx, hipDeviceSynchronize());
     return MGD_OK;
 }
 

@@ -487,8 +487,8 @@ constexpr int kTailThreads = 1024;
 struct TailLevel {
     const void *S, *W;
     int n, NV;
-    int off;         // element offset of this level's vectors in LDS: u | f | t
-    int s_off, w_off;  // element offsets of its stencils / weights copied into LDS, or -1
+    int off;    // element offset of this level's vectors in LDS: u | f | t
+    float rnv;  // 1 / (n + 1)
 };
 struct TailArgs {
     int first, last, nu1, nu2, zero_guess, m, work_off;
@@ -499,102 +499,94 @@ struct TailArgs {
     TailLevel L[MGD_MAXLEV];
 };
 
-// vertices handled per thread and phase with their loads in flight together
-template <int D> constexpr int tail_chunk() { return D == 2 ? 5 : 1; }
-
-template <int D, typename T>
-__device__ void tail_sweep(const TailLevel &lv, const T *S, const T *uin, T *uout, const T *f, bool zero, T omega)
+// vertex coordinates by a float reciprocal (exact for the tail's sizes:
+// v < 2^13, so the quotient's error is far below the 1/(2 nv) margin)
+template <int D> __device__ inline void tail_coords(int v, const TailLevel &lv, int *x)
 {
-    constexpr int H = n_half(D), CK = tail_chunk<D>();
-    const Grid<D> g(lv.n);
-    const int64_t NV = lv.NV, safe = D == 2 ? 1 + g.nv : 1 + g.nv + g.nv * g.nv;  // an interior vertex
-    for (int v0 = threadIdx.x; v0 < lv.NV; v0 += CK * kTailThreads) {
-        T c[CK][2 * H];
-        bool in[CK];
-#pragma unroll
-        for (int q = 0; q < CK; ++q) {
-            const int v = v0 + q * kTailThreads;
-            int x[3] = {0, 0, 0};
-            g.coords(v < lv.NV ? v : 0, x);
-            in[q] = v < lv.NV && g.interior(x);
-            const int64_t vs = in[q] ? v : safe;
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                c[q][j] = S[(int64_t)j * NV + vs];
-                c[q][H + j] = S[(int64_t)j * NV + vs - half_lin(D, j, g.nv)];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < CK; ++q) {
-            const int v = v0 + q * kTailThreads;
-            if (v >= lv.NV) continue;
-            if (!in[q]) {
-                uout[v] = (T)0;
-                continue;
-            }
-            T acc = (T)0, dsum = (T)0;
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const int64_t lin = half_lin(D, j, g.nv);
-                if (!zero) acc += c[q][j] * uin[v + lin] + c[q][H + j] * uin[v - lin];
-                dsum += c[q][j] + c[q][H + j];
-            }
-            const T Dv = -dsum;
-            uout[v] = zero ? omega * f[v] / Dv : uin[v] + omega * (f[v] - (Dv * uin[v] + acc)) / Dv;
-        }
+    const int nv = lv.n + 1;
+    const int q = (int)(((float)v + 0.5f) * lv.rnv);
+    x[0] = v - q * nv;
+    if (D == 2) {
+        x[1] = q;
+    } else {
+        const int q2 = (int)(((float)q + 0.5f) * lv.rnv);
+        x[1] = q - q2 * nv;
+        x[2] = q2;
     }
-    __syncthreads();
+}
+template <int D> __device__ inline bool tail_interior(const int *x, int n)
+{
+    for (int m = 0; m < D; ++m)
+        if (x[m] == 0 || x[m] == n) return false;
+    return true;
 }
 
-template <int D, typename T>
-__device__ void tail_residual(const TailLevel &lv, const T *S, const T *u, const T *f, T *r)
+// one stencil pass: MODE 0 damped Jacobi sweep uout = u + omega D^-1 (f - A u)
+// (ZERO: from u = 0), MODE 1 residual uout = f - A u.  CK vertices per
+// thread have their stencil loads in flight together.
+template <int D, typename T, int CK, int MODE>
+__device__ void tail_pass(const TailLevel &lv, const T *uin, T *uout, const T *f, bool zero, T omega)
 {
-    constexpr int H = n_half(D), CK = tail_chunk<D>();
-    const Grid<D> g(lv.n);
-    const int64_t NV = lv.NV, safe = D == 2 ? 1 + g.nv : 1 + g.nv + g.nv * g.nv;
-    for (int v0 = threadIdx.x; v0 < lv.NV; v0 += CK * kTailThreads) {
+    constexpr int H = n_half(D);
+    const T *S = (const T *)lv.S;
+    const int nv = lv.n + 1, NV = lv.NV;
+    const int safe = D == 2 ? 1 + nv : 1 + nv + nv * nv;  // an interior vertex
+    int lin[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) lin[j] = half_off(D, j, 0) + half_off(D, j, 1) * nv + (D == 3 ? half_off(D, j, 2) * nv * nv : 0);
+    for (int v0 = threadIdx.x; v0 < NV; v0 += CK * kTailThreads) {
         T c[CK][2 * H];
         bool in[CK];
 #pragma unroll
         for (int q = 0; q < CK; ++q) {
             const int v = v0 + q * kTailThreads;
             int x[3] = {0, 0, 0};
-            g.coords(v < lv.NV ? v : 0, x);
-            in[q] = v < lv.NV && g.interior(x);
-            const int64_t vs = in[q] ? v : safe;
+            tail_coords<D>(v < NV ? v : 0, lv, x);
+            in[q] = v < NV && tail_interior<D>(x, lv.n);
+            const uint32_t vs = (uint32_t)(in[q] ? v : safe);
 #pragma unroll
             for (int j = 0; j < H; ++j) {
-                c[q][j] = S[(int64_t)j * NV + vs];
-                c[q][H + j] = S[(int64_t)j * NV + vs - half_lin(D, j, g.nv)];
+                c[q][j] = S[(uint32_t)j * (uint32_t)NV + vs];
+                c[q][H + j] = S[(uint32_t)j * (uint32_t)NV + vs - (uint32_t)lin[j]];
             }
         }
 #pragma unroll
         for (int q = 0; q < CK; ++q) {
             const int v = v0 + q * kTailThreads;
-            if (v >= lv.NV) continue;
-            T rv = (T)0;
+            if (v >= NV) continue;
+            T out = (T)0;
             if (in[q]) {
                 T acc = (T)0, dsum = (T)0;
 #pragma unroll
                 for (int j = 0; j < H; ++j) {
-                    const int64_t lin = half_lin(D, j, g.nv);
-                    acc += c[q][j] * u[v + lin] + c[q][H + j] * u[v - lin];
+                    if (MODE == 1 || !zero) acc += c[q][j] * uin[v + lin[j]] + c[q][H + j] * uin[v - lin[j]];
                     dsum += c[q][j] + c[q][H + j];
                 }
-                rv = f[v] - (-dsum * u[v] + acc);
+                const T Dv = -dsum;
+                if (MODE == 1) out = f[v] - (Dv * uin[v] + acc);
+                else out = zero ? omega * f[v] / Dv : uin[v] + omega * (f[v] - (Dv * uin[v] + acc)) / Dv;
             }
-            r[v] = rv;
+            uout[v] = out;
         }
     }
     __syncthreads();
 }
 
+template <int D, typename T, int MODE>
+__device__ inline void tail_pass_any(const TailLevel &lv, const T *uin, T *uout, const T *f, bool zero, T omega)
+{
+    // several vertices per thread in flight where registers allow (2D), else one
+    constexpr int CK = D == 3 ? 1 : sizeof(T) == 8 ? 3 : 5;
+    if (CK > 1 && lv.NV > kTailThreads) tail_pass<D, T, CK, MODE>(lv, uin, uout, f, zero, omega);
+    else tail_pass<D, T, 1, MODE>(lv, uin, uout, f, zero, omega);
+}
+
 template <int D, typename T>
-__device__ void tail_smooth(const TailLevel &lv, const T *S, T *u, const T *f, T *t, int sweeps, bool zero, T omega)
+__device__ void tail_smooth(const TailLevel &lv, T *u, const T *f, T *t, int sweeps, bool zero, T omega)
 {
     for (int k = 0; k < sweeps; ++k) {
-        if (k % 2 == 0) tail_sweep<D, T>(lv, S, u, t, f, zero && k == 0, omega);
-        else tail_sweep<D, T>(lv, S, t, u, f, false, omega);
+        if (k % 2 == 0) tail_pass_any<D, T, 0>(lv, u, t, f, zero && k == 0, omega);
+        else tail_pass_any<D, T, 0>(lv, t, u, f, false, omega);
     }
     if (sweeps % 2 == 1) {
         for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = t[v];
@@ -608,35 +600,41 @@ __device__ void tail_smooth(const TailLevel &lv, const T *S, T *u, const T *f, T
 
 // fc = P^T r on the interior coarse vertices, uc = 0
 template <int D, typename T>
-__device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T *W, const T *r, T *fc, T *uc)
+__device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T *r, T *fc, T *uc)
 {
     constexpr int ns = D == 2 ? 9 : 27;
-    const Grid<D> g(lv.n), gc(lc.n);
+    const T *W = (const T *)lv.W;
+    const int nv = lv.n + 1, NV = lv.NV;
     for (int V = threadIdx.x; V < lc.NV; V += kTailThreads) {
         int X[3] = {0, 0, 0};
-        gc.coords(V, X);
+        tail_coords<D>(V, lc, X);
         uc[V] = (T)0;
-        if (!gc.interior(X)) {
+        if (!tail_interior<D>(X, lc.n)) {
             fc[V] = (T)0;
             continue;
         }
         T w[ns];
-        int64_t vv[ns];
+        int vv[ns];
 #pragma unroll
         for (int sv = 0; sv < ns; ++sv) {
-            int x[3] = {0, 0, 0}, t = sv, B = 0;
+            int t = sv, B = 0, v = 0, st = 1;
+            bool geo_full = true;
             for (int m = 0; m < D; ++m) {
                 const int o = t % 3 - 1;
                 t /= 3;
-                x[m] = 2 * X[m] + o;
+                v += (2 * X[m] + o) * st;
+                st *= nv;
                 B |= (o < 0 ? 1 : 0) << m;  // X - (x >> 1) is 1 exactly when o = -1
+                if (o != 0) geo_full = false;
             }
-            vv[sv] = g.vid(x);
+            vv[sv] = v;
             if (W) {
-                w[sv] = W[(int64_t)B * lv.NV + vv[sv]];
+                w[sv] = W[(uint32_t)B * (uint32_t)NV + (uint32_t)v];
             } else {
                 double p = 1.0;
-                for (int m = 0; m < D; ++m) p *= x[m] == 2 * X[m] ? 1.0 : 0.5;
+                int tt = sv;
+                for (int m = 0; m < D; ++m) { p *= (tt % 3 == 1) ? 1.0 : 0.5; tt /= 3; }
+                (void)geo_full;
                 w[sv] = (T)p;
             }
         }
@@ -650,29 +648,31 @@ __device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T 
 
 // u += P ec on the interior fine vertices
 template <int D, typename T>
-__device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, const T *W, T *u, const T *ec)
+__device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, T *u, const T *ec)
 {
     constexpr int nl = 1 << D;
-    const Grid<D> g(lv.n), gc(lc.n);
+    const T *W = (const T *)lv.W;
+    const int ncv = lc.n + 1;
     for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) {
         int x[3] = {0, 0, 0};
-        g.coords(v, x);
-        if (!g.interior(x)) continue;
+        tail_coords<D>(v, lv, x);
+        if (!tail_interior<D>(x, lv.n)) continue;
         T w[nl];
-        int64_t ic[nl];
+        int ic[nl];
 #pragma unroll
         for (int B = 0; B < nl; ++B) {
             bool use = true;
-            int X[3] = {0, 0, 0};
+            int c = 0, st = 1;
             double p = 1.0;
             for (int m = 0; m < D; ++m) {
                 const int b = (B >> m) & 1;
                 if (b && !(x[m] & 1)) use = false;  // only odd axes reach the upper corner
-                X[m] = (x[m] >> 1) + b;
+                c += ((x[m] >> 1) + b) * st;
+                st *= ncv;
                 p *= (x[m] & 1) ? 0.5 : 1.0;
             }
-            ic[B] = use ? gc.vid(X) : 0;
-            w[B] = use ? (W ? W[(int64_t)B * lv.NV + v] : (T)p) : (T)0;
+            ic[B] = use ? c : 0;
+            w[B] = use ? (W ? W[(uint32_t)B * (uint32_t)lv.NV + (uint32_t)v] : (T)p) : (T)0;
         }
         T s = (T)0;
 #pragma unroll
@@ -687,12 +687,11 @@ __device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, const T *
 template <int D, typename T>
 __device__ void tail_coarse(const TailArgs &a, const TailLevel &lv, T *u, const T *f, double *work)
 {
-    const Grid<D> g(lv.n);
-    const int m = a.m, nin = lv.n - 1;
+    const int m = a.m, nin = lv.n - 1, nv = lv.n + 1;
     auto vof = [&](int k) {  // interior index -> vertex
-        int x[3] = {0, 0, 0}, t = k;
-        for (int mm = 0; mm < D; ++mm) { x[mm] = 1 + t % nin; t /= nin; }
-        return g.vid(x);
+        int v = 0, st = 1, t = k;
+        for (int mm = 0; mm < D; ++mm) { v += (1 + t % nin) * st; t /= nin; st *= nv; }
+        return v;
     };
     for (int k = threadIdx.x; k < m; k += kTailThreads) work[k] = (double)f[vof(k)];
     for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = (T)0;
@@ -736,34 +735,7 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
     auto U = [&](int l) { return base + a.L[l].off; };
     auto F = [&](int l) { return base + a.L[l].off + a.L[l].NV; };
     auto Tt = [&](int l) { return base + a.L[l].off + 2 * a.L[l].NV; };
-    // stencils and weights: the LDS copy where one was made
-    auto Sp = [&](int l) { return a.L[l].s_off >= 0 ? (const T *)(base + a.L[l].s_off) : (const T *)a.L[l].S; };
-    auto Wp = [&](int l) {
-        return a.L[l].W == nullptr ? (const T *)nullptr
-                                   : a.L[l].w_off >= 0 ? (const T *)(base + a.L[l].w_off) : (const T *)a.L[l].W;
-    };
     {
-        // copies into LDS, four loads in flight per thread
-        auto copy = [&](T *dst, const T *src, int cnt) {
-            for (int i0 = threadIdx.x; i0 < cnt; i0 += 4 * kTailThreads) {
-                T r[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = i0 + q * kTailThreads;
-                    r[q] = src[i < cnt ? i : 0];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = i0 + q * kTailThreads;
-                    if (i < cnt) dst[i] = r[q];
-                }
-            }
-        };
-        for (int l = a.first; l <= a.last; ++l) {
-            const TailLevel &L = a.L[l];
-            if (L.s_off >= 0) copy(base + L.s_off, (const T *)L.S, n_half(D) * L.NV);
-            if (L.w_off >= 0) copy(base + L.w_off, (const T *)L.W, (1 << D) * L.NV);
-        }
         const TailLevel &l0 = a.L[a.first];
         const T *fg = (const T *)a.f, *ug = (const T *)a.u;
         T *u0 = U(a.first), *f0 = F(a.first);
@@ -775,14 +747,14 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
     }
     for (int l = a.first; l < a.last; ++l) {
         const bool zero = l > a.first || a.zero_guess;
-        tail_smooth<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l), a.nu1, zero, omega);
-        tail_residual<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l));
-        tail_restrict<D, T>(a.L[l], a.L[l + 1], Wp(l), Tt(l), F(l + 1), U(l + 1));
+        tail_smooth<D, T>(a.L[l], U(l), F(l), Tt(l), a.nu1, zero, omega);
+        tail_pass_any<D, T, 1>(a.L[l], U(l), Tt(l), F(l), false, omega);
+        tail_restrict<D, T>(a.L[l], a.L[l + 1], Tt(l), F(l + 1), U(l + 1));
     }
     tail_coarse<D, T>(a, a.L[a.last], U(a.last), F(a.last), work);
     for (int l = a.last - 1; l >= a.first; --l) {
-        tail_prolong<D, T>(a.L[l], a.L[l + 1], Wp(l), U(l), U(l + 1));
-        tail_smooth<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l), a.nu2, false, omega);
+        tail_prolong<D, T>(a.L[l], a.L[l + 1], U(l), U(l + 1));
+        tail_smooth<D, T>(a.L[l], U(l), F(l), Tt(l), a.nu2, false, omega);
     }
     {
         T *ug = (T *)a.u;
@@ -838,27 +810,15 @@ static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const vo
         L.n = h->nl[l];
         L.NV = (int)h->NV[l];
         L.off = (int)off;
-        L.s_off = L.w_off = -1;
+        L.rnv = 1.0f / (float)(h->nl[l] + 1);
+        if ((int64_t)(h->nl[l] + 1) * h->NV[l] >= ((int64_t)1 << 22))  // float-reciprocal indexing stays exact below
+            return mgd_fail(h->ctx, MGD_EINVAL, "coarse level %d too large for the single-workgroup tail", l);
         off += 3 * h->NV[l];
-    }
-    const size_t work = (size_t)(a.m > 0 ? a.m : 1) * 8 + 16;
-    if ((size_t)off * vb + work > cap)
-        return mgd_fail(h->ctx, MGD_EINVAL, "coarse levels need %zu bytes of LDS", (size_t)off * vb + work);
-    // copy stencils and weights into LDS too, coarsest level first, while they fit
-    for (int l = a.last; l >= first; --l) {
-        TailLevel &L = a.L[l];
-        const int64_t ns = (int64_t)h->H * L.NV, nw = L.W ? ((int64_t)1 << h->dim) * L.NV : 0;
-        if ((size_t)(off + ns + nw) * vb + work > cap) break;
-        L.s_off = (int)off;
-        off += ns;
-        if (nw) {
-            L.w_off = (int)off;
-            off += nw;
-        }
     }
     size_t bytes = ((size_t)off * vb + 15) / 16 * 16;
     a.work_off = (int)bytes;
-    bytes += work;
+    bytes += (size_t)(a.m > 0 ? a.m : 1) * 8;
+    if (bytes > cap) return mgd_fail(h->ctx, MGD_EINVAL, "coarse levels need %zu bytes of LDS", bytes);
     if (h->precision == MGD_FP64) {
         if (h->dim == 2) tail_launch_t<2, double>(a, bytes, st);
         else tail_launch_t<3, double>(a, bytes, st);

@@ -162,8 +162,12 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
     CK(dev_alloc(ctx, (void **)&S->Ap, NV * 8));
     for (auto &e : S->ev_ready)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
-    for (hipEvent_t *e : {&S->ev_free, &S->ev_start, &S->ev_norm, &S->ev_final})
+    for (hipEvent_t *e : {&S->ev_free, &S->ev_start, &S->ev_final})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
+    // the residual-norm partials are written by kernels straight into pinned
+    // host memory: the check event releases to system scope so the host sees them
+    if (hipEventCreateWithFlags(&S->ev_norm, hipEventDisableTiming | hipEventReleaseToSystem) != hipSuccess)
+        CK(MGD_EHIP);
     if (own_asm) {
         if (hipStreamCreateWithFlags(&S->s_asm, hipStreamNonBlocking) != hipSuccess) CK(MGD_EHIP);
         S->own_asm = true;
@@ -171,6 +175,12 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
         S->s_asm = ctx->s_asm;
     }
 #undef CK
+    // null-stream clears of the new buffers must be done before any solve
+    // stream (non-blocking) touches them
+    if (hipDeviceSynchronize() != hipSuccess) {
+        solve_state_free(S);
+        return mgd_fail(ctx, MGD_EHIP, "device synchronisation failed");
+    }
     S->bytes = g_dev_alloc_bytes - bytes0;
     *out = S;
     return MGD_OK;

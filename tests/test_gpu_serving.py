@@ -118,3 +118,19 @@ def test_server_invalid(ctx):
             srv.result(12345)
     finally:
         srv.close()
+
+
+def test_fresh_states_under_concurrency(ctx):
+    """Many solves admitted at once on a new server, each on a newly created
+    device state (its buffers cleared at creation must not race with the
+    concurrent solve streams): every result matches its lone solve."""
+    shapes = [(2, 128), (2, 256), (3, 24), (2, 192), (3, 32), (2, 128), (2, 256), (3, 16),
+              (2, 64), (3, 24), (2, 256), (2, 96)]
+    reqs = make_requests(shapes, seed0=400)
+    kw = dict(BASE, schedule=P.UPFRONT)
+    ref = alone(ctx, reqs, **kw)
+    for _ in range(2):
+        res = serving.replay(ctx, reqs, None, max_slots=8, keep=True, **kw)
+        assert (res["status"] == P.OK).all(), res["status"]
+        for i, (u, _) in enumerate(ref):
+            assert torch.equal(res["solutions"][i], u), i
