@@ -67,7 +67,7 @@ def cpu_baseline(fld, d, n, f, cycles):
                        f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
 
 
-SWEEP_KERNEL = "k_lev2<float, 16, 0, true, true, false>"  # fused pre half: 2 sweeps + residual, store
+SWEEP_KERNEL = "k_lev2<float, 16, 3, true, true, false, false>"  # pre half: 2 sweeps + residual + restriction
 # Memory traffic per launch of SWEEP_KERNEL at n (bytes), from FETCH_SIZE and
 # WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
 # copy; valid only for the kernel version they were taken on.
@@ -76,12 +76,12 @@ SWEEP_TRAFFIC = {}
 
 def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     """Pre-smoothing half of the finest level of the mixed V-cycle (two
-    damped-Jacobi sweeps from zero and the residual, one pass over the
-    compressed store): the kernel the mixed cycle moves most of its bytes in.
-    Timed with HIP events on the stream it runs on, same kernel and launch
-    shape as in the solve.  Algorithmic bytes per launch: store payload +
-    tier byte and offset per tile + FP32 centre sample per cell + FP32 f in,
-    u out, r out."""
+    damped-Jacobi sweeps from zero, the residual and its restriction, one
+    pass over the compressed store): the kernel the mixed cycle moves most
+    of its bytes in.  Timed with HIP events on the stream it runs on, same
+    kernel and launch shape as in the solve.  Algorithmic bytes per launch:
+    store payload + tier byte and offset per tile + FP32 centre sample per
+    cell + FP32 f in, u out, coarse rhs out, and the BoxMG weights read."""
     import torch
     h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
     K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
@@ -93,18 +93,21 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     ntile, payload, tier_tiles = h.store_info()
     NV = (n + 1) ** d
     store_bytes = payload + 5 * ntile + 4 * n ** d
-    alg_bytes = store_bytes + 12 * NV
+    # f in, u out (FP32), the coarse rhs out, and the BoxMG weights the
+    # restriction reads: 9 per interior coarse vertex
+    nc = n // 2
+    alg_bytes = store_bytes + 8 * NV + 4 * (nc + 1) ** d + 4 * 9 * (nc - 1) ** d
     f32 = torch.ones(NV, dtype=torch.float32, device="cuda")
     u32 = torch.zeros_like(f32)
-    r32 = torch.zeros_like(f32)
+    fc32 = torch.zeros(h.nv(1), dtype=torch.float32, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     st = torch.cuda.current_stream()
-    h.presmooth(0, None, f32, u32, r32)
+    h.presmooth_restrict(0, None, f32, u32, fc32)
     torch.cuda.synchronize()
     calls = max(sweeps, 1)
     ev[0].record(st)
     for _ in range(calls):
-        h.presmooth(0, None, f32, u32, r32)
+        h.presmooth_restrict(0, None, f32, u32, fc32)
     ev[1].record(st)
     torch.cuda.synchronize()
     avg_ms = ev[0].elapsed_time(ev[1]) / calls

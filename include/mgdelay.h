@@ -217,6 +217,12 @@ int mgd_vcycle(mgd_ctx *ctx, mgd_hier *h, void *u, const void *f, const mgd_cycl
  * kernels run. */
 int mgd_presmooth(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *u_out, void *r_out,
                   double omega, hipStream_t stream);
+/* The same pass followed by the restriction (Sec. 4): fc = P^T (f - A u_out)
+ * on level+1 (fc of the coarser level's vector type and size), instead of
+ * writing the residual.  This is the finest-to-coarse half of a V(2,.)
+ * level as the solver runs it; u_out must not alias u.  2D only. */
+int mgd_presmooth_restrict(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *u_out,
+                           void *fc, double omega, hipStream_t stream);
 
 /* FP64 outer residual r = f - A u of the finest operator as stored (the
  * compressed store decoded in FP64 for MGD_MIXED); u, f, r dev double. */

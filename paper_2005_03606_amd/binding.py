@@ -104,6 +104,7 @@ def lib():
         "mgd_level_weights": ([_P, _P, C.c_int, _P, _P], C.c_int),
         "mgd_smooth": ([_P, _P, C.c_int, _P, _P, _I, C.c_double, _P], C.c_int),
         "mgd_presmooth": ([_P, _P, _I, _P, _P, _P, _P, C.c_double, _P], C.c_int),
+        "mgd_presmooth_restrict": ([_P, _P, _I, _P, _P, _P, _P, C.c_double, _P], C.c_int),
         "mgd_residual": ([_P, _P, C.c_int, _P, _P, _P, _P], C.c_int),
         "mgd_restrict": ([_P, _P, C.c_int, _P, _P, _P], C.c_int),
         "mgd_prolong_add": ([_P, _P, C.c_int, _P, _P, _P], C.c_int),
@@ -308,6 +309,11 @@ class Hierarchy:
         """Two sweeps from u (None: zero) into u_out, then r_out = f - A u_out."""
         self.ctx.check(lib().mgd_presmooth(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(u_out), _ptr(r_out),
                                            omega, _stream(stream)))
+
+    def presmooth_restrict(self, l, u, f, u_out, fc, omega=0.6, stream=None):
+        """Two sweeps from u (None: zero) into u_out, fc = P^T (f - A u_out) on level l+1."""
+        self.ctx.check(lib().mgd_presmooth_restrict(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(u_out), _ptr(fc),
+                                                    omega, _stream(stream)))
 
     def residual(self, l, u, f, r, stream=None):
         self.ctx.check(lib().mgd_residual(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))

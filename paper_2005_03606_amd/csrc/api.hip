@@ -347,6 +347,18 @@ int mgd_presmooth(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const voi
     return cycle_residual(h, h->ops, level, u_out, f, r_out, stream);
 }
 
+int mgd_presmooth_restrict(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *u_out,
+                           void *fc, double omega, hipStream_t stream)
+{
+    if (!ctx) return MGD_EINVAL;
+    int rc;
+    if ((rc = check_level(ctx, h, level, true))) return rc;
+    if (!f || !u_out || !fc || u_out == u || fc == f || fc == u_out)
+        return mgd_fail(ctx, MGD_EINVAL, "bad presmooth_restrict arguments (null or aliased buffers)");
+    if (!lev2_ok(h, level, 2, 2)) return mgd_fail(ctx, MGD_EINVAL, "presmooth_restrict needs a 2D hierarchy");
+    return lev2_prer(h, h->ops, level, u, f, u_out, fc, omega, stream);
+}
+
 int mgd_residual(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, const void *f, void *r, hipStream_t stream)
 {
     if (!ctx) return MGD_EINVAL;

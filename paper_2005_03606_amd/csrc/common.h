@@ -287,6 +287,8 @@ int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega
 bool lev2_ok(const mgd_hier *h, int l, int nu1, int nu2);
 int lev2_pre(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *r_out,
              double omega, hipStream_t st);
+int lev2_prer(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *fc, double omega,
+              hipStream_t st);
 int lev2_post(mgd_hier *h, const OpSet &o, int l, const void *u, const void *ec, const void *f, void *u_out,
               double omega, const Lev2Dots *dots, hipStream_t st);
 int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, int *nparts,

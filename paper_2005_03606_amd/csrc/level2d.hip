@@ -16,7 +16,7 @@
 // coefficient (summed in fixed order by one reduction launch afterwards).
 #include "common.h"
 
-enum { L2_PRE = 0, L2_POST = 1, L2_PMV = 2 };
+enum { L2_PRE = 0, L2_POST = 1, L2_PMV = 2, L2_PRER = 3 };
 
 template <typename T> struct Lev2Args {
     const T *S;       // half stencils [4][NV] (unless the store is used)
@@ -88,16 +88,22 @@ __device__ inline uint32_t lev2_word(int tier, int l, int j)
 template <typename T, int BY, int KIND, bool COMP, bool ZERO, bool DOTS, bool ZF = false>
 __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
 {
-    constexpr int K = KIND == L2_PRE ? 3 : KIND == L2_POST ? 2 : 1;  // stencil applications
-    constexpr bool PMV = KIND == L2_PMV;
-    constexpr int BX = 66 - 2 * K;                      // tile width: the first application spans 64 columns
-    constexpr int UW = BX + 2 * K, UH = BY + 2 * K;     // iterate / rhs region (UW = 66)
+    constexpr bool PMV = KIND == L2_PMV, RST = KIND == L2_PRER;  // RST: pre half + restriction
+    constexpr bool PREK = KIND == L2_PRE || RST;
+    constexpr int K = PREK ? 3 : KIND == L2_POST ? 2 : 1;  // stencil applications
+    // halos: K vertices on the high side, K (K + 1 when restricting: the
+    // residual is needed one vertex below the tile) on the low side; the
+    // first application spans at most 64 columns (one lane each)
+    constexpr int HL = RST ? K + 1 : K, HH = K;
+    constexpr int BX = RST ? 58 : 66 - 2 * K;           // tile width (even when restricting)
+    constexpr int UW = BX + HL + HH, UH = BY + HL + HH; // iterate / rhs region
     constexpr int CH = UH - 1, EW = UW + 1, EH = UH;    // couplings, centre samples
     constexpr int XU = UW - 64, XE = EW - 64;           // columns beyond the 64 lanes
     constexpr int RU = (UH + 3) / 4, RC = (CH + 3) / 4, RE = (EH + 3) / 4;
-    constexpr int RA = (BY + 2 * (K - 1) + 3) / 4;      // rows per wave, first application
-    constexpr int RL = BY / 4;                          // rows per wave, last application
+    constexpr int RA = (UH - 2 + 3) / 4;                // rows per wave, first application
+    constexpr int RL = BY / 4;                          // rows per wave, last application (symmetric halos)
     static_assert(BY % 4 == 0, "tile height must be a multiple of 4");
+    static_assert(UW - 2 <= 64 && XU >= 0 && XU <= 3, "halo region must fit the lane layout");
     constexpr int UH2 = PMV ? 1 : UH;                   // arrays the product does not use
     __shared__ T sC[4][CH][UW];
     __shared__ T sU0[UH][UW], sU1[UH2][UW];
@@ -112,7 +118,7 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
     const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (tile >= nt) return;  // whole block: padding of the XCD-banded numbering
     const int x0 = (tile % ntx) * BX, y0 = (tile / ntx) * BY;
-    const int gx = x0 - K, gy = y0 - K;  // global coordinates of local (0, 0)
+    const int gx = x0 - HL, gy = y0 - HL;  // global coordinates of local (0, 0)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     auto in_dom = [&](int x, int y) { return x >= 0 && x <= n && y >= 0 && y <= n; };
     double beta = 0.0;
@@ -217,13 +223,19 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
 #pragma unroll
         for (int j = 0; j < RC; ++j) load_t(j, lane, wave + 4 * j, wave + 4 * j < CH);
         load_t(RC, 64 + tid % XU, tid / XU, tid < XU * CH);
-        // payload words (tier-0 items read the first centre sample instead)
+        // payload words: the vertex's scale byte and its four entries, read as
+        // the aligned 32-bit words holding them (tiles are 64-byte aligned);
+        // offsets in bytes from the payload start (tier-0 items read word 0)
+        const uint32_t *P32 = (const uint32_t *)a.sv.payload;
         auto load_p = [&](int s, int lx, int ly) {
-            const int l = (int)(vid(gx + lx, gy + ly) & 63u);
-            const uint8_t *bp = tt[s] ? a.sv.payload + (size_t)oo[s] * 64 : (const uint8_t *)a.sv.eps_c;
-            sw[s] = *(const uint32_t *)(bp + (tt[s] ? (uint32_t)(l & ~3) : 0u));
+            const uint32_t l = vid(gx + lx, gy + ly) & 63u;
+            const int tier = tt[s];
+            const uint32_t tb = tier == 3 ? 4u : (uint32_t)tier;
+            const uint32_t base = tier ? oo[s] * 64u : 0u;
+            const uint32_t o0 = tier ? base + 64u + ((l * tb) & ~3u) : 0u, step = 64u * tb;
+            sw[s] = P32[(base + (l & ~3u)) >> 2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) wv[s][j] = *(const uint32_t *)(bp + lev2_word(tt[s], l, j));
+            for (int j = 0; j < 4; ++j) wv[s][j] = P32[(o0 + (uint32_t)j * step) >> 2];
         };
 #pragma unroll
         for (int j = 0; j < RC; ++j) load_p(j, lane, wave + 4 * j);
@@ -236,12 +248,30 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
         const int vx = gx + 1 + lane;
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
-            const int vy = gy + K + wave * RL + r;
-            const bool ok = lane + 1 >= K && lane + 1 < K + BX && in_dom(vx, vy);
+            const int vy = gy + HL + wave * RL + r;
+            const bool ok = lane + 1 >= HL && lane + 1 < HL + BX && in_dom(vx, vy);
             const uint32_t v = ok ? vid(vx, vy) : 0u;
             const double x1 = a.r64[v], x2 = a.rold64[v];
             dr[r] = ok ? x1 : 0.0;
             dro[r] = ok ? x2 : 0.0;
+        }
+    }
+
+    // RST: the restriction weights of this thread's coarse vertex (9 fine neighbours)
+    T wres[RST ? 9 : 1];
+    if (RST) {
+        constexpr int CW = BX / 2;
+        const int cx = tid % CW, cy = tid / CW, nc = n / 2;
+        const int X = x0 / 2 + cx, Y = y0 / 2 + cy;
+        const bool use = tid < CW * (BY / 2) && X > 0 && X < nc && Y > 0 && Y < nc;
+#pragma unroll
+        for (int sv = 0; sv < 9; ++sv) {
+            const int ox = sv % 3 - 1, oy = sv / 3 - 1;
+            const int B = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0);  // X - (x >> 1) is 1 exactly where o = -1
+            const uint32_t v = use ? vid(2 * X + ox, 2 * Y + oy) : 0u;
+            const T wl = Wsrc[a.W && use ? (uint32_t)B * NV + v : 0u];
+            const T geo = (T)((ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0));
+            wres[sv] = use ? (a.W ? wl : geo) : (T)0;
         }
     }
 
@@ -284,12 +314,29 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
             // base + surplus rounded as the FP64 outer operator does (no fused multiply-add)
 #pragma clang fp contract(off)
             if (!ok) return;
-            const int l = (int)(vid(gx + lx, gy + ly) & 63u);
+            const uint32_t l = vid(gx + lx, gy + ly) & 63u;
             // cells around the vertex: (x, y-1), (x-1, y), (x, y) at sE[ly][lx+1], sE[ly+1][lx], sE[ly+1][lx+1]
             const T e10 = (T)sE[ly][lx + 1], e01 = (T)sE[ly + 1][lx], e11 = (T)sE[ly + 1][lx + 1];
-            const T base[4] = {(e10 + e11) * k6, e01 * k3, (e01 + e11) * k6, e11 * k3};
+            float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int tier = tt[s];
+            if (tier == 2) {
+                const float sc = e8m0_to_float((sw[s] >> ((l & 3u) * 8u)) & 0xffu);
+                const uint32_t sh = (l & 1u) * 16u;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sC[q][ly][lx] = base[q] + (T)lev2_decode(tt[s], l, sw[s], wv[s][q]);
+                for (int q = 0; q < 4; ++q) d[q] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wv[s][q] >> sh)) * sc;
+            } else if (tier == 1) {
+                const float sc = e8m0_to_float((sw[s] >> ((l & 3u) * 8u)) & 0xffu);
+                const uint32_t sh = (l & 3u) * 8u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[q] = e4m3_to_float((wv[s][q] >> sh) & 0xffu) * sc;
+            } else if (tier == 3) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[q] = __uint_as_float(wv[s][q]);
+            }
+            sC[0][ly][lx] = (e10 + e11) * k6 + (T)d[0];
+            sC[1][ly][lx] = e01 * k3 + (T)d[1];
+            sC[2][ly][lx] = (e01 + e11) * k6 + (T)d[2];
+            sC[3][ly][lx] = e11 * k3 + (T)d[3];
         };
 #pragma unroll
         for (int j = 0; j < RC; ++j) decode(j, lane, wave + 4 * j, wave + 4 * j < CH);
@@ -298,7 +345,9 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
     }
 
     // ---------------- phase 2b: omega / diagonal on the first application's region
-    const int lx = 1 + lane;  // this lane's column in every application
+    // this lane's column in every application (lanes beyond the region read
+    // a valid column and store nothing)
+    const int lx = 1 + lane < UW - 1 ? 1 + lane : UW - 2;
     const int vxc = gx + lx;
     const bool xin = vxc > 0 && vxc < n;
     const T om = a.omega, om1 = (T)1 - a.omega;
@@ -318,15 +367,15 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
     double pa = 0.0, pb = 0.0;
 #pragma unroll
     for (int k = 1; k <= K; ++k) {
-        const int e = K - k;
+        // application k covers local columns and rows [k, UW - k) x [k, UH - k)
         const bool last = k == K;
-        const bool on = lx >= K - e && lx < BX + K + e;
+        const bool on = 1 + lane == lx && lx >= k && lx < UW - k;
         T(*Ui)[UW] = (k & 1) ? sU0 : sU1;
         T(*Uo)[UW] = (k & 1) ? sU1 : sU0;
-        const bool need_u = !(KIND == L2_PRE && ZERO && k == 1);
+        const bool need_u = !(PREK && ZERO && k == 1);
         // this wave's band of rows
-        const int rh = BY + 2 * e, q = rh / 4, rr = rh % 4;
-        const int ys = K - e + wave * q + (wave < rr ? wave : rr), cnt = q + (wave < rr ? 1 : 0);
+        const int rh = UH - 2 * k, q = rh / 4, rr = rh % 4;
+        const int ys = k + wave * q + (wave < rr ? wave : rr), cnt = q + (wave < rr ? 1 : 0);
         T um0 = (T)0, um1 = (T)0, um2 = (T)0, uc0 = (T)0, uc1 = (T)0, uc2 = (T)0, pa2 = (T)0;
         if (need_u) {
             um0 = Ui[ys - 1][lx - 1]; um1 = Ui[ys - 1][lx]; um2 = Ui[ys - 1][lx + 1];
@@ -351,7 +400,7 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
                     if (PMV) {
                         const T Dv = -(((a0 + a1) + (a2 + a3)) + ((b0 + b1) + (b2 + b3)));
                         val = Dv * uc1 + acc;
-                    } else if (KIND == L2_PRE && last) {
+                    } else if (PREK && last) {
                         const T Dv = -(((a0 + a1) + (a2 + a3)) + ((b0 + b1) + (b2 + b3)));
                         val = fv - (Dv * uc1 + acc);
                     } else {
@@ -363,7 +412,9 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
                 pa2 = a2;
                 val = inner ? val : (T)0;
                 const bool dom = on && in_dom(vxc, vy);
-                if (last) {
+                if (last && RST) {
+                    if (on) Uo[ly][lx] = val;  // residual, restricted below
+                } else if (last) {
                     if (dom) {
                         const uint32_t v = vid(vxc, vy);
                         if (PMV) {
@@ -383,13 +434,35 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
                     }
                 } else {
                     if (on) Uo[ly][lx] = val;
-                    // the smoothed iterate of the tile itself (PRE: after the last sweep)
-                    if (KIND == L2_PRE && k == K - 1 && dom && lx >= K && lx < K + BX && ly >= K && ly < K + BY)
+                    // the smoothed iterate of the tile itself (after the last sweep)
+                    if (PREK && k == K - 1 && dom && lx >= HL && lx < HL + BX && ly >= HL && ly < HL + BY)
                         a.u_out[vid(vxc, vy)] = val;
                 }
             }
         }
-        if (!last) __syncthreads();
+        if (!last || RST) __syncthreads();
+    }
+    if (RST) {
+        // fc[X] = sum of P[v][X] r[v] over the 3 x 3 fine vertices around 2X,
+        // for the tile's coarse vertices X in [x0/2, x0/2 + BX/2) x [y0/2, y0/2 + BY/2)
+        const T(*R)[UW] = sU1;
+        constexpr int CW = BX / 2;
+        const int nc = n / 2;
+        if (tid < CW * (BY / 2)) {
+            const int cx = tid % CW, cy = tid / CW;
+            const int X = x0 / 2 + cx, Y = y0 / 2 + cy;
+            if (X <= nc && Y <= nc) {
+                T fc = (T)0;
+                if (X > 0 && X < nc && Y > 0 && Y < nc) {
+#pragma unroll
+                    for (int sv = 0; sv < 9; ++sv) {
+                        const int ox = sv % 3 - 1, oy = sv / 3 - 1;
+                        fc += wres[sv] * R[HL + 2 * cy + oy][HL + 2 * cx + ox];
+                    }
+                }
+                a.r_out[(uint32_t)Y * (uint32_t)(nc + 1) + (uint32_t)X] = fc;
+            }
+        }
     }
     if (DOTS) {
         double sa = lev2_block_sum(pa, red), sb = lev2_block_sum(pb, red);
@@ -411,7 +484,7 @@ StoreView store_view(const mgd_hier *h, const OpSet &o);
 // tiles of a level: 60 (pre half) or 62 (post half) columns by `by` rows
 static int lev2_tiles(int n, int kind, int by)
 {
-    int nv = n + 1, bx = kind == L2_PRE ? 60 : kind == L2_POST ? 62 : 64;
+    int nv = n + 1, bx = kind == L2_PRE ? 60 : kind == L2_POST ? 62 : kind == L2_PRER ? 58 : 64;
     return ((nv + bx - 1) / bx) * ((nv + by - 1) / by);
 }
 static dim3 lev2_grid(int n, int kind, int by)
@@ -524,6 +597,46 @@ int lev2_pmv(mgd_hier *h, const OpSet &o, const void *z, const double *pold, dou
     HIPCHK(h->ctx, hipGetLastError());
     h->p2_n = lev2_tiles(a.n, L2_PMV, BY);
     return MGD_OK;
+}
+
+// pre half with the restriction: u_out = S^2 u, fc = P^T (f - A u_out) on the coarser level
+template <typename T, int BY>
+static int lev2_prer_t(mgd_hier *h, const OpSet &o, int l, const T *u, const T *f, T *u_out, T *fc, double omega,
+                       hipStream_t st)
+{
+    Lev2Args<T> a;
+    memset(&a, 0, sizeof(a));
+    const bool comp = h->precision == MGD_MIXED && l == 0;
+    if (comp) a.sv = store_view(h, o);
+    else a.S = (const T *)(h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l]);
+    a.n = h->nl[l];
+    a.u = u;
+    a.f = f;
+    a.u_out = u_out;
+    a.r_out = fc;
+    a.W = h->transfer == MGD_BOXMG ? (const T *)o.W[l] : nullptr;
+    a.ec = f;  // any valid address for the weight loads that are not needed (d-linear)
+    a.omega = (T)omega;
+    dim3 g = lev2_grid(a.n, L2_PRER, BY);
+    if (comp) {
+        if (!u) hipLaunchKernelGGL((k_lev2<T, BY, L2_PRER, true, true, false>), g, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_lev2<T, BY, L2_PRER, true, false, false>), g, dim3(256), 0, st, a);
+    } else {
+        if (!u) hipLaunchKernelGGL((k_lev2<T, BY, L2_PRER, false, true, false>), g, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_lev2<T, BY, L2_PRER, false, false, false>), g, dim3(256), 0, st, a);
+    }
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int lev2_prer(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *fc, double omega,
+              hipStream_t st)
+{
+    if (h->precision == MGD_FP64)
+        return lev2_prer_t<double, kBYd>(h, o, l, (const double *)u, (const double *)f, (double *)u_out,
+                                         (double *)fc, omega, st);
+    return lev2_prer_t<float, kBYf>(h, o, l, (const float *)u, (const float *)f, (float *)u_out, (float *)fc, omega,
+                                    st);
 }
 
 int lev2_pre(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *r_out,

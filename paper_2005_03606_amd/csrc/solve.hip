@@ -433,7 +433,12 @@ int solve_step(SolveState *S, bool blocking)
     mgd_ctx *ctx = S->ctx;
     int rc;
     if (blocking) {
-        HIPCHK(ctx, hipEventSynchronize(S->ev_norm));
+        // spin on the event: a sleeping wait wakes tens of microseconds late,
+        // and every cycle passes through this point
+        hipError_t q;
+        while ((q = hipEventQuery(S->ev_norm)) == hipErrorNotReady) {
+        }
+        HIPCHK(ctx, q);
     } else {
         hipError_t q = hipEventQuery(S->ev_norm);
         if (q == hipErrorNotReady) return 2;

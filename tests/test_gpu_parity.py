@@ -306,6 +306,29 @@ def test_presmooth_fp64_matches_oracle_pieces(ctx, d, n, zero):
     assert rel_err(host(ro), O.residual(d, n, S, u2, f)) < 1e-12
 
 
+@pytest.mark.parametrize("transfer", [0, 1])
+@pytest.mark.parametrize("zero", [True, False])
+@pytest.mark.parametrize("n", [6, 40, 70, 136])
+def test_presmooth_restrict_fp64_matches_oracle_pieces(ctx, transfer, zero, n):
+    d = 2
+    S = _fine_stencils(d, n)
+    h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=transfer)
+    h.set_fine(dev(O.to_half(d, S)))
+    h.coarsen()
+    ref = O.Hierarchy(d, n, S, coarsest=2, transfer=transfer)
+    rng = np.random.default_rng(13)
+    inner = W.interior_mask(d, n)
+    u = np.zeros(inner.size) if zero else rng.standard_normal(inner.size) * inner
+    f = rng.standard_normal(inner.size) * inner
+    uo = torch.full((inner.size,), 7.0, dtype=torch.float64, device="cuda")
+    fc = torch.full((h.nv(1),), 7.0, dtype=torch.float64, device="cuda")
+    h.presmooth_restrict(0, None if zero else dev(u), dev(f), uo, fc, omega=0.6)
+    u2 = O.jacobi(d, n, S, O.jacobi(d, n, S, u, f, 0.6), f, 0.6)
+    assert rel_err(host(uo), u2) < 1e-12
+    fc_ref = O.restrict(d, n, O.residual(d, n, S, u2, f), ref.level_weights(0))
+    assert rel_err(host(fc), fc_ref) < 1e-12
+
+
 @pytest.mark.parametrize("n", [40, 136, 256])
 def test_presmooth_mixed_matches_separate_sweeps(ctx, n):
     """Compressed finest level and FP32 coarse levels: the fused pass equals
