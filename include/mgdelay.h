@@ -248,6 +248,12 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * and published and ||f - A u||_2 / ||r_0||_2 <= tol (interior vertices,
  * r_0 at cycle 0, Sec. 6); MGD_EDIVERGED when the residual exceeds
  * div_factor times the residual at the last operator change.
+ * prov_tol (MGD_LAZY with MGD_PUBLISH_ASYNC or MGD_PUBLISH_EVERY): once the
+ * residual on a provisional operator has dropped to prov_tol times the
+ * residual at the last operator change, the solver stops cycling on it and
+ * waits for the pending operator, leaving the device to the assembly stream
+ * (a provisional operator's solution is no closer to the final one than the
+ * operator is to the final operator); 0 cycles on until the publish.
  * f (dev double [NV]) is the load vector; u (dev double [NV]) is the initial
  * guess on entry and the solution on return. */
 typedef struct {
@@ -256,6 +262,7 @@ typedef struct {
     int32_t nu2, max_cycles, coarsest, pad;
     double C, omega, tol, div_factor;
     mgd_tier_policy tiers;
+    double prov_tol;
 } mgd_solve_opts;
 
 #define MGD_HIST 512

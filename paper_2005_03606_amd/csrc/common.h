@@ -208,6 +208,11 @@ struct mgd_hier {
     // scratch for compression
     float *delta = nullptr;
     uint8_t *vtier = nullptr;
+    // mixed form: FP64 coarsening scratch (stencils of a level and of the
+    // next, ping-pong; BoxMG weights of the current level), rounded once into
+    // the FP32 operators of the cycle
+    double *gal64[2] = {nullptr, nullptr};
+    double *w64 = nullptr;
     // reduction scratch and device scalars owned by this hierarchy
     double *partial = nullptr;    // block partial sums / coarse-solve work
     int64_t partial_cap = 0;
@@ -216,7 +221,7 @@ struct mgd_hier {
     double *partial2 = nullptr;   // second partial list (matrix-vector product of CG), partial_cap
     const double *p1 = nullptr;   // CG dot partials (z.r then z.(r - r_old)), p1_n each
     int64_t p1_n = 0, p2_n = 0;
-    double *host_part = nullptr;      // pinned [kHostParts]: partials of the residual norm
+    double *host_part = nullptr;      // pinned: squared norms of the last two residual checks
     double *host_part_dev = nullptr;  // its device address
     size_t vec_bytes() const { return precision == MGD_FP64 ? 8 : 4; }
 };
@@ -262,11 +267,17 @@ struct CgScalars {
     int zr_old, zr_new;
 };
 constexpr int kHostParts = 1024;
+// residual checks: the squared norm of check k lands in the device scalar
+// s[kChkSlot + (k & 1)] and in the pinned host slot host_part[k & 1]
+constexpr int kChkSlot = 24;
+int check_sum(mgd_hier *h, int nparts, int slot, hipStream_t st);
 int pcg_dots(mgd_hier *h, const void *z, const double *r, const double *rold, hipStream_t st);
 int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap,
                const CgScalars &c, hipStream_t st);
+// gate_slot >= 0: a cycle queued before check gate_slot was read; it leaves
+// x and r unchanged when that check's squared norm is <= thr (converged)
 int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap,
-               const CgScalars &c, int *nparts, hipStream_t st);
+               const CgScalars &c, int gate_slot, double thr, int *nparts, hipStream_t st);
 int compress_partials(mgd_hier *h, const double *partial, int64_t cnt, int nvec, double *out, hipStream_t st);
 int lev2_pmv(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap,
              const CgScalars &c, hipStream_t st);

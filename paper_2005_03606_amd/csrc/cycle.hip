@@ -950,12 +950,12 @@ static int outer_residual_t(mgd_hier *h, const OpSet &o, const double *u, const 
     return MGD_OK;
 }
 
-// r = f - A u (finest operator as stored, FP64); with nparts: the partials of
-// ||r||^2 go to the pinned host array h->host_part (*nparts of them)
+// r = f - A u (finest operator as stored, FP64); the partials of ||r||^2 go
+// to h->partial (*nparts of them, when asked)
 int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f, double *r, int *nparts,
                    hipStream_t st)
 {
-    double *partial = nparts ? h->host_part_dev : nullptr;
+    double *partial = h->partial;
     if (h->dim == 2 && h->precision == MGD_MIXED) {
         StageArgs<double> sa;
         memset(&sa, 0, sizeof(sa));
@@ -964,16 +964,16 @@ int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f
         sa.u = u;
         sa.f = f;
         sa.out = r;
-        sa.partial = partial ? partial : h->partial;
+        sa.partial = partial;
         sa.rf = (float *)h->f[0];
         stage2_tiles(h->n, sa.ntx, sa.nt);
-        const unsigned grid = (unsigned)std::min(sa.nt, kRedBlocks);
+        const unsigned grid = (unsigned)std::min<int64_t>({(int64_t)sa.nt, (int64_t)kRedBlocks, h->partial_cap});
         hipLaunchKernelGGL((k_stage2<double, ST_OUTER>), dim3(grid), dim3(256), 0, st, sa);
         HIPCHK(h->ctx, hipGetLastError());
         if (nparts) *nparts = (int)grid;
         return MGD_OK;
     }
-    const unsigned grid = red_grid(h->NV[0]);
+    const unsigned grid = (unsigned)std::min<int64_t>(red_grid(h->NV[0]), h->partial_cap);
     if (nparts) *nparts = (int)grid;
     return h->dim == 2 ? outer_residual_t<2>(h, o, u, f, r, partial, grid, st)
                        : outer_residual_t<3>(h, o, u, f, r, partial, grid, st);
@@ -1055,12 +1055,18 @@ __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, cons
 // r.r to pinned host memory; alpha = zr / p.Ap from the matvec's partials
 __global__ __launch_bounds__(256) void k_cg_update(double *x, const double *p, double *r, double *rold,
                                                    const double *Ap, int64_t n, CgScalars c, const double *p2,
-                                                   int64_t n2, double *partial, float *rf)
+                                                   int64_t n2, double *partial, float *rf, const double *gate,
+                                                   double thr)
 {
     __shared__ double red[256];
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[7] = 0.0;  // restart consumed
+    if (gate && *gate <= thr) {
+        // the previous check converged: no update, the check repeats its norm
+        if (threadIdx.x == 0) partial[blockIdx.x] = blockIdx.x == 0 ? *gate : 0.0;
+        return;
+    }
     const double pAp = sum_partials(p2, n2, red);
     const double alpha = c.s[c.zr_new] / pAp;
-    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[7] = 0.0;  // restart consumed
     double rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += alpha * p[i];
@@ -1137,15 +1143,43 @@ int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, d
 
 // x += alpha p, r -= alpha Ap; the partials of r.r to the pinned host array
 int pcg_update(mgd_hier *h, double *x, const double *p, double *r, double *rold, const double *Ap,
-               const CgScalars &c, int *nparts, hipStream_t st)
+               const CgScalars &c, int gate_slot, double thr, int *nparts, hipStream_t st)
 {
     int64_t n = h->NV[0];
-    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(n, 256), kHostParts);
+    const unsigned grid = (unsigned)std::min<int64_t>({grid_for(n, 256), kHostParts, h->partial_cap});
     float *rf = h->precision == MGD_MIXED ? (float *)h->f[0] : nullptr;
+    const double *gate = gate_slot >= 0 ? h->scal + kChkSlot + (gate_slot & 1) : nullptr;
     hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(256), 0, st, x, p, r, rold, Ap, n, c, (const double *)h->partial2,
-                       h->p2_n, h->host_part_dev, rf);
+                       h->p2_n, h->partial, rf, gate, thr);
     HIPCHK(h->ctx, hipGetLastError());
     *nparts = (int)grid;
+    return MGD_OK;
+}
+
+// squared norm of a residual check from its partials, summed in one fixed
+// order; to the device slot (the next cycle's gate) and the pinned host slot
+__global__ __launch_bounds__(1024) void k_check_sum(const double *part, int n, double *dev_slot, double *host_slot)
+{
+    __shared__ double red[1024];
+    red[threadIdx.x] = (int)threadIdx.x < n ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *dev_slot = red[0];
+        *host_slot = red[0];
+    }
+}
+
+int check_sum(mgd_hier *h, int nparts, int slot, hipStream_t st)
+{
+    if (nparts < 1 || nparts > 1024 || nparts > h->partial_cap)
+        return mgd_fail(h->ctx, MGD_EINVAL, "residual check with %d partials", nparts);
+    hipLaunchKernelGGL(k_check_sum, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nparts,
+                       h->scal + kChkSlot + (slot & 1), h->host_part_dev + (slot & 1));
+    HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
 

@@ -108,9 +108,12 @@ struct CandLDS {
     int wave_cnt[16];
 };
 
+// Each thread brings the box [lo, hi] of the cells it stands for (valid
+// false: none); the box is reduced across the wave first, so the LDS sees
+// one update per wave.
 template <int D>
-__device__ inline void build_candidates(const EpsDev &e, int n, bool valid, const int *ci, CandLDS &L,
-                                        const double **rows, int *count)
+__device__ inline void build_candidates(const EpsDev &e, int n, bool valid, const int *clo, const int *chi,
+                                        CandLDS &L, const double **rows, int *count)
 {
     *rows = e.data;
     *count = e.count;
@@ -122,11 +125,17 @@ __device__ inline void build_candidates(const EpsDev &e, int n, bool valid, cons
         L.overflow = 0;
     }
     __syncthreads();
-    if (valid)
-        for (int m = 0; m < D; ++m) {
-            atomicMin(&L.lo[m], ci[m]);
-            atomicMax(&L.hi[m], ci[m]);
+    for (int m = 0; m < D; ++m) {
+        int lo = valid ? clo[m] : 0x7fffffff, hi = valid ? chi[m] : -1;
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
         }
+        if ((tid & 63) == 0) {
+            atomicMin(&L.lo[m], lo);
+            atomicMax(&L.hi[m], hi);
+        }
+    }
     __syncthreads();
     if (L.hi[0] < 0) return;  // no valid cell in this workgroup
     double blo[3], bhi[3];
@@ -280,6 +289,9 @@ template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(Asm
     int64_t i = gid / G;
     int g = (int)(gid % G);
     int64_t cnt = asm_count(a);
+    // grids are sized for the host's bound on the device-side count: blocks
+    // past the count leave at once (uniformly, before any barrier)
+    if ((int64_t)blockIdx.x * blockDim.x / G >= cnt) return;
     bool valid = i < cnt;
     int s = a.s, n = a.n;
     int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
@@ -288,7 +300,7 @@ template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(Asm
     __shared__ CandLDS cand;
     const double *rows;
     int nrows;
-    build_candidates<D>(a.eps, n, valid, ci, cand, &rows, &nrows);
+    build_candidates<D>(a.eps, n, valid, ci, ci, cand, &rows, &nrows);
     int nlines = (D == 2) ? s : s * s;
     int64_t nq = (int64_t)nlines * s;
     // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
@@ -373,10 +385,12 @@ union BF8 {
     uint16_t u[8];
 };
 
-// One wave handles 16 cells; lane l owns cell row l & 15 and samples
-// 8 (l >> 4) .. +7 of every 32-sample chunk (the A-operand layout of
-// v_mfma_f32_16x16x32_bf16); the B operand (G terms) is pre-laid out per lane.
-template <int D, int NT, int NTERM>
+// A wave handles TPW groups of 16 cells; lane l owns cell row l & 15 and
+// samples 8 (l >> 4) .. +7 of every 32-sample chunk (the A-operand layout of
+// v_mfma_f32_16x16x32_bf16); the B operand (G terms) is pre-laid out per
+// lane.  The block's 64 TPW consecutive list entries share one candidate
+// list, so small s (one chunk per cell) takes TPW = 4.
+template <int D, int NT, int NTERM, int TPW>
 __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *Gtab, int nchunks,
                                                         float inv_den)
 {
@@ -384,68 +398,88 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int row = lane & 15, kg = lane >> 4;
     int64_t cnt = asm_count(a);
-    int64_t tile = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    int64_t i = tile + row;
-    bool valid = i < cnt;
+    const int64_t blk0 = (int64_t)blockIdx.x * (64 * TPW);
+    if (blk0 >= cnt) return;  // past the device-side count: the whole block leaves
     int s = a.s, n = a.n;
-    int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
-    int ci[3] = {0, 0, 0};
-    cell_coords<D>(cell, n, ci);
+    // candidate box: thread t stands for entries blk0 + t + 256 j
+    int clo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, chi[3] = {-1, -1, -1};
+    bool any = false;
+    for (int j = 0; j < TPW; ++j) {
+        int64_t i = blk0 + threadIdx.x + 256 * j;
+        if (i < cnt) {
+            int cj[3] = {0, 0, 0};
+            cell_coords<D>(a.cells ? a.cells[i] : i, n, cj);
+            for (int m = 0; m < D; ++m) {
+                clo[m] = min(clo[m], cj[m]);
+                chi[m] = max(chi[m], cj[m]);
+            }
+            any = true;
+        }
+    }
     __shared__ CandLDS cand;
     const double *rows;
     int nrows;
-    build_candidates<D>(a.eps, n, valid, ci, cand, &rows, &nrows);
+    build_candidates<D>(a.eps, n, any, clo, chi, cand, &rows, &nrows);
     int64_t nq = 1;
     for (int m = 0; m < D; ++m) nq *= s;
-    floatx4 acc[NT];
-    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    int nch = tile < cnt ? nchunks : 0;  // idle waves still reach the barrier
-    for (int ch = 0; ch < nch; ++ch) {
-        BF8 ahi, alo;
-        int64_t q0 = (int64_t)ch * 32 + kg * 8;
-        for (int e = 0; e < 8; ++e) {
-            int64_t q = q0 + e;
-            float ev = 0.0f;
-            if (valid && q < nq) {
-                if (a.eps.kind == MGD_EPS_SAMPLES) {
-                    ev = (float)a.samples[i * nq + q];
-                } else {
-                    int qx = (int)(q % s), qr = (int)(q / s);
-                    double x[3];
-                    x[0] = sample_coord(ci[0], qx, s, n);
-                    x[1] = sample_coord(ci[1], qr % s, s, n);
-                    if (D == 3) x[2] = sample_coord(ci[2], qr / s, s, n);
-                    ev = eps_eval<D, float>(a.eps, x, rows, nrows);
+    for (int j = 0; j < TPW; ++j) {
+        const int64_t tile = blk0 + (int64_t)(j * 4 + wave) * 16;
+        const int64_t i = tile + row;
+        const bool valid = i < cnt;
+        const int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
+        int ci[3] = {0, 0, 0};
+        cell_coords<D>(cell, n, ci);
+        floatx4 acc[NT];
+        for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        int nch = tile < cnt ? nchunks : 0;  // idle waves still reach the barriers
+        for (int ch = 0; ch < nch; ++ch) {
+            BF8 ahi, alo;
+            int64_t q0 = (int64_t)ch * 32 + kg * 8;
+            for (int e = 0; e < 8; ++e) {
+                int64_t q = q0 + e;
+                float ev = 0.0f;
+                if (valid && q < nq) {
+                    if (a.eps.kind == MGD_EPS_SAMPLES) {
+                        ev = (float)a.samples[i * nq + q];
+                    } else {
+                        int qx = (int)(q % s), qr = (int)(q / s);
+                        double x[3];
+                        x[0] = sample_coord(ci[0], qx, s, n);
+                        x[1] = sample_coord(ci[1], qr % s, s, n);
+                        if (D == 3) x[2] = sample_coord(ci[2], qr / s, s, n);
+                        ev = eps_eval<D, float>(a.eps, x, rows, nrows);
+                    }
+                }
+                uint16_t h = bf16_bits_rne(ev);
+                ahi.u[e] = h;
+                alo.u[e] = bf16_bits_rne(ev - bf16_value(h));
+            }
+            for (int t = 0; t < NT; ++t) {
+                const uint4 *gp = Gtab + ((size_t)(ch * NT + t) * NTERM) * 64 + lane;
+                BF8 g0, g1;
+                *(uint4 *)&g0 = gp[0];
+                *(uint4 *)&g1 = gp[64];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g0.v, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g1.v, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo.v, g0.v, acc[t], 0, 0, 0);
+                if (NTERM == 3) {
+                    BF8 g2;
+                    *(uint4 *)&g2 = gp[128];
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g2.v, acc[t], 0, 0, 0);
                 }
             }
-            uint16_t h = bf16_bits_rne(ev);
-            ahi.u[e] = h;
-            alo.u[e] = bf16_bits_rne(ev - bf16_value(h));
         }
-        for (int t = 0; t < NT; ++t) {
-            const uint4 *gp = Gtab + ((size_t)(ch * NT + t) * NTERM) * 64 + lane;
-            BF8 g0, g1;
-            *(uint4 *)&g0 = gp[0];
-            *(uint4 *)&g1 = gp[64];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g0.v, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g1.v, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo.v, g0.v, acc[t], 0, 0, 0);
-            if (NTERM == 3) {
-                BF8 g2;
-                *(uint4 *)&g2 = gp[128];
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi.v, g2.v, acc[t], 0, 0, 0);
-            }
+        // C layout: lane holds column lane & 15, rows 4 (lane >> 4) + r
+        if (j > 0) __syncthreads();  // the previous group's rows are read
+        for (int t = 0; t < NT; ++t)
+            for (int r = 0; r < 4; ++r) sm[wave][4 * kg + r][t * 16 + (lane & 15)] = acc[t][r] * inv_den;
+        __syncthreads();
+        if (lane < 16 && valid) {
+            constexpr int U = n_pairs(D);
+            float K[U];
+            for (int p = 0; p < U; ++p) K[p] = sm[wave][lane][p];
+            store_and_check<D, float>(a, i, cell, K);
         }
-    }
-    // C layout: lane holds column lane & 15, rows 4 (lane >> 4) + r
-    for (int t = 0; t < NT; ++t)
-        for (int r = 0; r < 4; ++r) sm[wave][4 * kg + r][t * 16 + (lane & 15)] = acc[t][r] * inv_den;
-    __syncthreads();
-    if (lane < 16 && valid) {
-        constexpr int U = n_pairs(D);
-        float K[U];
-        for (int p = 0; p < U; ++p) K[p] = sm[wave][lane][p];
-        store_and_check<D, float>(a, i, cell, K);
     }
 }
 
@@ -595,18 +629,20 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         int rc = get_gtable(ctx, dim, s, &T);
         if (rc) return rc;
         double inv_den = dim == 2 ? 1.0 / (6.0 * pow((double)s, 4)) : (1.0 / n) / (36.0 * pow((double)s, 7));
-        unsigned grid = grid_for(count, 64);
+        // one chunk per cell: four 16-cell groups per wave share the block's candidates
+        const bool small = T->nchunks == 1;
+        unsigned grid = grid_for(count, small ? 256 : 64);
+#define LM(DD, NT, NTERM, TPW)                                                                              \
+    hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW>), dim3(grid), dim3(256), 0, st, a, T->dev, \
+                       T->nchunks, (float)inv_den)
         if (dim == 2) {
-            if (T->nterm == 2)
-                hipLaunchKernelGGL((k_integrate_mfma<2, 1, 2>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
-            else
-                hipLaunchKernelGGL((k_integrate_mfma<2, 1, 3>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
+            if (T->nterm == 2) { if (small) LM(2, 1, 2, 4); else LM(2, 1, 2, 1); }
+            else { if (small) LM(2, 1, 3, 4); else LM(2, 1, 3, 1); }
         } else {
-            if (T->nterm == 2)
-                hipLaunchKernelGGL((k_integrate_mfma<3, 2, 2>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
-            else
-                hipLaunchKernelGGL((k_integrate_mfma<3, 2, 3>), dim3(grid), dim3(256), 0, st, a, T->dev, T->nchunks, (float)inv_den);
+            if (T->nterm == 2) { if (small) LM(3, 2, 2, 4); else LM(3, 2, 2, 1); }
+            else { if (small) LM(3, 2, 3, 4); else LM(3, 2, 3, 1); }
         }
+#undef LM
     }
     HIPCHK(ctx, hipGetLastError());
     return MGD_OK;
@@ -622,7 +658,7 @@ template <int D> __global__ void k_centre_eps(EpsDev e, int n, int64_t ncell, fl
     __shared__ CandLDS cand;
     const double *rows;
     int nrows;
-    build_candidates<D>(e, n, valid, ci, cand, &rows, &nrows);
+    build_candidates<D>(e, n, valid, ci, ci, cand, &rows, &nrows);
     if (!valid) return;
     double x[3];
     for (int m = 0; m < D; ++m) x[m] = sample_coord(ci[m], 0, 1, n);

@@ -27,7 +27,8 @@ struct SolveState {
     Ladder L;
     double *r = nullptr, *rold = nullptr, *p[2] = {nullptr, nullptr}, *Ap = nullptr;
     hipEvent_t ev_ready[8] = {};
-    hipEvent_t ev_free = nullptr, ev_start = nullptr, ev_norm = nullptr, ev_final = nullptr;
+    hipEvent_t ev_free = nullptr, ev_start = nullptr, ev_final = nullptr;
+    hipEvent_t ev_norm[2] = {nullptr, nullptr};  // residual check k completes ev_norm[k & 1]
     hipStream_t s_asm = nullptr, stream = nullptr;
     bool own_asm = false;
     size_t bytes = 0;
@@ -38,8 +39,12 @@ struct SolveState {
     double *u = nullptr;
     mgd_report *rep = nullptr;
     OpSet *sets[2] = {nullptr, nullptr};
-    int cur = 0, published = 0, built = 0, publishes = 0, ncyc = 0, k = 0, status = 0, publish_mode = 0, nparts = 0;
+    int cur = 0, published = 0, built = 0, publishes = 0, ncyc = 0, k = 0, status = 0, publish_mode = 0;
+    int kq = 0;         // residual checks queued (check k is read when k < kq)
+    bool spec = false;  // a cycle beyond the check being read is already queued
+    double thr = 0.0;   // (tol r_0)^2: squared-norm convergence threshold
     bool lazy = false, pcg = false, ladder_done = false, restart = true, done = false;
+    bool parked = false;  // done with the provisional operator, waiting for the pending one
     double r0 = 0, rk = 0, r_ref = 0, t0 = 0, t_first = 0, t_loop0 = 0;
 };
 

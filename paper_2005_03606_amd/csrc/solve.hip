@@ -117,7 +117,7 @@ void solve_state_free(SolveState *S)
     dev_free(S->r); dev_free(S->rold); dev_free(S->p[0]); dev_free(S->p[1]); dev_free(S->Ap);
     for (auto &e : S->ev_ready)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {S->ev_free, S->ev_start, S->ev_norm, S->ev_final})
+    for (hipEvent_t e : {S->ev_free, S->ev_start, S->ev_norm[0], S->ev_norm[1], S->ev_final})
         if (e) (void)hipEventDestroy(e);
     if (S->own_asm && S->s_asm) (void)hipStreamDestroy(S->s_asm);
     delete S;
@@ -164,10 +164,10 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
     for (hipEvent_t *e : {&S->ev_free, &S->ev_start, &S->ev_final})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
-    // the residual-norm partials are written by kernels straight into pinned
-    // host memory: the check event releases to system scope so the host sees them
-    if (hipEventCreateWithFlags(&S->ev_norm, hipEventDisableTiming | hipEventReleaseToSystem) != hipSuccess)
-        CK(MGD_EHIP);
+    // the squared residual norms are written by a kernel straight into pinned
+    // host memory: the check events release to system scope so the host sees them
+    for (hipEvent_t *e : {&S->ev_norm[0], &S->ev_norm[1]})
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming | hipEventReleaseToSystem) != hipSuccess) CK(MGD_EHIP);
     if (own_asm) {
         if (hipStreamCreateWithFlags(&S->s_asm, hipStreamNonBlocking) != hipSuccess) CK(MGD_EHIP);
         S->own_asm = true;
@@ -211,7 +211,8 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
     int sf = op->s_fixed, sm = op->s_max;
     if (sf > 0 && sf != 1 && sf != 2 && sf != 4 && sf != 8 && sf != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_fixed");
     if (sf <= 0 && sm != 1 && sm != 2 && sm != 4 && sm != 8 && sm != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_max");
-    if (op->nu1 < 0 || op->nu2 < 0 || op->max_cycles < 0 || !(op->tol >= 0.0) || !(op->div_factor > 0.0))
+    if (op->nu1 < 0 || op->nu2 < 0 || op->max_cycles < 0 || !(op->tol >= 0.0) || !(op->div_factor > 0.0) ||
+        !(op->prov_tol >= 0.0))
         return mgd_fail(ctx, MGD_EINVAL, "bad cycle options");
     if (op->precision == MGD_MIXED &&
         (op->tiers.min_tier < 1 || op->tiers.max_tier > 3 || op->tiers.min_tier > op->tiers.max_tier ||
@@ -220,10 +221,10 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
     return MGD_OK;
 }
 
-// enqueue the residual measurement of the next check (outer residual after
-// an operator change or for the stationary iteration, else the CG
-// recursion's, whose partials the update kernel already left in pinned host
-// memory); the host adds the partials when the event has completed
+// enqueue residual check kq (outer residual after an operator change or for
+// the stationary iteration, else the CG recursion's, whose partials the
+// update kernel already left in h->partial); its squared norm lands in slot
+// kq & 1, read by the host once ev_norm[kq & 1] has completed
 static int enqueue_check(SolveState *S, int nparts)
 {
     mgd_ctx *ctx = S->ctx;
@@ -233,9 +234,52 @@ static int enqueue_check(SolveState *S, int nparts)
         if ((rc = outer_residual(&H, *S->sets[S->cur], S->u, S->f, S->r, &nparts, S->stream))) return rc;
         if (S->pcg && S->restart && (rc = vec_fill_f64(ctx, H.scal + 7, 1, 1.0, S->stream))) return rc;
     }
-    S->nparts = nparts;
-    HIPCHK(ctx, hipEventRecord(S->ev_norm, S->stream));
+    const int slot = S->kq & 1;
+    if ((rc = check_sum(&H, nparts, slot, S->stream))) return rc;
+    HIPCHK(ctx, hipEventRecord(S->ev_norm[slot], S->stream));
+    S->kq++;
     return MGD_OK;
+}
+
+static int boundary_publish(SolveState *S, bool force_wait);
+
+// one preconditioned cycle with the current operator and its residual check;
+// `gated`: queued before the previous check was read, so the update is
+// skipped on the device if that check met the tolerance
+static int enqueue_cycle(SolveState *S, bool gated)
+{
+    mgd_hier &H = S->H;
+    const mgd_solve_opts &op = S->op;
+    const OpSet &O = *S->sets[S->cur];
+    hipStream_t st = S->stream;
+    int rc;
+    // rhs of the correction cycle: the FP64 residual itself, or the FP32 copy
+    // that the kernels producing r write beside it
+    const void *rhs = H.precision == MGD_FP64 ? (const void *)S->r : (const void *)H.f[0];
+    void *z = nullptr;
+    bool dots_done = false;
+    int nparts = 0;
+    Lev2Dots dots{S->r, S->rold, H.scal};
+    if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st, S->pcg ? &dots : nullptr, &z,
+                         &dots_done)))
+        return rc;
+    if (!S->pcg) {
+        if ((rc = vec_add_cycle(&H, S->u, z, st))) return rc;
+    } else {
+        if (!dots_done && (rc = pcg_dots(&H, z, S->r, S->rold, st))) return rc;
+        CgScalars c{H.scal, H.p1, H.p1_n, 8 + (S->ncyc & 1), 8 + ((S->ncyc + 1) & 1)};
+        if ((rc = pcg_matvec(&H, O, z, S->p[0], S->p[1], S->Ap, c, st))) return rc;
+        if ((rc = pcg_update(&H, S->u, S->p[1], S->r, S->rold, S->Ap, c, gated ? S->kq - 1 : -1, S->thr, &nparts,
+                             st)))
+            return rc;
+        double *t = S->p[0];
+        S->p[0] = S->p[1];
+        S->p[1] = t;
+    }
+    S->ncyc++;
+    S->restart = false;
+    if ((rc = boundary_publish(S, false))) return rc;
+    return enqueue_check(S, nparts);
 }
 
 // switch the solver to operator set `set`, built for rung `rung_no`
@@ -302,6 +346,32 @@ static int boundary_publish(SolveState *S, bool force_wait)
     return chain_next(S);
 }
 
+// the provisional operator has done its part: publish the pending one once
+// it is built and measure the residual against it (2 while it is not built
+// and the caller does not block)
+static int await_publish(SolveState *S, bool blocking)
+{
+    mgd_ctx *ctx = S->ctx;
+    hipEvent_t ev = S->publish_mode == MGD_PUBLISH_ASYNC ? S->ev_final : S->ev_ready[S->published + 1];
+    if (blocking) {
+        HIPCHK(ctx, hipEventSynchronize(ev));
+    } else {
+        hipError_t q = hipEventQuery(ev);
+        if (q == hipErrorNotReady) {
+            S->parked = true;
+            return 2;
+        }
+        HIPCHK(ctx, q);
+    }
+    S->parked = false;
+    int rc;
+    if ((rc = boundary_publish(S, true))) return rc;
+    S->k++;
+    if ((rc = enqueue_check(S, 0))) return rc;
+    return 0;
+}
+
+
 int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, const mgd_solve_opts *op,
                 mgd_report *rep, hipStream_t stream)
 {
@@ -328,6 +398,10 @@ int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, c
     S->r0 = S->rk = S->r_ref = 0.0;
     S->status = MGD_ENOCONV;
     S->done = false;
+    S->parked = false;
+    S->spec = false;
+    S->kq = 0;
+    S->thr = 0.0;
     S->restart = true;
     S->t_first = S->t_loop0 = 0.0;
     Ladder &L = S->L;
@@ -430,88 +504,74 @@ static void finish(SolveState *S)
 int solve_step(SolveState *S, bool blocking)
 {
     if (S->done) return 1;
+    if (S->parked) return await_publish(S, blocking);
     mgd_ctx *ctx = S->ctx;
+    const mgd_solve_opts &op = S->op;
     int rc;
+    // with the final operator in place, the next CG cycle is queued before
+    // check k is read, so the device does not idle while the host decides;
+    // its update is skipped on the device if check k has converged
+    if (!S->spec && S->pcg && S->ladder_done && !S->restart && S->k >= 1 && S->kq == S->k + 1 &&
+        S->ncyc < op.max_cycles) {
+        if ((rc = enqueue_cycle(S, true))) return rc;
+        S->spec = true;
+    }
+    hipEvent_t ev = S->ev_norm[S->k & 1];
     if (blocking) {
         // spin on the event: a sleeping wait wakes tens of microseconds late,
         // and every cycle passes through this point
         hipError_t q;
-        while ((q = hipEventQuery(S->ev_norm)) == hipErrorNotReady) {
+        while ((q = hipEventQuery(ev)) == hipErrorNotReady) {
         }
         HIPCHK(ctx, q);
     } else {
-        hipError_t q = hipEventQuery(S->ev_norm);
+        hipError_t q = hipEventQuery(ev);
         if (q == hipErrorNotReady) return 2;
         HIPCHK(ctx, q);
     }
-    mgd_hier &H = S->H;
-    const mgd_solve_opts &op = S->op;
-    double rr = 0.0;
-    for (int i = 0; i < S->nparts; ++i) rr += H.host_part[i];
+    const double rr = S->H.host_part[S->k & 1];
     S->rk = sqrt(rr);
     if (S->k == 0) {
         S->r0 = S->rk;
+        S->thr = (op.tol * S->r0) * (op.tol * S->r0);
         S->t_first = now_ms() - S->t0;
         S->t_loop0 = now_ms();
     }
     if (S->k == 0 || S->restart) S->r_ref = S->rk > S->r0 ? S->rk : S->r0;
     double rel = S->r0 > 0.0 ? S->rk / S->r0 : 0.0;
     if (S->k < MGD_HIST) S->rep->hist[S->k] = rel;
+    // the device gate of a queued cycle takes the same decision on the same value
+    const bool conv = rr <= S->thr;
     if (!(S->rk <= op.div_factor * S->r_ref)) {
         S->status = MGD_EDIVERGED;
         finish(S);
         return 1;
     }
-    if (rel <= op.tol) {
-        if (S->ladder_done) {
-            S->status = MGD_OK;
-            finish(S);
-            return 1;
-        }
-        // starvation guard: the tolerance was met on a provisional operator;
-        // the asynchronous modes wait for the pending operator and publish it
-        // at once, the deterministic mode keeps its schedule
-        if (S->publish_mode != MGD_PUBLISH_DETERMINISTIC) {
-            if ((rc = boundary_publish(S, true))) return rc;
-            S->k++;
-            if ((rc = enqueue_check(S, 0))) return rc;
-            return 0;
-        }
-    }
-    if (S->ncyc >= op.max_cycles) {
-        S->status = rel <= op.tol ? MGD_ESTARVED : MGD_ENOCONV;
+    if (conv && S->ladder_done) {
+        if (S->spec) S->ncyc--;  // the queued cycle made no update
+        S->status = MGD_OK;
         finish(S);
         return 1;
     }
-    // one preconditioned cycle with the current operator
-    const OpSet &O = *S->sets[S->cur];
-    hipStream_t st = S->stream;
-    // rhs of the correction cycle: the FP64 residual itself, or the FP32 copy
-    // that the kernels producing r write beside it
-    const void *rhs = H.precision == MGD_FP64 ? (const void *)S->r : (const void *)H.f[0];
-    void *z = nullptr;
-    bool dots_done = false;
-    int nparts = 0;
-    Lev2Dots dots{S->r, S->rold, H.scal};
-    if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st, S->pcg ? &dots : nullptr, &z,
-                         &dots_done)))
-        return rc;
-    if (!S->pcg) {
-        if ((rc = vec_add_cycle(&H, S->u, z, st))) return rc;
-    } else {
-        if (!dots_done && (rc = pcg_dots(&H, z, S->r, S->rold, st))) return rc;
-        CgScalars c{H.scal, H.p1, H.p1_n, 8 + (S->ncyc & 1), 8 + ((S->ncyc + 1) & 1)};
-        if ((rc = pcg_matvec(&H, O, z, S->p[0], S->p[1], S->Ap, c, st))) return rc;
-        if ((rc = pcg_update(&H, S->u, S->p[1], S->r, S->rold, S->Ap, c, &nparts, st))) return rc;
-        double *t = S->p[0];
-        S->p[0] = S->p[1];
-        S->p[1] = t;
-    }
-    S->ncyc++;
-    S->restart = false;
-    if ((rc = boundary_publish(S, false))) return rc;
+    // on a provisional operator, the asynchronous modes stop cycling once the
+    // tolerance (starvation guard) or the provisional target is met, wait for
+    // the pending operator and publish it at once; the deterministic mode
+    // keeps its schedule
+    if (!S->ladder_done && S->publish_mode != MGD_PUBLISH_DETERMINISTIC &&
+        (conv || (op.prov_tol > 0.0 && S->rk <= op.prov_tol * S->r_ref)))
+        return await_publish(S, blocking);
     S->k++;
-    if ((rc = enqueue_check(S, nparts))) return rc;
+    if (S->spec) {  // the next cycle and its check are queued already
+        S->spec = false;
+        return 0;
+    }
+    if (S->ncyc >= op.max_cycles) {
+        S->k--;
+        S->status = conv ? MGD_ESTARVED : MGD_ENOCONV;
+        finish(S);
+        return 1;
+    }
+    if ((rc = enqueue_cycle(S, false))) return rc;
     return 0;
 }
 
@@ -578,6 +638,13 @@ size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest
     ops += (size_t)(m > 0 ? m * m : 1) * 8;
     if (m <= kCinvMax) ops += (size_t)(m > 0 ? m * m : 1) * 8;
     size_t hier = ops + vec + (precision == MGD_MIXED ? (size_t)NV0 * H * 4 + NV0 : 0);
+    if (precision == MGD_MIXED) {  // FP64 coarsening scratch
+        hier += (size_t)NV0 * H * 8;
+        if (nlev > 1) {
+            hier += (size_t)ipow(nl[1] + 1, dim) * H * 8;
+            if (transfer == MGD_BOXMG) hier += (size_t)NV0 * nlw * 8;
+        }
+    }
     int64_t nb = (NV0 + 255) / 256 + (n + 1) / 4 + 64;
     int64_t pcap = 2 * nb > m + 64 ? 2 * nb : m + 64;
     hier += 2 * (size_t)pcap * 8 + 64 * 8;  // two partial lists, device scalars

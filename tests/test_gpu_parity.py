@@ -514,6 +514,32 @@ def test_solve_async_lazy_equals_upfront(ctx, d, n):
     assert rel_err(host(u2), host(u1)) < 1e-8
 
 
+@pytest.mark.parametrize("prov_tol", [0.1, 1.0])
+@pytest.mark.parametrize("publish", ["async", "every"])
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
+def test_solve_lazy_provisional_target_equals_upfront(ctx, d, n, publish, prov_tol):
+    """Cycling on a provisional operator stops at the provisional target and
+    the solver waits for the pending operator: same final operator, same
+    solution as the up-front schedule.  With a target of 1 every provisional
+    operator is published before any cycle runs on it, so the first checks
+    all see the zero initial guess."""
+    fld = W.balls_field(d, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=8, tol=1e-10, transfer=P.BOXMG, outer=P.PCG)
+    pub = P.PUBLISH_ASYNC if publish == "async" else P.PUBLISH_EVERY
+    u1, r1 = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.UPFRONT, **kw)
+    u2, r2 = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, publish=pub, prov_tol=prov_tol, **kw)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r1["cells_at_s"] == r2["cells_at_s"]
+    assert rel_err(host(u2), host(u1)) < 1e-8
+    assert r2["publishes"] >= 1
+    if prov_tol == 1.0:
+        npub = r2["publishes"]
+        assert r2["hist"][: npub + 1] == [1.0] * (npub + 1)
+        assert len(r2["hist"]) == r2["cycles"] + 1 + npub
+        assert abs(r2["cycles"] - r1["cycles"]) <= 1
+
+
 def test_solve_mixed_error_against_fp64_oracle(ctx):
     """Mixed form (bf16x2 MFMA integration, FP16 surplus store, FP32 cycle,
     FP64 outer PCG) against the FP64 oracle solution of the same problem:

@@ -65,6 +65,20 @@ def test_mix_matches_alone_async(ctx):
         assert e <= 1e-6, (i, e)
 
 
+def test_mix_equals_alone_parked(ctx):
+    """Provisional target 1: every request parks on its provisional operator
+    until the final one is built (without blocking the server), then cycles
+    from the zero guess: bitwise the same result alone and in the mix."""
+    kw = dict(BASE, publish=P.PUBLISH_ASYNC, prov_tol=1.0)
+    reqs = make_requests(SHAPES, seed0=300)
+    ref = alone(ctx, reqs, **kw)
+    res = serving.replay(ctx, reqs, None, max_slots=4, keep=True, **kw)
+    assert (res["status"] == P.OK).all()
+    for i, (u, cyc) in enumerate(ref):
+        assert res["cycles"][i] == cyc, i
+        assert torch.equal(res["solutions"][i], u), i
+
+
 def test_budget_admission(ctx):
     kw = dict(BASE, publish=P.PUBLISH_DETERMINISTIC)
     shapes = [(2, 64), (2, 32), (2, 64)]
