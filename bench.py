@@ -2,13 +2,15 @@
 """Benchmark of the delayed-assembly multigrid hot path on one MI355X.
 
 Workload: 2D unit square, 1024 x 1024 Q1 cells, eps = 1 with 200 seeded balls
-(radius 0.005-0.05) of eps = 1e3, load of u = sin(pi x) sin(pi y); the lazy
-ladder s = 2, 4, 8, 16 runs while V-cycles run.  One step = one complete
-solve to a 1e-8 relative residual of the mixed form (bf16 hi+lo MFMA
-integration, FP16 surplus store, FP32 BoxMG V(2,2), FP64 outer conjugate
-gradients) with lazy assembly; the plain FP64 form with up-front assembly is
-timed beside it.  Inputs (load vector, material data) are resident in HBM
-before timing.
+(radius 0.005-0.05) of eps = 1e3, load of u = sin(pi x) sin(pi y).  Lazily,
+V-cycles start on the centre-sample operator while the ladder s = 2, 4, 8,
+16 runs on a second stream.  One step = one complete solve to a 1e-8
+relative residual of the mixed form (bf16 hi+lo MFMA integration, FP16
+surplus store, FP32 BoxMG V(2,2), FP64 outer conjugate gradients) with lazy
+assembly; the plain FP64 form with up-front assembly is timed beside it.
+Inputs (load vector, material data) are resident in HBM before timing.  The
+same comparison is repeated at 4096^2 cells, where the operators no longer
+fit in the 256 MB Infinity Cache.
 
 Prints one JSON line.  `value` is the mixed-lazy form's fine-grid V-cycle
 throughput over the whole solve: (n-1)^2 DoF x V-cycles / time-to-solution.
@@ -67,21 +69,26 @@ def cpu_baseline(fld, d, n, f, cycles):
                        f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
 
 
-SWEEP_KERNEL = "k_lev2<float, 16, 3, true, true, false, false>"  # pre half: 2 sweeps + residual + restriction
+SWEEP_KERNEL = "k_lev2<float, 16, 0, true, true, false, false>"  # pre half: 2 sweeps + residual
+PASSES_PER_LAUNCH = 3  # stencil passes one launch performs: two Jacobi sweeps and the residual
 # Memory traffic per launch of SWEEP_KERNEL at n (bytes), from FETCH_SIZE and
 # WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
 # copy; valid only for the kernel version they were taken on.
-SWEEP_TRAFFIC = {}
+SWEEP_TRAFFIC = {1024: 23223264, 4096: 298786648}
 
 
 def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
-    """Pre-smoothing half of the finest level of the mixed V-cycle (two
-    damped-Jacobi sweeps from zero, the residual and its restriction, one
-    pass over the compressed store): the kernel the mixed cycle moves most
-    of its bytes in.  Timed with HIP events on the stream it runs on, same
-    kernel and launch shape as in the solve.  Algorithmic bytes per launch:
-    store payload + tier byte and offset per tile + FP32 centre sample per
-    cell + FP32 f in, u out, coarse rhs out, and the BoxMG weights read."""
+    """Pre-smoothing half of the finest level of the mixed V-cycle: two
+    damped-Jacobi sweeps from zero and the residual in one pass over the
+    compressed store, the kernel the mixed cycle moves most of its bytes in.
+    Timed with HIP events on the stream it runs on, same kernel and launch
+    shape as in the solve.
+
+    Algorithmic bytes, per DoF and stencil pass (a Jacobi sweep or the
+    residual): the stencil (store payload + tier byte and offset per tile +
+    FP32 centre sample per cell) + FP32 u in, f in, u (or r) out.  One launch
+    performs PASSES_PER_LAUNCH such passes; fused, it moves the bytes of about
+    one (store, f in, u out, r out), reported as the single-pass figure."""
     import torch
     h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
     K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
@@ -93,31 +100,75 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     ntile, payload, tier_tiles = h.store_info()
     NV = (n + 1) ** d
     store_bytes = payload + 5 * ntile + 4 * n ** d
-    # f in, u out (FP32), the coarse rhs out, and the BoxMG weights the
-    # restriction reads: 9 per interior coarse vertex
-    nc = n // 2
-    alg_bytes = store_bytes + 8 * NV + 4 * (nc + 1) ** d + 4 * 9 * (nc - 1) ** d
+    pass_bytes = store_bytes + 12 * NV
+    alg_bytes = PASSES_PER_LAUNCH * pass_bytes
     f32 = torch.ones(NV, dtype=torch.float32, device="cuda")
     u32 = torch.zeros_like(f32)
-    fc32 = torch.zeros(h.nv(1), dtype=torch.float32, device="cuda")
+    r32 = torch.zeros_like(f32)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     st = torch.cuda.current_stream()
-    h.presmooth_restrict(0, None, f32, u32, fc32)
+    h.presmooth(0, None, f32, u32, r32)
     torch.cuda.synchronize()
     calls = max(sweeps, 1)
     ev[0].record(st)
     for _ in range(calls):
-        h.presmooth_restrict(0, None, f32, u32, fc32)
+        h.presmooth(0, None, f32, u32, r32)
     ev[1].record(st)
     torch.cuda.synchronize()
     avg_ms = ev[0].elapsed_time(ev[1]) / calls
     h.close()
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    single = pass_bytes / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": SWEEP_TRAFFIC.get(n),
-            "kernel": SWEEP_KERNEL,
-            "bytes_per_launch": int(alg_bytes), "avg_launch_us": round(avg_ms * 1e3, 3),
-            "store_tiers": tier_tiles}
+            "kernel": SWEEP_KERNEL, "bytes_per_launch": int(alg_bytes),
+            "stencil_passes_per_launch": PASSES_PER_LAUNCH, "single_pass_bytes": int(pass_bytes),
+            "single_pass_frac": round(single / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(avg_ms * 1e3, 3), "store_tiers": tier_tiles}
+
+
+def solve_forms(P, W, n, steps, warmup, tiers):
+    """Time-to-1e-8 of the mixed-lazy and the FP64-up-front forms on the
+    balls workload at n^2 cells; each form keeps its device-resident solve
+    state in its own context, so neither timed loop re-creates the other's
+    workspace."""
+    import torch
+    d = 2
+    eps = P.Eps(W.config_field(1))
+    f_host = W.load_sine(d, n)
+    f = torch.from_numpy(f_host).cuda()
+    mixed = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=16,
+                 tol=1e-8, max_cycles=600, **tiers)
+    fp64 = dict(precision=P.FP64, schedule=P.UPFRONT, transfer=P.BOXMG, outer=P.PCG, s_max=16,
+                tol=1e-8, max_cycles=600)
+    ctx_m, ctx_f = P.Context(0), P.Context(0)
+
+    def run(kw):
+        u = torch.zeros_like(f)
+        return P.solve(ctx_m if kw is mixed else ctx_f, d, n, eps, f, u, **kw)
+
+    for _ in range(warmup):
+        run(mixed)
+        run(fp64)
+    torch.cuda.synchronize()
+    reps_m, reps_f = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        um, rm = run(mixed)
+        reps_m.append(rm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        uf, rf = run(fp64)
+        reps_f.append(rf)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert all(r["status"] == 0 for r in reps_m + reps_f), [r["status"] for r in reps_m + reps_f]
+    err = float(torch.linalg.norm(um - uf) / torch.linalg.norm(uf))
+    ctx_m.close()
+    ctx_f.close()
+    return dict(ms_mixed=(t1 - t0) / steps * 1e3, ms_fp64=(t2 - t1) / steps * 1e3, rep_m=reps_m[-1],
+                rep_f=reps_f[-1], err=err, eps=eps, f_host=f_host)
 
 
 def kernels_only(args):
@@ -135,7 +186,6 @@ def kernels_only(args):
     for _ in range(4):
         b.copy_(a)
     torch.cuda.synchronize()
-    ctx_f.close()
     ctx.close()
     print(json.dumps({"sweep": r, "copy_bytes_each_way": nbytes, "copies": 4}), flush=True)
 
@@ -206,48 +256,16 @@ def main():
     import workload as W
 
     d, n = 2, args.n
-    ctx = P.Context(0)
-    fld = W.config_field(1)
-    eps = P.Eps(fld)
-    f_host = W.load_sine(d, n)
-    f = torch.from_numpy(f_host).cuda()
     tiers = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
-    mixed = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=16,
-                 tol=1e-8, max_cycles=400, **tiers)
-    fp64 = dict(precision=P.FP64, schedule=P.UPFRONT, transfer=P.BOXMG, outer=P.PCG, s_max=16,
-                tol=1e-8, max_cycles=400)
-
-    # each form keeps its device-resident solve state in its own context, so
-    # neither timed loop pays for re-creating the other's workspace
-    ctx_f = P.Context(0)
-
-    def run(kw):
-        u = torch.zeros_like(f)
-        return P.solve(ctx if kw is mixed else ctx_f, d, n, eps, f, u, **kw)
-
-    for _ in range(args.warmup):
-        run(mixed)
-        run(fp64)
-    torch.cuda.synchronize()
-    reps_m, reps_f = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        um, rm = run(mixed)
-        reps_m.append(rm)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        uf, rf = run(fp64)
-        reps_f.append(rf)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ms_mixed = (t1 - t0) / args.steps * 1e3
-    ms_fp64 = (t2 - t1) / args.steps * 1e3
-    assert all(r["status"] == 0 for r in reps_m + reps_f), [r["status"] for r in reps_m + reps_f]
+    fld = W.config_field(1)
+    main_run = solve_forms(P, W, n, args.steps, args.warmup, tiers)
+    ms_mixed, ms_fp64 = main_run["ms_mixed"], main_run["ms_fp64"]
+    rep_m, rep_f = main_run["rep_m"], main_run["rep_f"]
+    eps, f_host, err = main_run["eps"], main_run["f_host"], main_run["err"]
     dof = (n - 1) ** d
-    cyc_m = reps_m[-1]["cycles"]
+    cyc_m = rep_m["cycles"]
     value = dof * cyc_m / (ms_mixed / 1e3)
-    err = float(torch.linalg.norm(um - uf) / torch.linalg.norm(uf))
+    ctx = P.Context(0)
 
     # cell integrations per second (all cells, s = 16), both precisions
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -263,43 +281,51 @@ def main():
         integ[name] = n ** d * reps / (ev[0].elapsed_time(ev[1]) / 1e3)
 
     roofline = sweep_roofline(ctx, P, d, n, eps, tiers, args.sweeps)
-    big = None
+    big = big_tts = None
     if args.big_n > 0:
         big_eps = P.Eps(W.config_field(1))
         big = sweep_roofline(ctx, P, d, args.big_n, big_eps, tiers, args.sweeps)
-        big = {k: big[k] for k in ("achieved", "frac", "bytes_per_launch", "avg_launch_us", "store_tiers")}
+        big = {k: big[k] for k in ("achieved", "frac", "single_pass_frac", "bytes_per_launch", "avg_launch_us",
+                                   "store_tiers")}
         big["workload"] = f"same material, {args.big_n}^2 cells (store and vectors beyond the 256 MB Infinity Cache)"
+        b = solve_forms(P, W, args.big_n, 2, 1, tiers)
+        big_tts = {"workload": f"same material and load at {args.big_n}^2 cells (beyond the Infinity Cache)",
+                   "time_to_1e8_mixed_lazy_ms": round(b["ms_mixed"], 3),
+                   "time_to_1e8_fp64_upfront_ms": round(b["ms_fp64"], 3),
+                   "speedup_mixed_lazy_vs_fp64_upfront": round(b["ms_fp64"] / b["ms_mixed"], 3),
+                   "cycles_mixed_lazy": b["rep_m"]["cycles"], "cycles_fp64_upfront": b["rep_f"]["cycles"],
+                   "mixed_vs_fp64_solution_rel_err": b["err"]}
     NV = (n + 1) ** d
 
     out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_mixed, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "bf16x2-mfma/f16-store/f32-cycle/f64-outer",
            "data": "synthetic",
-           "config": {"workload": WORKLOAD, "cells": n ** d, "dof": dof, "levels": reps_m[-1]["nlev"]},
+           "config": {"workload": WORKLOAD, "cells": n ** d, "dof": dof, "levels": rep_m["nlev"]},
            "components": {
                "time_to_1e8_mixed_lazy_ms": round(ms_mixed, 3),
                "time_to_1e8_fp64_upfront_ms": round(ms_fp64, 3),
                "speedup_mixed_lazy_vs_fp64_upfront": round(ms_fp64 / ms_mixed, 3),
-               "cycles_mixed_lazy": cyc_m, "cycles_fp64_upfront": reps_f[-1]["cycles"],
-               "publishes_mixed_lazy": reps_m[-1]["publishes"],
-               "vcycle_dof_per_s_fp64_upfront": dof * reps_f[-1]["cycles"] / (ms_fp64 / 1e3),
+               "cycles_mixed_lazy": cyc_m, "cycles_fp64_upfront": rep_f["cycles"],
+               "publishes_mixed_lazy": rep_m["publishes"],
+               "vcycle_dof_per_s_fp64_upfront": dof * rep_f["cycles"] / (ms_fp64 / 1e3),
                "cell_integrations_per_s_s16": {k: round(v, 1) for k, v in integ.items()},
-               "cell_integrations_per_solve": reps_m[-1]["integrations"],
-               "cells_at_s_1_2_4_8_16": reps_m[-1]["cells_at_s"],
-               "store_bytes_per_stencil_mixed": reps_m[-1]["store_bytes"] / NV,
-               "store_bytes_per_stencil_fp64": reps_f[-1]["store_bytes"] / NV,
+               "cell_integrations_per_solve": rep_m["integrations"],
+               "cells_at_s_1_2_4_8_16": rep_m["cells_at_s"],
+               "store_bytes_per_stencil_mixed": rep_m["store_bytes"] / NV,
+               "store_bytes_per_stencil_fp64": rep_f["store_bytes"] / NV,
                "mixed_vs_fp64_solution_rel_err": err,
-               "t_first_cycle_ms_mixed_lazy": round(reps_m[-1]["t_first_cycle_ms"], 3),
-               "t_first_cycle_ms_fp64_upfront": round(reps_f[-1]["t_first_cycle_ms"], 3),
+               "t_first_cycle_ms_mixed_lazy": round(rep_m["t_first_cycle_ms"], 3),
+               "t_first_cycle_ms_fp64_upfront": round(rep_f["t_first_cycle_ms"], 3),
            },
            "roofline": roofline}
     if big is not None:
         out["components"]["sweep_roofline_beyond_cache"] = big
+        out["components"]["time_to_solution_beyond_cache"] = big_tts
     if args.serve_requests > 0:
         out["components"]["serving"] = serving_bench(ctx, P, W, args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(fld, d, n, f_host, reps_f[-1]["cycles"])
-    ctx_f.close()
+        out["cpu_baseline"] = cpu_baseline(fld, d, n, f_host, rep_f["cycles"])
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -42,7 +42,7 @@ enum {
     MGD_ENOMEM = -2,    /* device allocation failed */
     MGD_EHIP = -3,      /* a HIP runtime call failed */
     MGD_ENOCONV = -4,   /* max_cycles reached before the tolerance */
-    MGD_EDIVERGED = -5, /* residual exceeded div_factor times its reference */
+    MGD_EDIVERGED = -5, /* stationary: residual above div_factor x reference; CG: non-finite */
     MGD_ESTARVED = -6   /* tolerance met but the assembly never completed */
 };
 
@@ -246,8 +246,10 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * conjugate gradients with one V-cycle as preconditioner (Polak-Ribiere
  * beta, restarted at every publish).  Stops when every cell's ladder is final
  * and published and ||f - A u||_2 / ||r_0||_2 <= tol (interior vertices,
- * r_0 at cycle 0, Sec. 6); MGD_EDIVERGED when the residual exceeds
- * div_factor times the residual at the last operator change.
+ * r_0 at cycle 0, Sec. 6); MGD_EDIVERGED when the residual of the
+ * stationary iteration exceeds div_factor times the residual at the last
+ * operator change, or when a CG residual is not finite (the CG residual
+ * norm is not monotone: its transients grow with the condition number).
  * prov_tol (MGD_LAZY with MGD_PUBLISH_ASYNC or MGD_PUBLISH_EVERY): once the
  * residual on a provisional operator has dropped to prov_tol times the
  * residual at the last operator change, the solver stops cycling on it and

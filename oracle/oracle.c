@@ -962,8 +962,9 @@ enum { ORC_OK = 0, ORC_ENOCONV = -4, ORC_EDIVERGED = -5 };
  * cell is integrated and published before cycle k (Sec. 5.1-5.3).  The
  * residual is measured at the start of each cycle with the operator current
  * then, normalised by the first one (Sec. 6); the run stops when every cell
- * is final and the normalised residual is at most tol, and aborts when it
- * exceeds div_factor.                                                      */
+ * is final and the normalised residual is at most tol; the stationary
+ * iteration aborts when the residual exceeds div_factor times its reference,
+ * CG only on a non-finite residual.                                        */
 int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, const orc_opts *op, orc_report *rep)
 {
     int nl = 1 << d, nn = nl * nl;
@@ -1045,7 +1046,9 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
         int all_done = 1;
         for (int64_t c = 0; c < nc && all_done; ++c) all_done = done[c];
         if (all_done && rel <= op->tol) { status = ORC_OK; break; }
-        if (!(rk <= op->div_factor * r_ref)) { status = ORC_EDIVERGED; break; }
+        /* the guard watches the stationary iteration; the CG residual norm is
+         * not monotone, so CG stops only on a non-finite residual */
+        if (op->outer == 0 ? !(rk <= op->div_factor * r_ref) : !isfinite(rk)) { status = ORC_EDIVERGED; break; }
         if (k == op->max_cycles) break;
         if (op->outer == 0) {
             orc_mg_vcycle(g, u, f, op->omega, op->nu1, op->nu2);

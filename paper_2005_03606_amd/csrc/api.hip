@@ -49,13 +49,6 @@ int hier_alloc_levels(mgd_hier *h)
     if (h->precision == MGD_MIXED) {
         if ((rc = dev_alloc(ctx, (void **)&h->delta, (size_t)h->NV[0] * h->H * 4))) return rc;
         if ((rc = dev_alloc(ctx, (void **)&h->vtier, (size_t)h->NV[0]))) return rc;
-        if ((rc = dev_alloc(ctx, (void **)&h->gal64[0], (size_t)h->NV[0] * h->H * 8))) return rc;
-        if (h->nlev > 1) {
-            if ((rc = dev_alloc(ctx, (void **)&h->gal64[1], (size_t)h->NV[1] * h->H * 8))) return rc;
-            if (h->transfer == MGD_BOXMG &&
-                (rc = dev_alloc(ctx, (void **)&h->w64, (size_t)h->NV[0] * ((size_t)1 << h->dim) * 8)))
-                return rc;
-        }
     }
     int64_t nb = (h->NV[0] + 255) / 256 + (h->nl[0] + 1) / 4 + 64;
     h->partial_cap = 2 * nb > h->m_coarse + 64 ? 2 * nb : h->m_coarse + 64;
@@ -86,8 +79,6 @@ void hier_free(mgd_hier *h)
     dev_free(h->delta); dev_free(h->vtier);
     h->delta = nullptr;
     h->vtier = nullptr;
-    dev_free(h->gal64[0]); dev_free(h->gal64[1]); dev_free(h->w64);
-    h->gal64[0] = h->gal64[1] = h->w64 = nullptr;
     dev_free(h->partial); dev_free(h->scal);
     h->partial = nullptr;
     h->scal = nullptr;

@@ -208,11 +208,6 @@ struct mgd_hier {
     // scratch for compression
     float *delta = nullptr;
     uint8_t *vtier = nullptr;
-    // mixed form: FP64 coarsening scratch (stencils of a level and of the
-    // next, ping-pong; BoxMG weights of the current level), rounded once into
-    // the FP32 operators of the cycle
-    double *gal64[2] = {nullptr, nullptr};
-    double *w64 = nullptr;
     // reduction scratch and device scalars owned by this hierarchy
     double *partial = nullptr;    // block partial sums / coarse-solve work
     int64_t partial_cap = 0;

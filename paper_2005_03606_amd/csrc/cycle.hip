@@ -842,7 +842,10 @@ static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f
     if (lev2_ok(h, l, nu1, nu2)) {
         // pre half: u (or its spare) <- S^2 u, r <- f - A u; post half into the other buffer
         void *us = zero_guess ? u : h->t[l];
-        if ((rc = lev2_prer(h, o, l, zero_guess ? nullptr : u, f, us, h->f[l + 1], omega, st))) return rc;
+        // (the restriction runs as its own pass: fused into the pre half it
+        // re-reads the transfer weights of the halo and is slower beyond the cache)
+        if ((rc = lev2_pre(h, o, l, zero_guess ? nullptr : u, f, us, h->r[l], omega, st))) return rc;
+        if ((rc = cycle_restrict(h, o, l, h->r[l], h->f[l + 1], st))) return rc;
         void *ec = nullptr;
         if ((rc = vcycle_rec(h, o, l + 1, h->u[l + 1], h->f[l + 1], omega, nu1, nu2, true, nullptr, nullptr, &ec, st)))
             return rc;

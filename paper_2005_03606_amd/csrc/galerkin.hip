@@ -45,21 +45,21 @@ template <int D, typename T> __device__ inline void geo_weights(const int *x, T 
 // BoxMG weights of an interior fine vertex v with odd coordinates: the row of
 // v with offsets along even axes summed (collapsed); each odd-axis neighbour
 // u contributes its own (final) weights wn(uv, u, wu); divided by the
-// collapsed diagonal.
+// collapsed diagonal.  Computed in FP64 whatever the stored type T.
 template <int D, typename T, class WN>
-__device__ inline void boxmg_row(const HalfRow<D, T> &A, const Grid<D> &g, int64_t v, const int *x, WN wn, T *w)
+__device__ inline void boxmg_row(const HalfRow<D, T> &A, const Grid<D> &g, int64_t v, const int *x, WN wn, double *w)
 {
     constexpr int nl = 1 << D, ns = D == 2 ? 9 : 27, c = ns / 2;
-    T acc[nl], diag = (T)0;
-    for (int B = 0; B < nl; ++B) acc[B] = (T)0;
+    double acc[nl], diag = 0.0;
+    for (int B = 0; B < nl; ++B) acc[B] = 0.0;
     // diagonal of the row: minus the sum of its couplings
-    T dsum = (T)0;
+    double dsum = 0.0;
     for (int oi = 0; oi < ns; ++oi)
-        if (oi != c) dsum += A.at(v, oi);
+        if (oi != c) dsum += (double)A.at(v, oi);
     for (int oi = 0; oi < ns; ++oi) {
         int o[3] = {0, 0, 0}, u[3] = {0, 0, 0};
         off_of(D, oi, o);
-        T a = oi == c ? -dsum : A.at(v, oi);
+        double a = oi == c ? -dsum : (double)A.at(v, oi);
         bool self = true;
         for (int m = 0; m < D; ++m) {
             int om = (x[m] & 1) ? o[m] : 0;
@@ -67,10 +67,10 @@ __device__ inline void boxmg_row(const HalfRow<D, T> &A, const Grid<D> &g, int64
             if (om) self = false;
         }
         if (self) { diag += a; continue; }
-        T wu[nl];
+        double wu[nl];
         wn(g.vid(u), u, wu);
         for (int Bu = 0; Bu < nl; ++Bu) {
-            if (wu[Bu] == (T)0) continue;
+            if (wu[Bu] == 0.0) continue;
             int B = 0;
             for (int m = 0; m < D; ++m) B |= (((u[m] >> 1) + ((Bu >> m) & 1)) - (x[m] >> 1)) << m;
             acc[B] -= a * wu[Bu];
@@ -93,27 +93,27 @@ __global__ void k_weights(HalfRow<D, T> A, int n, int pass, T *W)
     for (int m = 0; m < D; ++m) odd += x[m] & 1;
     bool bnd = !g.interior(x);
     constexpr int nl = 1 << D;
-    T w[nl];
+    double w[nl];
     if (pass == 0) {
         if (!(bnd || odd == 0)) return;
-        geo_weights<D, T>(x, w);
+        geo_weights<D, double>(x, w);
     } else {
         if (bnd || odd != pass) return;
         boxmg_row<D, T>(A, g, v, x,
-                        [&](int64_t uv, const int *, T *wu) {
-                            for (int Bu = 0; Bu < nl; ++Bu) wu[Bu] = W[(int64_t)Bu * g.NV + uv];
+                        [&](int64_t uv, const int *, double *wu) {
+                            for (int Bu = 0; Bu < nl; ++Bu) wu[Bu] = (double)W[(int64_t)Bu * g.NV + uv];
                         },
                         w);
     }
-    for (int B = 0; B < nl; ++B) W[(int64_t)B * g.NV + v] = w[B];
+    for (int B = 0; B < nl; ++B) W[(int64_t)B * g.NV + v] = (T)w[B];
 }
 
 // 2D in two launches: phase 0 sets the boundary, even-even (d-linear) and
 // one-odd vertices (their odd-axis neighbours are even-even, whose weights
 // are d-linear); phase 1 the vertices with both coordinates odd, from the
-// stored weights of their neighbours.  W32: optional FP32 copy.
+// stored weights of their neighbours
 template <typename T, int PHASE>
-__global__ __launch_bounds__(256) void k_weights2(HalfRow<2, T> A, int n, T *W, float *W32)
+__global__ __launch_bounds__(256) void k_weights2(HalfRow<2, T> A, int n, T *W)
 {
     Grid<2> g(n);
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,22 +123,19 @@ __global__ __launch_bounds__(256) void k_weights2(HalfRow<2, T> A, int n, T *W, 
     const int odd = (x[0] & 1) + (x[1] & 1);
     const bool in = g.interior(x);
     if ((PHASE == 1) != (in && odd == 2)) return;
-    T w[4];
+    double w[4];
     if (!in || odd == 0) {
-        geo_weights<2, T>(x, w);
+        geo_weights<2, double>(x, w);
     } else if (odd == 1) {
-        boxmg_row<2, T>(A, g, v, x, [&](int64_t, const int *u, T *wu) { geo_weights<2, T>(u, wu); }, w);
+        boxmg_row<2, T>(A, g, v, x, [&](int64_t, const int *u, double *wu) { geo_weights<2, double>(u, wu); }, w);
     } else {
         boxmg_row<2, T>(A, g, v, x,
-                        [&](int64_t uv, const int *, T *wu) {
-                            for (int Bu = 0; Bu < 4; ++Bu) wu[Bu] = W[(int64_t)Bu * g.NV + uv];
+                        [&](int64_t uv, const int *, double *wu) {
+                            for (int Bu = 0; Bu < 4; ++Bu) wu[Bu] = (double)W[(int64_t)Bu * g.NV + uv];
                         },
                         w);
     }
-    for (int B = 0; B < 4; ++B) {
-        W[(int64_t)B * g.NV + v] = w[B];
-        if (W32) W32[(int64_t)B * g.NV + v] = (float)w[B];
-    }
+    for (int B = 0; B < 4; ++B) W[(int64_t)B * g.NV + v] = (T)w[B];
 }
 
 // weight of fine vertex x toward coarse vertex X (0 unless X is a corner of x's box)
@@ -161,19 +158,18 @@ __device__ inline T weight_to(const T *W, int64_t NV, int64_t v, const int *x, c
 // valid because every row of A sums to zero and P reproduces constants.  The
 // 3^d fine vertices v around 2X are taken by separate threads (CPB coarse
 // vertices per workgroup) and their partial sums are added in v order.
-// Sc32: optional FP32 copy.
+// Computed in FP64 whatever the stored type T.
 template <int D> constexpr int gal_cpb() { return D == 2 ? 32 : 8; }
 template <int D, typename T>
-__global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T> A, const T *W, int nf, T *Sc,
-                                                                    float *Sc32)
+__global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T> A, const T *W, int nf, T *Sc)
 {
     constexpr int H = n_half(D), ns = D == 2 ? 9 : 27, c = ns / 2, CPB = gal_cpb<D>();
-    __shared__ T part[ns][CPB][H];
+    __shared__ double part[ns][CPB][H];
     Grid<D> gf(nf), gc(nf / 2);
     const int cv = threadIdx.x % CPB, sv = threadIdx.x / CPB;
     const int64_t V = (int64_t)blockIdx.x * CPB + cv;
-    T acc[H];
-    for (int j = 0; j < H; ++j) acc[j] = (T)0;
+    double acc[H];
+    for (int j = 0; j < H; ++j) acc[j] = 0.0;
     int X[3] = {0, 0, 0};
     if (V < gc.NV) {
         gc.coords(V, X);
@@ -185,13 +181,13 @@ __global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T>
             if (x[m] < 0 || x[m] > nf) ok = false;
         }
         const int64_t v = ok ? gf.vid(x) : 0;
-        const T pV = ok ? weight_to<D, T>(W, gf.NV, v, x, X) : (T)0;
-        if (pV != (T)0) {
-            T pvW[H];
+        const double pV = ok ? (double)weight_to<D, T>(W, gf.NV, v, x, X) : 0.0;
+        if (pV != 0.0) {
+            double pvW[H];
             for (int j = 0; j < H; ++j) {
                 int XW[3] = {0, 0, 0};
                 for (int m = 0; m < D; ++m) XW[m] = X[m] + half_off(D, j, m);
-                pvW[j] = weight_to<D, T>(W, gf.NV, v, x, XW);
+                pvW[j] = (double)weight_to<D, T>(W, gf.NV, v, x, XW);
             }
             for (int oi = 0; oi < ns; ++oi) {
                 if (oi == c) continue;
@@ -204,13 +200,13 @@ __global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T>
                 }
                 if (!okw) continue;
                 const int64_t w = gf.vid(y);
-                const T a = A.at(v, oi);
-                if (a == (T)0) continue;
-                const T pa = pV * a;
+                const double a = (double)A.at(v, oi);
+                if (a == 0.0) continue;
+                const double pa = pV * a;
                 for (int j = 0; j < H; ++j) {
                     int XW[3] = {0, 0, 0};
                     for (int m = 0; m < D; ++m) XW[m] = X[m] + half_off(D, j, m);
-                    acc[j] += pa * (weight_to<D, T>(W, gf.NV, w, y, XW) - pvW[j]);
+                    acc[j] += pa * ((double)weight_to<D, T>(W, gf.NV, w, y, XW) - pvW[j]);
                 }
             }
         }
@@ -221,7 +217,7 @@ __global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T>
         const int c2 = t / H, j = t % H;
         const int64_t V2 = (int64_t)blockIdx.x * CPB + c2;
         if (V2 >= gc.NV) continue;
-        T sum = (T)0;
+        double sum = 0.0;
         for (int k = 0; k < ns; ++k) sum += part[k][c2][j];
         int X2[3] = {0, 0, 0};
         gc.coords(V2, X2);
@@ -231,9 +227,7 @@ __global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T>
             int Y = X2[m] + half_off(D, j, m);
             if (Y < 0 || Y > gc.n) inside = false;
         }
-        const T out = inside ? sum : (T)0;
-        Sc[(int64_t)j * gc.NV + V2] = out;
-        if (Sc32) Sc32[(int64_t)j * gc.NV + V2] = (float)out;
+        Sc[(int64_t)j * gc.NV + V2] = inside ? (T)sum : (T)0;
     }
 }
 
@@ -315,45 +309,40 @@ __global__ void k_chol_inverse(const double *L, int64_t m, double *Ainv)
     }
 }
 
-int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st);
-
-__global__ void k_f64_to_f32(const double *in, int64_t cnt, float *out)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) out[i] = (float)in[i];
-}
-
 template <int D, typename T>
-static void weights_launch(const HalfRow<D, T> &A, int nf, int64_t NV, T *W, float *W32, hipStream_t st)
+static void weights_launch(const HalfRow<D, T> &A, int nf, int64_t NV, T *W, hipStream_t st)
 {
     dim3 gv(grid_for(NV, 256));
     if constexpr (D == 2) {
-        hipLaunchKernelGGL((k_weights2<T, 0>), gv, dim3(256), 0, st, A, nf, W, W32);
-        hipLaunchKernelGGL((k_weights2<T, 1>), gv, dim3(256), 0, st, A, nf, W, W32);
+        hipLaunchKernelGGL((k_weights2<T, 0>), gv, dim3(256), 0, st, A, nf, W);
+        hipLaunchKernelGGL((k_weights2<T, 1>), gv, dim3(256), 0, st, A, nf, W);
     } else {
         for (int pass = 0; pass <= D; ++pass)
             hipLaunchKernelGGL((k_weights<D, T>), gv, dim3(256), 0, st, A, nf, pass, W);
-        if constexpr (sizeof(T) == 8)
-            if (W32) hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(NV << D, 256)), dim3(256), 0, st, W, NV << D, W32);
     }
 }
 
 template <int D, typename T>
-static void galerkin_launch(const HalfRow<D, T> &A, const T *W, int nf, int64_t NVc, T *Sc, float *Sc32, hipStream_t st)
+static void galerkin_launch(const HalfRow<D, T> &A, const T *W, int nf, int64_t NVc, T *Sc, hipStream_t st)
 {
     constexpr int CPB = gal_cpb<D>(), ns = D == 2 ? 9 : 27;
-    hipLaunchKernelGGL((k_galerkin_p<D, T>), dim3(grid_for(NVc, CPB)), dim3(CPB * ns), 0, st, A, W, nf, Sc, Sc32);
+    hipLaunchKernelGGL((k_galerkin_p<D, T>), dim3(grid_for(NVc, CPB)), dim3(CPB * ns), 0, st, A, W, nf, Sc);
 }
 
+int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st);
+
+// weights, Galerkin products and the coarsest matrix in FP64 arithmetic; the
+// mixed form stores the levels in FP32 (its finest level: the FP32 decode of
+// the store)
 template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *const *S, hipStream_t st)
 {
     mgd_ctx *ctx = h->ctx;
     for (int l = 0; l + 1 < h->nlev; ++l) {
         HalfRow<D, T> A{S[l], h->NV[l], (int64_t)h->nl[l] + 1};
         T *W = (T *)o.W[l];
-        if (h->transfer == MGD_BOXMG) weights_launch<D, T>(A, h->nl[l], h->NV[l], W, nullptr, st);
+        if (h->transfer == MGD_BOXMG) weights_launch<D, T>(A, h->nl[l], h->NV[l], W, st);
         galerkin_launch<D, T>(A, (const T *)(h->transfer == MGD_BOXMG ? W : nullptr), h->nl[l], h->NV[l + 1],
-                              S[l + 1], nullptr, st);
+                              S[l + 1], st);
     }
     int lc = h->nlev - 1;
     HalfRow<D, T> Ac{S[lc], h->NV[lc], (int64_t)h->nl[lc] + 1};
@@ -364,42 +353,13 @@ template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *cons
     return MGD_OK;
 }
 
-int decode_level_f64(mgd_hier *h, const OpSet &o, int level, double *out, hipStream_t st);
-
-// Mixed form: the weights, the Galerkin products and the coarsest matrix are
-// computed in FP64 from the FP64 decode of the finest store, level by level
-// on two scratch buffers, and each level's result is rounded once to FP32
-// for the cycle.  (Accumulating the products in FP32 loses the small
-// eigenvalues that high-contrast inclusions leave on the coarse grids.)
-template <int D> static int coarsen_mixed_t(mgd_hier *h, OpSet &o, hipStream_t st)
-{
-    mgd_ctx *ctx = h->ctx;
-    int rc;
-    if ((rc = decode_store_f32(h, o, st))) return rc;  // the FP32 finest operator of the unfused kernels
-    if ((rc = decode_level_f64(h, o, 0, h->gal64[0], st))) return rc;
-    const double *Sin = h->gal64[0];
-    for (int l = 0; l + 1 < h->nlev; ++l) {
-        double *Sout = h->gal64[(l + 1) & 1];
-        HalfRow<D, double> A{Sin, h->NV[l], (int64_t)h->nl[l] + 1};
-        const bool box = h->transfer == MGD_BOXMG;
-        if (box) weights_launch<D, double>(A, h->nl[l], h->NV[l], h->w64, (float *)o.W[l], st);
-        galerkin_launch<D, double>(A, box ? h->w64 : nullptr, h->nl[l], h->NV[l + 1], Sout, o.S32[l + 1], st);
-        Sin = Sout;
-    }
-    int lc = h->nlev - 1;
-    HalfRow<D, double> Ac{Sin, h->NV[lc], (int64_t)h->nl[lc] + 1};
-    hipLaunchKernelGGL((k_dense_assemble<D, double>), dim3(1), dim3(256), 0, st, Ac, h->nl[lc], h->m_coarse, o.chol);
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, st, o.chol, h->m_coarse);
-    if (o.cinv) hipLaunchKernelGGL(k_chol_inverse, dim3(1), dim3((unsigned)kCinvMax), 0, st, o.chol, h->m_coarse, o.cinv);
-    HIPCHK(ctx, hipGetLastError());
-    return MGD_OK;
-}
-
 int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st)
 {
     if (h->precision == MGD_FP64)
         return h->dim == 2 ? coarsen_t<2, double>(h, o, o.S64, st) : coarsen_t<3, double>(h, o, o.S64, st);
-    return h->dim == 2 ? coarsen_mixed_t<2>(h, o, st) : coarsen_mixed_t<3>(h, o, st);
+    int rc = decode_store_f32(h, o, st);
+    if (rc) return rc;
+    return h->dim == 2 ? coarsen_t<2, float>(h, o, o.S32, st) : coarsen_t<3, float>(h, o, o.S32, st);
 }
 
 template <typename TI> __global__ void k_w_to_f64(const TI *in, int64_t cnt, double *out)

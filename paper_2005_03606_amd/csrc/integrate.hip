@@ -401,12 +401,14 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
     const int64_t blk0 = (int64_t)blockIdx.x * (64 * TPW);
     if (blk0 >= cnt) return;  // past the device-side count: the whole block leaves
     int s = a.s, n = a.n;
-    // candidate box: thread t stands for entries blk0 + t + 256 j
+    // candidate box: thread t stands for entries blk0 + t + 256 j of the
+    // block's 64 TPW
     int clo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, chi[3] = {-1, -1, -1};
     bool any = false;
-    for (int j = 0; j < TPW; ++j) {
-        int64_t i = blk0 + threadIdx.x + 256 * j;
-        if (i < cnt) {
+    for (int j = 0; j * 256 < 64 * TPW; ++j) {
+        const int t = (int)threadIdx.x + 256 * j;
+        int64_t i = blk0 + t;
+        if (t < 64 * TPW && i < cnt) {
             int cj[3] = {0, 0, 0};
             cell_coords<D>(a.cells ? a.cells[i] : i, n, cj);
             for (int m = 0; m < D; ++m) {

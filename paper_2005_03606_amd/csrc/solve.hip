@@ -9,6 +9,8 @@
 
 #include <chrono>
 
+#include <cmath>
+
 #include "common.h"
 #include "solve.h"
 
@@ -542,7 +544,10 @@ int solve_step(SolveState *S, bool blocking)
     if (S->k < MGD_HIST) S->rep->hist[S->k] = rel;
     // the device gate of a queued cycle takes the same decision on the same value
     const bool conv = rr <= S->thr;
-    if (!(S->rk <= op.div_factor * S->r_ref)) {
+    // divergence guard of the stationary iteration; the CG residual norm is
+    // not monotone (its transients grow with the condition number), so CG
+    // stops only on a non-finite residual
+    if (S->pcg ? !std::isfinite(S->rk) : !(S->rk <= op.div_factor * S->r_ref)) {
         S->status = MGD_EDIVERGED;
         finish(S);
         return 1;
@@ -638,13 +643,6 @@ size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest
     ops += (size_t)(m > 0 ? m * m : 1) * 8;
     if (m <= kCinvMax) ops += (size_t)(m > 0 ? m * m : 1) * 8;
     size_t hier = ops + vec + (precision == MGD_MIXED ? (size_t)NV0 * H * 4 + NV0 : 0);
-    if (precision == MGD_MIXED) {  // FP64 coarsening scratch
-        hier += (size_t)NV0 * H * 8;
-        if (nlev > 1) {
-            hier += (size_t)ipow(nl[1] + 1, dim) * H * 8;
-            if (transfer == MGD_BOXMG) hier += (size_t)NV0 * nlw * 8;
-        }
-    }
     int64_t nb = (NV0 + 255) / 256 + (n + 1) / 4 + 64;
     int64_t pcap = 2 * nb > m + 64 ? 2 * nb : m + 64;
     hier += 2 * (size_t)pcap * 8 + 64 * 8;  // two partial lists, device scalars

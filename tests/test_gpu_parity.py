@@ -540,6 +540,19 @@ def test_solve_lazy_provisional_target_equals_upfront(ctx, d, n, publish, prov_t
         assert abs(r2["cycles"] - r1["cycles"]) <= 1
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_divergence_guard_only_for_stationary(ctx, precision):
+    d, n = 2, 32
+    fld, f = W.const_field(2, 1.0), dev(W.load_const(d, n))
+    prec = P.FP64 if precision == "fp64" else P.MIXED
+    _, rs = P.solve(ctx, d, n, P.Eps(fld), f, s_fixed=1, tol=1e-10, div_factor=1e-3, precision=prec,
+                    outer=P.STATIONARY)
+    _, rp = P.solve(ctx, d, n, P.Eps(fld), f, s_fixed=1, tol=1e-10, div_factor=1e-3, precision=prec,
+                    outer=P.PCG)
+    assert rs["status"] == P.EDIVERGED and rs["cycles"] == 0
+    assert rp["status"] == P.OK
+
+
 def test_solve_mixed_error_against_fp64_oracle(ctx):
     """Mixed form (bf16x2 MFMA integration, FP16 surplus store, FP32 cycle,
     FP64 outer PCG) against the FP64 oracle solution of the same problem:

@@ -604,6 +604,18 @@ def test_divergence_guard():
     assert rep["status"] == O.EDIVERGED
 
 
+def test_divergence_guard_is_for_the_stationary_iteration():
+    """The CG residual norm is not monotone, so the guard ends only the
+    stationary iteration: with a guard factor below 1 the stationary run
+    stops at its first check, CG runs to the tolerance."""
+    d, n = 2, 16
+    fld, f = W.const_field(2, 1.0), W.load_const(d, n)
+    _, rs = O.solve(fld, d, n, f, s_fixed=1, tol=1e-10, div_factor=1e-3, outer=O.STATIONARY)
+    _, rp = O.solve(fld, d, n, f, s_fixed=1, tol=1e-10, div_factor=1e-3, outer=O.PCG)
+    assert rs["status"] == O.EDIVERGED and rs["cycles"] == 0
+    assert rp["status"] == O.OK
+
+
 # ------------------------------------------------------------------ encoder
 def _rand_deltas(rng, k, H):
     mag = 10.0 ** rng.uniform(-12, 3, size=(k, 1))
