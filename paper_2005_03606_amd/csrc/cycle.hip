@@ -525,10 +525,9 @@ template <int D> __device__ inline bool tail_interior(const int *x, int n)
 // (ZERO: from u = 0), MODE 1 residual uout = f - A u.  CK vertices per
 // thread have their stencil loads in flight together.
 template <int D, typename T, int CK, int MODE>
-__device__ void tail_pass(const TailLevel &lv, const T *uin, T *uout, const T *f, bool zero, T omega)
+__device__ void tail_pass(const TailLevel &lv, const T *S, const T *uin, T *uout, const T *f, bool zero, T omega)
 {
     constexpr int H = n_half(D);
-    const T *S = (const T *)lv.S;
     const int nv = lv.n + 1, NV = lv.NV;
     const int safe = D == 2 ? 1 + nv : 1 + nv + nv * nv;  // an interior vertex
     int lin[H];
@@ -573,20 +572,21 @@ __device__ void tail_pass(const TailLevel &lv, const T *uin, T *uout, const T *f
 }
 
 template <int D, typename T, int MODE>
-__device__ inline void tail_pass_any(const TailLevel &lv, const T *uin, T *uout, const T *f, bool zero, T omega)
+__device__ inline void tail_pass_any(const TailLevel &lv, const T *S, const T *uin, T *uout, const T *f, bool zero,
+                                     T omega)
 {
     // several vertices per thread in flight where registers allow (2D), else one
     constexpr int CK = D == 3 ? 1 : sizeof(T) == 8 ? 3 : 5;
-    if (CK > 1 && lv.NV > kTailThreads) tail_pass<D, T, CK, MODE>(lv, uin, uout, f, zero, omega);
-    else tail_pass<D, T, 1, MODE>(lv, uin, uout, f, zero, omega);
+    if (CK > 1 && lv.NV > kTailThreads) tail_pass<D, T, CK, MODE>(lv, S, uin, uout, f, zero, omega);
+    else tail_pass<D, T, 1, MODE>(lv, S, uin, uout, f, zero, omega);
 }
 
 template <int D, typename T>
-__device__ void tail_smooth(const TailLevel &lv, T *u, const T *f, T *t, int sweeps, bool zero, T omega)
+__device__ void tail_smooth(const TailLevel &lv, const T *S, T *u, const T *f, T *t, int sweeps, bool zero, T omega)
 {
     for (int k = 0; k < sweeps; ++k) {
-        if (k % 2 == 0) tail_pass_any<D, T, 0>(lv, u, t, f, zero && k == 0, omega);
-        else tail_pass_any<D, T, 0>(lv, t, u, f, false, omega);
+        if (k % 2 == 0) tail_pass_any<D, T, 0>(lv, S, u, t, f, zero && k == 0, omega);
+        else tail_pass_any<D, T, 0>(lv, S, t, u, f, false, omega);
     }
     if (sweeps % 2 == 1) {
         for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = t[v];
@@ -600,10 +600,9 @@ __device__ void tail_smooth(const TailLevel &lv, T *u, const T *f, T *t, int swe
 
 // fc = P^T r on the interior coarse vertices, uc = 0
 template <int D, typename T>
-__device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T *r, T *fc, T *uc)
+__device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T *W, const T *r, T *fc, T *uc)
 {
     constexpr int ns = D == 2 ? 9 : 27;
-    const T *W = (const T *)lv.W;
     const int nv = lv.n + 1, NV = lv.NV;
     for (int V = threadIdx.x; V < lc.NV; V += kTailThreads) {
         int X[3] = {0, 0, 0};
@@ -648,10 +647,9 @@ __device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T 
 
 // u += P ec on the interior fine vertices
 template <int D, typename T>
-__device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, T *u, const T *ec)
+__device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, const T *W, T *u, const T *ec)
 {
     constexpr int nl = 1 << D;
-    const T *W = (const T *)lv.W;
     const int ncv = lc.n + 1;
     for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) {
         int x[3] = {0, 0, 0};
@@ -735,6 +733,11 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
     auto U = [&](int l) { return base + a.L[l].off; };
     auto F = [&](int l) { return base + a.L[l].off + a.L[l].NV; };
     auto Tt = [&](int l) { return base + a.L[l].off + 2 * a.L[l].NV; };
+    // stencils and weights are read from memory (L2): a phase is bound by its
+    // barrier-to-barrier dependency chain, and staging them in LDS as well
+    // was measured slower
+    auto Sp = [&](int l) { return (const T *)a.L[l].S; };
+    auto Wp = [&](int l) { return (const T *)a.L[l].W; };
     {
         const TailLevel &l0 = a.L[a.first];
         const T *fg = (const T *)a.f, *ug = (const T *)a.u;
@@ -747,14 +750,14 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
     }
     for (int l = a.first; l < a.last; ++l) {
         const bool zero = l > a.first || a.zero_guess;
-        tail_smooth<D, T>(a.L[l], U(l), F(l), Tt(l), a.nu1, zero, omega);
-        tail_pass_any<D, T, 1>(a.L[l], U(l), Tt(l), F(l), false, omega);
-        tail_restrict<D, T>(a.L[l], a.L[l + 1], Tt(l), F(l + 1), U(l + 1));
+        tail_smooth<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l), a.nu1, zero, omega);
+        tail_pass_any<D, T, 1>(a.L[l], Sp(l), U(l), Tt(l), F(l), false, omega);
+        tail_restrict<D, T>(a.L[l], a.L[l + 1], Wp(l), Tt(l), F(l + 1), U(l + 1));
     }
     tail_coarse<D, T>(a, a.L[a.last], U(a.last), F(a.last), work);
     for (int l = a.last - 1; l >= a.first; --l) {
-        tail_prolong<D, T>(a.L[l], a.L[l + 1], U(l), U(l + 1));
-        tail_smooth<D, T>(a.L[l], U(l), F(l), Tt(l), a.nu2, false, omega);
+        tail_prolong<D, T>(a.L[l], a.L[l + 1], Wp(l), U(l), U(l + 1));
+        tail_smooth<D, T>(a.L[l], Sp(l), U(l), F(l), Tt(l), a.nu2, false, omega);
     }
     {
         T *ug = (T *)a.u;
@@ -833,6 +836,8 @@ static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const vo
 // multiplicative V(nu1,nu2) correction scheme from level l down; *res: the
 // buffer holding the level's result (u, or the level's spare buffer when the
 // fused 2D kernels ran from a zero start)
+constexpr int64_t kPrerMaxNV = 300000;  // levels up to 513 x 513 vertices
+
 static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f, double omega, int nu1, int nu2,
                       bool zero_guess, const Lev2Dots *dots, bool *dots_done, void **res, hipStream_t st)
 {
@@ -842,10 +847,15 @@ static int vcycle_rec(mgd_hier *h, const OpSet &o, int l, void *u, const void *f
     if (lev2_ok(h, l, nu1, nu2)) {
         // pre half: u (or its spare) <- S^2 u, r <- f - A u; post half into the other buffer
         void *us = zero_guess ? u : h->t[l];
-        // (the restriction runs as its own pass: fused into the pre half it
-        // re-reads the transfer weights of the halo and is slower beyond the cache)
-        if ((rc = lev2_pre(h, o, l, zero_guess ? nullptr : u, f, us, h->r[l], omega, st))) return rc;
-        if ((rc = cycle_restrict(h, o, l, h->r[l], h->f[l + 1], st))) return rc;
+        // small levels restrict inside the pre half (one launch less, the
+        // weights stay in cache); large ones run the restriction as its own
+        // pass, since the fused form re-reads the halo's transfer weights
+        if (h->NV[l] <= kPrerMaxNV) {
+            if ((rc = lev2_prer(h, o, l, zero_guess ? nullptr : u, f, us, h->f[l + 1], omega, st))) return rc;
+        } else {
+            if ((rc = lev2_pre(h, o, l, zero_guess ? nullptr : u, f, us, h->r[l], omega, st))) return rc;
+            if ((rc = cycle_restrict(h, o, l, h->r[l], h->f[l + 1], st))) return rc;
+        }
         void *ec = nullptr;
         if ((rc = vcycle_rec(h, o, l + 1, h->u[l + 1], h->f[l + 1], omega, nu1, nu2, true, nullptr, nullptr, &ec, st)))
             return rc;
