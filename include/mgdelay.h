@@ -225,7 +225,8 @@ int mgd_presmooth_restrict(mgd_ctx *ctx, mgd_hier *h, int level, const void *u, 
                            void *fc, double omega, hipStream_t stream);
 
 /* FP64 outer residual r = f - A u of the finest operator as stored (the
- * compressed store decoded in FP64 for MGD_MIXED); u, f, r dev double. */
+ * compressed store's decode for MGD_MIXED: base + surplus summed in FP64
+ * and rounded once to FP32); u, f, r dev double, FP64 arithmetic. */
 int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double *f, double *r,
                        hipStream_t stream);
 

@@ -15,35 +15,6 @@ template <typename T> struct OpHalf {
     __device__ inline T c(int64_t v, int j, const int *) const { return S[(int64_t)j * NV + v]; }
 };
 
-// compressed fine store: base from the centre samples (in T) + decoded delta
-template <int D, typename T> struct OpComp {
-    StoreView sv;
-    int n;
-    T hp;
-    __device__ inline T c(int64_t v, int j, const int *x) const
-    {
-        // x: coordinates of v
-        int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
-        int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
-        T base = (T)0;
-        if (!(D == 3 && nz == 1)) {
-            T sum = (T)0;
-            for (int B = (1 << D) - 1; B >= 0; --B) {
-                bool ok = true;
-                int64_t cc = 0, stride = 1;
-                for (int m = 0; m < D; ++m) {
-                    int bm = (B >> m) & 1, cm = x[m] - bm, wm = bm + o[m];
-                    if (cm < 0 || cm >= n || wm < 0 || wm > 1) ok = false;
-                    cc += (int64_t)cm * stride;
-                    stride *= n;
-                }
-                if (ok) sum += (T)sv.eps_c[cc];
-            }
-            base = sum * (T)kref_unit(D, nz) * hp;
-        }
-        return base + (T)sv.delta(v, j, n_half(D));
-    }
-};
 
 // ------------------------------------------------------------ reductions
 template <int BS> __device__ inline double block_sum(double v, double *red)
@@ -287,7 +258,7 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
             int64_t t = v >> 6;
             int tt = a.sv.tier[t];
             if (tt == 0) {
-                for (int j = 0; j < 4; ++j) c[j] = base[j];
+                for (int j = 0; j < 4; ++j) c[j] = (TC)(float)base[j];  // rounded as the decoded operator
             } else {
                 const uint8_t *bp = a.sv.payload + (size_t)a.sv.off[t] * 64;
                 int l = (int)(v & 63);
@@ -297,7 +268,7 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
                     if (tt == 2) d = (float)__builtin_bit_cast(_Float16, ((const uint16_t *)(bp + 64 + j * 128))[l]) * sc;
                     else if (tt == 1) d = e4m3_to_float(bp[64 + j * 64 + l]) * sc;
                     else d = ((const float *)(bp + 64 + j * 256))[l];
-                    c[j] = base[j] + (TC)d;
+                    c[j] = (TC)(float)(base[j] + (TC)d);
                 }
             }
         }
@@ -392,8 +363,7 @@ static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *
         return MGD_OK;
     };
     if (h->precision == MGD_FP64) go(OpHalf<double>{o.S64[level], h->NV[level]});
-    else if (level > 0) go(OpHalf<float>{o.S32[level], h->NV[level]});
-    else go(OpComp<D, float>{store_view(h, o), h->n, (float)(D == 2 ? 1.0 : 1.0 / h->n)});
+    else go(OpHalf<float>{o.S32[level], h->NV[level]});  // level 0: the store's FP32 decode
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
@@ -895,15 +865,6 @@ int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega
 }
 
 // ------------------------------------------------------------ FP64 outer
-template <int D> struct OpComp64 {
-    StoreView sv;
-    int n;
-    __device__ inline double c(int64_t v, int j, const int *x) const
-    {
-#pragma clang fp contract(off)
-        return base_coupling64<D>(sv.eps_c, n, x, j, nullptr) + (double)sv.delta(v, j, n_half(D));
-    }
-};
 
 template <int D, class Op>
 __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const double *u, const double *f, double *r,
@@ -957,8 +918,9 @@ static int outer_residual_t(mgd_hier *h, const OpSet &o, const double *u, const 
         hipLaunchKernelGGL((k_outer_residual<D, OpHalf<double>>), dim3(grid), dim3(256), 0, st,
                            OpHalf<double>{o.S64[0], h->NV[0]}, h->n, u, f, r, partial, (float *)nullptr);
     else
-        hipLaunchKernelGGL((k_outer_residual<D, OpComp64<D>>), dim3(grid), dim3(256), 0, st,
-                           OpComp64<D>{store_view(h, o), h->n}, h->n, u, f, r, partial, (float *)h->f[0]);
+        // the mixed operator is the store's FP32 decode (kept current in S32[0]), applied in FP64
+        hipLaunchKernelGGL((k_outer_residual<D, OpHalf<float>>), dim3(grid), dim3(256), 0, st,
+                           OpHalf<float>{o.S32[0], h->NV[0]}, h->n, u, f, r, partial, (float *)h->f[0]);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }
@@ -1135,8 +1097,8 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
         hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
                            OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
     else
-        hipLaunchKernelGGL((k_p_matvec<D, OpComp64<D>, TZ>), dim3(grid), dim3(256), 0, st,
-                           OpComp64<D>{store_view(h, o), h->n}, h->n, z, pold, pnew, Ap, c, h->partial2);
+        hipLaunchKernelGGL((k_p_matvec<D, OpHalf<float>, TZ>), dim3(grid), dim3(256), 0, st,
+                           OpHalf<float>{o.S32[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
     HIPCHK(h->ctx, hipGetLastError());
     h->p2_n = grid;
     return MGD_OK;

@@ -329,11 +329,9 @@ static void galerkin_launch(const HalfRow<D, T> &A, const T *W, int nf, int64_t 
     hipLaunchKernelGGL((k_galerkin_p<D, T>), dim3(grid_for(NVc, CPB)), dim3(CPB * ns), 0, st, A, W, nf, Sc);
 }
 
-int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st);
-
 // weights, Galerkin products and the coarsest matrix in FP64 arithmetic; the
 // mixed form stores the levels in FP32 (its finest level: the FP32 decode of
-// the store)
+// the store, kept current by every change of the store)
 template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *const *S, hipStream_t st)
 {
     mgd_ctx *ctx = h->ctx;
@@ -357,8 +355,6 @@ int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st)
 {
     if (h->precision == MGD_FP64)
         return h->dim == 2 ? coarsen_t<2, double>(h, o, o.S64, st) : coarsen_t<3, double>(h, o, o.S64, st);
-    int rc = decode_store_f32(h, o, st);
-    if (rc) return rc;
     return h->dim == 2 ? coarsen_t<2, float>(h, o, o.S32, st) : coarsen_t<3, float>(h, o, o.S32, st);
 }
 

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
     if (COMP) {
         const T k6 = (T)(-1.0 / 6.0), k3 = (T)(-1.0 / 3.0);
         auto decode = [&](int s, int lx, int ly, bool ok) {
-            // base + surplus rounded as the FP64 outer operator does (no fused multiply-add)
+            // base + surplus without fused multiply-add, as the store's decode does
 #pragma clang fp contract(off)
             if (!ok) return;
             const uint32_t l = vid(gx + lx, gy + ly) & 63u;
@@ -333,10 +333,11 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) d[q] = __uint_as_float(wv[s][q]);
             }
-            sC[0][ly][lx] = (e10 + e11) * k6 + (T)d[0];
-            sC[1][ly][lx] = e01 * k3 + (T)d[1];
-            sC[2][ly][lx] = (e01 + e11) * k6 + (T)d[2];
-            sC[3][ly][lx] = e11 * k3 + (T)d[3];
+            // (in FP64, the mixed form's operator: the sum rounded once to FP32)
+            sC[0][ly][lx] = (T)(float)((e10 + e11) * k6 + (T)d[0]);
+            sC[1][ly][lx] = (T)(float)(e01 * k3 + (T)d[1]);
+            sC[2][ly][lx] = (T)(float)((e01 + e11) * k6 + (T)d[2]);
+            sC[3][ly][lx] = (T)(float)(e11 * k3 + (T)d[3]);
         };
 #pragma unroll
         for (int j = 0; j < RC; ++j) decode(j, lane, wave + 4 * j, wave + 4 * j < CH);

@@ -193,7 +193,8 @@ __global__ void k_encode(const float *delta, int64_t NV, int64_t ntile, const ui
     }
 }
 
-// FP64 decode of the store: base + delta (the outer operator of the mixed path)
+// the decoded store, i.e. the mixed form's operator: base + delta summed in
+// FP64 and rounded once to FP32 (written as FP32 or widened to FP64)
 template <int D, typename TO>
 __global__ void k_decode_store(StoreView sv, int n, TO *out)
 {
@@ -206,9 +207,11 @@ __global__ void k_decode_store(StoreView sv, int n, TO *out)
     constexpr int H = n_half(D);
     for (int j = 0; j < H; ++j) {
         double b = base_coupling64<D>(sv.eps_c, n, x, j, nullptr);
-        out[(int64_t)j * g.NV + v] = (TO)(b + (double)sv.delta(v, j, H));
+        out[(int64_t)j * g.NV + v] = (TO)(float)(b + (double)sv.delta(v, j, H));
     }
 }
+
+int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st);
 
 template <typename TI> __global__ void k_to_f64(const TI *in, int64_t cnt, double *out)
 {
@@ -241,7 +244,7 @@ int compress_into(mgd_hier *h, OpSet &o, const float *S32, const float *eps_c,
     else
         hipLaunchKernelGGL(k_encode<3>, ge, dim3(256), 0, st, h->delta, NV, o.ntile, o.tier, o.toff, o.payload);
     HIPCHK(ctx, hipGetLastError());
-    return MGD_OK;
+    return decode_store_f32(h, o, st);  // the FP32 finest operator follows the store
 }
 
 // every tile at tier 0: the operator is exactly the centre-sample base
@@ -255,7 +258,7 @@ int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st)
     HIPCHK(ctx, hipMemsetAsync(o.tier, 0, o.ntile, st));
     HIPCHK(ctx, hipMemsetAsync(o.toff, 0, sizeof(uint32_t) * o.ntile, st));
     HIPCHK(ctx, hipMemsetAsync(o.units_total, 0, sizeof(uint32_t), st));
-    return MGD_OK;
+    return decode_store_f32(h, o, st);
 }
 
 StoreView store_view(const mgd_hier *h, const OpSet &o)
@@ -266,7 +269,8 @@ StoreView store_view(const mgd_hier *h, const OpSet &o)
     return sv;
 }
 
-// decoded level-0 operator of the mixed path: FP32 copy (for coarsening)
+// decoded level-0 operator of the mixed path, FP32 (Galerkin input, unfused
+// kernels, the 3D outer operator); kept current with every change of the store
 int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st)
 {
     StoreView sv = store_view(h, o);

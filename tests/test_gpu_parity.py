@@ -212,6 +212,17 @@ def test_compress_payload_bit_exact(ctx, d, n, policy):
     assert np.array_equal(words[stored], owords[stored].astype(np.int64))
     if policy[0] == 1 and policy[1] == 3 and len(ott) >= 4:
         assert len(set(ott.tolist())) >= 2, ott
+    # the decoded operator: the oracle's base plus the oracle's decode of the
+    # stored surplus, summed in FP64 and rounded once to FP32
+    got = host(h.level_stencils(0))
+    want = np.zeros((H, NV))
+    for v in range(NV):
+        t = int(ott[v // 64])
+        for j, oi in enumerate(O.half_offsets(d)):
+            b = O.base_coupling(d, n, eps_c, v, oi)[0]
+            dv = O.decode_entry(t, int(oe8[v]), int(owords[v, j])) if t > 0 else 0.0
+            want[j, v] = float(np.float32(b + dv))
+    assert np.array_equal(got, want)
 
 
 # ------------------------------------------------------------ Galerkin
