@@ -10,7 +10,8 @@ surplus store, FP32 BoxMG V(2,2), FP64 outer conjugate gradients) with lazy
 assembly; the plain FP64 form with up-front assembly is timed beside it.
 Inputs (load vector, material data) are resident in HBM before timing.  The
 same comparison is repeated at 4096^2 cells, where the operators no longer
-fit in the 256 MB Infinity Cache.
+fit in the 256 MB Infinity Cache, and on the 3D Gaussian-field workload at
+256^3 cells (27-point stencils, ladder to s = 8).
 
 Prints one JSON line.  `value` is the mixed-lazy form's fine-grid V-cycle
 throughput over the whole solve: (n-1)^2 DoF x V-cycles / time-to-solution.
@@ -44,6 +45,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--big-n", type=int, default=4096,
                     help="also time the sweep at this size, beyond the Infinity Cache (0 skips)")
+    ap.add_argument("--n3d", type=int, default=256,
+                    help="also time both forms on the 3D Gaussian-field workload at this size (0 skips)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline sweep and a calibration copy (for counter runs)")
     return ap.parse_args()
@@ -127,19 +130,18 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
             "avg_launch_us": round(avg_ms * 1e3, 3), "store_tiers": tier_tiles}
 
 
-def solve_forms(P, W, n, steps, warmup, tiers):
-    """Time-to-1e-8 of the mixed-lazy and the FP64-up-front forms on the
-    balls workload at n^2 cells; each form keeps its device-resident solve
-    state in its own context, so neither timed loop re-creates the other's
-    workspace."""
+def solve_forms(P, W, n, steps, warmup, tiers, d=2, fld=None, s_max=16):
+    """Time-to-1e-8 of the mixed-lazy and the FP64-up-front forms at n^d
+    cells (default: the 2D balls workload); each form keeps its
+    device-resident solve state in its own context, so neither timed loop
+    re-creates the other's workspace."""
     import torch
-    d = 2
-    eps = P.Eps(W.config_field(1))
+    eps = P.Eps(fld if fld is not None else W.config_field(1))
     f_host = W.load_sine(d, n)
     f = torch.from_numpy(f_host).cuda()
-    mixed = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=16,
+    mixed = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=s_max,
                  tol=1e-8, max_cycles=600, **tiers)
-    fp64 = dict(precision=P.FP64, schedule=P.UPFRONT, transfer=P.BOXMG, outer=P.PCG, s_max=16,
+    fp64 = dict(precision=P.FP64, schedule=P.UPFRONT, transfer=P.BOXMG, outer=P.PCG, s_max=s_max,
                 tol=1e-8, max_cycles=600)
     ctx_m, ctx_f = P.Context(0), P.Context(0)
 
@@ -322,6 +324,23 @@ def main():
     if big is not None:
         out["components"]["sweep_roofline_beyond_cache"] = big
         out["components"]["time_to_solution_beyond_cache"] = big_tts
+    if args.n3d > 0:
+        m = args.n3d
+        b = solve_forms(P, W, m, 2, 1, tiers, d=3, fld=W.config_field(2, n=m), s_max=8)
+        out["components"]["time_to_solution_3d"] = {
+            "workload": (f"3D {m}^3 Q1 cells (27-point stencils), eps = exp(g), g a seeded Gaussian field "
+                         "(correlation length 1/32, sigma 1), ladder s = 2..8, manufactured sine load"),
+            "time_to_1e8_mixed_lazy_ms": round(b["ms_mixed"], 3),
+            "time_to_1e8_fp64_upfront_ms": round(b["ms_fp64"], 3),
+            "speedup_mixed_lazy_vs_fp64_upfront": round(b["ms_fp64"] / b["ms_mixed"], 3),
+            "cycles_mixed_lazy": b["rep_m"]["cycles"], "cycles_fp64_upfront": b["rep_f"]["cycles"],
+            "t_first_cycle_ms_mixed_lazy": round(b["rep_m"]["t_first_cycle_ms"], 3),
+            "t_first_cycle_ms_fp64_upfront": round(b["rep_f"]["t_first_cycle_ms"], 3),
+            "store_bytes_per_stencil_mixed": b["rep_m"]["store_bytes"] / (m + 1) ** 3,
+            "store_bytes_per_stencil_fp64": b["rep_f"]["store_bytes"] / (m + 1) ** 3,
+            "mixed_vs_fp64_solution_rel_err": b["err"]}
+        del b
+        torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["components"]["serving"] = serving_bench(ctx, P, W, args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
