@@ -103,6 +103,7 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
     constexpr int RA = (UH - 2 + 3) / 4;                // rows per wave, first application
     constexpr int RL = BY / 4;                          // rows per wave, last application (symmetric halos)
     static_assert(BY % 4 == 0, "tile height must be a multiple of 4");
+    static_assert(!RST || (BX / 2) * (BY / 2) <= 256, "restriction: one thread per coarse vertex of the tile");
     static_assert(UW - 2 <= 64 && XU >= 0 && XU <= 3, "halo region must fit the lane layout");
     constexpr int UH2 = PMV ? 1 : UH;                   // arrays the product does not use
     __shared__ T sC[4][CH][UW];
