@@ -72,28 +72,40 @@ def cpu_baseline(fld, d, n, f, cycles):
                        f"extrapolated to {cycles} cycles = {t_tts:.1f} s time-to-solution")}
 
 
-SWEEP_KERNEL = "k_lev2<float, 16, 0, true, true, false, false>"  # pre half: 2 sweeps + residual
+# pre half (2 sweeps + residual) of the mixed form's finest level, by the
+# source of its operator: the compressed store, or the store's FP32 decode
+SWEEP_KERNEL = {"decode": "k_lev2<float, 16, 0, true, true, false, false>",
+                "copy": "k_lev2<float, 16, 0, false, true, false, false>"}
+# the library's automatic choice: decode the store from this many finest
+# vertices on (levels streamed from HBM), read the FP32 decode below
+STORE_MIN_NV = 1 << 22
 PASSES_PER_LAUNCH = 3  # stencil passes one launch performs: two Jacobi sweeps and the residual
-# Memory traffic per launch of SWEEP_KERNEL at n (bytes), from FETCH_SIZE and
-# WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
+# Memory traffic per launch of the timed kernel at n (bytes), from FETCH_SIZE
+# and WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
 # copy; valid only for the kernel version they were taken on.
-SWEEP_TRAFFIC = {1024: 23223264, 4096: 298786648}
+SWEEP_TRAFFIC = {}
 
 
 def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     """Pre-smoothing half of the finest level of the mixed V-cycle: two
     damped-Jacobi sweeps from zero and the residual in one pass over the
-    compressed store, the kernel the mixed cycle moves most of its bytes in.
-    Timed with HIP events on the stream it runs on, same kernel and launch
-    shape as in the solve.
+    finest operator, the kernel the mixed cycle moves most of its bytes in,
+    with the operator source the solve uses at this size (the compressed
+    store from STORE_MIN_NV vertices on, its FP32 decode below).  Timed with
+    HIP events on the stream it runs on, same kernel and launch shape as in
+    the solve.
 
     Algorithmic bytes, per DoF and stencil pass (a Jacobi sweep or the
-    residual): the stencil (store payload + tier byte and offset per tile +
-    FP32 centre sample per cell) + FP32 u in, f in, u (or r) out.  One launch
-    performs PASSES_PER_LAUNCH such passes; fused, it moves the bytes of about
-    one (store, f in, u out, r out), reported as the single-pass figure."""
+    residual): the stencil (store: payload + tier byte and offset per tile +
+    FP32 centre sample per cell; FP32 decode: 4 couplings of 4 bytes) + FP32
+    u in, f in, u (or r) out.  One launch performs PASSES_PER_LAUNCH such
+    passes; fused, it moves the bytes of about one (stencil, f in, u out, r
+    out), reported as the single-pass figure."""
     import torch
-    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    NV = (n + 1) ** d
+    path = "decode" if NV >= STORE_MIN_NV else "copy"
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG,
+                    store_path=P.STORE_DECODE if path == "decode" else P.STORE_COPY)
     K16, _, _ = P.assemble_cells(ctx, d, n, 16, eps, P.MIXED)
     S32 = P.gather_stencils(ctx, d, n, K16, P.MIXED, P.MIXED)
     eps_c = P.centre_samples(ctx, d, n, eps)
@@ -101,9 +113,8 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     h.coarsen()
     del K16, S32
     ntile, payload, tier_tiles = h.store_info()
-    NV = (n + 1) ** d
-    store_bytes = payload + 5 * ntile + 4 * n ** d
-    pass_bytes = store_bytes + 12 * NV
+    stencil_bytes = payload + 5 * ntile + 4 * n ** d if path == "decode" else 16 * NV
+    pass_bytes = stencil_bytes + 12 * NV
     alg_bytes = PASSES_PER_LAUNCH * pass_bytes
     f32 = torch.ones(NV, dtype=torch.float32, device="cuda")
     u32 = torch.zeros_like(f32)
@@ -124,7 +135,8 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
     single = pass_bytes / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": SWEEP_TRAFFIC.get(n),
-            "kernel": SWEEP_KERNEL, "bytes_per_launch": int(alg_bytes),
+            "kernel": SWEEP_KERNEL[path], "operator": "compressed store" if path == "decode" else "FP32 decode",
+            "bytes_per_launch": int(alg_bytes),
             "stencil_passes_per_launch": PASSES_PER_LAUNCH, "single_pass_bytes": int(pass_bytes),
             "single_pass_frac": round(single / HBM_PEAK_GBS, 4),
             "avg_launch_us": round(avg_ms * 1e3, 3), "store_tiers": tier_tiles}

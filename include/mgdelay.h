@@ -51,6 +51,7 @@ enum { MGD_GEOMETRIC = 0, MGD_BOXMG = 1 };     /* transfer operators */
 enum { MGD_STATIONARY = 0, MGD_PCG = 1 };      /* FP64 outer iteration */
 enum { MGD_UPFRONT = 0, MGD_LAZY = 1 };        /* assembly schedule */
 enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1, MGD_PUBLISH_EVERY = 2 };
+enum { MGD_STORE_AUTO = 0, MGD_STORE_DECODE = 1, MGD_STORE_COPY = 2 }; /* finest-level source */
 
 typedef struct mgd_ctx mgd_ctx;   /* per-device context: streams, scratch */
 typedef struct mgd_hier mgd_hier; /* device-resident multigrid hierarchy */
@@ -127,11 +128,20 @@ int mgd_gather_stencils(mgd_ctx *ctx, int32_t dim, int32_t n, const void *K, int
 /* ------------------------------------------------------------------------
  * Hierarchy.  precision MGD_FP64: every level FP64 half stencils, FP64
  * vectors.  MGD_MIXED: the finest level is the compressed store of (2b),
- * coarse levels are FP32 half stencils, cycle vectors are FP32.
+ * beside it the store's decode (base + surplus summed in FP64, rounded once
+ * to FP32: the mixed operator), coarse levels are FP32 half stencils, cycle
+ * vectors are FP32.
  * Levels: n_0 = n, halved while even and n/2 >= coarsest (>= 2).
+ * store_path (MGD_MIXED, 2D V(2,2) fused level kernels and the CG product):
+ * MGD_STORE_DECODE decodes the compressed store in every pass,
+ * MGD_STORE_COPY reads the FP32 decode; both apply the same operator values
+ * and give the same results bit for bit.  MGD_STORE_AUTO (0) decodes the
+ * store when the finest level has at least 2^22 vertices (streamed from HBM,
+ * where the store's fewer bytes set the pace) and reads the FP32 decode on
+ * smaller levels (cache-resident between passes, bound by arithmetic).
  * ---------------------------------------------------------------------- */
 typedef struct {
-    int32_t dim, n, precision, transfer, coarsest, pad;
+    int32_t dim, n, precision, transfer, coarsest, store_path;
 } mgd_hier_desc;
 
 int mgd_hier_create(mgd_ctx *ctx, const mgd_hier_desc *desc, mgd_hier **out);
@@ -257,12 +267,13 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * waits for the pending operator, leaving the device to the assembly stream
  * (a provisional operator's solution is no closer to the final one than the
  * operator is to the final operator); 0 cycles on until the publish.
+ * store_path: as for a hierarchy (MGD_MIXED).
  * f (dev double [NV]) is the load vector; u (dev double [NV]) is the initial
  * guess on entry and the solution on return. */
 typedef struct {
     int32_t precision, transfer, outer, schedule;
     int32_t publish, s_fixed, s_max, nu1;
-    int32_t nu2, max_cycles, coarsest, pad;
+    int32_t nu2, max_cycles, coarsest, store_path;
     double C, omega, tol, div_factor;
     mgd_tier_policy tiers;
     double prov_tol;

@@ -9,7 +9,8 @@ load the library; the first call does, and raises if it is missing.
 from .binding import (  # noqa: F401
     OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED, ESTARVED,
     FP64, MIXED, GEOMETRIC, BOXMG, STATIONARY, PCG, UPFRONT, LAZY,
-    PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY, MgdError, Context, Eps, Hierarchy,
+    PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY, STORE_AUTO, STORE_DECODE, STORE_COPY,
+    MgdError, Context, Eps, Hierarchy,
     assemble_cells, centre_samples, gather_stencils, solve, solve_opts, solve_footprint, Server,
     n_half, n_pairs, lib, library_path,
 )

@@ -15,6 +15,7 @@ GEOMETRIC, BOXMG = 0, 1
 STATIONARY, PCG = 0, 1
 UPFRONT, LAZY = 0, 1
 PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY = 0, 1, 2
+STORE_AUTO, STORE_DECODE, STORE_COPY = 0, 1, 2
 EPS_SAMPLES = 6
 HIST = 512
 
@@ -32,7 +33,7 @@ class _Eps(C.Structure):
 
 class _HierDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("precision", C.c_int32),
-                ("transfer", C.c_int32), ("coarsest", C.c_int32), ("pad", C.c_int32)]
+                ("transfer", C.c_int32), ("coarsest", C.c_int32), ("store_path", C.c_int32)]
 
 
 class _Tier(C.Structure):
@@ -48,7 +49,7 @@ class _SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("transfer", C.c_int32), ("outer", C.c_int32),
                 ("schedule", C.c_int32), ("publish", C.c_int32), ("s_fixed", C.c_int32),
                 ("s_max", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
-                ("max_cycles", C.c_int32), ("coarsest", C.c_int32), ("pad", C.c_int32),
+                ("max_cycles", C.c_int32), ("coarsest", C.c_int32), ("store_path", C.c_int32),
                 ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
                 ("div_factor", C.c_double), ("tiers", _Tier), ("prov_tol", C.c_double)]
 
@@ -232,9 +233,9 @@ def gather_stencils(ctx, dim, n, K, k_mode=FP64, s_mode=FP64, stream=None):
 
 
 class Hierarchy:
-    def __init__(self, ctx, dim, n, precision=FP64, transfer=GEOMETRIC, coarsest=2):
+    def __init__(self, ctx, dim, n, precision=FP64, transfer=GEOMETRIC, coarsest=2, store_path=STORE_AUTO):
         self.ctx, self.dim, self.n, self.precision = ctx, dim, n, precision
-        d = _HierDesc(dim, n, precision, transfer, coarsest, 0)
+        d = _HierDesc(dim, n, precision, transfer, coarsest, store_path)
         h = _P()
         ctx.check(lib().mgd_hier_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
@@ -335,9 +336,9 @@ class Hierarchy:
 def solve_opts(precision=FP64, transfer=GEOMETRIC, outer=STATIONARY, schedule=UPFRONT,
                publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6, nu1=2, nu2=2,
                tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0, min_tier=2, max_tier=2,
-               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0):
+               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0):
     return _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
-                      max_cycles, coarsest, 0, C_thr, omega, tol, div_factor,
+                      max_cycles, coarsest, store_path, C_thr, omega, tol, div_factor,
                       _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol)
 
 

@@ -212,10 +212,13 @@ int mgd_hier_create(mgd_ctx *ctx, const mgd_hier_desc *d, mgd_hier **out)
     if (d->precision != MGD_FP64 && d->precision != MGD_MIXED) return mgd_fail(ctx, MGD_EINVAL, "bad precision");
     if (d->transfer != MGD_GEOMETRIC && d->transfer != MGD_BOXMG) return mgd_fail(ctx, MGD_EINVAL, "bad transfer");
     if (d->coarsest < 2) return mgd_fail(ctx, MGD_EINVAL, "coarsest must be >= 2");
+    if (d->store_path < MGD_STORE_AUTO || d->store_path > MGD_STORE_COPY)
+        return mgd_fail(ctx, MGD_EINVAL, "bad store_path");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     mgd_hier *h = new mgd_hier();
     h->ctx = ctx;
     h->dim = d->dim; h->n = d->n; h->precision = d->precision; h->transfer = d->transfer; h->coarsest = d->coarsest;
+    h->store_path = d->store_path;
     rc = hier_alloc_levels(h);
     if (rc) { hier_free(h); delete h; return rc; }
     *out = h;

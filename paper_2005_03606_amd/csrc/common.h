@@ -198,6 +198,7 @@ constexpr int64_t kCinvMax = 128;
 struct mgd_hier {
     mgd_ctx *ctx = nullptr;
     int dim = 2, n = 0, precision = MGD_FP64, transfer = MGD_GEOMETRIC, coarsest = 2;
+    int store_path = MGD_STORE_AUTO;  // MGD_MIXED: source of the finest operator in the fused 2D kernels
     int nlev = 0, H = 4;
     int nl[MGD_MAXLEV] = {};
     int64_t NV[MGD_MAXLEV] = {};

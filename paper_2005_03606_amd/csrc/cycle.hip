@@ -251,10 +251,11 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
         if (vx >= 0 && vx < nv && vy >= 0 && vy < nv) {
             int64_t v = (int64_t)vy * nv + vx;
             // cells around (vx, vy): e(cx, cy) at s_eps[cy - y0 + 2][cx - x0 + 2]
-            TC e00 = (TC)s_eps[ly][lx], e10 = (TC)s_eps[ly][lx + 1];       // (vx-1, vy-1), (vx, vy-1)
-            TC e01 = (TC)s_eps[ly + 1][lx], e11 = (TC)s_eps[ly + 1][lx + 1]; // (vx-1, vy), (vx, vy)
-            const TC k6 = (TC)(-1.0 / 6.0), k3 = (TC)(-1.0 / 3.0);
-            TC base[4] = {(e10 + e11) * k6, e01 * k3, (e01 + e11) * k6, e11 * k3};
+            // base + surplus in FP64, rounded once to FP32 (the store's decode, bit for bit)
+            const double e10 = s_eps[ly][lx + 1];                                 // (vx, vy-1)
+            const double e01 = s_eps[ly + 1][lx], e11 = s_eps[ly + 1][lx + 1];  // (vx-1, vy), (vx, vy)
+            const double k6 = -1.0 / 6.0, k3 = -1.0 / 3.0;
+            const double base[4] = {(e10 + e11) * k6, e01 * k3, (e01 + e11) * k6, e11 * k3};
             int64_t t = v >> 6;
             int tt = a.sv.tier[t];
             if (tt == 0) {
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(256) void k_stage2(StageArgs<TC> a)
                     if (tt == 2) d = (float)__builtin_bit_cast(_Float16, ((const uint16_t *)(bp + 64 + j * 128))[l]) * sc;
                     else if (tt == 1) d = e4m3_to_float(bp[64 + j * 64 + l]) * sc;
                     else d = ((const float *)(bp + 64 + j * 256))[l];
-                    c[j] = (TC)(float)(base[j] + (TC)d);
+                    c[j] = (TC)(float)(base[j] + (double)d);
                 }
             }
         }
@@ -460,6 +461,14 @@ struct TailLevel {
     int off;    // element offset of this level's vectors in LDS: u | f | t
     float rnv;  // 1 / (n + 1)
 };
+// 2D: global arrays copied into LDS when the tail starts.  Each segment
+// starts at a multiple of the block size in the flat item space, so a
+// thread's k-th item belongs to segment seg_of[k] for every thread alike.
+constexpr int kTailSegs = 2 * MGD_MAXLEV + 2, kTailStageK = 24;
+struct TailSeg {
+    const void *src;
+    int dst, cnt;  // LDS element offset, items
+};
 struct TailArgs {
     int first, last, nu1, nu2, zero_guess, m, work_off;
     double omega;
@@ -467,6 +476,10 @@ struct TailArgs {
     const void *f;
     const double *chol, *cinv;
     TailLevel L[MGD_MAXLEV];
+    int nslot;                // 2D staging: item slots per thread in use
+    int8_t seg_of[kTailStageK];  // segment of each slot
+    int16_t seg_k0[kTailStageK]; // the segment's first slot
+    TailSeg seg[kTailSegs];
 };
 
 // vertex coordinates by a float reciprocal (exact for the tail's sizes:
@@ -736,6 +749,166 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
     }
 }
 
+// ---- 2D tail with the operators in LDS.  Every tail level's half stencils
+// and transfer weights are copied into LDS once per call (all loads of a
+// thread in flight together), with the first level's right-hand side and
+// iterate; from then on every phase reads and writes LDS only.  Level
+// layout (element offsets from L[l].off): u | f | t | S [4][NV] | W [4][NV].
+__device__ inline void t2_coords(int v, const TailLevel &lv, int &x, int &y)
+{
+    const int nv = lv.n + 1;
+    y = (int)(((float)v + 0.5f) * lv.rnv);
+    x = v - y * nv;
+}
+
+// stencil application at interior vertex v: acc = sum of the 8 couplings
+// times the neighbours' iterate, dsum = sum of the 8 couplings
+template <typename T>
+__device__ inline void t2_apply(const T *S, int NV, int nv, const T *u, int v, T &acc, T &dsum, bool need_acc)
+{
+    const int lin[4] = {1, nv - 1, nv, nv + 1};
+    const T a0 = S[v], a1 = S[NV + v], a2 = S[2 * NV + v], a3 = S[3 * NV + v];
+    const T b0 = S[v - lin[0]], b1 = S[NV + v - lin[1]], b2 = S[2 * NV + v - lin[2]], b3 = S[3 * NV + v - lin[3]];
+    dsum = ((a0 + a1) + (a2 + a3)) + ((b0 + b1) + (b2 + b3));
+    acc = (T)0;
+    if (need_acc)
+        acc = a0 * u[v + lin[0]] + a1 * u[v + lin[1]] + a2 * u[v + lin[2]] + a3 * u[v + lin[3]] + b0 * u[v - lin[0]] +
+              b1 * u[v - lin[1]] + b2 * u[v - lin[2]] + b3 * u[v - lin[3]];
+}
+
+// MODE 0: damped Jacobi sweep uout = (1 - omega) u + (omega / D) (f - offdiag u)
+// (ZERO: from u = 0); MODE 1: residual uout = f - A u
+template <typename T, int MODE>
+__device__ void t2_pass(const TailLevel &lv, T *base, const T *uin, T *uout, bool zero, T omega)
+{
+    const int nv = lv.n + 1, NV = lv.NV;
+    const T *f = base + lv.off + NV, *S = base + lv.off + 3 * NV;
+    for (int v = threadIdx.x; v < NV; v += kTailThreads) {
+        int x, y;
+        t2_coords(v, lv, x, y);
+        T out = (T)0;
+        if (x > 0 && x < lv.n && y > 0 && y < lv.n) {
+            T acc, dsum;
+            t2_apply(S, NV, nv, uin, v, acc, dsum, MODE == 1 || !zero);
+            if (MODE == 1) out = f[v] - (-dsum * uin[v] + acc);
+            else if (zero) out = (omega / -dsum) * f[v];
+            else out = ((T)1 - omega) * uin[v] + (omega / -dsum) * (f[v] - acc);
+        }
+        uout[v] = out;
+    }
+    __syncthreads();
+}
+
+template <typename T> __global__ __launch_bounds__(1024) void k_tail2d(TailArgs a)
+{
+    extern __shared__ __align__(16) unsigned char tail_lds[];
+    T *base = (T *)tail_lds;
+    double *work = (double *)(tail_lds + a.work_off);
+    const T omega = (T)a.omega;
+    const int tid = threadIdx.x;
+    // ---- staging: slot k of every thread lies in segment seg_of[k] (uniform),
+    // all loads issued before the LDS stores
+    {
+        T val[kTailStageK];
+        int dst[kTailStageK];
+#pragma unroll
+        for (int k = 0; k < kTailStageK; ++k) {
+            dst[k] = -1;
+            val[k] = (T)0;
+            if (k < a.nslot) {
+                const TailSeg &sg = a.seg[a.seg_of[k]];
+                const int i = tid + (k - a.seg_k0[k]) * kTailThreads;
+                if (i < sg.cnt) {
+                    val[k] = ((const T *)sg.src)[i];
+                    dst[k] = sg.dst + i;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTailStageK; ++k)
+            if (dst[k] >= 0) base[dst[k]] = val[k];
+        if (a.zero_guess) {
+            const TailLevel &l0 = a.L[a.first];
+            for (int v = tid; v < l0.NV; v += kTailThreads) base[l0.off + v] = (T)0;
+        }
+        __syncthreads();
+    }
+    auto U = [&](int l) { return base + a.L[l].off; };
+    auto F = [&](int l) { return base + a.L[l].off + a.L[l].NV; };
+    auto Tt = [&](int l) { return base + a.L[l].off + 2 * a.L[l].NV; };
+    auto Wl = [&](int l) { return a.L[l].W ? base + a.L[l].off + 7 * a.L[l].NV : nullptr; };
+    auto smooth = [&](int l, int sweeps, bool zero) {
+        for (int k = 0; k < sweeps; ++k) {
+            if (k % 2 == 0) t2_pass<T, 0>(a.L[l], base, U(l), Tt(l), zero && k == 0, omega);
+            else t2_pass<T, 0>(a.L[l], base, Tt(l), U(l), false, omega);
+        }
+        if (sweeps % 2 == 1) {
+            for (int v = tid; v < a.L[l].NV; v += kTailThreads) U(l)[v] = Tt(l)[v];
+            __syncthreads();
+        }
+        if (sweeps == 0 && zero) {
+            for (int v = tid; v < a.L[l].NV; v += kTailThreads) U(l)[v] = (T)0;
+            __syncthreads();
+        }
+    };
+    for (int l = a.first; l < a.last; ++l) {
+        const TailLevel &lv = a.L[l], &lc = a.L[l + 1];
+        smooth(l, a.nu1, l > a.first || a.zero_guess);
+        t2_pass<T, 1>(lv, base, U(l), Tt(l), false, omega);
+        // fc = P^T r on the interior coarse vertices, uc = 0
+        const T *r = Tt(l), *W = Wl(l);
+        const int nv = lv.n + 1;
+        T *fc = F(l + 1), *uc = U(l + 1);
+        for (int V = tid; V < lc.NV; V += kTailThreads) {
+            int X, Y;
+            t2_coords(V, lc, X, Y);
+            T s = (T)0;
+            if (X > 0 && X < lc.n && Y > 0 && Y < lc.n) {
+#pragma unroll
+                for (int sv = 0; sv < 9; ++sv) {
+                    const int ox = sv % 3 - 1, oy = sv / 3 - 1;
+                    const int B = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0);  // X - (x >> 1) is 1 exactly where o = -1
+                    const int v = (2 * Y + oy) * nv + 2 * X + ox;
+                    const T w = W ? W[B * lv.NV + v] : (T)((ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0));
+                    s += w * r[v];
+                }
+            }
+            fc[V] = s;
+            uc[V] = (T)0;
+        }
+        __syncthreads();
+    }
+    tail_coarse<2, T>(a, a.L[a.last], U(a.last), F(a.last), work);
+    for (int l = a.last - 1; l >= a.first; --l) {
+        // u += P ec on the interior fine vertices
+        const TailLevel &lv = a.L[l], &lc = a.L[l + 1];
+        const T *W = Wl(l), *ec = U(l + 1);
+        T *u = U(l);
+        const int ncv = lc.n + 1;
+        for (int v = tid; v < lv.NV; v += kTailThreads) {
+            int x, y;
+            t2_coords(v, lv, x, y);
+            if (!(x > 0 && x < lv.n && y > 0 && y < lv.n)) continue;
+            T s = (T)0;
+#pragma unroll
+            for (int B = 0; B < 4; ++B) {
+                const int bx = B & 1, by = B >> 1;
+                if ((bx && !(x & 1)) || (by && !(y & 1))) continue;  // only odd axes reach the upper corner
+                const T w = W ? W[B * lv.NV + v] : (T)(((x & 1) ? 0.5 : 1.0) * ((y & 1) ? 0.5 : 1.0));
+                if (w != (T)0) s += w * ec[((y >> 1) + by) * ncv + (x >> 1) + bx];
+            }
+            u[v] += s;
+        }
+        __syncthreads();
+        smooth(l, a.nu2, false);
+    }
+    {
+        T *ug = (T *)a.u;
+        const T *u0 = U(a.first);
+        for (int v = tid; v < a.L[a.first].NV; v += kTailThreads) ug[v] = u0[v];
+    }
+}
+
 // first level handled by the single-workgroup tail: in 2D the levels up to
 // 33 x 33 vertices (larger ones run faster as fused multi-block passes), in
 // 3D up to 17^3 (their vectors still fit in LDS)
@@ -746,6 +919,16 @@ static int tail_first(const mgd_hier *h)
     while (l > 0 && h->NV[l - 1] <= kTailNV) --l;
     if (h->precision == MGD_MIXED && l == 0) l = h->nlev > 1 ? 1 : 0;  // level 0 is the compressed store
     return l;
+}
+
+template <typename T> static void tail2d_launch_t(const TailArgs &a, size_t lds, hipStream_t st)
+{
+    static bool attr = false;  // once per instantiation: allow more than 64 KB of dynamic LDS
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_tail2d<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_tail2d<T>), dim3(1), dim3(kTailThreads), lds, st, a);
 }
 
 template <int D, typename T> static void tail_launch_t(const TailArgs &a, size_t lds, hipStream_t st)
@@ -775,6 +958,59 @@ static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const vo
     a.cinv = o.cinv;
     a.m = (int)h->m_coarse;
     const size_t vb = h->vec_bytes(), cap = 160 * 1024;
+    if (h->dim == 2) {
+        // operators, weights and the first level's vectors staged in LDS
+        int64_t off = 0;
+        int ns = 0, nslot = 0;
+        bool fits = true;
+        auto seg = [&](const void *src, int64_t dst, int64_t cnt) {
+            const int k = (int)((cnt + kTailThreads - 1) / kTailThreads);
+            if (nslot + k > kTailStageK) {
+                fits = false;
+                return;
+            }
+            a.seg[ns].src = src;
+            a.seg[ns].dst = (int)dst;
+            a.seg[ns].cnt = (int)cnt;
+            for (int q = 0; q < k; ++q) {
+                a.seg_of[nslot + q] = (int8_t)ns;
+                a.seg_k0[nslot + q] = (int16_t)nslot;
+            }
+            nslot += k;
+            ns++;
+        };
+        for (int l = first; l <= a.last && fits; ++l) {
+            TailLevel &L = a.L[l];
+            const int64_t NV = h->NV[l];
+            L.S = h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l];
+            L.W = h->transfer == MGD_BOXMG && l < a.last ? o.W[l] : nullptr;
+            L.n = h->nl[l];
+            L.NV = (int)NV;
+            L.off = (int)off;
+            L.rnv = 1.0f / (float)(h->nl[l] + 1);
+            if ((int64_t)(h->nl[l] + 1) * NV >= ((int64_t)1 << 22) || ns + 4 > kTailSegs) {
+                fits = false;
+                break;
+            }
+            seg(L.S, off + 3 * NV, 4 * NV);
+            if (L.W) seg(L.W, off + 7 * NV, 4 * NV);
+            if (l == first) {
+                seg(f, off + NV, NV);
+                if (!zero_guess) seg(u, off, NV);
+            }
+            off += (L.W ? 11 : 7) * NV;
+        }
+        size_t bytes = ((size_t)off * vb + 15) / 16 * 16;
+        a.work_off = (int)bytes;
+        bytes += (size_t)(a.m > 0 ? a.m : 1) * 8;
+        if (fits && bytes <= cap) {
+            a.nslot = nslot;
+            if (h->precision == MGD_FP64) tail2d_launch_t<double>(a, bytes, st);
+            else tail2d_launch_t<float>(a, bytes, st);
+            HIPCHK(h->ctx, hipGetLastError());
+            return MGD_OK;
+        }
+    }
     int64_t off = 0;
     for (int l = first; l <= a.last; ++l) {
         TailLevel &L = a.L[l];

@@ -20,6 +20,7 @@ enum { L2_PRE = 0, L2_POST = 1, L2_PMV = 2, L2_PRER = 3 };
 
 template <typename T> struct Lev2Args {
     const T *S;       // half stencils [4][NV] (unless the store is used)
+    const float *Sf;  // PMV with an FP32 iterate: the FP32 half stencils (mixed form, store not used)
     StoreView sv;     // compressed finest-level store
     int n;            // cells per axis of this level
     const T *u;       // PRE: start iterate (unless zero); POST: iterate before prolongation
@@ -195,7 +196,9 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
             const uint32_t v = dom ? vid(vx, vy) : 0u;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const T c = a.S[(uint32_t)j * NV + v];
+                T c;
+                if constexpr (PMV && ZF) c = (T)a.Sf[(uint32_t)j * NV + v];
+                else c = a.S[(uint32_t)j * NV + v];
                 cr[s][j] = dom ? c : (T)0;
             }
         };
@@ -310,14 +313,15 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
 
     // ---------------- phase 2 (store): centre-sample base + decoded surplus
     if (COMP) {
-        const T k6 = (T)(-1.0 / 6.0), k3 = (T)(-1.0 / 3.0);
+        const double k6 = -1.0 / 6.0, k3 = -1.0 / 3.0;
         auto decode = [&](int s, int lx, int ly, bool ok) {
-            // base + surplus without fused multiply-add, as the store's decode does
+            // base + surplus in FP64 without fused multiply-add, rounded once
+            // to FP32: the store's decode, bit for bit
 #pragma clang fp contract(off)
             if (!ok) return;
             const uint32_t l = vid(gx + lx, gy + ly) & 63u;
             // cells around the vertex: (x, y-1), (x-1, y), (x, y) at sE[ly][lx+1], sE[ly+1][lx], sE[ly+1][lx+1]
-            const T e10 = (T)sE[ly][lx + 1], e01 = (T)sE[ly + 1][lx], e11 = (T)sE[ly + 1][lx + 1];
+            const double e10 = sE[ly][lx + 1], e01 = sE[ly + 1][lx], e11 = sE[ly + 1][lx + 1];
             float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             const int tier = tt[s];
             if (tier == 2) {
@@ -334,11 +338,10 @@ __global__ __launch_bounds__(256) void k_lev2(Lev2Args<T> a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) d[q] = __uint_as_float(wv[s][q]);
             }
-            // (in FP64, the mixed form's operator: the sum rounded once to FP32)
-            sC[0][ly][lx] = (T)(float)((e10 + e11) * k6 + (T)d[0]);
-            sC[1][ly][lx] = (T)(float)(e01 * k3 + (T)d[1]);
-            sC[2][ly][lx] = (T)(float)((e01 + e11) * k6 + (T)d[2]);
-            sC[3][ly][lx] = (T)(float)(e11 * k3 + (T)d[3]);
+            sC[0][ly][lx] = (T)(float)((e10 + e11) * k6 + (double)d[0]);
+            sC[1][ly][lx] = (T)(float)(e01 * k3 + (double)d[1]);
+            sC[2][ly][lx] = (T)(float)((e01 + e11) * k6 + (double)d[2]);
+            sC[3][ly][lx] = (T)(float)(e11 * k3 + (double)d[3]);
         };
 #pragma unroll
         for (int j = 0; j < RC; ++j) decode(j, lane, wave + 4 * j, wave + 4 * j < CH);
@@ -498,6 +501,21 @@ static dim3 lev2_grid(int n, int kind, int by)
 // tile heights: 16 rows in FP32 (about 50 KB of LDS), 8 in FP64
 constexpr int kBYf = 16, kBYd = 8;
 
+// The mixed form's finest level: the fused kernels decode the compressed
+// store when the level is large enough to stream from HBM, where its fewer
+// bytes set the pace.  Smaller levels stay in the 256 MB Infinity Cache
+// between passes, the kernels are bound by vector instructions there, and
+// they read the FP32 copy of the same operator (the store's decode, kept
+// current beside it) instead of decoding per pass.  Either way the tile's
+// operator in LDS holds the same values, so the results agree bit for bit.
+constexpr int64_t kStoreMinNV = (int64_t)1 << 22;
+static bool lev2_store(const mgd_hier *h, int l)
+{
+    if (h->precision != MGD_MIXED || l != 0) return false;
+    if (h->store_path == MGD_STORE_AUTO) return h->NV[0] >= kStoreMinNV;
+    return h->store_path == MGD_STORE_DECODE;
+}
+
 // 2D, V(2,2), a coarser level below, and 32-bit indices into [4][NV] arrays
 bool lev2_ok(const mgd_hier *h, int l, int nu1, int nu2)
 {
@@ -510,7 +528,7 @@ static int lev2_pre_t(mgd_hier *h, const OpSet &o, int l, const T *u, const T *f
 {
     Lev2Args<T> a;
     memset(&a, 0, sizeof(a));
-    const bool comp = h->precision == MGD_MIXED && l == 0;
+    const bool comp = lev2_store(h, l);
     if (comp) a.sv = store_view(h, o);
     else a.S = (const T *)(h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l]);
     a.n = h->nl[l];
@@ -537,7 +555,7 @@ static int lev2_post_t(mgd_hier *h, const OpSet &o, int l, const T *u, const T *
 {
     Lev2Args<T> a;
     memset(&a, 0, sizeof(a));
-    const bool comp = h->precision == MGD_MIXED && l == 0;
+    const bool comp = lev2_store(h, l);
     if (comp) a.sv = store_view(h, o);
     else a.S = (const T *)(h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l]);
     a.n = h->nl[l];
@@ -583,8 +601,9 @@ int lev2_pmv(mgd_hier *h, const OpSet &o, const void *z, const double *pold, dou
     constexpr int BY = 16;
     Lev2Args<double> a;
     memset(&a, 0, sizeof(a));
-    const bool comp = h->precision == MGD_MIXED;
+    const bool mixed = h->precision == MGD_MIXED, comp = lev2_store(h, 0);
     if (comp) a.sv = store_view(h, o);
+    else if (mixed) a.Sf = (const float *)o.S32[0];
     else a.S = o.S64[0];
     a.n = h->nl[0];
     a.z = z;
@@ -595,6 +614,7 @@ int lev2_pmv(mgd_hier *h, const OpSet &o, const void *z, const double *pold, dou
     a.partial = h->partial2;
     dim3 g = lev2_grid(a.n, L2_PMV, BY);
     if (comp) hipLaunchKernelGGL((k_lev2<double, BY, L2_PMV, true, false, false, true>), g, dim3(256), 0, st, a);
+    else if (mixed) hipLaunchKernelGGL((k_lev2<double, BY, L2_PMV, false, false, false, true>), g, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_lev2<double, BY, L2_PMV, false, false, false, false>), g, dim3(256), 0, st, a);
     HIPCHK(h->ctx, hipGetLastError());
     h->p2_n = lev2_tiles(a.n, L2_PMV, BY);
@@ -608,7 +628,7 @@ static int lev2_prer_t(mgd_hier *h, const OpSet &o, int l, const T *u, const T *
 {
     Lev2Args<T> a;
     memset(&a, 0, sizeof(a));
-    const bool comp = h->precision == MGD_MIXED && l == 0;
+    const bool comp = lev2_store(h, l);
     if (comp) a.sv = store_view(h, o);
     else a.S = (const T *)(h->precision == MGD_FP64 ? (const void *)o.S64[l] : (const void *)o.S32[l]);
     a.n = h->nl[l];

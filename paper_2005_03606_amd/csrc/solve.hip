@@ -210,6 +210,8 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
     if (op->schedule != MGD_UPFRONT && op->schedule != MGD_LAZY) return mgd_fail(ctx, MGD_EINVAL, "bad schedule");
     if (op->publish < MGD_PUBLISH_ASYNC || op->publish > MGD_PUBLISH_EVERY)
         return mgd_fail(ctx, MGD_EINVAL, "bad publish mode");
+    if (op->store_path < MGD_STORE_AUTO || op->store_path > MGD_STORE_COPY)
+        return mgd_fail(ctx, MGD_EINVAL, "bad store_path");
     int sf = op->s_fixed, sm = op->s_max;
     if (sf > 0 && sf != 1 && sf != 2 && sf != 4 && sf != 8 && sf != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_fixed");
     if (sf <= 0 && sm != 1 && sm != 2 && sm != 4 && sm != 8 && sm != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_max");
@@ -390,6 +392,7 @@ int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, c
     S->lazy = op->schedule == MGD_LAZY && sf <= 0 && sm >= 2;
     S->pcg = op->outer == MGD_PCG;
     S->publish_mode = op->publish;
+    S->H.store_path = op->store_path;
     S->sets[0] = &S->H.ops;
     S->sets[1] = &S->O1;
     S->cur = 0;

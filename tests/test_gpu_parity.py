@@ -340,15 +340,19 @@ def test_presmooth_restrict_fp64_matches_oracle_pieces(ctx, transfer, zero, n):
     assert rel_err(host(fc), fc_ref) < 1e-12
 
 
+@pytest.mark.parametrize("store_path", ["decode", "copy"])
 @pytest.mark.parametrize("n", [40, 136, 256])
-def test_presmooth_mixed_matches_separate_sweeps(ctx, n):
+def test_presmooth_mixed_matches_separate_sweeps(ctx, n, store_path):
     """Compressed finest level and FP32 coarse levels: the fused pass equals
-    two sweeps plus a residual of the separate kernels up to FP32 rounding."""
+    two sweeps plus a residual of the separate kernels up to FP32 rounding,
+    with the finest operator decoded from the store or read as its FP32
+    decode."""
     d = 2
     fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
     K, _, _ = P.assemble_cells(ctx, d, n, 4, P.Eps(fld), P.MIXED)
     S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
-    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    sp = P.STORE_DECODE if store_path == "decode" else P.STORE_COPY
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG, store_path=sp)
     h.compress(S32, P.centre_samples(ctx, d, n, P.Eps(fld)), 1, 3, 0.0, 1e-4)
     h.coarsen()
     rng = np.random.default_rng(12)
@@ -436,7 +440,8 @@ def _vcycle_rate(h, f, dtype):
     return (norms[-1] / norms[0]) ** (1.0 / 5)
 
 
-def test_mixed_vcycle_contracts_fused(ctx):
+@pytest.mark.parametrize("store_path", ["decode", "copy"])
+def test_mixed_vcycle_contracts_fused(ctx, store_path):
     """Fused finest and middle levels in the mixed form (compressed store,
     FP32 cycle): per-cycle contraction as a stationary iteration within 0.02
     of the FP64 cycle on the oracle's stencils of the same material."""
@@ -450,12 +455,72 @@ def test_mixed_vcycle_contracts_fused(ctx):
     rate64 = _vcycle_rate(h64, f, torch.float64)
     K, _, _ = P.assemble_cells(ctx, d, n, 8, P.Eps(fld), P.MIXED)
     S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
-    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    sp = P.STORE_DECODE if store_path == "decode" else P.STORE_COPY
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG, store_path=sp)
     h.compress(S32, P.centre_samples(ctx, d, n, P.Eps(fld)), 2, 2, 0.0, 1e-7)
     h.coarsen()
     rate32 = _vcycle_rate(h, f, torch.float32)
     assert rate64 < 1.0
     assert rate32 <= rate64 + 0.02, (rate32, rate64)
+
+
+@pytest.mark.parametrize("transfer", [0, 1])
+@pytest.mark.parametrize("n", [70, 136])
+def test_store_paths_bit_identical(ctx, transfer, n):
+    """Mixed finest level: the fused 2D kernels that decode the compressed
+    store (FP8 / FP16 / FP32 tiers) and those that read its FP32 decode hold
+    the same operator values, so pre-smoothing (from zero and from a given
+    iterate), pre-smoothing with restriction and V-cycles agree bit for bit."""
+    d = 2
+    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    K, _, _ = P.assemble_cells(ctx, d, n, 4, P.Eps(fld), P.MIXED)
+    S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
+    eps_c = P.centre_samples(ctx, d, n, P.Eps(fld))
+    rng = np.random.default_rng(21)
+    inner = W.interior_mask(d, n)
+    f = dev(rng.standard_normal(inner.size) * inner, torch.float32)
+    u = dev(rng.standard_normal(inner.size) * inner, torch.float32)
+    outs = {}
+    for sp in (P.STORE_DECODE, P.STORE_COPY):
+        h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=transfer, store_path=sp)
+        h.compress(S32, eps_c, 1, 3, 0.0, 1e-5)
+        h.coarsen()
+        tiers = h.store_info()[2]
+        res = []
+        for start in (None, u):
+            uo, ro, uo2 = torch.zeros_like(f), torch.zeros_like(f), torch.zeros_like(f)
+            fc = torch.zeros(h.nv(1), dtype=torch.float32, device="cuda")
+            h.presmooth(0, start, f, uo, ro)
+            h.presmooth_restrict(0, start, f, uo2, fc)
+            res += [uo, ro, uo2, fc]
+        z = u.clone()
+        for _ in range(3):
+            h.vcycle(z, f)
+        res.append(z)
+        outs[sp] = [host(t) for t in res]
+        h.close()
+    assert sum(1 for t in tiers[1:] if t > 0) >= 2, tiers
+    for k, (a, b) in enumerate(zip(outs[P.STORE_DECODE], outs[P.STORE_COPY])):
+        assert np.array_equal(a, b), k
+
+
+@pytest.mark.parametrize("schedule", ["upfront", "lazy"])
+def test_solve_store_paths_bit_identical(ctx, schedule):
+    """A mixed PCG solve (fused pre and post halves with the dot partials,
+    fused CG product) gives the same history and solution bit for bit with
+    the finest operator decoded from the store or read as its FP32 decode."""
+    d, n = 2, 96
+    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+    f = dev(W.load_sine(d, n))
+    kw = dict(s_max=8, tol=1e-9, transfer=P.BOXMG, outer=P.PCG, precision=P.MIXED, min_tier=1, max_tier=3,
+              tau_rel=1e-6, schedule=P.UPFRONT if schedule == "upfront" else P.LAZY,
+              publish=P.PUBLISH_DETERMINISTIC)
+    u1, r1 = P.solve(ctx, d, n, P.Eps(fld), f, store_path=P.STORE_DECODE, **kw)
+    u2, r2 = P.solve(ctx, d, n, P.Eps(fld), f, store_path=P.STORE_COPY, **kw)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r1["cycles"] == r2["cycles"]
+    assert list(r1["hist"]) == list(r2["hist"])
+    assert torch.equal(u1, u2)
 
 
 def test_mixed_vcycle_contracts(ctx):
