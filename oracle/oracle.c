@@ -961,10 +961,12 @@ enum { ORC_OK = 0, ORC_ENOCONV = -4, ORC_EDIVERGED = -5 };
  * on the centre-sample operator and rung k (s = 2^k) of every unfinished
  * cell is integrated and published before cycle k (Sec. 5.1-5.3).  The
  * residual is measured at the start of each cycle with the operator current
- * then, normalised by the first one (Sec. 6); the run stops when every cell
- * is final and the normalised residual is at most tol; the stationary
- * iteration aborts when the residual exceeds div_factor times its reference,
- * CG only on a non-finite residual.                                        */
+ * then, normalised by the first one (Sec. 6); after an operator change the
+ * iteration continues from the carried iterate or from the zero start,
+ * whichever has the smaller residual on the new operator; the run stops
+ * when every cell is final and the normalised residual is at most tol; the
+ * stationary iteration aborts when the residual exceeds div_factor times its
+ * reference, CG only on a non-finite residual.                             */
 int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, const orc_opts *op, orc_report *rep)
 {
     int nl = 1 << d, nn = nl * nl;
@@ -1037,6 +1039,24 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
         if (op->outer == 0 || restart)
             orc_residual(d, N, g->S[0], u, f, r);
         rk = orc_norm_interior(d, N, r);
+        /* start after an operator change (this implementation's reading; the
+         * paper carries the iterate over): the carried iterate unless its
+         * residual on the new operator exceeds that of the zero start (the
+         * interior set to zero, boundary values kept), in which case the
+         * iteration restarts from the zero start */
+        if (restart && k > 0) {
+            double *uz = malloc(sizeof(double) * NV), *rz = malloc(sizeof(double) * NV);
+            for (int64_t v = 0; v < NV; ++v) uz[v] = is_interior(d, N + 1, v, vi) ? 0.0 : u[v];
+            orc_residual(d, N, g->S[0], uz, f, rz);
+            double rzn = orc_norm_interior(d, N, rz);
+            if (rk > rzn) {
+                memcpy(u, uz, sizeof(double) * NV);
+                memcpy(r, rz, sizeof(double) * NV);
+                rk = rzn;
+            }
+            free(uz);
+            free(rz);
+        }
         if (k == 0) r0 = rk;
         /* the divergence guard (Sec. 6.2) watches the solver, not operator
          * updates: its reference is re-taken whenever the operator changes */

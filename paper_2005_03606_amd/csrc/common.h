@@ -266,7 +266,17 @@ constexpr int kHostParts = 1024;
 // residual checks: the squared norm of check k lands in the device scalar
 // s[kChkSlot + (k & 1)] and in the pinned host slot host_part[k & 1]
 constexpr int kChkSlot = 24;
+// s[kRRuSlot]: the carried iterate's squared residual at an operator change
+// (kRRuSlot + 1: scratch); s[kZeroSlot]: 1 when that change restarted from
+// the zero start
+constexpr int kRRuSlot = 28, kZeroSlot = 30;
 int check_sum(mgd_hier *h, int nparts, int slot, hipStream_t st);
+// after an operator change (the carried iterate's outer residual partials in
+// h->partial): keep the iterate or take the zero start (interior zeroed),
+// whichever has the smaller residual; uz, rz: scratch vectors; the chosen
+// start's squared residual to check slot `slot`
+int restart_pick(mgd_hier *h, const OpSet &o, int nparts, int slot, const double *f, double *u, double *r,
+                 double *uz, double *rz, hipStream_t st);
 int pcg_dots(mgd_hier *h, const void *z, const double *r, const double *rold, hipStream_t st);
 int pcg_matvec(mgd_hier *h, const OpSet &o, const void *z, const double *pold, double *pnew, double *Ap,
                const CgScalars &c, hipStream_t st);

@@ -1394,6 +1394,86 @@ int check_sum(mgd_hier *h, int nparts, int slot, hipStream_t st)
     return MGD_OK;
 }
 
+// ---- start of the iteration after an operator change.  The iterate carried
+// over from the previous operator is kept unless its residual on the new
+// operator exceeds that of the zero start (interior zeroed, boundary values
+// kept); then the iteration restarts from the zero start.  Both squared
+// norms are FP64 sums of block partials in fixed order.
+
+// uz = u with the interior zeroed
+template <int D> __global__ __launch_bounds__(256) void k_zero_interior(const double *u, int n, double *uz)
+{
+    Grid<D> g(n);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int xc[3] = {0, 0, 0};
+    g.coords(v, xc);
+    uz[v] = g.interior(xc) ? 0.0 : u[v];
+}
+
+// the zero start's squared residual from its partials against the carried
+// iterate's (*rr_u): the choice to *flag (1: zero start), the chosen start's
+// squared residual to the check slots
+__global__ __launch_bounds__(1024) void k_restart_pick(const double *part, int n, const double *rr_u, double *flag,
+                                                       double *dev_slot, double *host_slot)
+{
+    __shared__ double red[1024];
+    red[threadIdx.x] = (int)threadIdx.x < n ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool zero = *rr_u > red[0];
+        *flag = zero ? 1.0 : 0.0;
+        const double v = zero ? red[0] : *rr_u;
+        *dev_slot = v;
+        *host_slot = v;
+    }
+}
+
+// the chosen start: u, r replaced by the zero start's when *flag is set; the
+// FP32 copy of r (FP32 cycles) rewritten from the chosen residual
+__global__ __launch_bounds__(256) void k_apply_start(const double *flag, const double *uz, const double *rz, int64_t n,
+                                                     double *u, double *r, float *rf)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    double rv = r[v];
+    if (*flag != 0.0) {
+        u[v] = uz[v];
+        rv = rz[v];
+        r[v] = rv;
+    }
+    if (rf) rf[v] = (float)rv;
+}
+
+int restart_pick(mgd_hier *h, const OpSet &o, int nparts, int slot, const double *f, double *u, double *r,
+                 double *uz, double *rz, hipStream_t st)
+{
+    if (nparts < 1 || nparts > 1024 || nparts > h->partial_cap)
+        return mgd_fail(h->ctx, MGD_EINVAL, "restart check with %d partials", nparts);
+    // the carried iterate's squared residual (its partials are in h->partial)
+    hipLaunchKernelGGL(k_check_sum, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nparts,
+                       h->scal + kRRuSlot, h->scal + kRRuSlot + 1);
+    dim3 gv(grid_for(h->NV[0], 256));
+    if (h->dim == 2) hipLaunchKernelGGL(k_zero_interior<2>, gv, dim3(256), 0, st, (const double *)u, h->n, uz);
+    else hipLaunchKernelGGL(k_zero_interior<3>, gv, dim3(256), 0, st, (const double *)u, h->n, uz);
+    HIPCHK(h->ctx, hipGetLastError());
+    int nz = 0, rc;
+    if ((rc = outer_residual(h, o, uz, f, rz, &nz, st))) return rc;
+    if (nz < 1 || nz > 1024) return mgd_fail(h->ctx, MGD_EINVAL, "restart check with %d partials", nz);
+    hipLaunchKernelGGL(k_restart_pick, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nz,
+                       (const double *)(h->scal + kRRuSlot), h->scal + kZeroSlot, h->scal + kChkSlot + (slot & 1),
+                       h->host_part_dev + (slot & 1));
+    float *rf = h->precision == MGD_MIXED ? (float *)h->f[0] : nullptr;
+    hipLaunchKernelGGL(k_apply_start, gv, dim3(256), 0, st, (const double *)(h->scal + kZeroSlot),
+                       (const double *)uz, (const double *)rz, h->NV[0], u, r, rf);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
 int vec_fill_f64(mgd_ctx *ctx, double *a, int64_t n, double v, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, a, n, v);

@@ -47,7 +47,7 @@ template <int D, typename T> __device__ inline void geo_weights(const int *x, T 
 // u contributes its own (final) weights wn(uv, u, wu); divided by the
 // collapsed diagonal.  Computed in FP64 whatever the stored type T.
 template <int D, typename T, class WN>
-__device__ inline void boxmg_row(const HalfRow<D, T> &A, const Grid<D> &g, int64_t v, const int *x, WN wn, double *w)
+__device__ __forceinline__ void boxmg_row(const HalfRow<D, T> &A, const Grid<D> &g, int64_t v, const int *x, WN wn, double *w)
 {
     constexpr int nl = 1 << D, ns = D == 2 ? 9 : 27, c = ns / 2;
     double acc[nl], diag = 0.0;
@@ -82,11 +82,8 @@ __device__ inline void boxmg_row(const HalfRow<D, T> &A, const Grid<D> &g, int64
 // pass k: fine vertices with k odd coordinates (k = 0 also sets every
 // boundary vertex, d-linear weights); pass k reads the weights of pass k - 1
 template <int D, typename T>
-__global__ void k_weights(HalfRow<D, T> A, int n, int pass, T *W)
+__device__ __forceinline__ void weights_vertex(const HalfRow<D, T> &A, const Grid<D> &g, int pass, int64_t v, T *W)
 {
-    Grid<D> g(n);
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.NV) return;
     int x[3] = {0, 0, 0};
     g.coords(v, x);
     int odd = 0;
@@ -108,16 +105,21 @@ __global__ void k_weights(HalfRow<D, T> A, int n, int pass, T *W)
     for (int B = 0; B < nl; ++B) W[(int64_t)B * g.NV + v] = (T)w[B];
 }
 
-// 2D in two launches: phase 0 sets the boundary, even-even (d-linear) and
+template <int D, typename T>
+__global__ void k_weights(HalfRow<D, T> A, int n, int pass, T *W)
+{
+    Grid<D> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < g.NV) weights_vertex<D, T>(A, g, pass, v, W);
+}
+
+// 2D in two phases: phase 0 sets the boundary, even-even (d-linear) and
 // one-odd vertices (their odd-axis neighbours are even-even, whose weights
 // are d-linear); phase 1 the vertices with both coordinates odd, from the
 // stored weights of their neighbours
 template <typename T, int PHASE>
-__global__ __launch_bounds__(256) void k_weights2(HalfRow<2, T> A, int n, T *W)
+__device__ __forceinline__ void weights2_vertex(const HalfRow<2, T> &A, const Grid<2> &g, int64_t v, T *W)
 {
-    Grid<2> g(n);
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.NV) return;
     int x[3] = {0, 0, 0};
     g.coords(v, x);
     const int odd = (x[0] & 1) + (x[1] & 1);
@@ -136,6 +138,14 @@ __global__ __launch_bounds__(256) void k_weights2(HalfRow<2, T> A, int n, T *W)
                         w);
     }
     for (int B = 0; B < 4; ++B) W[(int64_t)B * g.NV + v] = (T)w[B];
+}
+
+template <typename T, int PHASE>
+__global__ __launch_bounds__(256) void k_weights2(HalfRow<2, T> A, int n, T *W)
+{
+    Grid<2> g(n);
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < g.NV) weights2_vertex<T, PHASE>(A, g, v, W);
 }
 
 // weight of fine vertex x toward coarse vertex X (0 unless X is a corner of x's box)
@@ -160,18 +170,23 @@ __device__ inline T weight_to(const T *W, int64_t NV, int64_t v, const int *x, c
 // vertices per workgroup) and their partial sums are added in v order.
 // Computed in FP64 whatever the stored type T.
 template <int D> constexpr int gal_cpb() { return D == 2 ? 32 : 8; }
+template <int D> constexpr int gal_threads() { return gal_cpb<D>() * (D == 2 ? 9 : 27); }
+
+// one group of gal_threads() threads (tg: index in the group, -1 for a
+// thread of the workgroup outside every group) computes the coarse vertices
+// V0 .. V0 + CPB - 1; every thread of the workgroup calls it (one barrier)
 template <int D, typename T>
-__global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T> A, const T *W, int nf, T *Sc)
+__device__ __forceinline__ void galerkin_group(const HalfRow<D, T> &A, const T *W, int nf, T *Sc, int64_t V0, int tg,
+                                      double (*part)[gal_cpb<D>()][n_half(D)])
 {
     constexpr int H = n_half(D), ns = D == 2 ? 9 : 27, c = ns / 2, CPB = gal_cpb<D>();
-    __shared__ double part[ns][CPB][H];
     Grid<D> gf(nf), gc(nf / 2);
-    const int cv = threadIdx.x % CPB, sv = threadIdx.x / CPB;
-    const int64_t V = (int64_t)blockIdx.x * CPB + cv;
+    const int cv = tg % CPB, sv = tg / CPB;
+    const int64_t V = V0 + cv;
     double acc[H];
     for (int j = 0; j < H; ++j) acc[j] = 0.0;
     int X[3] = {0, 0, 0};
-    if (V < gc.NV) {
+    if (tg >= 0 && V < gc.NV) {
         gc.coords(V, X);
         int dv[3] = {0, 0, 0}, x[3] = {0, 0, 0};
         off_of(D, sv, dv);
@@ -211,11 +226,12 @@ __global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T>
             }
         }
     }
-    for (int j = 0; j < H; ++j) part[sv][cv][j] = acc[j];
+    if (tg >= 0)
+        for (int j = 0; j < H; ++j) part[sv][cv][j] = acc[j];
     __syncthreads();
-    for (int t = threadIdx.x; t < CPB * H; t += blockDim.x) {
+    for (int t = tg; t >= 0 && t < CPB * H; t += CPB * ns) {
         const int c2 = t / H, j = t % H;
-        const int64_t V2 = (int64_t)blockIdx.x * CPB + c2;
+        const int64_t V2 = V0 + c2;
         if (V2 >= gc.NV) continue;
         double sum = 0.0;
         for (int k = 0; k < ns; ++k) sum += part[k][c2][j];
@@ -229,6 +245,13 @@ __global__ __launch_bounds__(D == 2 ? 288 : 216) void k_galerkin_p(HalfRow<D, T>
         }
         Sc[(int64_t)j * gc.NV + V2] = inside ? (T)sum : (T)0;
     }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(gal_threads<D>()) void k_galerkin_p(HalfRow<D, T> A, const T *W, int nf, T *Sc)
+{
+    __shared__ double part[D == 2 ? 9 : 27][gal_cpb<D>()][n_half(D)];
+    galerkin_group<D, T>(A, W, nf, Sc, (int64_t)blockIdx.x * gal_cpb<D>(), (int)threadIdx.x, part);
 }
 
 // ------------------------------------------------------------ coarsest solve

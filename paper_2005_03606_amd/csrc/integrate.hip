@@ -14,6 +14,7 @@
 #include <stdio.h>
 
 #include "common.h"
+#include <algorithm>
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
@@ -188,6 +189,71 @@ __device__ inline void build_candidates(const EpsDev &e, int n, bool valid, cons
     }
 }
 
+// The same list for the cells of one wavefront (scattered cells: the open
+// cells of a ladder rung), built by the wave alone into its own LDS rows
+// (capacity cap; on overflow the full list stays in use).
+constexpr int kWaveCand = 64;
+template <int D>
+__device__ inline void build_candidates_wave(const EpsDev &e, int n, bool valid, const int *c, double *wrows,
+                                             const double **rows, int *count)
+{
+    *rows = e.data;
+    *count = e.count;
+    if (e.kind != MGD_EPS_BALLS && e.kind != MGD_EPS_BOXES) return;  // uniform branch
+    const int lane = threadIdx.x & 63;
+    int lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+    for (int m = 0; m < D; ++m) {
+        int l = valid ? c[m] : 0x7fffffff, h = valid ? c[m] : -1;
+        for (int off = 32; off > 0; off >>= 1) {
+            l = min(l, __shfl_xor(l, off));
+            h = max(h, __shfl_xor(h, off));
+        }
+        lo[m] = l;
+        hi[m] = h;
+    }
+    if (hi[0] < 0) return;  // no valid cell in this wave
+    double blo[3], bhi[3];
+    for (int m = 0; m < D; ++m) {
+        blo[m] = (double)lo[m] / n;
+        bhi[m] = (double)(hi[m] + 1) / n;
+    }
+    const int stride = e.kind == MGD_EPS_BALLS ? D + 1 : 2 * D + 1;
+    int cnt = 0;
+    for (int base = 0; base < e.count; base += 64) {
+        const int b = base + lane;
+        bool keep = false;
+        if (b < e.count) {
+            const double *row = e.data + (size_t)b * stride;
+            if (e.kind == MGD_EPS_BALLS) {
+                double d2 = 0.0;
+                for (int m = 0; m < D; ++m) {
+                    double cc = row[m], q = cc < blo[m] ? blo[m] : (cc > bhi[m] ? bhi[m] : cc);
+                    d2 += (cc - q) * (cc - q);
+                }
+                keep = d2 <= row[D] * row[D] * (1.0 + 1e-12) + 1e-300;
+            } else {
+                keep = true;
+                for (int m = 0; m < D; ++m) keep = keep && row[m] < bhi[m] && row[D + m] > blo[m];
+            }
+        }
+        const unsigned long long mask = __ballot(keep);
+        const int pos = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+        if (keep && pos < kWaveCand) {
+            const double *row = e.data + (size_t)b * stride;
+            for (int k = 0; k < stride; ++k) wrows[pos * stride + k] = row[k];
+        }
+        cnt += __popcll(mask);
+    }
+    // the wave's LDS rows are written before any lane reads them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (cnt <= kWaveCand) {
+        *rows = wrows;
+        *count = cnt;
+    }
+}
+
 // ------------------------------------------------------ shared argument pack
 struct AsmArgs {
     int n, s;
@@ -283,15 +349,14 @@ __device__ inline void store_and_check(const AsmArgs &a, int64_t i, int64_t cell
 
 // ------------------------------------------------------------ FP64 (VALU)
 // G lanes cooperate on one cell; lane g takes x-lines g, g+G, ...
-template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
+// block-tile `blk` of 256 / G cells (G threads per cell); the element
+// matrix is computed in FP64 and stored as TO (double, or float for the
+// mixed form's short rungs)
+template <int D, int G, typename TO> __device__ inline void integrate64_tile(const AsmArgs &a, int64_t blk, int64_t cnt)
 {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gid = blk * blockDim.x + threadIdx.x;
     int64_t i = gid / G;
     int g = (int)(gid % G);
-    int64_t cnt = asm_count(a);
-    // grids are sized for the host's bound on the device-side count: blocks
-    // past the count leave at once (uniformly, before any barrier)
-    if ((int64_t)blockIdx.x * blockDim.x / G >= cnt) return;
     bool valid = i < cnt;
     int s = a.s, n = a.n;
     int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
@@ -369,7 +434,29 @@ template <int D, int G> __global__ __launch_bounds__(256) void k_integrate64(Asm
             }
             K[pair_index(D, aa, bb)] = v;
         }
-    store_and_check<D, double>(a, i, cell, K);
+    if constexpr (sizeof(TO) == 8) {
+        store_and_check<D, double>(a, i, cell, K);
+    } else {
+        TO Kt[U];
+        for (int p = 0; p < U; ++p) Kt[p] = (TO)K[p];
+        store_and_check<D, TO>(a, i, cell, Kt);
+    }
+}
+
+// one tile per block for a count known on the host; for a device-side count
+// (the ladder's open cells, bounded on the host by every cell) a capped grid
+// strides over the tiles up to the count, so the bound costs nothing
+template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
+{
+    const int64_t cnt = asm_count(a);
+    if (!STRIDE) {
+        if ((int64_t)blockIdx.x * blockDim.x / G < cnt) integrate64_tile<D, G, TO>(a, blockIdx.x, cnt);
+        return;
+    }
+    for (int64_t blk = blockIdx.x; blk * (int64_t)blockDim.x / G < cnt; blk += gridDim.x) {
+        integrate64_tile<D, G, TO>(a, blk, cnt);
+        __syncthreads();  // the candidate list is rebuilt for the next tile
+    }
 }
 
 // ------------------------------------------------------------ mixed (MFMA)
@@ -390,16 +477,14 @@ union BF8 {
 // v_mfma_f32_16x16x32_bf16); the B operand (G terms) is pre-laid out per
 // lane.  The block's 64 TPW consecutive list entries share one candidate
 // list, so small s (one chunk per cell) takes TPW = 4.
-template <int D, int NT, int NTERM, int TPW>
-__global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *Gtab, int nchunks,
-                                                        float inv_den)
+template <int D, int NT, int NTERM, int TPW, bool WL>
+__device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint4 *Gtab, int nchunks, float inv_den,
+                                                    int64_t blk, int64_t cnt, float (*sm)[16][NT * 16 + 1],
+                                                    CandLDS &cand, double (*wrows)[kWaveCand * 7])
 {
-    __shared__ float sm[4][16][NT * 16 + 1];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int row = lane & 15, kg = lane >> 4;
-    int64_t cnt = asm_count(a);
-    const int64_t blk0 = (int64_t)blockIdx.x * (64 * TPW);
-    if (blk0 >= cnt) return;  // past the device-side count: the whole block leaves
+    const int64_t blk0 = blk * (64 * TPW);
     int s = a.s, n = a.n;
     // candidate box: thread t stands for entries blk0 + t + 256 j of the
     // block's 64 TPW
@@ -418,10 +503,11 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
             any = true;
         }
     }
-    __shared__ CandLDS cand;
-    const double *rows;
-    int nrows;
-    build_candidates<D>(a.eps, n, any, clo, chi, cand, &rows, &nrows);
+    const double *rows = a.eps.data;
+    int nrows = a.eps.count;
+    // contiguous cells share one list per block; scattered ones (WL) take
+    // one per wave below
+    if (!WL) build_candidates<D>(a.eps, n, any, clo, chi, cand, &rows, &nrows);
     int64_t nq = 1;
     for (int m = 0; m < D; ++m) nq *= s;
     for (int j = 0; j < TPW; ++j) {
@@ -431,6 +517,7 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
         const int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
         int ci[3] = {0, 0, 0};
         cell_coords<D>(cell, n, ci);
+        if (WL) build_candidates_wave<D>(a.eps, n, valid, ci, wrows[wave], &rows, &nrows);
         floatx4 acc[NT];
         for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         int nch = tile < cnt ? nchunks : 0;  // idle waves still reach the barriers
@@ -482,6 +569,25 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
             for (int p = 0; p < U; ++p) K[p] = sm[wave][lane][p];
             store_and_check<D, float>(a, i, cell, K);
         }
+    }
+}
+
+template <int D, int NT, int NTERM, int TPW, bool STRIDE>
+__global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *Gtab, int nchunks,
+                                                        float inv_den)
+{
+    __shared__ float sm[4][16][NT * 16 + 1];
+    __shared__ CandLDS cand;
+    __shared__ double wrows[STRIDE ? 4 : 1][kWaveCand * 7];
+    const int64_t cnt = asm_count(a);
+    if (!STRIDE) {
+        if ((int64_t)blockIdx.x * (64 * TPW) < cnt)
+            integrate_mfma_tile<D, NT, NTERM, TPW, false>(a, Gtab, nchunks, inv_den, blockIdx.x, cnt, sm, cand, wrows);
+        return;
+    }
+    for (int64_t blk = blockIdx.x; blk * (64 * TPW) < cnt; blk += gridDim.x) {
+        integrate_mfma_tile<D, NT, NTERM, TPW, true>(a, Gtab, nchunks, inv_den, blk, cnt, sm, cand, wrows);
+        __syncthreads();  // the candidate list and the row buffer are reused by the next tile
     }
 }
 
@@ -618,14 +724,32 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
     a.samples = eps->kind == MGD_EPS_SAMPLES ? eps->data : nullptr;
     a.K_out = K_out; a.K_old = K_old;
     a.k_by_cell = k_by_cell; a.C = C; a.rel_out = rel_out; a.done_out = done_out;
-    if (mode == MGD_FP64) {
+    // block-stride kernels: a capped grid covers any count (the ladder's
+    // counts live on the device; `count` is only the host's bound)
+    constexpr unsigned kAsmMaxBlocks = 4096;
+    // the mixed form's rungs with s <= 2 (at most 2^d samples per cell) are
+    // too short a contraction for the matrix cores: FP64 on the vector
+    // units, rounded to FP32
+    if (mode == MGD_FP64 || s <= 2) {
         int lines = dim == 2 ? s : s * s;
         int G = lines >= 16 ? 16 : lines >= 4 ? 4 : 1;
+        const bool stride = count_dev != nullptr;
         unsigned grid = grid_for(count * G, 256);
-#define L64(DD, GG) hipLaunchKernelGGL((k_integrate64<DD, GG>), dim3(grid), dim3(256), 0, st, a)
+        if (stride) grid = std::min<unsigned>(grid, kAsmMaxBlocks);
+#define L64T(DD, GG, TO)                                                                                       \
+    do {                                                                                                       \
+        if (stride) hipLaunchKernelGGL((k_integrate64<DD, GG, true, TO>), dim3(grid), dim3(256), 0, st, a);    \
+        else hipLaunchKernelGGL((k_integrate64<DD, GG, false, TO>), dim3(grid), dim3(256), 0, st, a);          \
+    } while (0)
+#define L64(DD, GG)                                  \
+    do {                                             \
+        if (mode == MGD_FP64) L64T(DD, GG, double);  \
+        else L64T(DD, GG, float);                    \
+    } while (0)
         if (dim == 2) { if (G == 16) L64(2, 16); else if (G == 4) L64(2, 4); else L64(2, 1); }
         else { if (G == 16) L64(3, 16); else if (G == 4) L64(3, 4); else L64(3, 1); }
 #undef L64
+#undef L64T
     } else {
         GTable *T = nullptr;
         int rc = get_gtable(ctx, dim, s, &T);
@@ -633,10 +757,18 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         double inv_den = dim == 2 ? 1.0 / (6.0 * pow((double)s, 4)) : (1.0 / n) / (36.0 * pow((double)s, 7));
         // one chunk per cell: four 16-cell groups per wave share the block's candidates
         const bool small = T->nchunks == 1;
+        const bool stride = count_dev != nullptr;
         unsigned grid = grid_for(count, small ? 256 : 64);
-#define LM(DD, NT, NTERM, TPW)                                                                              \
-    hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW>), dim3(grid), dim3(256), 0, st, a, T->dev, \
-                       T->nchunks, (float)inv_den)
+        if (stride) grid = std::min<unsigned>(grid, kAsmMaxBlocks);
+#define LM(DD, NT, NTERM, TPW)                                                                                   \
+    do {                                                                                                         \
+        if (stride)                                                                                              \
+            hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, true>), dim3(grid), dim3(256), 0, st, a,    \
+                               T->dev, T->nchunks, (float)inv_den);                                              \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, false>), dim3(grid), dim3(256), 0, st, a,   \
+                               T->dev, T->nchunks, (float)inv_den);                                              \
+    } while (0)
         if (dim == 2) {
             if (T->nterm == 2) { if (small) LM(2, 1, 2, 4); else LM(2, 1, 2, 1); }
             else { if (small) LM(2, 1, 3, 4); else LM(2, 1, 3, 1); }

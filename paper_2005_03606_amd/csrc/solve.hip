@@ -239,7 +239,14 @@ static int enqueue_check(SolveState *S, int nparts)
         if (S->pcg && S->restart && (rc = vec_fill_f64(ctx, H.scal + 7, 1, 1.0, S->stream))) return rc;
     }
     const int slot = S->kq & 1;
-    if ((rc = check_sum(&H, nparts, slot, S->stream))) return rc;
+    if (S->restart && S->kq > 0) {
+        // an operator change: the carried iterate or the zero start
+        // (the CG direction and product vectors restart too: free as scratch)
+        if ((rc = restart_pick(&H, *S->sets[S->cur], nparts, slot, S->f, S->u, S->r, S->p[0], S->Ap, S->stream)))
+            return rc;
+    } else if ((rc = check_sum(&H, nparts, slot, S->stream))) {
+        return rc;
+    }
     HIPCHK(ctx, hipEventRecord(S->ev_norm[slot], S->stream));
     S->kq++;
     return MGD_OK;

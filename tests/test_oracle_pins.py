@@ -507,6 +507,43 @@ def test_lazy_schedule_reaches_the_upfront_operator():
         assert np.abs(u[inner] - ue).max() < 1e-8 * np.abs(ue).max()
 
 
+def test_lazy_restart_takes_the_better_start():
+    """After an operator change the iteration continues from the carried
+    iterate or from the zero start (interior zeroed, boundary values kept),
+    whichever has the smaller residual on the new operator.  With u0 = 0 and a
+    zero boundary the zero start's residual is |f| = r_0: no check after a
+    publish exceeds 1, and a check where the zero start was taken reads
+    exactly 1.  That the rule has something to decide is checked apart: one
+    CG step on the centre-sample operator (built here from the oracle's
+    pieces) leaves a residual on the s = 2 operator far above |f|."""
+    d, n = 2, 32
+    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=16, tol=1e-10, transfer=O.BOXMG, outer=O.PCG)
+    u, rep = O.solve(fld, d, n, f, lazy=True, **kw)
+    h = rep["hist"]
+    assert rep["status"] == O.OK
+    assert all(h[k] <= 1.0 for k in range(1, 5))
+    assert h[1] == 1.0
+    # first cycle on the centre-sample operator, then the s = 2 operator's residual
+    inner = _interior(d, n)
+    S1 = O.stencils(d, n, O.assemble(fld, d, n, 1))
+    H1 = O.Hierarchy(d, n, S1, transfer=O.BOXMG)
+    z = H1.vcycle(np.zeros_like(f), f)
+    Az = O.dense_matrix(d, n, S1) @ z[inner]
+    u1 = np.zeros_like(f)
+    u1[inner] = (z[inner] @ f[inner]) / (z[inner] @ Az) * z[inner]
+    S2 = O.stencils(d, n, O.assemble(fld, d, n, 2))
+    r2 = O.residual(d, n, S2, u1, f)
+    assert np.linalg.norm(r2[inner]) > 10.0 * np.linalg.norm(f[inner])
+    # boundary values of the iterate are kept through a zero start
+    u0 = np.zeros_like(f)
+    u0[~inner] = 0.3
+    ub, rb = O.solve(fld, d, n, f, u0=u0, lazy=True, **kw)
+    assert rb["status"] == O.OK
+    assert np.array_equal(ub[~inner], u0[~inner])
+
+
 def test_boxmg_weights_reduce_to_dlinear_for_constant_eps():
     for d, n in [(2, 8), (3, 4)]:
         S = O.stencils(d, n, O.assemble(W.const_field(d, 3.0), d, n, 1))
