@@ -516,12 +516,12 @@ __device__ void tail_pass(const TailLevel &lv, const T *S, const T *uin, T *uout
     int lin[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) lin[j] = half_off(D, j, 0) + half_off(D, j, 1) * nv + (D == 3 ? half_off(D, j, 2) * nv * nv : 0);
-    for (int v0 = threadIdx.x; v0 < NV; v0 += CK * kTailThreads) {
+    for (int v0 = threadIdx.x; v0 < NV; v0 += CK * (int)blockDim.x) {
         T c[CK][2 * H];
         bool in[CK];
 #pragma unroll
         for (int q = 0; q < CK; ++q) {
-            const int v = v0 + q * kTailThreads;
+            const int v = v0 + q * (int)blockDim.x;
             int x[3] = {0, 0, 0};
             tail_coords<D>(v < NV ? v : 0, lv, x);
             in[q] = v < NV && tail_interior<D>(x, lv.n);
@@ -534,7 +534,7 @@ __device__ void tail_pass(const TailLevel &lv, const T *S, const T *uin, T *uout
         }
 #pragma unroll
         for (int q = 0; q < CK; ++q) {
-            const int v = v0 + q * kTailThreads;
+            const int v = v0 + q * (int)blockDim.x;
             if (v >= NV) continue;
             T out = (T)0;
             if (in[q]) {
@@ -560,7 +560,7 @@ __device__ inline void tail_pass_any(const TailLevel &lv, const T *S, const T *u
 {
     // several vertices per thread in flight where registers allow (2D), else one
     constexpr int CK = D == 3 ? 1 : sizeof(T) == 8 ? 3 : 5;
-    if (CK > 1 && lv.NV > kTailThreads) tail_pass<D, T, CK, MODE>(lv, S, uin, uout, f, zero, omega);
+    if (CK > 1 && lv.NV > (int)blockDim.x) tail_pass<D, T, CK, MODE>(lv, S, uin, uout, f, zero, omega);
     else tail_pass<D, T, 1, MODE>(lv, S, uin, uout, f, zero, omega);
 }
 
@@ -572,11 +572,11 @@ __device__ void tail_smooth(const TailLevel &lv, const T *S, T *u, const T *f, T
         else tail_pass_any<D, T, 0>(lv, S, t, u, f, false, omega);
     }
     if (sweeps % 2 == 1) {
-        for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = t[v];
+        for (int v = threadIdx.x; v < lv.NV; v += (int)blockDim.x) u[v] = t[v];
         __syncthreads();
     }
     if (sweeps == 0 && zero) {
-        for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = (T)0;
+        for (int v = threadIdx.x; v < lv.NV; v += (int)blockDim.x) u[v] = (T)0;
         __syncthreads();
     }
 }
@@ -587,7 +587,7 @@ __device__ void tail_restrict(const TailLevel &lv, const TailLevel &lc, const T 
 {
     constexpr int ns = D == 2 ? 9 : 27;
     const int nv = lv.n + 1, NV = lv.NV;
-    for (int V = threadIdx.x; V < lc.NV; V += kTailThreads) {
+    for (int V = threadIdx.x; V < lc.NV; V += (int)blockDim.x) {
         int X[3] = {0, 0, 0};
         tail_coords<D>(V, lc, X);
         uc[V] = (T)0;
@@ -634,7 +634,7 @@ __device__ void tail_prolong(const TailLevel &lv, const TailLevel &lc, const T *
 {
     constexpr int nl = 1 << D;
     const int ncv = lc.n + 1;
-    for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) {
+    for (int v = threadIdx.x; v < lv.NV; v += (int)blockDim.x) {
         int x[3] = {0, 0, 0};
         tail_coords<D>(v, lv, x);
         if (!tail_interior<D>(x, lv.n)) continue;
@@ -674,11 +674,11 @@ __device__ void tail_coarse(const TailArgs &a, const TailLevel &lv, T *u, const 
         for (int mm = 0; mm < D; ++mm) { v += (1 + t % nin) * st; t /= nin; st *= nv; }
         return v;
     };
-    for (int k = threadIdx.x; k < m; k += kTailThreads) work[k] = (double)f[vof(k)];
-    for (int v = threadIdx.x; v < lv.NV; v += kTailThreads) u[v] = (T)0;
+    for (int k = threadIdx.x; k < m; k += (int)blockDim.x) work[k] = (double)f[vof(k)];
+    for (int v = threadIdx.x; v < lv.NV; v += (int)blockDim.x) u[v] = (T)0;
     __syncthreads();
     if (a.cinv) {
-        for (int i = threadIdx.x; i < m; i += kTailThreads) {
+        for (int i = threadIdx.x; i < m; i += (int)blockDim.x) {
             double s = 0.0;
             for (int k = 0; k < m; ++k) s += a.cinv[(int64_t)i * m + k] * work[k];
             u[vof(i)] = (T)s;
@@ -692,7 +692,7 @@ __device__ void tail_coarse(const TailArgs &a, const TailLevel &lv, T *u, const 
         const double yi = work[i] / L[(int64_t)i * m + i];
         __syncthreads();
         if (threadIdx.x == 0) work[i] = yi;
-        for (int k = i + 1 + threadIdx.x; k < m; k += kTailThreads) work[k] -= L[(int64_t)k * m + i] * yi;
+        for (int k = i + 1 + threadIdx.x; k < m; k += (int)blockDim.x) work[k] -= L[(int64_t)k * m + i] * yi;
         __syncthreads();
     }
     // backward: L^T x = y, row i needs x_k for k > i
@@ -700,10 +700,10 @@ __device__ void tail_coarse(const TailArgs &a, const TailLevel &lv, T *u, const 
         const double xi = work[i] / L[(int64_t)i * m + i];
         __syncthreads();
         if (threadIdx.x == 0) work[i] = xi;
-        for (int k = threadIdx.x; k < i; k += kTailThreads) work[k] -= L[(int64_t)i * m + k] * xi;
+        for (int k = threadIdx.x; k < i; k += (int)blockDim.x) work[k] -= L[(int64_t)i * m + k] * xi;
         __syncthreads();
     }
-    for (int k = threadIdx.x; k < m; k += kTailThreads) u[vof(k)] = (T)work[k];
+    for (int k = threadIdx.x; k < m; k += (int)blockDim.x) u[vof(k)] = (T)work[k];
     __syncthreads();
 }
 
@@ -725,7 +725,7 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
         const TailLevel &l0 = a.L[a.first];
         const T *fg = (const T *)a.f, *ug = (const T *)a.u;
         T *u0 = U(a.first), *f0 = F(a.first);
-        for (int v = threadIdx.x; v < l0.NV; v += kTailThreads) {
+        for (int v = threadIdx.x; v < l0.NV; v += (int)blockDim.x) {
             f0[v] = fg[v];
             u0[v] = a.zero_guess ? (T)0 : ug[v];
         }
@@ -745,7 +745,7 @@ template <int D, typename T> __global__ __launch_bounds__(1024) void k_tail(Tail
     {
         T *ug = (T *)a.u;
         const T *u0 = U(a.first);
-        for (int v = threadIdx.x; v < a.L[a.first].NV; v += kTailThreads) ug[v] = u0[v];
+        for (int v = threadIdx.x; v < a.L[a.first].NV; v += (int)blockDim.x) ug[v] = u0[v];
     }
 }
 
@@ -911,10 +911,12 @@ template <typename T> __global__ __launch_bounds__(1024) void k_tail2d(TailArgs 
 
 // first level handled by the single-workgroup tail: in 2D the levels up to
 // 33 x 33 vertices (larger ones run faster as fused multi-block passes), in
-// 3D up to 17^3 (their vectors still fit in LDS)
+// 3D up to 9^3 (17^3 runs as multi-block passes: a single workgroup large
+// enough for it waits long for a free CU while assembly runs beside the
+// cycles)
 static int tail_first(const mgd_hier *h)
 {
-    const int64_t kTailNV = h->dim == 2 ? 1100 : 5000;
+    const int64_t kTailNV = h->dim == 2 ? 1100 : 800;
     int l = h->nlev - 1;
     while (l > 0 && h->NV[l - 1] <= kTailNV) --l;
     if (h->precision == MGD_MIXED && l == 0) l = h->nlev > 1 ? 1 : 0;  // level 0 is the compressed store
@@ -938,7 +940,9 @@ template <int D, typename T> static void tail_launch_t(const TailArgs &a, size_t
         (void)hipFuncSetAttribute((const void *)k_tail<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_tail<D, T>), dim3(1), dim3(kTailThreads), lds, st, a);
+    // 3D tails hold only small levels: one quarter of the threads, so the
+    // workgroup finds room beside a concurrent assembly kernel
+    hipLaunchKernelGGL((k_tail<D, T>), dim3(1), dim3(D == 3 ? kTailThreads / 4 : kTailThreads), lds, st, a);
 }
 
 static int launch_tail(mgd_hier *h, const OpSet &o, int first, void *u, const void *f, double omega, int nu1, int nu2,

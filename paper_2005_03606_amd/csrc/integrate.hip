@@ -348,113 +348,121 @@ __device__ inline void store_and_check(const AsmArgs &a, int64_t i, int64_t cell
 }
 
 // ------------------------------------------------------------ FP64 (VALU)
-// G lanes cooperate on one cell; lane g takes x-lines g, g+G, ...
-// block-tile `blk` of 256 / G cells (G threads per cell); the element
-// matrix is computed in FP64 and stored as TO (double, or float for the
-// mixed form's short rungs)
-template <int D, int G, typename TO> __device__ inline void integrate64_tile(const AsmArgs &a, int64_t blk, int64_t cnt)
-{
-    int64_t gid = blk * blockDim.x + threadIdx.x;
-    int64_t i = gid / G;
-    int g = (int)(gid % G);
-    bool valid = i < cnt;
-    int s = a.s, n = a.n;
-    int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
-    int ci[3] = {0, 0, 0};
-    cell_coords<D>(cell, n, ci);
-    __shared__ CandLDS cand;
-    const double *rows;
-    int nrows;
-    build_candidates<D>(a.eps, n, valid, ci, ci, cand, &rows, &nrows);
-    int nlines = (D == 2) ? s : s * s;
-    int64_t nq = (int64_t)nlines * s;
-    // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
-    // T3[tx][ty] = sum eps Mx My (2D: T1[ty], T2[tx])
-    double T1[9], T2[9], T3[9];
-    for (int k = 0; k < 9; ++k) T1[k] = T2[k] = T3[k] = 0.0;
-    if (valid) {
-        for (int line = g; line < nlines; line += G) {
-            int qy = line % s, qz = line / s;
-            double My[3], Mz[3] = {1.0, 1.0, 1.0};
-            moments64(s, qy, My);
-            if (D == 3) moments64(s, qz, Mz);
-            double L0 = 0.0, L[3] = {0.0, 0.0, 0.0};
-            double x[3];
-            x[1] = sample_coord(ci[1], qy, s, n);
-            if (D == 3) x[2] = sample_coord(ci[2], qz, s, n);
-            for (int qx = 0; qx < s; ++qx) {
-                double e;
-                if (a.eps.kind == MGD_EPS_SAMPLES) {
-                    int64_t q = qx + (int64_t)s * line;
-                    e = a.samples[i * nq + q];
-                } else {
-                    x[0] = sample_coord(ci[0], qx, s, n);
-                    e = eps_eval<D, double>(a.eps, x, rows, nrows);
-                }
-                double Mx[3];
-                moments64(s, qx, Mx);
-                L0 += e;
-                for (int t = 0; t < 3; ++t) L[t] += e * Mx[t];
-            }
-            if (D == 2) {
-                for (int t = 0; t < 3; ++t) { T1[t] += L0 * My[t]; T2[t] += L[t]; }
-            } else {
-                for (int ty = 0; ty < 3; ++ty)
-                    for (int tz = 0; tz < 3; ++tz) T1[ty * 3 + tz] += L0 * My[ty] * Mz[tz];
-                for (int tx = 0; tx < 3; ++tx)
-                    for (int tz = 0; tz < 3; ++tz) T2[tx * 3 + tz] += L[tx] * Mz[tz];
-                for (int tx = 0; tx < 3; ++tx)
-                    for (int ty = 0; ty < 3; ++ty) T3[tx * 3 + ty] += L[tx] * My[ty];
-            }
-        }
-    }
-    // reduce over the G lanes of the cell (fixed butterfly order)
-    for (int off = G / 2; off > 0; off >>= 1)
-        for (int k = 0; k < 9; ++k) {
-            T1[k] += __shfl_xor(T1[k], off, 64);
-            T2[k] += __shfl_xor(T2[k], off, 64);
-            T3[k] += __shfl_xor(T3[k], off, 64);
-        }
-    if (!valid || g != 0) return;
-    constexpr int nl = 1 << D, U = n_pairs(D);
-    double K[U];
-    double inv_s = 1.0 / s, hp = (D == 2) ? 1.0 : 1.0 / n;
-    for (int aa = 0; aa < nl; ++aa)
-        for (int bb = aa + 1; bb < nl; ++bb) {
-            int ax = aa & 1, bx = bb & 1, ay = (aa >> 1) & 1, by = (bb >> 1) & 1;
-            double sx = ax == bx ? inv_s : -inv_s, sy = ay == by ? inv_s : -inv_s;
-            double v;
-            if (D == 2) {
-                v = sx * T1[mtype(ay, by)] + sy * T2[mtype(ax, bx)];
-            } else {
-                int az = (aa >> 2) & 1, bz = (bb >> 2) & 1;
-                double sz = az == bz ? inv_s : -inv_s;
-                int tx = mtype(ax, bx), ty = mtype(ay, by), tz = mtype(az, bz);
-                v = hp * (sx * T1[ty * 3 + tz] + sy * T2[tx * 3 + tz] + sz * T3[tx * 3 + ty]);
-            }
-            K[pair_index(D, aa, bb)] = v;
-        }
-    if constexpr (sizeof(TO) == 8) {
-        store_and_check<D, double>(a, i, cell, K);
-    } else {
-        TO Kt[U];
-        for (int p = 0; p < U; ++p) Kt[p] = (TO)K[p];
-        store_and_check<D, TO>(a, i, cell, Kt);
-    }
-}
-
-// one tile per block for a count known on the host; for a device-side count
-// (the ladder's open cells, bounded on the host by every cell) a capped grid
-// strides over the tiles up to the count, so the bound costs nothing
+// G lanes cooperate on one cell; lane g takes x-lines g, g+G, ...  The
+// element matrix is computed in FP64 and stored as TO (double, or float for
+// the mixed form's short rungs).  One tile of 256 / G cells per block for a
+// count known on the host; for a device-side count (the ladder's open
+// cells, bounded on the host by every cell) a capped grid strides over the
+// tiles up to the count, so the bound costs nothing.  (The tile is written
+// inline: as a called function its accumulators leave the registers.)
 template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
 {
+    __shared__ CandLDS cand;
     const int64_t cnt = asm_count(a);
-    if (!STRIDE) {
-        if ((int64_t)blockIdx.x * blockDim.x / G < cnt) integrate64_tile<D, G, TO>(a, blockIdx.x, cnt);
-        return;
-    }
-    for (int64_t blk = blockIdx.x; blk * (int64_t)blockDim.x / G < cnt; blk += gridDim.x) {
-        integrate64_tile<D, G, TO>(a, blk, cnt);
+    for (int64_t blk = blockIdx.x;; blk += gridDim.x) {
+        if (blk * (int64_t)blockDim.x / G >= cnt) return;  // uniform, before any barrier
+        int64_t gid = blk * blockDim.x + threadIdx.x;
+        int64_t i = gid / G;
+        int g = (int)(gid % G);
+        bool valid = i < cnt;
+        int s = a.s, n = a.n;
+        int64_t cell = valid ? (a.cells ? a.cells[i] : i) : 0;
+        int ci[3] = {0, 0, 0};
+        cell_coords<D>(cell, n, ci);
+        const double *rows;
+        int nrows;
+        build_candidates<D>(a.eps, n, valid, ci, ci, cand, &rows, &nrows);
+        int nlines = (D == 2) ? s : s * s;
+        int64_t nq = (int64_t)nlines * s;
+        // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
+        // T3[tx][ty] = sum eps Mx My (2D: T1[ty], T2[tx])
+        double T1[9], T2[9], T3[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) T1[k] = T2[k] = T3[k] = 0.0;
+        if (valid) {
+            for (int line = g; line < nlines; line += G) {
+                int qy = line % s, qz = line / s;
+                double My[3], Mz[3] = {1.0, 1.0, 1.0};
+                moments64(s, qy, My);
+                if (D == 3) moments64(s, qz, Mz);
+                double L0 = 0.0, L[3] = {0.0, 0.0, 0.0};
+                double x[3];
+                x[1] = sample_coord(ci[1], qy, s, n);
+                if (D == 3) x[2] = sample_coord(ci[2], qz, s, n);
+                for (int qx = 0; qx < s; ++qx) {
+                    double e;
+                    if (a.eps.kind == MGD_EPS_SAMPLES) {
+                        int64_t q = qx + (int64_t)s * line;
+                        e = a.samples[i * nq + q];
+                    } else {
+                        x[0] = sample_coord(ci[0], qx, s, n);
+                        e = eps_eval<D, double>(a.eps, x, rows, nrows);
+                    }
+                    double Mx[3];
+                    moments64(s, qx, Mx);
+                    L0 += e;
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) L[t] += e * Mx[t];
+                }
+                if (D == 2) {
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) { T1[t] += L0 * My[t]; T2[t] += L[t]; }
+                } else {
+#pragma unroll
+                    for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+                        for (int tz = 0; tz < 3; ++tz) T1[ty * 3 + tz] += L0 * My[ty] * Mz[tz];
+#pragma unroll
+                    for (int tx = 0; tx < 3; ++tx)
+#pragma unroll
+                        for (int tz = 0; tz < 3; ++tz) T2[tx * 3 + tz] += L[tx] * Mz[tz];
+#pragma unroll
+                    for (int tx = 0; tx < 3; ++tx)
+#pragma unroll
+                        for (int ty = 0; ty < 3; ++ty) T3[tx * 3 + ty] += L[tx] * My[ty];
+                }
+            }
+        }
+        // reduce over the G lanes of the cell (fixed butterfly order)
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                T1[k] += __shfl_xor(T1[k], off, 64);
+                T2[k] += __shfl_xor(T2[k], off, 64);
+                T3[k] += __shfl_xor(T3[k], off, 64);
+            }
+        if (valid && g == 0) {
+            constexpr int nl = 1 << D, U = n_pairs(D);
+            double K[U];
+            double inv_s = 1.0 / s, hp = (D == 2) ? 1.0 : 1.0 / n;
+#pragma unroll
+            for (int aa = 0; aa < nl; ++aa)
+#pragma unroll
+                for (int bb = aa + 1; bb < nl; ++bb) {
+                    int ax = aa & 1, bx = bb & 1, ay = (aa >> 1) & 1, by = (bb >> 1) & 1;
+                    double sx = ax == bx ? inv_s : -inv_s, sy = ay == by ? inv_s : -inv_s;
+                    double v;
+                    if (D == 2) {
+                        v = sx * T1[mtype(ay, by)] + sy * T2[mtype(ax, bx)];
+                    } else {
+                        int az = (aa >> 2) & 1, bz = (bb >> 2) & 1;
+                        double sz = az == bz ? inv_s : -inv_s;
+                        int tx = mtype(ax, bx), ty = mtype(ay, by), tz = mtype(az, bz);
+                        v = hp * (sx * T1[ty * 3 + tz] + sy * T2[tx * 3 + tz] + sz * T3[tx * 3 + ty]);
+                    }
+                    K[pair_index(D, aa, bb)] = v;
+                }
+            if constexpr (sizeof(TO) == 8) {
+                store_and_check<D, double>(a, i, cell, K);
+            } else {
+                TO Kt[U];
+#pragma unroll
+                for (int p = 0; p < U; ++p) Kt[p] = (TO)K[p];
+                store_and_check<D, TO>(a, i, cell, Kt);
+            }
+        }
+        if (!STRIDE) return;
         __syncthreads();  // the candidate list is rebuilt for the next tile
     }
 }
