@@ -113,6 +113,7 @@ def lib():
         L.orc_mg_level_weights.restype = C.POINTER(C.c_double)
         L.orc_mg_create.restype = C.c_void_p
         L.orc_mg_set_fine.argtypes = [C.c_void_p, _D]
+        L.orc_mg_set_geometric.argtypes = [C.c_void_p, _D, _D]
         L.orc_mg_levels.argtypes = [C.c_void_p]
         L.orc_mg_level_n.argtypes = [C.c_void_p, C.c_int]
         L.orc_mg_level_stencils.argtypes = [C.c_void_p, C.c_int]
@@ -327,6 +328,12 @@ class Hierarchy:
 
     def set_fine(self, S0):
         lib().orc_mg_set_fine(self.h, np.ascontiguousarray(S0).ravel())
+
+    def set_geometric(self, S0, eps_c0):
+        """Finest level S0; coarser levels rediscretised from child-averaged
+        cell values (finest: eps_c0 per fine cell), d-linear transfers."""
+        lib().orc_mg_set_geometric(self.h, np.ascontiguousarray(S0, dtype=np.float64).ravel(),
+                                   np.ascontiguousarray(eps_c0, dtype=np.float64).ravel())
 
     def vcycle(self, u, f, omega=0.6, nu1=2, nu2=2):
         u = np.array(u, dtype=np.float64, copy=True)

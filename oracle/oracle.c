@@ -860,6 +860,57 @@ void orc_mg_set_fine(orc_mg *g, const double *S0)
     mg_coarsen(g);
 }
 
+/* Geometric hierarchy of a provisional operator (Sec. 1: multigrid starts
+ * from crude fine grid stencils with geometric coarse grid and inter-grid
+ * transfer operators): S0 on the finest level; level l >= 1 is the Q1
+ * rediscretisation whose cell values average the 2^d child cells' (the
+ * finest level's: eps_c0, one value per fine cell, cell index x fastest);
+ * d-linear transfer weights; the coarsest matrix factored as usual. */
+void orc_mg_set_geometric(orc_mg *g, const double *S0, const double *eps_c0)
+{
+    int d = g->d, nl = 1 << d;
+    memcpy(g->S[0], S0, sizeof(double) * npow(g->n[0] + 1, d) * nst(d));
+    double *ef = malloc(sizeof(double) * npow(g->n[0], d));
+    memcpy(ef, eps_c0, sizeof(double) * npow(g->n[0], d));
+    for (int l = 1; l < g->nlev; ++l) {
+        int nf = g->n[l - 1], nc = g->n[l];
+        int64_t NC = npow(nc, d);
+        orc_transfer_weights(d, nf, g->S[l - 1], T_GEOMETRIC, g->Pw[l - 1]);
+        double *ec = malloc(sizeof(double) * NC);
+        double *K = malloc(sizeof(double) * NC * nl * nl);
+        double G[64];
+        int32_t q0[3] = {0, 0, 0};
+        orc_subcell_matrix(d, 1, q0, 1.0 / nc, G); /* unit-eps Q1 element matrix */
+        for (int64_t c = 0; c < NC; ++c) {
+            int X[3] = {0, 0, 0};
+            int64_t t = c;
+            for (int m = 0; m < d; ++m) { X[m] = (int)(t % nc); t /= nc; }
+            double sum = 0.0;
+            for (int B = 0; B < nl; ++B) {
+                int64_t fi = 0, st = 1;
+                for (int m = 0; m < d; ++m) {
+                    fi += (int64_t)(2 * X[m] + ((B >> m) & 1)) * st;
+                    st *= nf;
+                }
+                sum += ef[fi];
+            }
+            ec[c] = sum / nl;
+            for (int i = 0; i < nl * nl; ++i) K[c * nl * nl + i] = ec[c] * G[i];
+        }
+        orc_stencils(d, nc, K, g->S[l]);
+        free(K);
+        free(ef);
+        ef = ec;
+    }
+    free(ef);
+    int lc = g->nlev - 1, n = g->n[lc];
+    free(g->L);
+    g->m = orc_dense_matrix(d, n, g->S[lc], NULL);
+    g->L = malloc(sizeof(double) * (g->m > 0 ? g->m * g->m : 1));
+    orc_dense_matrix(d, n, g->S[lc], g->L);
+    orc_cholesky(g->m, g->L);
+}
+
 int orc_mg_levels(const orc_mg *g) { return g->nlev; }
 int orc_mg_level_n(const orc_mg *g, int l) { return g->n[l]; }
 const double *orc_mg_level_stencils(const orc_mg *g, int l) { return g->S[l]; }
@@ -959,7 +1010,8 @@ enum { ORC_OK = 0, ORC_ENOCONV = -4, ORC_EDIVERGED = -5 };
  * the end before the first cycle (eq. level-operator-sequence-explicit-
  * assembly, all markers final).  Lazy (deterministic schedule): cycle 0 runs
  * on the centre-sample operator and rung k (s = 2^k) of every unfinished
- * cell is integrated and published before cycle k (Sec. 5.1-5.3).  The
+ * cell is integrated and published before cycle k (Sec. 5.1-5.3); cycles
+ * on the centre-sample operator use a geometric hierarchy (Sec. 1).  The
  * residual is measured at the start of each cycle with the operator current
  * then, normalised by the first one (Sec. 6); after an operator change the
  * iteration continues from the carried iterate or from the zero start,
@@ -1000,6 +1052,20 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
     }
     orc_stencils(d, N, K, S);
     orc_mg *g = orc_mg_create(d, N, op->coarsest, op->transfer, S);
+    if (ladder && op->lazy) {
+        /* the provisional (centre-sample) operator starts on a geometric
+         * hierarchy; every publish rebuilds the hierarchy of op->transfer */
+        double *ec = malloc(sizeof(double) * nc);
+        for (int64_t c = 0; c < nc; ++c) {
+            int ci[3];
+            double x[3] = {0.0, 0.0, 0.0};
+            cell_coords(d, N, c, ci);
+            for (int m = 0; m < d; ++m) x[m] = (ci[m] + 0.5) / N;
+            ec[c] = orc_eps(fld, x);
+        }
+        orc_mg_set_geometric(g, S, ec);
+        free(ec);
+    }
     rep->nlev = g->nlev;
     int status = ORC_ENOCONV, k, rung = 1;
     double r0 = 0.0, rk = 0.0;

@@ -246,6 +246,10 @@ void opset_free(OpSet &o);
 int compress_into(mgd_hier *h, OpSet &o, const float *S32, const float *eps_c,
                   const mgd_tier_policy *pol, hipStream_t st);
 int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st);
+// geometric hierarchy of a provisional operator: coarse levels rediscretised
+// from child-averaged cell values (finest: eps_c0), d-linear weights;
+// scratch: (n/2)^d + (n/4)^d floats
+int coarsen_geometric(mgd_hier *h, OpSet &o, const float *eps_c0, float *scratch, hipStream_t st);
 int decode_level_f64(mgd_hier *h, const OpSet &o, int level, double *out, hipStream_t st);
 int weights_f64(mgd_hier *h, const OpSet &o, int level, double *out, hipStream_t st);
 int cycle_smooth(mgd_hier *h, const OpSet &o, int level, void *u, const void *f, void *tmp,

@@ -374,6 +374,97 @@ template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *cons
     return MGD_OK;
 }
 
+// ---- geometric hierarchy of a provisional operator (Sec. 1: multigrid
+// starts from crude fine grid stencils with geometric coarse grid and
+// inter-grid transfer operators, cheap to set up): every coarser level is
+// the Q1 rediscretisation with cell values that average the 2^d child
+// cells' (the finest level's: the centre samples), transfer weights are
+// d-linear, and the coarsest matrix is factored as usual.
+
+// coarse cell values: the mean of the 2^d children on the nf-grid (FP64 sum)
+template <int D> __global__ void k_avg_children(const float *ef, int nf, float *ec)
+{
+    const int nc = nf / 2;
+    int64_t NC = 1;
+    for (int m = 0; m < D; ++m) NC *= nc;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= NC) return;
+    int X[3] = {0, 0, 0};
+    int64_t t = c;
+    for (int m = 0; m < D; ++m) { X[m] = (int)(t % nc); t /= nc; }
+    double sum = 0.0;
+    for (int B = 0; B < (1 << D); ++B) {
+        int64_t f = 0, st = 1;
+        for (int m = 0; m < D; ++m) {
+            f += (int64_t)(2 * X[m] + ((B >> m) & 1)) * st;
+            st *= nf;
+        }
+        sum += (double)ef[f];
+    }
+    ec[c] = (float)(sum / (double)(1 << D));
+}
+
+// half stencils of the cell-value rediscretisation on the n-grid (the
+// store's base couplings), computed in FP64 and stored as T
+template <int D, typename T> __global__ void k_base_stencils(const float *ec, int n, T *S)
+{
+    Grid<D> g(n);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3] = {0, 0, 0};
+    g.coords(v, x);
+    for (int j = 0; j < n_half(D); ++j) S[(int64_t)j * g.NV + v] = (T)base_coupling64<D>(ec, n, x, j, nullptr);
+}
+
+template <int D, typename T> __global__ void k_geo_weights_t(int n, T *W)
+{
+    Grid<D> g(n);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3] = {0, 0, 0};
+    g.coords(v, x);
+    double w[1 << D];
+    geo_weights<D, double>(x, w);
+    for (int B = 0; B < (1 << D); ++B) W[(int64_t)B * g.NV + v] = (T)w[B];
+}
+
+template <int D, typename T>
+static int coarsen_geometric_t(mgd_hier *h, OpSet &o, T *const *S, const float *eps_c0, float *scratch, hipStream_t st)
+{
+    // cell values of level l in scratch, alternating between two halves
+    int64_t nc1 = 1;
+    for (int m = 0; m < D; ++m) nc1 *= h->nl[0] / 2;
+    const float *ef = eps_c0;
+    for (int l = 1; l < h->nlev; ++l) {
+        int64_t ncl = 1;
+        for (int m = 0; m < D; ++m) ncl *= h->nl[l];
+        float *ec = scratch + ((l & 1) ? 0 : nc1);
+        hipLaunchKernelGGL(k_avg_children<D>, dim3(grid_for(ncl, 256)), dim3(256), 0, st, ef, h->nl[l - 1], ec);
+        hipLaunchKernelGGL((k_base_stencils<D, T>), dim3(grid_for(h->NV[l], 256)), dim3(256), 0, st,
+                           (const float *)ec, h->nl[l], S[l]);
+        if (h->transfer == MGD_BOXMG)
+            hipLaunchKernelGGL((k_geo_weights_t<D, T>), dim3(grid_for(h->NV[l - 1], 256)), dim3(256), 0, st,
+                               h->nl[l - 1], (T *)o.W[l - 1]);
+        ef = ec;
+    }
+    int lc = h->nlev - 1;
+    HalfRow<D, T> Ac{S[lc], h->NV[lc], (int64_t)h->nl[lc] + 1};
+    hipLaunchKernelGGL((k_dense_assemble<D, T>), dim3(1), dim3(256), 0, st, Ac, h->nl[lc], h->m_coarse, o.chol);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, st, o.chol, h->m_coarse);
+    if (o.cinv) hipLaunchKernelGGL(k_chol_inverse, dim3(1), dim3((unsigned)kCinvMax), 0, st, o.chol, h->m_coarse, o.cinv);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+int coarsen_geometric(mgd_hier *h, OpSet &o, const float *eps_c0, float *scratch, hipStream_t st)
+{
+    if (h->precision == MGD_FP64)
+        return h->dim == 2 ? coarsen_geometric_t<2, double>(h, o, o.S64, eps_c0, scratch, st)
+                           : coarsen_geometric_t<3, double>(h, o, o.S64, eps_c0, scratch, st);
+    return h->dim == 2 ? coarsen_geometric_t<2, float>(h, o, o.S32, eps_c0, scratch, st)
+                       : coarsen_geometric_t<3, float>(h, o, o.S32, eps_c0, scratch, st);
+}
+
 int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st)
 {
     if (h->precision == MGD_FP64)

@@ -67,8 +67,9 @@ static int rung0(Ladder &L, hipStream_t st)
     for (int r = 0; r < 8; ++r) L.cnt_host[r] = 0;
     L.cnt_host[0] = L.ncell;
     L.cnt_host[1] = L.R >= 1 ? L.ncell : 0;
-    if (L.h->precision == MGD_MIXED) return launch_centre_eps(ctx, L.h->dim, L.h->n, &L.eps, L.eps_c, st);
-    return MGD_OK;
+    // centre samples: the mixed store's base, and the cell values of a lazy
+    // solve's provisional geometric hierarchy
+    return launch_centre_eps(ctx, L.h->dim, L.h->n, &L.eps, L.eps_c, st);
 }
 
 // rung r >= 1: integrate the open cells at s = 2^r in place, criterion
@@ -91,14 +92,12 @@ static int rung(Ladder &L, int r, hipStream_t st)
 }
 
 // operator set from the current element matrices
-static int build(Ladder &L, OpSet &o, bool base_only, hipStream_t st)
+static int build(Ladder &L, OpSet &o, hipStream_t st)
 {
     mgd_hier *h = L.h;
     int rc;
     if (h->precision == MGD_FP64) {
         if ((rc = launch_gather(h->ctx, h->dim, h->n, L.K, MGD_FP64, o.S64[0], MGD_FP64, st))) return rc;
-    } else if (base_only) {
-        if ((rc = store_set_base(h, o, L.eps_c, st))) return rc;
     } else {
         if ((rc = launch_gather(h->ctx, h->dim, h->n, L.K, MGD_MIXED, L.Sg, MGD_MIXED, st))) return rc;
         if ((rc = compress_into(h, o, L.Sg, L.eps_c, &L.tiers, st))) return rc;
@@ -318,7 +317,7 @@ static int chain_next(SolveState *S)
     }
     int rc;
     HIPCHK(S->ctx, hipStreamWaitEvent(S->s_asm, S->ev_free, 0));
-    if ((rc = build(L, *S->sets[1 - S->cur], false, S->s_asm))) return rc;
+    if ((rc = build(L, *S->sets[1 - S->cur], S->s_asm))) return rc;
     HIPCHK(S->ctx, hipEventRecord(S->ev_ready[r + 1], S->s_asm));
     S->built = r + 1;
     if (r + 2 <= L.R && (rc = rung(L, r + 2, S->s_asm))) return rc;
@@ -438,23 +437,35 @@ int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, c
     if (!S->lazy) {
         for (int rr = 1; rr <= L.R; ++rr)
             if ((rc = rung(L, rr, stream))) return rc;
-        if ((rc = build(L, S->H.ops, false, stream))) return rc;
+        if ((rc = build(L, S->H.ops, stream))) return rc;
         S->published = S->built = L.R;
         S->ladder_done = true;
     } else {
-        if ((rc = build(L, S->H.ops, true, stream))) return rc;
+        // the provisional operator: the ladder rewrites the element matrices
+        // in place, so it starts once the provisional stencils have read them
+        // (FP64: the gather; mixed: the centre-sample base needs none) and
+        // runs beside the provisional coarsening
+        mgd_hier *h = L.h;
+        if (h->precision == MGD_FP64)
+            rc = launch_gather(ctx, h->dim, h->n, L.K, MGD_FP64, S->H.ops.S64[0], MGD_FP64, stream);
+        else
+            rc = store_set_base(h, S->H.ops, L.eps_c, stream);
+        if (rc) return rc;
         HIPCHK(ctx, hipEventRecord(S->ev_start, stream));
         HIPCHK(ctx, hipStreamWaitEvent(S->s_asm, S->ev_start, 0));
+        // geometric coarse levels and transfers for the provisional operator
+        // (the cycle vector t[0] is free scratch before the first cycle)
+        if ((rc = coarsen_geometric(h, S->H.ops, L.eps_c, (float *)S->H.t[0], stream))) return rc;
         if (S->publish_mode == MGD_PUBLISH_ASYNC) {
             // the whole ladder back to back, then one build of the final operator
             for (int rr = 1; rr <= L.R; ++rr)
                 if ((rc = rung(L, rr, S->s_asm))) return rc;
-            if ((rc = build(L, S->O1, false, S->s_asm))) return rc;
+            if ((rc = build(L, S->O1, S->s_asm))) return rc;
             HIPCHK(ctx, hipEventRecord(S->ev_final, S->s_asm));
             S->built = L.R;
         } else {
             if ((rc = rung(L, 1, S->s_asm))) return rc;
-            if ((rc = build(L, S->O1, false, S->s_asm))) return rc;
+            if ((rc = build(L, S->O1, S->s_asm))) return rc;
             HIPCHK(ctx, hipEventRecord(S->ev_ready[1], S->s_asm));
             S->built = 1;
             if (L.R >= 2 && (rc = rung(L, 2, S->s_asm))) return rc;

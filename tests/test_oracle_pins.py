@@ -544,6 +544,42 @@ def test_lazy_restart_takes_the_better_start():
     assert np.array_equal(ub[~inner], u0[~inner])
 
 
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+def test_geometric_provisional_hierarchy(d, n):
+    """The provisional operator's geometric hierarchy (coarse levels
+    rediscretised from child-averaged cell values, d-linear transfers):
+    for constant eps it equals the Galerkin hierarchy with d-linear
+    transfers (which reproduces the Q1 operator at 2h); for a varying eps
+    every level keeps symmetric stencils with zero interior row sums, and a
+    coarse cell's value is the mean of its children (checked on a field that
+    is constant on each coarse cell's children)."""
+    fld = W.const_field(d, 2.5)
+    S0 = O.stencils(d, n, O.assemble(fld, d, n, 1))
+    Hg = O.Hierarchy(d, n, S0)
+    Hg.set_geometric(S0, np.full(n ** d, 2.5))
+    Hr = O.Hierarchy(d, n, S0, transfer=O.GEOMETRIC)
+    for l in range(1, Hg.nlev):
+        np.testing.assert_allclose(Hg.level_stencils(l), Hr.level_stencils(l), rtol=1e-13, atol=1e-13)
+        np.testing.assert_array_equal(Hg.level_weights(l - 1), Hr.level_weights(l - 1))
+    # values constant on the children of each level-1 cell: level 1 is the
+    # fine-grid assembly of those values at 2h
+    rng = np.random.default_rng(3)
+    nc = n // 2
+    vals = 10.0 ** rng.uniform(-1, 1, size=(nc,) * d)
+    idx = np.indices((n,) * d)
+    ec = vals[tuple(idx[m] // 2 for m in range(d))].transpose(*reversed(range(d))).ravel()
+    Hg.set_geometric(S0, ec)
+    Kc = np.array([v * O.subcell_matrix(d, 1, np.zeros(d, np.int32), 1.0 / nc)
+                   for v in vals.transpose(*reversed(range(d))).ravel()])
+    np.testing.assert_allclose(Hg.level_stencils(1), O.stencils(d, nc, Kc), rtol=1e-13, atol=1e-15)
+    for l in range(1, Hg.nlev):
+        Sl = Hg.level_stencils(l)
+        A = O.dense_matrix(d, Hg.level_n(l), Sl)
+        np.testing.assert_allclose(A, A.T, atol=1e-13 * np.abs(A).max())
+        inner = _interior(d, Hg.level_n(l))
+        np.testing.assert_allclose(Sl[inner].sum(axis=1), 0.0, atol=1e-12 * np.abs(Sl).max())
+
+
 def test_boxmg_weights_reduce_to_dlinear_for_constant_eps():
     for d, n in [(2, 8), (3, 4)]:
         S = O.stencils(d, n, O.assemble(W.const_field(d, 3.0), d, n, 1))
