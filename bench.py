@@ -7,11 +7,13 @@ V-cycles start on the centre-sample operator while the ladder s = 2, 4, 8,
 16 runs on a second stream.  One step = one complete solve to a 1e-8
 relative residual of the mixed form (bf16 hi+lo MFMA integration, FP16
 surplus store, FP32 BoxMG V(2,2), FP64 outer conjugate gradients) with lazy
-assembly; the plain FP64 form with up-front assembly is timed beside it.
-Inputs (load vector, material data) are resident in HBM before timing.  The
-same comparison is repeated at 4096^2 cells, where the operators no longer
-fit in the 256 MB Infinity Cache, and on the 3D Gaussian-field workload at
-256^3 cells (27-point stencils, ladder to s = 8).
+assembly; the same lazy assembly without cycles on provisional operators,
+the mixed form with up-front assembly and the plain FP64 form with up-front
+assembly are timed beside it.  Inputs (load vector, material data) are
+resident in HBM before timing.  The same comparison is repeated at 4096^2
+cells, where the operators no longer fit in the 256 MB Infinity Cache, on
+the 3D Gaussian-field workload at 256^3 cells (27-point stencils, ladder to
+s = 8), and as a mean over seeded instances of the 1024^2 balls material.
 
 Prints one JSON line.  `value` is the mixed-lazy form's fine-grid V-cycle
 throughput over the whole solve: (n-1)^2 DoF x V-cycles / time-to-solution.
@@ -47,6 +49,8 @@ def parse():
                     help="also time the sweep at this size, beyond the Infinity Cache (0 skips)")
     ap.add_argument("--n3d", type=int, default=256,
                     help="also time both forms on the 3D Gaussian-field workload at this size (0 skips)")
+    ap.add_argument("--seeds", type=int, default=8,
+                    help="seeded instances of the 1024^2 balls material for the mean times (0: none)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline sweep and a calibration copy (for counter runs)")
     return ap.parse_args()
@@ -83,7 +87,7 @@ PASSES_PER_LAUNCH = 3  # stencil passes one launch performs: two Jacobi sweeps a
 # Memory traffic per launch of the timed kernel at n (bytes), from FETCH_SIZE
 # and WRITE_SIZE counter runs of `bench.py --kernels-only` scaled by a 256 MiB
 # copy; valid only for the kernel version they were taken on.
-SWEEP_TRAFFIC = {}
+SWEEP_TRAFFIC = {1024: 30443057, 4096: 298793616}
 
 
 def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
@@ -142,47 +146,85 @@ def sweep_roofline(ctx, P, d, n, eps, tiers, sweeps):
             "avg_launch_us": round(avg_ms * 1e3, 3), "store_tiers": tier_tiles}
 
 
+FORMS = ("mixed_lazy", "mixed_lazy_parked", "mixed_upfront", "fp64_upfront")
+
+
 def solve_forms(P, W, n, steps, warmup, tiers, d=2, fld=None, s_max=16):
-    """Time-to-1e-8 of the mixed-lazy and the FP64-up-front forms at n^d
-    cells (default: the 2D balls workload); each form keeps its
-    device-resident solve state in its own context, so neither timed loop
-    re-creates the other's workspace."""
+    """Time-to-1e-8 at n^d cells (default: the 2D balls workload) of
+    - mixed_lazy: the paper's schedule, cycling on the provisional operator
+      while the ladder runs on the assembly stream;
+    - mixed_lazy_parked: the same lazy assembly with the provisional target
+      1 (no cycles on a provisional operator: the assembly has the GPU);
+    - mixed_upfront and fp64_upfront: every cell's ladder first.
+    Each form keeps its device-resident solve state in its own context, so
+    no timed loop re-creates another's workspace."""
     import torch
     eps = P.Eps(fld if fld is not None else W.config_field(1))
     f_host = W.load_sine(d, n)
     f = torch.from_numpy(f_host).cuda()
-    mixed = dict(precision=P.MIXED, schedule=P.LAZY, transfer=P.BOXMG, outer=P.PCG, s_max=s_max,
-                 tol=1e-8, max_cycles=600, **tiers)
-    fp64 = dict(precision=P.FP64, schedule=P.UPFRONT, transfer=P.BOXMG, outer=P.PCG, s_max=s_max,
-                tol=1e-8, max_cycles=600)
-    ctx_m, ctx_f = P.Context(0), P.Context(0)
+    base = dict(transfer=P.BOXMG, outer=P.PCG, s_max=s_max, tol=1e-8, max_cycles=600)
+    kws = {"mixed_lazy": dict(base, precision=P.MIXED, schedule=P.LAZY, **tiers),
+           "mixed_lazy_parked": dict(base, precision=P.MIXED, schedule=P.LAZY, prov_tol=1.0, **tiers),
+           "mixed_upfront": dict(base, precision=P.MIXED, schedule=P.UPFRONT, **tiers),
+           "fp64_upfront": dict(base, precision=P.FP64, schedule=P.UPFRONT)}
+    ctxs = {k: P.Context(0) for k in FORMS}
+    out = {"eps": eps, "f_host": f_host, "ms": {}, "rep": {}}
+    sol = {}
+    for k in FORMS:
+        for _ in range(warmup):
+            P.solve(ctxs[k], d, n, eps, f, torch.zeros_like(f), **kws[k])
+        torch.cuda.synchronize()
+        reps = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            u, r = P.solve(ctxs[k], d, n, eps, f, torch.zeros_like(f), **kws[k])
+            reps.append(r)
+        torch.cuda.synchronize()
+        out["ms"][k] = (time.perf_counter() - t0) / steps * 1e3
+        assert all(r["status"] == 0 for r in reps), (k, [r["status"] for r in reps])
+        out["rep"][k] = reps[-1]
+        sol[k] = u
+    uf = sol["fp64_upfront"]
+    out["err"] = float(torch.linalg.norm(sol["mixed_lazy"] - uf) / torch.linalg.norm(uf))
+    for c in ctxs.values():
+        c.close()
+    return out
 
-    def run(kw):
-        u = torch.zeros_like(f)
-        return P.solve(ctx_m if kw is mixed else ctx_f, d, n, eps, f, u, **kw)
 
-    for _ in range(warmup):
-        run(mixed)
-        run(fp64)
-    torch.cuda.synchronize()
-    reps_m, reps_f = [], []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        um, rm = run(mixed)
-        reps_m.append(rm)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(steps):
-        uf, rf = run(fp64)
-        reps_f.append(rf)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    assert all(r["status"] == 0 for r in reps_m + reps_f), [r["status"] for r in reps_m + reps_f]
-    err = float(torch.linalg.norm(um - uf) / torch.linalg.norm(uf))
-    ctx_m.close()
-    ctx_f.close()
-    return dict(ms_mixed=(t1 - t0) / steps * 1e3, ms_fp64=(t2 - t1) / steps * 1e3, rep_m=reps_m[-1],
-                rep_f=reps_f[-1], err=err, eps=eps, f_host=f_host)
+def forms_summary(b):
+    """Times, cycles and speedups over FP64 up front of every form."""
+    ms, rep = b["ms"], b["rep"]
+    o = {}
+    for k in FORMS:
+        o[f"time_to_1e8_{k}_ms"] = round(ms[k], 3)
+        o[f"cycles_{k}"] = rep[k]["cycles"]
+    for k in FORMS[:-1]:
+        o[f"speedup_{k}_vs_fp64_upfront"] = round(ms["fp64_upfront"] / ms[k], 3)
+    for k in ("mixed_lazy", "mixed_upfront", "fp64_upfront"):
+        o[f"t_first_cycle_ms_{k}"] = round(rep[k]["t_first_cycle_ms"], 3)
+    o["mixed_vs_fp64_solution_rel_err"] = b["err"]
+    return o
+
+
+def seed_instances(P, W, n, tiers, seeds):
+    """Mean time-to-1e-8 of each form over seeded instances of the balls
+    material (200 balls, radii 0.005-0.05, eps 1e3): the cycle count near
+    the 1e-8 target varies by a few cycles from instance to instance."""
+    import numpy as np
+    acc = {k: [] for k in FORMS}
+    cyc = {k: [] for k in FORMS}
+    for sd in range(seeds):
+        b = solve_forms(P, W, n, 1, 1, tiers, fld=W.balls_field(2, 200, 20260 + sd))
+        for k in FORMS:
+            acc[k].append(b["ms"][k])
+            cyc[k].append(b["rep"][k]["cycles"])
+    o = {"instances": seeds, "material": "200 balls (r 0.005-0.05, eps 1e3), seeds 20260.."}
+    for k in FORMS:
+        o[f"mean_time_{k}_ms"] = round(float(np.mean(acc[k])), 3)
+        o[f"mean_cycles_{k}"] = round(float(np.mean(cyc[k])), 2)
+    for k in FORMS[:-1]:
+        o[f"mean_speedup_{k}_vs_fp64_upfront"] = round(float(np.mean(acc["fp64_upfront"]) / np.mean(acc[k])), 3)
+    return o
 
 
 def kernels_only(args):
@@ -273,8 +315,8 @@ def main():
     tiers = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
     fld = W.config_field(1)
     main_run = solve_forms(P, W, n, args.steps, args.warmup, tiers)
-    ms_mixed, ms_fp64 = main_run["ms_mixed"], main_run["ms_fp64"]
-    rep_m, rep_f = main_run["rep_m"], main_run["rep_f"]
+    ms_mixed, ms_fp64 = main_run["ms"]["mixed_lazy"], main_run["ms"]["fp64_upfront"]
+    rep_m, rep_f = main_run["rep"]["mixed_lazy"], main_run["rep"]["fp64_upfront"]
     eps, f_host, err = main_run["eps"], main_run["f_host"], main_run["err"]
     dof = (n - 1) ** d
     cyc_m = rep_m["cycles"]
@@ -299,16 +341,12 @@ def main():
     if args.big_n > 0:
         big_eps = P.Eps(W.config_field(1))
         big = sweep_roofline(ctx, P, d, args.big_n, big_eps, tiers, args.sweeps)
-        big = {k: big[k] for k in ("achieved", "frac", "single_pass_frac", "bytes_per_launch", "avg_launch_us",
-                                   "store_tiers")}
+        big = {k: big[k] for k in ("achieved", "frac", "single_pass_frac", "bytes_per_launch", "single_pass_bytes",
+                                   "traffic", "avg_launch_us", "kernel", "operator", "store_tiers")}
         big["workload"] = f"same material, {args.big_n}^2 cells (store and vectors beyond the 256 MB Infinity Cache)"
         b = solve_forms(P, W, args.big_n, 2, 1, tiers)
         big_tts = {"workload": f"same material and load at {args.big_n}^2 cells (beyond the Infinity Cache)",
-                   "time_to_1e8_mixed_lazy_ms": round(b["ms_mixed"], 3),
-                   "time_to_1e8_fp64_upfront_ms": round(b["ms_fp64"], 3),
-                   "speedup_mixed_lazy_vs_fp64_upfront": round(b["ms_fp64"] / b["ms_mixed"], 3),
-                   "cycles_mixed_lazy": b["rep_m"]["cycles"], "cycles_fp64_upfront": b["rep_f"]["cycles"],
-                   "mixed_vs_fp64_solution_rel_err": b["err"]}
+                   **forms_summary(b)}
     NV = (n + 1) ** d
 
     out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
@@ -317,10 +355,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": WORKLOAD, "cells": n ** d, "dof": dof, "levels": rep_m["nlev"]},
            "components": {
-               "time_to_1e8_mixed_lazy_ms": round(ms_mixed, 3),
-               "time_to_1e8_fp64_upfront_ms": round(ms_fp64, 3),
-               "speedup_mixed_lazy_vs_fp64_upfront": round(ms_fp64 / ms_mixed, 3),
-               "cycles_mixed_lazy": cyc_m, "cycles_fp64_upfront": rep_f["cycles"],
+               **forms_summary(main_run),
                "publishes_mixed_lazy": rep_m["publishes"],
                "vcycle_dof_per_s_fp64_upfront": dof * rep_f["cycles"] / (ms_fp64 / 1e3),
                "cell_integrations_per_s_s16": {k: round(v, 1) for k, v in integ.items()},
@@ -328,9 +363,6 @@ def main():
                "cells_at_s_1_2_4_8_16": rep_m["cells_at_s"],
                "store_bytes_per_stencil_mixed": rep_m["store_bytes"] / NV,
                "store_bytes_per_stencil_fp64": rep_f["store_bytes"] / NV,
-               "mixed_vs_fp64_solution_rel_err": err,
-               "t_first_cycle_ms_mixed_lazy": round(rep_m["t_first_cycle_ms"], 3),
-               "t_first_cycle_ms_fp64_upfront": round(rep_f["t_first_cycle_ms"], 3),
            },
            "roofline": roofline}
     if big is not None:
@@ -342,17 +374,13 @@ def main():
         out["components"]["time_to_solution_3d"] = {
             "workload": (f"3D {m}^3 Q1 cells (27-point stencils), eps = exp(g), g a seeded Gaussian field "
                          "(correlation length 1/32, sigma 1), ladder s = 2..8, manufactured sine load"),
-            "time_to_1e8_mixed_lazy_ms": round(b["ms_mixed"], 3),
-            "time_to_1e8_fp64_upfront_ms": round(b["ms_fp64"], 3),
-            "speedup_mixed_lazy_vs_fp64_upfront": round(b["ms_fp64"] / b["ms_mixed"], 3),
-            "cycles_mixed_lazy": b["rep_m"]["cycles"], "cycles_fp64_upfront": b["rep_f"]["cycles"],
-            "t_first_cycle_ms_mixed_lazy": round(b["rep_m"]["t_first_cycle_ms"], 3),
-            "t_first_cycle_ms_fp64_upfront": round(b["rep_f"]["t_first_cycle_ms"], 3),
-            "store_bytes_per_stencil_mixed": b["rep_m"]["store_bytes"] / (m + 1) ** 3,
-            "store_bytes_per_stencil_fp64": b["rep_f"]["store_bytes"] / (m + 1) ** 3,
-            "mixed_vs_fp64_solution_rel_err": b["err"]}
+            **forms_summary(b),
+            "store_bytes_per_stencil_mixed": b["rep"]["mixed_lazy"]["store_bytes"] / (m + 1) ** 3,
+            "store_bytes_per_stencil_fp64": b["rep"]["fp64_upfront"]["store_bytes"] / (m + 1) ** 3}
         del b
         torch.cuda.empty_cache()
+    if args.seeds > 0:
+        out["components"]["instances_1024"] = seed_instances(P, W, n, tiers, args.seeds)
     if args.serve_requests > 0:
         out["components"]["serving"] = serving_bench(ctx, P, W, args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
