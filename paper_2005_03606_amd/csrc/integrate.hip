@@ -97,6 +97,60 @@ __device__ inline T eps_eval(const EpsDev &e, const double *x, const double *row
     return (T)NAN;
 }
 
+// Lattice fields: when every sample point of a cell lies in one lattice cell
+// (the lattice resolution divides the grid's), the cell's 2^d corner values
+// are loaded once and each sample only interpolates; the arithmetic is
+// eps_eval's, in the same order, so the values are identical.
+template <int D, typename T> struct EpsCell {
+    bool ok = false;
+    int base[3] = {0, 0, 0};
+    T corner[1 << D];
+};
+
+template <int D, typename T>
+__device__ inline void eps_cell_prepare(const EpsDev &e, int n, bool valid, const int *ci, EpsCell<D, T> &c)
+{
+    c.ok = false;
+    if (e.kind != MGD_EPS_LATTICE || !valid) return;
+    const int64_t L = e.count;
+    bool one = true;
+    for (int m = 0; m < D; ++m) {
+        const int64_t lo = (int64_t)ci[m] * L, hi = (int64_t)(ci[m] + 1) * L;
+        const int64_t b = lo / n, top = (hi + n - 1) / n - 1;  // floor of every interior point
+        one = one && b == top && b <= L - 1;
+        c.base[m] = (int)b;
+    }
+    if (!one) return;
+    c.ok = true;
+    for (int a = 0; a < (1 << D); ++a) {
+        int64_t idx = 0, stride = 1;
+        for (int m = 0; m < D; ++m) {
+            idx += (int64_t)(c.base[m] + ((a >> m) & 1)) * stride;
+            stride *= (L + 1);
+        }
+        c.corner[a] = (T)e.data[idx];
+    }
+}
+
+template <int D, typename T>
+__device__ inline T eps_eval_cell(const EpsDev &e, const EpsCell<D, T> &c, const double *x, const double *rows,
+                                  int count)
+{
+    if (!c.ok) return eps_eval<D, T>(e, x, rows, count);
+    const int L = e.count;
+    T t[3];
+    for (int m = 0; m < D; ++m) t[m] = (T)(x[m] * L - c.base[m]);
+    T g = (T)0;
+#pragma unroll
+    for (int a = 0; a < (1 << D); ++a) {
+        T w = (T)1;
+#pragma unroll
+        for (int m = 0; m < D; ++m) w *= ((a >> m) & 1) ? t[m] : (T)1 - t[m];
+        g += w * c.corner[a];
+    }
+    return exp((T)e.p0 * g);
+}
+
 // ------------------------------------------------------ candidate culling
 // A workgroup evaluates eps only inside the bounding box of its cells; balls
 // and boxes that cannot reach the box are dropped once per workgroup.  The
@@ -289,7 +343,9 @@ template <int D> __device__ inline void cell_coords(int64_t c, int n, int *ci)
 
 __device__ inline double sample_coord(int ci, int q, int s, int n)
 {
-    return ((double)ci + ((double)q + 0.5) / (double)s) / (double)n;
+    // s is a power of two: (q + 1/2) / s is the exact product with 1 / s,
+    // which the compiler hoists out of the sample loops
+    return ((double)ci + ((double)q + 0.5) * (1.0 / (double)s)) / (double)n;
 }
 
 // M_q(a,b) over the q-th of s sub-intervals: index 0 = (0,0), 1 = (0,1), 2 = (1,1)
@@ -372,6 +428,8 @@ template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(2
         const double *rows;
         int nrows;
         build_candidates<D>(a.eps, n, valid, ci, ci, cand, &rows, &nrows);
+        EpsCell<D, double> ecell;
+        eps_cell_prepare<D, double>(a.eps, n, valid, ci, ecell);
         int nlines = (D == 2) ? s : s * s;
         int64_t nq = (int64_t)nlines * s;
         // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
@@ -396,7 +454,7 @@ template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(2
                         e = a.samples[i * nq + q];
                     } else {
                         x[0] = sample_coord(ci[0], qx, s, n);
-                        e = eps_eval<D, double>(a.eps, x, rows, nrows);
+                        e = eps_eval_cell<D, double>(a.eps, ecell, x, rows, nrows);
                     }
                     double Mx[3];
                     moments64(s, qx, Mx);
@@ -526,25 +584,39 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
         int ci[3] = {0, 0, 0};
         cell_coords<D>(cell, n, ci);
         if (WL) build_candidates_wave<D>(a.eps, n, valid, ci, wrows[wave], &rows, &nrows);
+        EpsCell<D, float> ecell;
+        eps_cell_prepare<D, float>(a.eps, n, valid, ci, ecell);
+        // sample q = ch 32 + kg 8 + e has x-index q mod s = (kg 8 + e) mod s
+        // for every chunk (s divides 32): the lane's eight x coordinates are
+        // computed once; y and z only when q / s changes
+        const int ls = 31 - __clz(s);
+        double xq[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xq[e] = sample_coord(ci[0], (kg * 8 + e) & (s - 1), s, n);
+        int qr_last = -1;
+        double xy = 0.0, xz = 0.0;
         floatx4 acc[NT];
         for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         int nch = tile < cnt ? nchunks : 0;  // idle waves still reach the barriers
         for (int ch = 0; ch < nch; ++ch) {
             BF8 ahi, alo;
-            int64_t q0 = (int64_t)ch * 32 + kg * 8;
+            const int q0 = ch * 32 + kg * 8;
+#pragma unroll
             for (int e = 0; e < 8; ++e) {
-                int64_t q = q0 + e;
+                const int q = q0 + e;
                 float ev = 0.0f;
                 if (valid && q < nq) {
                     if (a.eps.kind == MGD_EPS_SAMPLES) {
                         ev = (float)a.samples[i * nq + q];
                     } else {
-                        int qx = (int)(q % s), qr = (int)(q / s);
-                        double x[3];
-                        x[0] = sample_coord(ci[0], qx, s, n);
-                        x[1] = sample_coord(ci[1], qr % s, s, n);
-                        if (D == 3) x[2] = sample_coord(ci[2], qr / s, s, n);
-                        ev = eps_eval<D, float>(a.eps, x, rows, nrows);
+                        const int qr = q >> ls;
+                        if (qr != qr_last) {
+                            xy = sample_coord(ci[1], qr & (s - 1), s, n);
+                            if (D == 3) xz = sample_coord(ci[2], qr >> ls, s, n);
+                            qr_last = qr;
+                        }
+                        const double x[3] = {xq[e], xy, xz};
+                        ev = eps_eval_cell<D, float>(a.eps, ecell, x, rows, nrows);
                     }
                 }
                 uint16_t h = bf16_bits_rne(ev);
