@@ -142,7 +142,12 @@ __global__ void k_prolong(const T *W, int nf, const T *ec, T *u)
     gf.coords(v, x);
     if (!gf.interior(x)) return;
     T s = (T)0;
+    // along an axis where x is even only the corner x / 2 carries weight: the
+    // other corners' weights are structural zeros and are not read
+    int evenmask = 0;
+    for (int m = 0; m < D; ++m) evenmask |= ((x[m] & 1) ^ 1) << m;
     for (int B = 0; B < (1 << D); ++B) {
+        if (B & evenmask) continue;
         int X[3] = {0, 0, 0};
         bool ok = true;
         for (int m = 0; m < D; ++m) {
@@ -168,8 +173,10 @@ template <typename T> __global__ void k_fill(T *a, int64_t n, T val)
 // fixed order (so the result is deterministic and identical in all blocks);
 // the residual norm's partials go straight to pinned host memory and the host
 // adds them.  Reducing kernels therefore run at most kRedBlocks persistent
-// blocks, which keeps the partial lists short.
+// blocks, which keeps the partial lists short; the generic product p -> A p
+// of the outer iteration runs up to kPmvBlocks.
 constexpr int kRedBlocks = 512;
+constexpr int kPmvBlocks = 4096;
 static inline unsigned red_grid(int64_t items) { return (unsigned)std::min<int64_t>(grid_for(items, 256), kRedBlocks); }
 
 __device__ inline double sum_partials(const double *p, int64_t cnt, double *red)
@@ -1332,7 +1339,9 @@ template <int D, typename TZ>
 static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *pold, double *pnew, double *Ap,
                         const CgScalars &c, hipStream_t st)
 {
-    const unsigned grid = red_grid(h->NV[0]);
+    // more blocks than the other reducing kernels: each thread's rows gather
+    // 27 neighbours, and the product needs the occupancy to hide that latency
+    const unsigned grid = (unsigned)std::min<int64_t>({grid_for(h->NV[0], 256), (int64_t)kPmvBlocks, h->partial_cap});
     if (h->precision == MGD_FP64)
         hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
                            OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);

@@ -926,6 +926,92 @@ __global__ void k_gather(const TK *K, int n, TS *S)
     }
 }
 
+// 3D gather staged through LDS.  A block owns the vertices
+// [x0, x0 + 64) x [y0, y0 + TY) and marches over the vertex planes
+// [z0, z0 + kGatherZ).  A coupling of vertex v is a pair (a, b), a < b, of
+// local vertices of a cell with v at corner a; pairs with a on the cell's low
+// z face (pair indices 0..21) come from cell layer z, those with a on its high
+// z face (22..27) from layer z - 1.  Each step loads cell layer z whole, in
+// 16-byte pieces along contiguous cell rows, and keeps its high-face pairs
+// for the next plane, so every element matrix is read once per march.  The
+// sums run over the same cells in the same order as k_gather.
+constexpr int kGatherZ = 16;
+template <typename TK, typename TS, int TY>
+__global__ __launch_bounds__(64 * TY) void k_gather3(const TK *K, int n, TS *S)
+{
+    constexpr int U = 28, LO = 22, HI = U - LO, CX = 65, CY = TY + 1;
+    constexpr int RL = 23, RH = 7;  // odd row strides: conflict-free lanes
+    constexpr int VW = 16 / sizeof(TK), NQ = U / VW, NT = 64 * TY;
+    __shared__ TK lo[CY][CX][RL];
+    __shared__ TK hi[2][CY][CX][RH];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * TY, z0 = blockIdx.z * kGatherZ;
+    const int64_t nv = n + 1, NV = nv * nv * nv;
+    // every thread issues all its loads of a layer before any LDS store
+    constexpr int NI = (CY * CX * NQ + NT - 1) / NT;
+    using V16 = typename std::conditional<VW == 4, float4, double2>::type;
+    auto load_layer = [&](int cz, int hb) {
+        if (cz < 0 || cz >= n) return;
+        V16 w[NI];
+        bool ok[NI];
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const int e = tid + it * NT;
+            const int r = e / (CX * NQ), k = e - r * (CX * NQ), i = k / NQ, q = k - i * NQ;
+            const int cy = y0 - 1 + r, cx = x0 - 1 + i;
+            ok[it] = e < CY * CX * NQ && cy >= 0 && cy < n && cx >= 0 && cx < n;
+            if (ok[it]) w[it] = *reinterpret_cast<const V16 *>(K + (cx + (int64_t)n * (cy + (int64_t)n * cz)) * U + q * VW);
+        }
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            if (!ok[it]) continue;
+            const int e = tid + it * NT;
+            const int r = e / (CX * NQ), k = e - r * (CX * NQ), i = k / NQ, q = k - i * NQ;
+            const TK *wv = reinterpret_cast<const TK *>(&w[it]);
+#pragma unroll
+            for (int t = 0; t < VW; ++t) {
+                const int pi = q * VW + t;
+                if (pi < LO) lo[r][i][pi] = wv[t];
+                else hi[hb][r][i][pi - LO] = wv[t];
+            }
+        }
+    };
+    load_layer(z0 - 1, (z0 - 1) & 1);
+    const int zend = min(z0 + kGatherZ, n + 1);
+    const int x = x0 + tx, y = y0 + ty;
+    for (int z = z0; z < zend; ++z) {
+        __syncthreads();  // the previous plane has read lo and hi[z & 1]
+        load_layer(z, z & 1);
+        __syncthreads();
+        if (x > n || y > n) continue;
+        const int xv[3] = {x, y, z};
+        const int64_t v = x + nv * (y + nv * (int64_t)z);
+#pragma unroll
+        for (int j = 0; j < 13; ++j) {
+            const int o[3] = {half_off(3, j, 0), half_off(3, j, 1), half_off(3, j, 2)};
+            TK acc = 0;
+            bool first = true;
+#pragma unroll
+            for (int B = 7; B >= 0; --B) {
+                bool ok = true;
+                int lw = 0;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const int bm = (B >> m) & 1, cm = xv[m] - bm, wm = bm + o[m];
+                    if (cm < 0 || cm >= n || wm < 0 || wm > 1) ok = false;
+                    lw |= wm << m;
+                }
+                if (!ok) continue;
+                const int pi = pair_index(3, B, lw), r = ty + 1 - ((B >> 1) & 1), i = tx + 1 - (B & 1);
+                const TK k = (B & 4) ? hi[(z - 1) & 1][r][i][pi - LO] : lo[r][i][pi];
+                acc = first ? k : acc + k;
+                first = false;
+            }
+            S[(int64_t)j * NV + v] = (TS)acc;
+        }
+    }
+}
+
 int launch_gather(mgd_ctx *ctx, int dim, int n, const void *K, int k_mode, void *S, int s_mode,
                   hipStream_t st)
 {
@@ -933,14 +1019,22 @@ int launch_gather(mgd_ctx *ctx, int dim, int n, const void *K, int k_mode, void 
     for (int m = 0; m < dim; ++m) NV *= (n + 1);
     dim3 gr(grid_for(NV, 256)), bl(256);
 #define LG(DD, TK, TS) hipLaunchKernelGGL((k_gather<DD, TK, TS>), gr, bl, 0, st, (const TK *)K, n, (TS *)S)
+#define LG3(TK, TS, TY)                                                                                \
+    hipLaunchKernelGGL((k_gather3<TK, TS, TY>), dim3((n + 64) / 64, (n + TY) / TY, (n + kGatherZ) / kGatherZ), \
+                       dim3(64 * TY), 0, st, (const TK *)K, n, (TS *)S)
     if (dim == 2) {
         if (k_mode == MGD_FP64) { if (s_mode == MGD_FP64) LG(2, double, double); else LG(2, double, float); }
         else { if (s_mode == MGD_FP64) LG(2, float, double); else LG(2, float, float); }
-    } else {
+    } else if ((uintptr_t)K % 16 != 0) {
+        // the staged kernel reads 16-byte pieces
         if (k_mode == MGD_FP64) { if (s_mode == MGD_FP64) LG(3, double, double); else LG(3, double, float); }
         else { if (s_mode == MGD_FP64) LG(3, float, double); else LG(3, float, float); }
+    } else {
+        if (k_mode == MGD_FP64) { if (s_mode == MGD_FP64) LG3(double, double, 2); else LG3(double, float, 2); }
+        else { if (s_mode == MGD_FP64) LG3(float, double, 4); else LG3(float, float, 4); }
     }
 #undef LG
+#undef LG3
     HIPCHK(ctx, hipGetLastError());
     return MGD_OK;
 }

@@ -136,7 +136,7 @@ def test_ladder_criterion_matches_oracle(ctx):
 
 
 # ------------------------------------------------------------ stencils
-@pytest.mark.parametrize("d,n", [(2, 9), (3, 4)])
+@pytest.mark.parametrize("d,n", [(2, 9), (3, 4), (3, 70)])
 def test_gather_fp64_bit_exact(ctx, d, n):
     rng = np.random.default_rng(2)
     nl = 1 << d
@@ -154,6 +154,25 @@ def test_gather_fp32_within_rounding(ctx):
     S = P.gather_stencils(ctx, d, n, dev(O.pack_pairs(d, Kf), torch.float32), P.MIXED, P.MIXED)
     ref = O.to_half(d, O.stencils(d, n, Kf))
     assert rel_err(host(S), ref) < 1e-6
+
+
+@pytest.mark.parametrize("n", [37, 66])
+def test_gather3_fp32_tiles_and_alignment(ctx, n):
+    # several 64 x 4 x 16 vertex tiles with ragged edges; FP32 sums of at
+    # most 4 terms; the same element matrices at a 4-byte offset (not 16-byte
+    # aligned) must give the same bits
+    d = 3
+    rng = np.random.default_rng(n)
+    Kfull = rng.standard_normal((n ** d, 8, 8)).astype(np.float32).astype(np.float64)
+    Kfull = Kfull + Kfull.transpose(0, 2, 1)
+    packed = O.pack_pairs(d, Kfull)
+    S = host(P.gather_stencils(ctx, d, n, dev(packed, torch.float32), P.MIXED, P.MIXED))
+    ref = O.to_half(d, O.stencils(d, n, Kfull))
+    assert rel_err(S, ref) < 1e-6
+    buf = torch.zeros(packed.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = dev(packed.reshape(-1), torch.float32)
+    S_off = host(P.gather_stencils(ctx, d, n, buf[1:], P.MIXED, P.MIXED))
+    assert np.array_equal(S.view(np.uint32), S_off.view(np.uint32))
 
 
 # ------------------------------------------------------------ compressed store
