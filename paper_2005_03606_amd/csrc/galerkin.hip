@@ -2,6 +2,8 @@
 // operator-dependent interpolation), R = P^T and the Ritz-Galerkin product
 // A_{l+1} = P^T A_l P, computed stencil-wise for every coarse vertex; plus the
 // dense FP64 Cholesky factor of the coarsest interior matrix.
+#include <type_traits>
+
 #include "common.h"
 
 // ----------------------------------------------------- half-stencil rows
@@ -175,18 +177,50 @@ template <int D> constexpr int gal_threads() { return gal_cpb<D>() * (D == 2 ? 9
 // one group of gal_threads() threads (tg: index in the group, -1 for a
 // thread of the workgroup outside every group) computes the coarse vertices
 // V0 .. V0 + CPB - 1; every thread of the workgroup calls it (one barrier)
-template <int D, typename T>
+// k-th vertex on the boundary of the 3D grid with nc cells per axis: the
+// planes z = 0 and z = nc, then per interior plane the rows y = 0 and y = nc
+// and the two end vertices of every other row
+__device__ inline int64_t bnd_vertex3(int64_t k, int nc)
+{
+    const int64_t nv = nc + 1, face = nv * nv;
+    int x, y, z;
+    if (k < 2 * face) {
+        z = k < face ? 0 : nc;
+        const int64_t r = k < face ? k : k - face;
+        x = (int)(r % nv);
+        y = (int)(r / nv);
+    } else {
+        const int64_t kk = k - 2 * face, per = 4 * (int64_t)nc;
+        z = 1 + (int)(kk / per);
+        const int64_t r = kk % per;
+        if (r < 2 * nv) {
+            y = r < nv ? 0 : nc;
+            x = (int)(r % nv);
+        } else {
+            const int64_t q = r - 2 * nv;
+            y = 1 + (int)(q / 2);
+            x = (q & 1) ? nc : 0;
+        }
+    }
+    return x + nv * (y + nv * (int64_t)z);
+}
+__host__ __device__ inline int64_t bnd_count3(int nc) { return 2 * (int64_t)(nc + 1) * (nc + 1) + (int64_t)(nc - 1) * 4 * nc; }
+
+// BND: the group's vertices are boundary vertices (bnd_vertex3 order)
+template <int D, typename T, bool BND = false>
 __device__ __forceinline__ void galerkin_group(const HalfRow<D, T> &A, const T *W, int nf, T *Sc, int64_t V0, int tg,
                                       double (*part)[gal_cpb<D>()][n_half(D)])
 {
     constexpr int H = n_half(D), ns = D == 2 ? 9 : 27, c = ns / 2, CPB = gal_cpb<D>();
     Grid<D> gf(nf), gc(nf / 2);
     const int cv = tg % CPB, sv = tg / CPB;
-    const int64_t V = V0 + cv;
+    const int64_t cnt = BND ? bnd_count3(gc.n) : gc.NV;
+    auto vert = [&](int64_t k) { if constexpr (BND) return bnd_vertex3(k, gc.n); else return k; };
+    const int64_t V = V0 + cv < cnt ? vert(V0 + cv) : 0;
     double acc[H];
     for (int j = 0; j < H; ++j) acc[j] = 0.0;
     int X[3] = {0, 0, 0};
-    if (tg >= 0 && V < gc.NV) {
+    if (tg >= 0 && V0 + cv < cnt) {
         gc.coords(V, X);
         int dv[3] = {0, 0, 0}, x[3] = {0, 0, 0};
         off_of(D, sv, dv);
@@ -231,8 +265,8 @@ __device__ __forceinline__ void galerkin_group(const HalfRow<D, T> &A, const T *
     __syncthreads();
     for (int t = tg; t >= 0 && t < CPB * H; t += CPB * ns) {
         const int c2 = t / H, j = t % H;
-        const int64_t V2 = V0 + c2;
-        if (V2 >= gc.NV) continue;
+        if (V0 + c2 >= cnt) continue;
+        const int64_t V2 = vert(V0 + c2);
         double sum = 0.0;
         for (int k = 0; k < ns; ++k) sum += part[k][c2][j];
         int X2[3] = {0, 0, 0};
@@ -247,11 +281,114 @@ __device__ __forceinline__ void galerkin_group(const HalfRow<D, T> &A, const T *
     }
 }
 
-template <int D, typename T>
+template <int D, typename T, bool BND = false>
 __global__ __launch_bounds__(gal_threads<D>()) void k_galerkin_p(HalfRow<D, T> A, const T *W, int nf, T *Sc)
 {
     __shared__ double part[D == 2 ? 9 : 27][gal_cpb<D>()][n_half(D)];
-    galerkin_group<D, T>(A, W, nf, Sc, (int64_t)blockIdx.x * gal_cpb<D>(), (int)threadIdx.x, part);
+    galerkin_group<D, T, BND>(A, W, nf, Sc, (int64_t)blockIdx.x * gal_cpb<D>(), (int)threadIdx.x, part);
+}
+
+// 3D interior coarse vertices (1 <= X_m <= nc - 1), one thread each, every
+// fine vertex v = 2X + dv of the support and every neighbour w = v + o
+// unrolled.  With X interior the whole 5^3 fine neighbourhood exists, and
+// whether P[v'][X + O] can be nonzero depends only on v' - 2X and O (P is
+// supported on the box corners of v' and, along an even axis of v', only on
+// the coarse vertex v'_m / 2), so every structurally zero term is dropped at
+// compile time: 1707 FP64 terms, 702 coupling and 185 weight loads per
+// coarse vertex.  The sums run in galerkin_group's order (per fine vertex
+// over its neighbours, then over the fine vertices), so both give the same
+// bits.
+template <int N, class F> __device__ __forceinline__ void unroll(F &&f)
+{
+    if constexpr (N > 0) {
+        unroll<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
+}
+__host__ __device__ constexpr int floor_half(int e) { return (e + 4) / 2 - 2; }
+// corner index (bit m set: corner X_m + 1 of v's box) of X + O for v = 2X + e
+// when P[v][X + O] can be nonzero, else -1
+__host__ __device__ constexpr int p_corner(int e0, int e1, int e2, int O0, int O1, int O2)
+{
+    const int e[3] = {e0, e1, e2}, O[3] = {O0, O1, O2};
+    int B = 0;
+    for (int m = 0; m < 3; ++m) {
+        const int b = O[m] - floor_half(e[m]);
+        if (b < 0 || b > 1 || (e[m] % 2 == 0 && b == 1)) return -1;
+        B |= b << m;
+    }
+    return B;
+}
+__host__ __device__ constexpr int hoff(int j, int m)
+{
+    int i = 14 + j;
+    for (int k = 0; k < m; ++k) i /= 3;
+    return i % 3 - 1;
+}
+
+template <typename T, bool GEO>
+__global__ __launch_bounds__(256) void k_galerkin3_int(HalfRow<3, T> A, const T *W, int nf, T *Sc)
+{
+    const int nc = nf / 2, ni = nc - 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)ni * ni * ni) return;
+    const int X0 = 1 + (int)(idx % ni), X1 = 1 + (int)((idx / ni) % ni), X2 = 1 + (int)(idx / ((int64_t)ni * ni));
+    const int64_t nv = A.nv, nv2 = nv * nv, NVf = A.NV;
+    const int64_t c0 = 2 * (int64_t)X0 + nv * 2 * X1 + nv2 * 2 * X2;  // fine index of 2X
+    auto fidx = [&](int e0, int e1, int e2) { return c0 + e0 + e1 * nv + e2 * nv2; };
+    // P[2X + e][X + O], B its corner index (compile-time)
+    auto pw = [&](int B, int e0, int e1, int e2, int O0, int O1, int O2) -> double {
+        if constexpr (GEO) {
+            double p = 1.0;
+            const int d[3] = {e0 - 2 * O0, e1 - 2 * O1, e2 - 2 * O2};
+            for (int m = 0; m < 3; ++m) p *= d[m] == 0 ? 1.0 : 0.5;
+            return p;
+        } else {
+            return (double)W[(int64_t)B * NVf + fidx(e0, e1, e2)];
+        }
+    };
+    double acc[13];
+#pragma unroll
+    for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+    unroll<27>([&](auto SV) {
+        constexpr int sv = decltype(SV)::value;
+        constexpr int d0 = sv % 3 - 1, d1 = sv / 3 % 3 - 1, d2 = sv / 9 - 1;
+        constexpr int BX = p_corner(d0, d1, d2, 0, 0, 0);
+        const double pV = pw(BX, d0, d1, d2, 0, 0, 0);
+        if (pV == 0.0) return;
+        double pvW[13];
+        unroll<13>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int B = p_corner(d0, d1, d2, hoff(j, 0), hoff(j, 1), hoff(j, 2));
+            if constexpr (B >= 0) pvW[j] = pw(B, d0, d1, d2, hoff(j, 0), hoff(j, 1), hoff(j, 2));
+            else pvW[j] = 0.0;
+        });
+        const int64_t v = fidx(d0, d1, d2);
+        double t[13];
+#pragma unroll
+        for (int j = 0; j < 13; ++j) t[j] = 0.0;
+        unroll<27>([&](auto OI) {
+            constexpr int oi = decltype(OI)::value;
+            if constexpr (oi != 13) {
+                constexpr int o0 = oi % 3 - 1, o1 = oi / 3 % 3 - 1, o2 = oi / 9 - 1;
+                constexpr int e0 = d0 + o0, e1 = d1 + o1, e2 = d2 + o2;
+                const double pa = pV * (double)A.at(v, oi);
+                unroll<13>([&](auto J) {
+                    constexpr int j = decltype(J)::value;
+                    constexpr int O0 = hoff(j, 0), O1 = hoff(j, 1), O2 = hoff(j, 2);
+                    constexpr int Bw = p_corner(e0, e1, e2, O0, O1, O2);
+                    constexpr int Bv = p_corner(d0, d1, d2, O0, O1, O2);
+                    if constexpr (Bw >= 0) t[j] += pa * (pw(Bw, e0, e1, e2, O0, O1, O2) - pvW[j]);
+                    else if constexpr (Bv >= 0) t[j] += pa * (0.0 - pvW[j]);
+                });
+            }
+        });
+#pragma unroll
+        for (int j = 0; j < 13; ++j) acc[j] += t[j];
+    });
+    const int64_t nvc = nc + 1, V = X0 + nvc * (X1 + nvc * (int64_t)X2), NVc = nvc * nvc * nvc;
+#pragma unroll
+    for (int j = 0; j < 13; ++j) Sc[(int64_t)j * NVc + V] = (T)acc[j];
 }
 
 // ------------------------------------------------------------ coarsest solve
@@ -349,6 +486,18 @@ template <int D, typename T>
 static void galerkin_launch(const HalfRow<D, T> &A, const T *W, int nf, int64_t NVc, T *Sc, hipStream_t st)
 {
     constexpr int CPB = gal_cpb<D>(), ns = D == 2 ? 9 : 27;
+    const int nc = nf / 2;
+    if constexpr (D == 3) {
+        if (nc >= 4) {
+            // interior vertices unrolled, the boundary surface by groups
+            const int64_t ni = (int64_t)(nc - 1) * (nc - 1) * (nc - 1);
+            if (W) hipLaunchKernelGGL((k_galerkin3_int<T, false>), dim3(grid_for(ni, 256)), dim3(256), 0, st, A, W, nf, Sc);
+            else hipLaunchKernelGGL((k_galerkin3_int<T, true>), dim3(grid_for(ni, 256)), dim3(256), 0, st, A, W, nf, Sc);
+            hipLaunchKernelGGL((k_galerkin_p<D, T, true>), dim3(grid_for(bnd_count3(nc), CPB)), dim3(CPB * ns), 0, st,
+                               A, W, nf, Sc);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_galerkin_p<D, T>), dim3(grid_for(NVc, CPB)), dim3(CPB * ns), 0, st, A, W, nf, Sc);
 }
 

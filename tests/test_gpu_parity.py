@@ -250,8 +250,29 @@ def _fine_stencils(d, n, s=4, seed=8):
     return O.stencils(d, n, O.assemble(fld, d, n, s))
 
 
+def _full_from_half(d, n, Sh):
+    """Full stencils [NV][3^d] from upper-half couplings [H][NV]: the lower
+    half is the neighbour's upper coupling, the centre minus the row sum."""
+    nv = n + 1
+    NV = nv ** d
+    ns = 3 ** d
+    c = ns // 2
+    S = np.zeros((NV, ns))
+    x = np.stack(np.unravel_index(np.arange(NV), (nv,) * d, order="F"), 1)
+    for j in range(ns // 2):
+        oi = c + 1 + j
+        o = np.array([(oi // 3 ** m) % 3 - 1 for m in range(d)])
+        S[:, oi] = Sh[j]
+        src = x - o
+        ok = ((src >= 0) & (src <= n)).all(1)
+        lin = (src[ok] * nv ** np.arange(d)).sum(1)
+        S[ok, c - 1 - j] = Sh[j][lin]
+    S[:, c] = -S.sum(1)
+    return S
+
+
 @pytest.mark.parametrize("transfer", [0, 1])
-@pytest.mark.parametrize("d,n", [(2, 16), (2, 12), (3, 8)])
+@pytest.mark.parametrize("d,n", [(2, 16), (2, 12), (3, 8), (3, 32)])
 def test_galerkin_and_weights_fp64(ctx, transfer, d, n):
     S = _fine_stencils(d, n)
     h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=transfer)
@@ -259,14 +280,28 @@ def test_galerkin_and_weights_fp64(ctx, transfer, d, n):
     h.coarsen()
     ref = O.Hierarchy(d, n, S, coarsest=2, transfer=transfer)
     assert h.nlev == ref.nlev
+    # one level at a time: weights and Galerkin product of the GPU's own level
+    # l against the oracle's from the same operator, within 1e-12
+    for l in range(h.nlev - 1):
+        nl = h.level_n(l)
+        Sf = _full_from_half(d, nl, host(h.level_stencils(l)))
+        Pw = O.transfer_weights(d, nl, Sf, transfer)
+        np.testing.assert_allclose(host(h.level_weights(l)).T, Pw, rtol=0, atol=1e-13)
+        want = O.to_half(d, O.galerkin(d, nl, Sf, Pw))
+        got = host(h.level_stencils(l + 1))
+        m = half_mask(d, h.level_n(l + 1))
+        assert np.abs(got - want)[m].max() <= 1e-12 * np.abs(want[m]).max()
+    # the whole chain against the oracle's own hierarchy: rounding differences
+    # pass through every level's weights (divisions by collapsed diagonals),
+    # so deep levels of high-contrast operators agree to 1e-11
     for l in range(1, h.nlev):
         nl = h.level_n(l)
         got = host(h.level_stencils(l))
         want = O.to_half(d, ref.level_stencils(l))
         m = half_mask(d, nl)
-        assert np.abs(got - want)[m].max() <= 1e-12 * np.abs(want[m]).max()
+        assert np.abs(got - want)[m].max() <= 1e-11 * np.abs(want[m]).max()
     for l in range(h.nlev - 1):
-        np.testing.assert_allclose(host(h.level_weights(l)).T, ref.level_weights(l), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(host(h.level_weights(l)).T, ref.level_weights(l), rtol=0, atol=1e-12)
 
 
 # ------------------------------------------------------------ cycle pieces
