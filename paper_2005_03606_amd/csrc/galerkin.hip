@@ -469,6 +469,60 @@ __global__ void k_chol_inverse(const double *L, int64_t m, double *Ainv)
     }
 }
 
+// 3D BoxMG weights of the interior fine vertices whose odd axes are the set
+// bits of ODD, one thread each, the 27 offsets unrolled.  The neighbour u of
+// the collapsed row has odd coordinates only where x is odd and the offset
+// is 0, and its weights vanish structurally along its even axes, so the
+// corner of every term is fixed at compile time; the sums run in
+// boxmg_row's order and give the same bits.
+template <typename T, int ODD>
+__global__ __launch_bounds__(256) void k_weights3_class(HalfRow<3, T> A, int nf, T *W)
+{
+    constexpr int p0 = ODD & 1, p1 = (ODD >> 1) & 1, p2 = (ODD >> 2) & 1;
+    const int nc = nf / 2;
+    const int c0 = p0 ? nc : nc - 1, c1 = p1 ? nc : nc - 1, c2 = p2 ? nc : nc - 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)c0 * c1 * c2) return;
+    const int i0 = (int)(idx % c0), i1 = (int)((idx / c0) % c1), i2 = (int)(idx / ((int64_t)c0 * c1));
+    const int x0 = 2 * i0 + (p0 ? 1 : 2), x1 = 2 * i1 + (p1 ? 1 : 2), x2 = 2 * i2 + (p2 ? 1 : 2);
+    const int64_t nv = A.nv, nv2 = nv * nv, NV = A.NV;
+    const int64_t v = x0 + nv * x1 + nv2 * x2;
+    double dsum = 0.0;
+    unroll<27>([&](auto OI) {
+        constexpr int oi = decltype(OI)::value;
+        if constexpr (oi != 13) dsum += (double)A.at(v, oi);
+    });
+    double acc[8], diag = 0.0;
+#pragma unroll
+    for (int B = 0; B < 8; ++B) acc[B] = 0.0;
+    unroll<27>([&](auto OI) {
+        constexpr int oi = decltype(OI)::value;
+        constexpr int o0 = oi % 3 - 1, o1 = oi / 3 % 3 - 1, o2 = oi / 9 - 1;
+        constexpr int m0 = p0 ? o0 : 0, m1 = p1 ? o1 : 0, m2 = p2 ? o2 : 0;  // collapsed offset
+        const double a = oi == 13 ? -dsum : (double)A.at(v, oi);
+        if constexpr (m0 == 0 && m1 == 0 && m2 == 0) {
+            diag += a;
+        } else {
+            // u = x + m: odd exactly where x is odd and m is 0
+            constexpr int q0 = p0 && m0 == 0, q1 = p1 && m1 == 0, q2 = p2 && m2 == 0;
+            const int64_t uv = v + m0 + m1 * nv + m2 * nv2;
+            unroll<8>([&](auto BU) {
+                constexpr int Bu = decltype(BU)::value;
+                constexpr int b0 = Bu & 1, b1 = (Bu >> 1) & 1, b2 = (Bu >> 2) & 1;
+                if constexpr ((!b0 || q0) && (!b1 || q1) && (!b2 || q2)) {
+                    // corner of x's box: floor((p + m) / 2) + b per axis
+                    constexpr int B = ((floor_half(p0 + m0) + b0) << 0) | ((floor_half(p1 + m1) + b1) << 1) |
+                                      ((floor_half(p2 + m2) + b2) << 2);
+                    const double wu = (double)W[(int64_t)Bu * NV + uv];
+                    if (wu != 0.0) acc[B] -= a * wu;
+                }
+            });
+        }
+    });
+#pragma unroll
+    for (int B = 0; B < 8; ++B) W[(int64_t)B * NV + v] = (T)(acc[B] / diag);
+}
+
 template <int D, typename T>
 static void weights_launch(const HalfRow<D, T> &A, int nf, int64_t NV, T *W, hipStream_t st)
 {
@@ -477,8 +531,22 @@ static void weights_launch(const HalfRow<D, T> &A, int nf, int64_t NV, T *W, hip
         hipLaunchKernelGGL((k_weights2<T, 0>), gv, dim3(256), 0, st, A, nf, W);
         hipLaunchKernelGGL((k_weights2<T, 1>), gv, dim3(256), 0, st, A, nf, W);
     } else {
-        for (int pass = 0; pass <= D; ++pass)
-            hipLaunchKernelGGL((k_weights<D, T>), gv, dim3(256), 0, st, A, nf, pass, W);
+        hipLaunchKernelGGL((k_weights<D, T>), gv, dim3(256), 0, st, A, nf, 0, W);
+        const int64_t nc = nf / 2;
+        // pass k: the interior vertices with k odd coordinates, one launch per
+        // odd set (nc odd and nc - 1 even interior coordinates per axis)
+        const int64_t n1 = nc * (nc - 1) * (nc - 1), n2 = nc * nc * (nc - 1), n3 = nc * nc * nc;
+        if (n1 > 0) {
+            hipLaunchKernelGGL((k_weights3_class<T, 1>), dim3(grid_for(n1, 256)), dim3(256), 0, st, A, nf, W);
+            hipLaunchKernelGGL((k_weights3_class<T, 2>), dim3(grid_for(n1, 256)), dim3(256), 0, st, A, nf, W);
+            hipLaunchKernelGGL((k_weights3_class<T, 4>), dim3(grid_for(n1, 256)), dim3(256), 0, st, A, nf, W);
+        }
+        if (n2 > 0) {
+            hipLaunchKernelGGL((k_weights3_class<T, 3>), dim3(grid_for(n2, 256)), dim3(256), 0, st, A, nf, W);
+            hipLaunchKernelGGL((k_weights3_class<T, 5>), dim3(grid_for(n2, 256)), dim3(256), 0, st, A, nf, W);
+            hipLaunchKernelGGL((k_weights3_class<T, 6>), dim3(grid_for(n2, 256)), dim3(256), 0, st, A, nf, W);
+        }
+        if (n3 > 0) hipLaunchKernelGGL((k_weights3_class<T, 7>), dim3(grid_for(n3, 256)), dim3(256), 0, st, A, nf, W);
     }
 }
 
