@@ -30,10 +30,11 @@ struct EpsDev {
 // transcendental laws in T (float for the mixed path).  Balls and boxes are
 // taken from `rows` / `count`: the block's candidate list (same row layout,
 // same order as the descriptor) or the descriptor's own data.
-template <int D, typename T>
-__device__ inline T eps_eval(const EpsDev &e, const double *x, const double *rows, int count)
+template <int D, typename T, int EK>
+__device__ inline T eps_eval_k(const EpsDev &e, const double *x, const double *rows, int count)
 {
-    switch (e.kind) {
+    // EK >= 0: the field kind known at compile time, the other cases dropped
+    switch (EK >= 0 ? EK : e.kind) {
     case MGD_EPS_CONST:
         return (T)e.p0;
     case MGD_EPS_SINE: {
@@ -97,6 +98,12 @@ __device__ inline T eps_eval(const EpsDev &e, const double *x, const double *row
     return (T)NAN;
 }
 
+template <int D, typename T>
+__device__ inline T eps_eval(const EpsDev &e, const double *x, const double *rows, int count)
+{
+    return eps_eval_k<D, T, -1>(e, x, rows, count);
+}
+
 // Lattice fields: when every sample point of a cell lies in one lattice cell
 // (the lattice resolution divides the grid's), the cell's 2^d corner values
 // are loaded once and each sample only interpolates; the arithmetic is
@@ -132,11 +139,11 @@ __device__ inline void eps_cell_prepare(const EpsDev &e, int n, bool valid, cons
     }
 }
 
-template <int D, typename T>
+template <int D, typename T, int EK = -1>
 __device__ inline T eps_eval_cell(const EpsDev &e, const EpsCell<D, T> &c, const double *x, const double *rows,
                                   int count)
 {
-    if (!c.ok) return eps_eval<D, T>(e, x, rows, count);
+    if (!c.ok) return eps_eval_k<D, T, EK>(e, x, rows, count);
     const int L = e.count;
     T t[3];
     for (int m = 0; m < D; ++m) t[m] = (T)(x[m] * L - c.base[m]);
@@ -411,7 +418,7 @@ __device__ inline void store_and_check(const AsmArgs &a, int64_t i, int64_t cell
 // cells, bounded on the host by every cell) a capped grid strides over the
 // tiles up to the count, so the bound costs nothing.  (The tile is written
 // inline: as a called function its accumulators leave the registers.)
-template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
+template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
 {
     __shared__ CandLDS cand;
     const int64_t cnt = asm_count(a);
@@ -449,12 +456,12 @@ template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(2
                 if (D == 3) x[2] = sample_coord(ci[2], qz, s, n);
                 for (int qx = 0; qx < s; ++qx) {
                     double e;
-                    if (a.eps.kind == MGD_EPS_SAMPLES) {
+                    if ((EK >= 0 ? EK : a.eps.kind) == MGD_EPS_SAMPLES) {
                         int64_t q = qx + (int64_t)s * line;
                         e = a.samples[i * nq + q];
                     } else {
                         x[0] = sample_coord(ci[0], qx, s, n);
-                        e = eps_eval_cell<D, double>(a.eps, ecell, x, rows, nrows);
+                        e = eps_eval_cell<D, double, EK>(a.eps, ecell, x, rows, nrows);
                     }
                     double Mx[3];
                     moments64(s, qx, Mx);
@@ -526,11 +533,8 @@ template <int D, int G, bool STRIDE, typename TO> __global__ __launch_bounds__(2
 }
 
 // ------------------------------------------------------------ mixed (MFMA)
-__device__ inline uint16_t bf16_bits_rne(float f)
-{
-    uint32_t b = __float_as_uint(f);
-    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
-}
+// bf16 bits of f, rounded to nearest even by the hardware conversion
+__device__ inline uint16_t bf16_rne_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 union BF8 {
@@ -543,7 +547,7 @@ union BF8 {
 // v_mfma_f32_16x16x32_bf16); the B operand (G terms) is pre-laid out per
 // lane.  The block's 64 TPW consecutive list entries share one candidate
 // list, so small s (one chunk per cell) takes TPW = 4.
-template <int D, int NT, int NTERM, int TPW, bool WL>
+template <int D, int NT, int NTERM, int TPW, bool WL, int EK>
 __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint4 *Gtab, int nchunks, float inv_den,
                                                     int64_t blk, int64_t cnt, float (*sm)[16][NT * 16 + 1],
                                                     CandLDS &cand, double (*wrows)[kWaveCand * 7])
@@ -595,6 +599,18 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
         for (int e = 0; e < 8; ++e) xq[e] = sample_coord(ci[0], (kg * 8 + e) & (s - 1), s, n);
         int qr_last = -1;
         double xy = 0.0, xz = 0.0;
+        // a lattice field on a cell inside one lattice cell: eps = exp(p0 g)
+        // with g trilinear in the corner values, so along the lane's x-line
+        // (y and z fixed) p0 g log2(e) = ga + t_x gb, and a sample costs one
+        // FMA and one exp2; ga and gb change with y and z only
+        const int kind = EK >= 0 ? EK : a.eps.kind;
+        const bool lat = kind == MGD_EPS_LATTICE && ecell.ok;
+        const float kexp = (float)(a.eps.p0 * 1.4426950408889634);
+        float txl[8], ga = 0.0f, gb = 0.0f;
+        if (lat) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) txl[e] = (float)(xq[e] * a.eps.count - ecell.base[0]);
+        }
         floatx4 acc[NT];
         for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         int nch = tile < cnt ? nchunks : 0;  // idle waves still reach the barriers
@@ -606,7 +622,7 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
                 const int q = q0 + e;
                 float ev = 0.0f;
                 if (valid && q < nq) {
-                    if (a.eps.kind == MGD_EPS_SAMPLES) {
+                    if (kind == MGD_EPS_SAMPLES) {
                         ev = (float)a.samples[i * nq + q];
                     } else {
                         const int qr = q >> ls;
@@ -614,14 +630,33 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
                             xy = sample_coord(ci[1], qr & (s - 1), s, n);
                             if (D == 3) xz = sample_coord(ci[2], qr >> ls, s, n);
                             qr_last = qr;
+                            if (lat) {
+                                const float t1 = (float)(xy * a.eps.count - ecell.base[1]);
+                                const float t2 = D == 3 ? (float)(xz * a.eps.count - ecell.base[2]) : 0.0f;
+                                float f0 = 0.0f, f1 = 0.0f;  // faces x = 0 and x = 1
+#pragma unroll
+                                for (int c = 0; c < (1 << (D - 1)); ++c) {
+                                    const float w = ((c & 1) ? t1 : 1.0f - t1) *
+                                                    (D == 3 ? ((c & 2) ? t2 : 1.0f - t2) : 1.0f);
+                                    f0 += w * ecell.corner[2 * c];
+                                    f1 += w * ecell.corner[2 * c + 1];
+                                }
+                                ga = kexp * f0;
+                                gb = kexp * (f1 - f0);
+                            }
                         }
-                        const double x[3] = {xq[e], xy, xz};
-                        ev = eps_eval_cell<D, float>(a.eps, ecell, x, rows, nrows);
+                        if (lat) {
+                            // |p0 g| stays far inside the normal range of exp2
+                            ev = __builtin_amdgcn_exp2f(ga + txl[e] * gb);
+                        } else {
+                            const double x[3] = {xq[e], xy, xz};
+                            ev = eps_eval_cell<D, float, EK>(a.eps, ecell, x, rows, nrows);
+                        }
                     }
                 }
-                uint16_t h = bf16_bits_rne(ev);
+                uint16_t h = bf16_rne_hw(ev);
                 ahi.u[e] = h;
-                alo.u[e] = bf16_bits_rne(ev - bf16_value(h));
+                alo.u[e] = bf16_rne_hw(ev - bf16_value(h));
             }
             for (int t = 0; t < NT; ++t) {
                 const uint4 *gp = Gtab + ((size_t)(ch * NT + t) * NTERM) * 64 + lane;
@@ -652,7 +687,7 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
     }
 }
 
-template <int D, int NT, int NTERM, int TPW, bool STRIDE>
+template <int D, int NT, int NTERM, int TPW, bool STRIDE, int EK>
 __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *Gtab, int nchunks,
                                                         float inv_den)
 {
@@ -662,11 +697,11 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
     const int64_t cnt = asm_count(a);
     if (!STRIDE) {
         if ((int64_t)blockIdx.x * (64 * TPW) < cnt)
-            integrate_mfma_tile<D, NT, NTERM, TPW, false>(a, Gtab, nchunks, inv_den, blockIdx.x, cnt, sm, cand, wrows);
+            integrate_mfma_tile<D, NT, NTERM, TPW, false, EK>(a, Gtab, nchunks, inv_den, blockIdx.x, cnt, sm, cand, wrows);
         return;
     }
     for (int64_t blk = blockIdx.x; blk * (64 * TPW) < cnt; blk += gridDim.x) {
-        integrate_mfma_tile<D, NT, NTERM, TPW, true>(a, Gtab, nchunks, inv_den, blk, cnt, sm, cand, wrows);
+        integrate_mfma_tile<D, NT, NTERM, TPW, true, EK>(a, Gtab, nchunks, inv_den, blk, cnt, sm, cand, wrows);
         __syncthreads();  // the candidate list and the row buffer are reused by the next tile
     }
 }
@@ -816,10 +851,16 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         const bool stride = count_dev != nullptr;
         unsigned grid = grid_for(count * G, 256);
         if (stride) grid = std::min<unsigned>(grid, kAsmMaxBlocks);
-#define L64T(DD, GG, TO)                                                                                       \
+#define L64K(DD, GG, TO, EK)                                                                                   \
     do {                                                                                                       \
-        if (stride) hipLaunchKernelGGL((k_integrate64<DD, GG, true, TO>), dim3(grid), dim3(256), 0, st, a);    \
-        else hipLaunchKernelGGL((k_integrate64<DD, GG, false, TO>), dim3(grid), dim3(256), 0, st, a);          \
+        if (stride) hipLaunchKernelGGL((k_integrate64<DD, GG, true, TO, EK>), dim3(grid), dim3(256), 0, st, a); \
+        else hipLaunchKernelGGL((k_integrate64<DD, GG, false, TO, EK>), dim3(grid), dim3(256), 0, st, a);       \
+    } while (0)
+        // lattice fields in 3D: an instantiation without the other kinds' code
+#define L64T(DD, GG, TO)                                                                  \
+    do {                                                                                  \
+        if (DD == 3 && a.eps.kind == MGD_EPS_LATTICE) L64K(DD, GG, TO, MGD_EPS_LATTICE); \
+        else L64K(DD, GG, TO, -1);                                                        \
     } while (0)
 #define L64(DD, GG)                                  \
     do {                                             \
@@ -830,6 +871,7 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         else { if (G == 16) L64(3, 16); else if (G == 4) L64(3, 4); else L64(3, 1); }
 #undef L64
 #undef L64T
+#undef L64K
     } else {
         GTable *T = nullptr;
         int rc = get_gtable(ctx, dim, s, &T);
@@ -840,14 +882,21 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         const bool stride = count_dev != nullptr;
         unsigned grid = grid_for(count, small ? 256 : 64);
         if (stride) grid = std::min<unsigned>(grid, kAsmMaxBlocks);
-#define LM(DD, NT, NTERM, TPW)                                                                                   \
+#define LMK(DD, NT, NTERM, TPW, EK)                                                                              \
     do {                                                                                                         \
         if (stride)                                                                                              \
-            hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, true>), dim3(grid), dim3(256), 0, st, a,    \
-                               T->dev, T->nchunks, (float)inv_den);                                              \
+            hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, true, EK>), dim3(grid), dim3(256), 0, st,   \
+                               a, T->dev, T->nchunks, (float)inv_den);                                           \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, false>), dim3(grid), dim3(256), 0, st, a,   \
-                               T->dev, T->nchunks, (float)inv_den);                                              \
+            hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, false, EK>), dim3(grid), dim3(256), 0, st,  \
+                               a, T->dev, T->nchunks, (float)inv_den);                                           \
+    } while (0)
+        // lattice fields get an instantiation without the other kinds' code
+        // (the unrolled sample loop then fits the instruction cache)
+#define LM(DD, NT, NTERM, TPW)                                                     \
+    do {                                                                           \
+        if (DD == 3 && a.eps.kind == MGD_EPS_LATTICE) LMK(DD, NT, NTERM, TPW, MGD_EPS_LATTICE); \
+        else LMK(DD, NT, NTERM, TPW, -1);                                          \
     } while (0)
         if (dim == 2) {
             if (T->nterm == 2) { if (small) LM(2, 1, 2, 4); else LM(2, 1, 2, 1); }
@@ -857,6 +906,7 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
             else { if (small) LM(3, 2, 3, 4); else LM(3, 2, 3, 1); }
         }
 #undef LM
+#undef LMK
     }
     HIPCHK(ctx, hipGetLastError());
     return MGD_OK;

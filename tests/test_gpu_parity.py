@@ -767,6 +767,45 @@ def test_full_size_balls_1024_sampled_rows(ctx):
         assert abs(rv) <= 1e-8 * fn + 1e-12 * sum(abs(a * ug[w]) for w, a in row.items())
 
 
+# 3D sweeps, residual and zero-start sweeps on a 144^3 level (ragged against
+# every block shape); centre-sample element matrices keep the oracle's setup short
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep3_large_matches_oracle(ctx, precision):
+    from _gpu_util import half_to_full
+    d, n = 3, 144
+    fld = W.balls_field(d, 6, 8, r_lo=0.05, r_hi=0.3, eps_in=1e3)
+    S = O.stencils(d, n, O.assemble(fld, d, n, 1))
+    rng = np.random.default_rng(21)
+    inner = W.interior_mask(d, n)
+    u = rng.standard_normal(inner.size) * inner
+    f = rng.standard_normal(inner.size) * inner
+    if precision == "fp64":
+        h = P.Hierarchy(ctx, d, n, precision=P.FP64, transfer=P.BOXMG)
+        h.set_fine(dev(O.to_half(d, S)))
+        Sop, dt, tol = S, torch.float64, 1e-12
+    else:
+        h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+        h.compress(dev(O.to_half(d, S), torch.float32), P.centre_samples(ctx, d, n, P.Eps(fld)), 1, 3, 0.0, 1e-6)
+        Sop, dt, tol = None, torch.float32, 2e-5
+    h.coarsen()
+    if Sop is None:
+        Sop = half_to_full(d, n, host(h.level_stencils(0)))
+    ut = dev(u, dt)
+    h.smooth(0, ut, dev(f, dt), sweeps=1, omega=0.6)
+    assert rel_err(host(ut), O.jacobi(d, n, Sop, u, f, 0.6)) < tol
+    r = torch.zeros(inner.size, dtype=dt, device="cuda")
+    h.residual(0, dev(u, dt), dev(f, dt), r)
+    assert rel_err(host(r), O.residual(d, n, Sop, u, f)) < tol
+    # from a zero start: two sweeps, then the residual
+    uo = torch.zeros(inner.size, dtype=dt, device="cuda")
+    ro = torch.zeros_like(uo)
+    h.presmooth(0, None, dev(f, dt), uo, ro, omega=0.6)
+    z1 = O.jacobi(d, n, Sop, np.zeros_like(u), f, 0.6)
+    z2 = O.jacobi(d, n, Sop, z1, f, 0.6)
+    assert rel_err(host(uo), z2) < tol
+    assert rel_err(host(ro), O.residual(d, n, Sop, z2, f)) < tol
+
+
 # ------------------------------------------------------------ mixed operator views
 @pytest.mark.parametrize("d,n", [(2, 24), (2, 70), (3, 8)])
 def test_mixed_outer_residual_is_the_decoded_operator(ctx, d, n):
