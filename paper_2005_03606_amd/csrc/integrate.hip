@@ -856,11 +856,12 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         if (stride) hipLaunchKernelGGL((k_integrate64<DD, GG, true, TO, EK>), dim3(grid), dim3(256), 0, st, a); \
         else hipLaunchKernelGGL((k_integrate64<DD, GG, false, TO, EK>), dim3(grid), dim3(256), 0, st, a);       \
     } while (0)
-        // lattice fields in 3D: an instantiation without the other kinds' code
-#define L64T(DD, GG, TO)                                                                  \
-    do {                                                                                  \
-        if (DD == 3 && a.eps.kind == MGD_EPS_LATTICE) L64K(DD, GG, TO, MGD_EPS_LATTICE); \
-        else L64K(DD, GG, TO, -1);                                                        \
+        // lattice and ball fields: instantiations without the other kinds' code
+#define L64T(DD, GG, TO)                                                                 \
+    do {                                                                                 \
+        if (a.eps.kind == MGD_EPS_LATTICE) L64K(DD, GG, TO, MGD_EPS_LATTICE);           \
+        else if (a.eps.kind == MGD_EPS_BALLS) L64K(DD, GG, TO, MGD_EPS_BALLS);          \
+        else L64K(DD, GG, TO, -1);                                                       \
     } while (0)
 #define L64(DD, GG)                                  \
     do {                                             \
@@ -891,12 +892,13 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
             hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, false, EK>), dim3(grid), dim3(256), 0, st,  \
                                a, T->dev, T->nchunks, (float)inv_den);                                           \
     } while (0)
-        // lattice fields get an instantiation without the other kinds' code
-        // (the unrolled sample loop then fits the instruction cache)
-#define LM(DD, NT, NTERM, TPW)                                                     \
-    do {                                                                           \
-        if (DD == 3 && a.eps.kind == MGD_EPS_LATTICE) LMK(DD, NT, NTERM, TPW, MGD_EPS_LATTICE); \
-        else LMK(DD, NT, NTERM, TPW, -1);                                          \
+        // lattice and ball fields get instantiations without the other kinds'
+        // code (the unrolled sample loop then fits the instruction cache)
+#define LM(DD, NT, NTERM, TPW)                                                                  \
+    do {                                                                                        \
+        if (a.eps.kind == MGD_EPS_LATTICE) LMK(DD, NT, NTERM, TPW, MGD_EPS_LATTICE);           \
+        else if (a.eps.kind == MGD_EPS_BALLS) LMK(DD, NT, NTERM, TPW, MGD_EPS_BALLS);          \
+        else LMK(DD, NT, NTERM, TPW, -1);                                                       \
     } while (0)
         if (dim == 2) {
             if (T->nterm == 2) { if (small) LM(2, 1, 2, 4); else LM(2, 1, 2, 1); }
