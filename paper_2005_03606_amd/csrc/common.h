@@ -149,33 +149,60 @@ __host__ __device__ inline double kref_unit(int D, int nz)
     return nz == 1 ? 0.0 : -1.0 / 12.0;
 }
 
-// centre-sample base coupling of slot j at vertex v (FP64, fixed order:
-// cells holding v and v+o in ascending index, then * k(o), then * h^{d-2}).
+// centre samples of the 2^d cells around vertex x (index B: the cell x - B),
+// loaded once per vertex; coupling(j) is the centre-sample base coupling of
+// slot j (FP64, fixed order: cells holding v and v+o in descending B, i.e.
+// ascending index, then * k(o), then * h^{d-2})
+template <int D> struct BaseCells {
+    double e[1 << D];
+    bool ok[1 << D];
+    int n;
+    __device__ inline void load(const float *eps_c, int n_, const int *x)
+    {
+        n = n_;
+#pragma unroll
+        for (int B = 0; B < (1 << D); ++B) {
+            bool in = true;
+            int64_t c = 0, stride = 1;
+            for (int m = 0; m < D; ++m) {
+                const int cm = x[m] - ((B >> m) & 1);
+                if (cm < 0 || cm >= n) in = false;
+                c += (int64_t)cm * stride;
+                stride *= n;
+            }
+            ok[B] = in;
+            e[B] = in ? (double)eps_c[c] : 0.0;
+        }
+    }
+    __device__ inline double coupling(int j, double *ref) const
+    {
+#pragma clang fp contract(off)
+        const int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
+        const int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
+        double sum = 0.0, sall = 0.0;
+#pragma unroll
+        for (int B = (1 << D) - 1; B >= 0; --B) {
+            bool shared = true;
+            for (int m = 0; m < D; ++m) {
+                const int wm = ((B >> m) & 1) + o[m];
+                if (wm < 0 || wm > 1) shared = false;
+            }
+            if (!ok[B]) continue;
+            sall = sall + e[B];
+            if (shared) sum = sum + e[B];
+        }
+        const double hp = (D == 2) ? 1.0 : 1.0 / (double)n;
+        if (ref) *ref = sall * hp;
+        return (sum * kref_unit(D, nz)) * hp;
+    }
+};
+
 template <int D>
 __device__ inline double base_coupling64(const float *eps_c, int n, const int *x, int j, double *ref)
 {
-#pragma clang fp contract(off)
-    int o[3] = {half_off(D, j, 0), half_off(D, j, 1), D == 3 ? half_off(D, j, 2) : 0};
-    int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
-    double sum = 0.0, sall = 0.0;
-    for (int B = (1 << D) - 1; B >= 0; --B) {
-        bool ok = true, shared = true;
-        int64_t c = 0, stride = 1;
-        for (int m = 0; m < D; ++m) {
-            int bm = (B >> m) & 1, cm = x[m] - bm, wm = bm + o[m];
-            if (cm < 0 || cm >= n) ok = false;
-            if (wm < 0 || wm > 1) shared = false;
-            c += (int64_t)cm * stride;
-            stride *= n;
-        }
-        if (!ok) continue;
-        double e = (double)eps_c[c];
-        sall = sall + e;
-        if (shared) sum = sum + e;
-    }
-    double hp = (D == 2) ? 1.0 : 1.0 / (double)n;
-    if (ref) *ref = sall * hp;
-    return (sum * kref_unit(D, nz)) * hp;
+    BaseCells<D> bc;
+    bc.load(eps_c, n, x);
+    return bc.coupling(j, ref);
 }
 
 // ------------------------------------------------------- host objects

@@ -1195,7 +1195,9 @@ int outer_residual(mgd_hier *h, const OpSet &o, const double *u, const double *f
         if (nparts) *nparts = (int)grid;
         return MGD_OK;
     }
-    const unsigned grid = (unsigned)std::min<int64_t>(red_grid(h->NV[0]), h->partial_cap);
+    // as many blocks as the host-side sum takes (kHostParts): each thread's
+    // rows gather 3^d FP64 neighbours, so occupancy hides their latency
+    const unsigned grid = (unsigned)std::min<int64_t>({grid_for(h->NV[0], 256), (int64_t)kHostParts, h->partial_cap});
     if (nparts) *nparts = (int)grid;
     return h->dim == 2 ? outer_residual_t<2>(h, o, u, f, r, partial, grid, st)
                        : outer_residual_t<3>(h, o, u, f, r, partial, grid, st);

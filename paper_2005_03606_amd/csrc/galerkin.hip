@@ -630,7 +630,10 @@ template <int D, typename T> __global__ void k_base_stencils(const float *ec, in
     if (v >= g.NV) return;
     int x[3] = {0, 0, 0};
     g.coords(v, x);
-    for (int j = 0; j < n_half(D); ++j) S[(int64_t)j * g.NV + v] = (T)base_coupling64<D>(ec, n, x, j, nullptr);
+    BaseCells<D> bc;
+    bc.load(ec, n, x);
+#pragma unroll
+    for (int j = 0; j < n_half(D); ++j) S[(int64_t)j * g.NV + v] = (T)bc.coupling(j, nullptr);
 }
 
 template <int D, typename T> __global__ void k_geo_weights_t(int n, T *W)

@@ -94,8 +94,11 @@ __global__ void k_deltas(const float *S32, const float *eps_c, int n, int64_t NV
     float d[H];
     double ref = 0.0;
     float mx = 0.0f;
+    BaseCells<D> bc;
+    bc.load(eps_c, n, x);
+#pragma unroll
     for (int j = 0; j < H; ++j) {
-        double b = base_coupling64<D>(eps_c, n, x, j, &ref);
+        double b = bc.coupling(j, &ref);
         d[j] = (float)((double)S32[(int64_t)j * NV + v] - b);
         delta[(int64_t)j * NV + v] = d[j];
         mx = fmaxf(mx, fabsf(d[j]));
@@ -205,8 +208,11 @@ __global__ void k_decode_store(StoreView sv, int n, TO *out)
     int x[3] = {0, 0, 0};
     g.coords(v, x);
     constexpr int H = n_half(D);
+    BaseCells<D> bc;
+    bc.load(sv.eps_c, n, x);
+#pragma unroll
     for (int j = 0; j < H; ++j) {
-        double b = base_coupling64<D>(sv.eps_c, n, x, j, nullptr);
+        double b = bc.coupling(j, nullptr);
         out[(int64_t)j * g.NV + v] = (TO)(float)(b + (double)sv.delta(v, j, H));
     }
 }
