@@ -59,6 +59,22 @@ __host__ __device__ inline int pair_index(int D, int a, int b)
     return a * (nl - 1) - a * (a - 1) / 2 + (b - a - 1);
 }
 
+// workgroups go to the 8 XCDs in turn (block b to XCD b mod 8); this order
+// gives each XCD a contiguous range of vertices instead, so in 3D the plane
+// below a block was read by the same XCD and its L2 may still hold it
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// the block's index in that order for 3D grids (plain order in 2D, whose
+// row neighbours are near in any order)
+template <int D> __device__ inline int64_t block_index()
+{
+    return D == 3 ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+}
+
 template <int D> struct Grid {
     int n;      // cells per axis
     int64_t nv; // vertices per axis

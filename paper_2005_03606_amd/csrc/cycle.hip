@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_sweep(Op A, int n, const T *u, const T 
     constexpr bool zero_guess = ZERO;
     __shared__ double red[256];
     Grid<D> g(n);
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t v = block_index<D>() * blockDim.x + threadIdx.x;
     double rr = 0.0;
     if (v < g.NV) {
         int x[3] = {0, 0, 0};
@@ -115,7 +115,7 @@ template <int D, typename T>
 __global__ void k_restrict(const T *W, int nf, const T *r, T *fc)
 {
     Grid<D> gf(nf), gc(nf / 2);
-    int64_t V = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t V = block_index<D>() * blockDim.x + threadIdx.x;
     if (V >= gc.NV) return;
     int X[3] = {0, 0, 0};
     gc.coords(V, X);
@@ -136,7 +136,7 @@ template <int D, typename T>
 __global__ void k_prolong(const T *W, int nf, const T *ec, T *u)
 {
     Grid<D> gf(nf), gc(nf / 2);
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t v = block_index<D>() * blockDim.x + threadIdx.x;
     if (v >= gf.NV) return;
     int x[3] = {0, 0, 0};
     gf.coords(v, x);
@@ -1120,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_outer_residual(Op A, int n, const doubl
     __shared__ double red[256];
     Grid<D> g(n);
     double rr = 0.0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t v = block_index<D>() * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
         int x[3] = {0, 0, 0};
         g.coords(v, x);
         double rv = 0.0;
@@ -1246,7 +1246,7 @@ __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, cons
     const double beta = c.s[7] != 0.0 ? 0.0 : zdr / c.s[c.zr_old];
     if (blockIdx.x == 0 && threadIdx.x == 0) c.s[c.zr_new] = zr;
     double prod = 0.0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t v = block_index<D>() * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
         int x[3] = {0, 0, 0};
         g.coords(v, x);
         double pv = (double)z[v] + beta * pold[v];

@@ -330,7 +330,7 @@ template <typename T, bool GEO>
 __global__ __launch_bounds__(256) void k_galerkin3_int(HalfRow<3, T> A, const T *W, int nf, T *Sc)
 {
     const int nc = nf / 2, ni = nc - 1;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = block_index<3>() * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)ni * ni * ni) return;
     const int X0 = 1 + (int)(idx % ni), X1 = 1 + (int)((idx / ni) % ni), X2 = 1 + (int)(idx / ((int64_t)ni * ni));
     const int64_t nv = A.nv, nv2 = nv * nv, NVf = A.NV;
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_weights3_class(HalfRow<3, T> A, int nf,
     constexpr int p0 = ODD & 1, p1 = (ODD >> 1) & 1, p2 = (ODD >> 2) & 1;
     const int nc = nf / 2;
     const int c0 = p0 ? nc : nc - 1, c1 = p1 ? nc : nc - 1, c2 = p2 ? nc : nc - 1;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = block_index<3>() * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)c0 * c1 * c2) return;
     const int i0 = (int)(idx % c0), i1 = (int)((idx / c0) % c1), i2 = (int)(idx / ((int64_t)c0 * c1));
     const int x0 = 2 * i0 + (p0 ? 1 : 2), x1 = 2 * i1 + (p1 ? 1 : 2), x2 = 2 * i2 + (p2 ? 1 : 2);
