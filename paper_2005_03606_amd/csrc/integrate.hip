@@ -454,11 +454,30 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
                 double x[3];
                 x[1] = sample_coord(ci[1], qy, s, n);
                 if (D == 3) x[2] = sample_coord(ci[2], qz, s, n);
+                // a lattice cell inside one lattice cell: along the x-line
+                // p0 g = ga + t_x gb (FP64), one exp per sample
+                const bool latl = EK == MGD_EPS_LATTICE && ecell.ok;
+                double ga = 0.0, gb = 0.0;
+                if (latl) {
+                    const double t1 = x[1] * a.eps.count - ecell.base[1];
+                    const double t2 = D == 3 ? x[2] * a.eps.count - ecell.base[2] : 0.0;
+                    double f0 = 0.0, f1 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < (1 << (D - 1)); ++c) {
+                        const double w = ((c & 1) ? t1 : 1.0 - t1) * (D == 3 ? ((c & 2) ? t2 : 1.0 - t2) : 1.0);
+                        f0 += w * ecell.corner[2 * c];
+                        f1 += w * ecell.corner[2 * c + 1];
+                    }
+                    ga = a.eps.p0 * f0;
+                    gb = a.eps.p0 * (f1 - f0);
+                }
                 for (int qx = 0; qx < s; ++qx) {
                     double e;
                     if ((EK >= 0 ? EK : a.eps.kind) == MGD_EPS_SAMPLES) {
                         int64_t q = qx + (int64_t)s * line;
                         e = a.samples[i * nq + q];
+                    } else if (latl) {
+                        e = exp(ga + (sample_coord(ci[0], qx, s, n) * a.eps.count - ecell.base[0]) * gb);
                     } else {
                         x[0] = sample_coord(ci[0], qx, s, n);
                         e = eps_eval_cell<D, double, EK>(a.eps, ecell, x, rows, nrows);
