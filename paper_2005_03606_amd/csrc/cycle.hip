@@ -1275,6 +1275,51 @@ __global__ __launch_bounds__(256) void k_p_matvec(Op A, int n, const TZ *z, cons
     if (threadIdx.x == 0) partial[blockIdx.x] = sum;
 }
 
+// 3D form of the same step: A p_new = A z + beta A p_old, with A p_old the
+// previous step's product (the restart sets beta = 0 and the old product is
+// not read), so the 27-point gather reads the FP32 z instead of the FP64
+// p_old; the FP64 vectors are read and written at the vertex only
+template <int D, class Op, typename TZ>
+__global__ __launch_bounds__(256) void k_p_matvec_rec(Op A, int n, const TZ *z, const double *pold, double *pnew,
+                                                      double *Ap, CgScalars c, double *partial)
+{
+    __shared__ double red[256];
+    Grid<D> g(n);
+    const double zr = sum_partials(c.p1, c.n1, red), zdr = sum_partials(c.p1 + c.n1, c.n1, red);
+    const double beta = c.s[7] != 0.0 ? 0.0 : zdr / c.s[c.zr_old];
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[c.zr_new] = zr;
+    double prod = 0.0;
+    for (int64_t v = block_index<D>() * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        const double zv = (double)z[v];
+        const double pv = beta != 0.0 ? zv + beta * pold[v] : zv;
+        pnew[v] = pv;
+        if (g.interior(x)) {
+            constexpr int H = n_half(D);
+            double acc = 0.0, dsum = 0.0;
+            for (int j = 0; j < H; ++j) {
+                int64_t lin = half_lin(D, j, g.nv);
+                double a = A.c(v, j, x);
+                acc += a * (double)z[v + lin];
+                dsum += a;
+                int y[3] = {x[0] - half_off(D, j, 0), x[1] - half_off(D, j, 1), D == 3 ? x[2] - half_off(D, j, 2) : 0};
+                double b = A.c(v - lin, j, y);
+                acc += b * (double)z[v - lin];
+                dsum += b;
+            }
+            const double az = -dsum * zv + acc;
+            const double apv = beta != 0.0 ? az + beta * Ap[v] : az;
+            Ap[v] = apv;
+            prod += pv * apv;
+        } else {
+            Ap[v] = 0.0;
+        }
+    }
+    double sum = block_sum<256>(prod, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
 // x += alpha p; r_old = r; r -= alpha Ap (and its FP32 copy); partials of
 // r.r to pinned host memory; alpha = zr / p.Ap from the matvec's partials
 __global__ __launch_bounds__(256) void k_cg_update(double *x, const double *p, double *r, double *rold,
@@ -1344,7 +1389,14 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
     // more blocks than the other reducing kernels: each thread's rows gather
     // 27 neighbours, and the product needs the occupancy to hide that latency
     const unsigned grid = (unsigned)std::min<int64_t>({grid_for(h->NV[0], 256), (int64_t)kPmvBlocks, h->partial_cap});
-    if (h->precision == MGD_FP64)
+    if (D == 3) {
+        if (h->precision == MGD_FP64)
+            hipLaunchKernelGGL((k_p_matvec_rec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
+                               OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
+        else
+            hipLaunchKernelGGL((k_p_matvec_rec<D, OpHalf<float>, TZ>), dim3(grid), dim3(256), 0, st,
+                               OpHalf<float>{o.S32[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
+    } else if (h->precision == MGD_FP64)
         hipLaunchKernelGGL((k_p_matvec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
                            OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
     else
