@@ -161,6 +161,73 @@ __global__ void k_prolong(const T *W, int nf, const T *ec, T *u)
     u[v] += s;
 }
 
+// 3D restriction with the 27 fine vertices 2X + d unrolled: the corner of X
+// in the box of 2X + d is B_m = 1 where d_m = -1, else 0, fixed at compile
+// time; the same terms in the same order as k_restrict, so the same bits
+template <typename T, bool GEO>
+__global__ __launch_bounds__(256) void k_restrict3(const T *W, int nf, const T *r, T *fc)
+{
+    const int nc = nf / 2;
+    const int64_t nvc = nc + 1, NVc = nvc * nvc * nvc, nvf = nf + 1, NVf = nvf * nvf * nvf;
+    const int64_t V = block_index<3>() * blockDim.x + threadIdx.x;
+    if (V >= NVc) return;
+    const int X0 = (int)(V % nvc), X1 = (int)((V / nvc) % nvc), X2 = (int)(V / (nvc * nvc));
+    if (X0 == 0 || X0 == nc || X1 == 0 || X1 == nc || X2 == 0 || X2 == nc) {
+        fc[V] = (T)0;
+        return;
+    }
+    const int64_t c0 = 2 * (int64_t)X0 + nvf * (2 * (int64_t)X1 + nvf * 2 * (int64_t)X2);
+    T s = (T)0;
+#pragma unroll
+    for (int sv = 0; sv < 27; ++sv) {
+        const int d0 = sv % 3 - 1, d1 = sv / 3 % 3 - 1, d2 = sv / 9 - 1;
+        const int B = (d0 < 0 ? 1 : 0) | (d1 < 0 ? 2 : 0) | (d2 < 0 ? 4 : 0);
+        const int64_t v = c0 + d0 + nvf * (d1 + nvf * d2);
+        T w;
+        if (GEO) w = (T)((d0 ? 0.5 : 1.0) * (d1 ? 0.5 : 1.0) * (d2 ? 0.5 : 1.0));
+        else w = W[(int64_t)B * NVf + v];
+        s += w * r[v];
+    }
+    fc[V] = s;
+}
+
+// 3D prolongation by coarse vertex: the thread of X updates the fine
+// vertices 2X + b, b in {0,1}^3.  Child b takes the corners X + B with B a
+// subset of b (along an even axis only the corner X_m carries weight), in
+// ascending B as k_prolong, so the same bits; the 8 corner values are loaded
+// once for the 8 children.
+template <typename T, bool GEO>
+__global__ __launch_bounds__(256) void k_prolong3(const T *W, int nf, const T *ec, T *u)
+{
+    const int nc = nf / 2;
+    const int64_t nvc = nc + 1, NVc = nvc * nvc * nvc, nvf = nf + 1, NVf = nvf * nvf * nvf;
+    const int64_t V = block_index<3>() * blockDim.x + threadIdx.x;
+    if (V >= NVc) return;
+    const int X0 = (int)(V % nvc), X1 = (int)((V / nvc) % nvc), X2 = (int)(V / (nvc * nvc));
+    T e[8];
+#pragma unroll
+    for (int B = 0; B < 8; ++B) {
+        const int Y0 = X0 + (B & 1), Y1 = X1 + ((B >> 1) & 1), Y2 = X2 + (B >> 2);
+        e[B] = (Y0 <= nc && Y1 <= nc && Y2 <= nc) ? ec[Y0 + nvc * (Y1 + nvc * (int64_t)Y2)] : (T)0;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int x0 = 2 * X0 + (b & 1), x1 = 2 * X1 + ((b >> 1) & 1), x2 = 2 * X2 + (b >> 2);
+        if (x0 < 1 || x0 > nf - 1 || x1 < 1 || x1 > nf - 1 || x2 < 1 || x2 > nf - 1) continue;
+        const int64_t v = x0 + nvf * (x1 + nvf * (int64_t)x2);
+        T acc = (T)0;
+#pragma unroll
+        for (int B = 0; B < 8; ++B) {
+            if (B & ~b) continue;  // compile time after unrolling
+            T w;
+            if (GEO) w = (T)((b & 1 ? 0.5 : 1.0) * ((b >> 1) & 1 ? 0.5 : 1.0) * ((b >> 2) & 1 ? 0.5 : 1.0));
+            else w = W[(int64_t)B * NVf + v];
+            if (w != (T)0) acc += w * e[B];
+        }
+        u[v] += acc;
+    }
+}
+
 template <typename T> __global__ void k_fill(T *a, int64_t n, T val)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,11 +482,13 @@ int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *
     if (h->precision == MGD_FP64) {
         const double *W = box ? (const double *)o.W[level] : nullptr;
         if (h->dim == 2) hipLaunchKernelGGL((k_restrict<2, double>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
-        else hipLaunchKernelGGL((k_restrict<3, double>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+        else if (W) hipLaunchKernelGGL((k_restrict3<double, false>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+        else hipLaunchKernelGGL((k_restrict3<double, true>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
     } else {
         const float *W = box ? (const float *)o.W[level] : nullptr;
         if (h->dim == 2) hipLaunchKernelGGL((k_restrict<2, float>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
-        else hipLaunchKernelGGL((k_restrict<3, float>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+        else if (W) hipLaunchKernelGGL((k_restrict3<float, false>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+        else hipLaunchKernelGGL((k_restrict3<float, true>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
     }
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
@@ -428,16 +497,18 @@ int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *
 int cycle_prolong(mgd_hier *h, const OpSet &o, int level, const void *ec, void *u, hipStream_t st)
 {
     int nf = h->nl[level];
-    dim3 gr(grid_for(h->NV[level], 256));
+    dim3 gr(grid_for(h->NV[level], 256)), gc3(grid_for(h->NV[level + 1], 256));
     bool box = h->transfer == MGD_BOXMG;
     if (h->precision == MGD_FP64) {
         const double *W = box ? (const double *)o.W[level] : nullptr;
         if (h->dim == 2) hipLaunchKernelGGL((k_prolong<2, double>), gr, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
-        else hipLaunchKernelGGL((k_prolong<3, double>), gr, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
+        else if (W) hipLaunchKernelGGL((k_prolong3<double, false>), gc3, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
+        else hipLaunchKernelGGL((k_prolong3<double, true>), gc3, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
     } else {
         const float *W = box ? (const float *)o.W[level] : nullptr;
         if (h->dim == 2) hipLaunchKernelGGL((k_prolong<2, float>), gr, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
-        else hipLaunchKernelGGL((k_prolong<3, float>), gr, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
+        else if (W) hipLaunchKernelGGL((k_prolong3<float, false>), gc3, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
+        else hipLaunchKernelGGL((k_prolong3<float, true>), gc3, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
     }
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
