@@ -110,26 +110,6 @@ __device__ inline T wt(const TW *W, int64_t NV, int64_t v, const int *x, const i
     return (T)p;
 }
 
-// fc[X] = sum_v P[v][X] r[v] over the 3^d fine vertices around 2X (interior X)
-template <int D, typename T>
-__global__ void k_restrict(const T *W, int nf, const T *r, T *fc)
-{
-    Grid<D> gf(nf), gc(nf / 2);
-    int64_t V = block_index<D>() * blockDim.x + threadIdx.x;
-    if (V >= gc.NV) return;
-    int X[3] = {0, 0, 0};
-    gc.coords(V, X);
-    if (!gc.interior(X)) { fc[V] = (T)0; return; }
-    T s = (T)0;
-    constexpr int ns = D == 2 ? 9 : 27;
-    for (int sv = 0; sv < ns; ++sv) {
-        int x[3] = {0, 0, 0}, t = sv;
-        for (int m = 0; m < D; ++m) { x[m] = 2 * X[m] + t % 3 - 1; t /= 3; }
-        int64_t v = gf.vid(x);
-        s += wt<D, T, T>(W, gf.NV, v, x, X) * r[v];
-    }
-    fc[V] = s;
-}
 
 // u[v] += sum_B P[v][corner B] e[corner B] (interior fine v)
 template <int D, typename T>
@@ -161,9 +141,38 @@ __global__ void k_prolong(const T *W, int nf, const T *ec, T *u)
     u[v] += s;
 }
 
+// 2D restriction with the 9 fine vertices 2X + d unrolled (as k_restrict3);
+// fc[X] = sum_v P[v][X] r[v] on interior X, 0 on the boundary
+template <typename T, bool GEO>
+__global__ __launch_bounds__(256) void k_restrict2(const T *W, int nf, const T *r, T *fc)
+{
+    const int nc = nf / 2;
+    const int64_t nvc = nc + 1, NVc = nvc * nvc, nvf = nf + 1, NVf = nvf * nvf;
+    const int64_t V = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (V >= NVc) return;
+    const int X0 = (int)(V % nvc), X1 = (int)(V / nvc);
+    if (X0 == 0 || X0 == nc || X1 == 0 || X1 == nc) {
+        fc[V] = (T)0;
+        return;
+    }
+    const int64_t c0 = 2 * (int64_t)X0 + nvf * 2 * (int64_t)X1;
+    T s = (T)0;
+#pragma unroll
+    for (int sv = 0; sv < 9; ++sv) {
+        const int d0 = sv % 3 - 1, d1 = sv / 3 - 1;
+        const int B = (d0 < 0 ? 1 : 0) | (d1 < 0 ? 2 : 0);
+        const int64_t v = c0 + d0 + nvf * d1;
+        T w;
+        if (GEO) w = (T)((d0 ? 0.5 : 1.0) * (d1 ? 0.5 : 1.0));
+        else w = W[(int64_t)B * NVf + v];
+        s += w * r[v];
+    }
+    fc[V] = s;
+}
+
 // 3D restriction with the 27 fine vertices 2X + d unrolled: the corner of X
 // in the box of 2X + d is B_m = 1 where d_m = -1, else 0, fixed at compile
-// time; the same terms in the same order as k_restrict, so the same bits
+// time; the terms of R = P^T in the order of the fine offsets (x fastest)
 template <typename T, bool GEO>
 __global__ __launch_bounds__(256) void k_restrict3(const T *W, int nf, const T *r, T *fc)
 {
@@ -481,12 +490,14 @@ int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *
     bool box = h->transfer == MGD_BOXMG;
     if (h->precision == MGD_FP64) {
         const double *W = box ? (const double *)o.W[level] : nullptr;
-        if (h->dim == 2) hipLaunchKernelGGL((k_restrict<2, double>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+        if (h->dim == 2 && W) hipLaunchKernelGGL((k_restrict2<double, false>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+        else if (h->dim == 2) hipLaunchKernelGGL((k_restrict2<double, true>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
         else if (W) hipLaunchKernelGGL((k_restrict3<double, false>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
         else hipLaunchKernelGGL((k_restrict3<double, true>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
     } else {
         const float *W = box ? (const float *)o.W[level] : nullptr;
-        if (h->dim == 2) hipLaunchKernelGGL((k_restrict<2, float>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+        if (h->dim == 2 && W) hipLaunchKernelGGL((k_restrict2<float, false>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+        else if (h->dim == 2) hipLaunchKernelGGL((k_restrict2<float, true>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
         else if (W) hipLaunchKernelGGL((k_restrict3<float, false>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
         else hipLaunchKernelGGL((k_restrict3<float, true>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
     }
