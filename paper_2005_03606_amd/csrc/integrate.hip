@@ -569,7 +569,8 @@ union BF8 {
 template <int D, int NT, int NTERM, int TPW, bool WL, int EK>
 __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint4 *Gtab, int nchunks, float inv_den,
                                                     int64_t blk, int64_t cnt, float (*sm)[16][NT * 16 + 1],
-                                                    CandLDS &cand, double (*wrows)[kWaveCand * 7])
+                                                    float (*ko)[16][n_pairs(D) + 1], CandLDS &cand,
+                                                    double (*wrows)[kWaveCand * 7])
 {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int row = lane & 15, kg = lane >> 4;
@@ -697,8 +698,26 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
         for (int t = 0; t < NT; ++t)
             for (int r = 0; r < 4; ++r) sm[wave][4 * kg + r][t * 16 + (lane & 15)] = acc[t][r] * inv_den;
         __syncthreads();
-        if (lane < 16 && valid) {
-            constexpr int U = n_pairs(D);
+        constexpr int U = n_pairs(D);
+        if (!a.k_by_cell || !a.cells) {
+            // the group's 16 rows are contiguous in K_old and K_out: all 64
+            // lanes move them in contiguous pieces through LDS
+            const int nrow = tile < cnt ? (int)min((int64_t)16, cnt - tile) : 0;
+            if (a.K_old) {
+                const float *Ko = (const float *)a.K_old + tile * U;
+                for (int e = lane; e < nrow * U; e += 64) ko[wave][e / U][e % U] = Ko[e];
+                __syncthreads();
+                if (lane < 16 && valid) {
+                    float K[U], old[U];
+                    for (int p = 0; p < U; ++p) { K[p] = sm[wave][lane][p]; old[p] = ko[wave][lane][p]; }
+                    const double rel = ladder_rel<D, float>(K, old);
+                    if (a.rel_out) a.rel_out[i] = rel;
+                    if (a.done_out) a.done_out[i] = rel < a.C ? 1 : 0;
+                }
+            }
+            float *Kout = (float *)a.K_out + tile * U;
+            for (int e = lane; e < nrow * U; e += 64) Kout[e] = sm[wave][e / U][e % U];
+        } else if (lane < 16 && valid) {
             float K[U];
             for (int p = 0; p < U; ++p) K[p] = sm[wave][lane][p];
             store_and_check<D, float>(a, i, cell, K);
@@ -711,16 +730,18 @@ __global__ __launch_bounds__(256) void k_integrate_mfma(AsmArgs a, const uint4 *
                                                         float inv_den)
 {
     __shared__ float sm[4][16][NT * 16 + 1];
+    __shared__ float ko[4][16][n_pairs(D) + 1];
     __shared__ CandLDS cand;
     __shared__ double wrows[STRIDE ? 4 : 1][kWaveCand * 7];
     const int64_t cnt = asm_count(a);
     if (!STRIDE) {
         if ((int64_t)blockIdx.x * (64 * TPW) < cnt)
-            integrate_mfma_tile<D, NT, NTERM, TPW, false, EK>(a, Gtab, nchunks, inv_den, blockIdx.x, cnt, sm, cand, wrows);
+            integrate_mfma_tile<D, NT, NTERM, TPW, false, EK>(a, Gtab, nchunks, inv_den, blockIdx.x, cnt, sm, ko, cand,
+                                                              wrows);
         return;
     }
     for (int64_t blk = blockIdx.x; blk * (64 * TPW) < cnt; blk += gridDim.x) {
-        integrate_mfma_tile<D, NT, NTERM, TPW, true, EK>(a, Gtab, nchunks, inv_den, blk, cnt, sm, cand, wrows);
+        integrate_mfma_tile<D, NT, NTERM, TPW, true, EK>(a, Gtab, nchunks, inv_den, blk, cnt, sm, ko, cand, wrows);
         __syncthreads();  // the candidate list and the row buffer are reused by the next tile
     }
 }
