@@ -886,8 +886,13 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
     // too short a contraction for the matrix cores: FP64 on the vector
     // units, rounded to FP32
     if (mode == MGD_FP64 || s <= 2) {
+        // lanes per cell: the per-cell tail (element matrix, criterion,
+        // stores) runs on one lane of the G.  In 3D (28 pairs per cell) the
+        // tail dominates short rungs, so fewer lanes per cell (more sample
+        // lines per lane) spread it over more cells per wave; in 2D (6 pairs)
+        // the later rungs' few open cells need the lanes for parallelism
         int lines = dim == 2 ? s : s * s;
-        int G = lines >= 16 ? 16 : lines >= 4 ? 4 : 1;
+        int G = dim == 3 ? (lines >= 256 ? 16 : lines >= 16 ? 4 : 1) : (lines >= 16 ? 16 : lines >= 4 ? 4 : 1);
         const bool stride = count_dev != nullptr;
         unsigned grid = grid_for(count * G, 256);
         if (stride) grid = std::min<unsigned>(grid, kAsmMaxBlocks);
