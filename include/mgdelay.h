@@ -52,6 +52,7 @@ enum { MGD_STATIONARY = 0, MGD_PCG = 1 };      /* FP64 outer iteration */
 enum { MGD_UPFRONT = 0, MGD_LAZY = 1 };        /* assembly schedule */
 enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1, MGD_PUBLISH_EVERY = 2 };
 enum { MGD_STORE_AUTO = 0, MGD_STORE_DECODE = 1, MGD_STORE_COPY = 2 }; /* finest-level source */
+enum { MGD_START_CARRY = 0, MGD_START_BEST = 1 }; /* iterate after an operator change */
 
 typedef struct mgd_ctx mgd_ctx;   /* per-device context: streams, scratch */
 typedef struct mgd_hier mgd_hier; /* device-resident multigrid hierarchy */
@@ -268,6 +269,11 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * (a provisional operator's solution is no closer to the final one than the
  * operator is to the final operator); 0 cycles on until the publish.
  * store_path: as for a hierarchy (MGD_MIXED).
+ * start: the iterate after an operator change.  MGD_START_CARRY (0, the
+ * paper's schedule, Sec. 5.1-5.3) carries it over; MGD_START_BEST keeps the
+ * carried iterate unless its residual on the new operator exceeds that of
+ * the zero start (interior set to zero, boundary values kept), and then
+ * continues from the zero start (decided on the device).
  * f (dev double [NV]) is the load vector; u (dev double [NV]) is the initial
  * guess on entry and the solution on return. */
 typedef struct {
@@ -277,6 +283,7 @@ typedef struct {
     double C, omega, tol, div_factor;
     mgd_tier_policy tiers;
     double prov_tol;
+    int32_t start, pad;
 } mgd_solve_opts;
 
 #define MGD_HIST 512

@@ -47,7 +47,7 @@ class Opts(C.Structure):
     _fields_ = [("s_fixed", C.c_int32), ("s_max", C.c_int32), ("lazy", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("coarsest", C.c_int32),
                 ("max_cycles", C.c_int32), ("transfer", C.c_int32),
-                ("outer", C.c_int32), ("pad2", C.c_int32),
+                ("outer", C.c_int32), ("start", C.c_int32),
                 ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
                 ("div_factor", C.c_double)]
 
@@ -343,10 +343,13 @@ class Hierarchy:
 
 def solve(fld, d, n, f, u0=None, s_fixed=0, s_max=16, lazy=False, C_thr=0.01, omega=0.6,
           nu1=2, nu2=2, coarsest=2, tol=1e-10, max_cycles=200, div_factor=100.0,
-          transfer=GEOMETRIC, outer=0):
+          transfer=GEOMETRIC, outer=0, start=0):
+    """start: after an operator change 0 carries the iterate over (the
+    paper), 1 takes the carried iterate or the zero start, whichever has the
+    smaller residual on the new operator."""
     r = _FieldRef(fld)
     u = np.zeros(nvert(d, n)) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
-    op = Opts(s_fixed, s_max, int(lazy), nu1, nu2, coarsest, max_cycles, transfer, outer, 0,
+    op = Opts(s_fixed, s_max, int(lazy), nu1, nu2, coarsest, max_cycles, transfer, outer, start,
               C_thr, omega, tol, div_factor)
     rep = Report()
     st = lib().orc_solve(r.ptr, d, n, np.ascontiguousarray(f, dtype=np.float64), u,

@@ -992,7 +992,8 @@ typedef struct {
     int32_t max_cycles;
     int32_t transfer;   /* 0 geometric d-linear, 1 BoxMG */
     int32_t outer;      /* 0 stationary (u += V r), 1 conjugate gradients with V as preconditioner */
-    int32_t pad;
+    int32_t start;      /* after an operator change: 0 carry the iterate over (Sec. 5.1-5.3),
+                           1 the carried iterate or the zero start, whichever has the smaller residual */
     double C, omega, tol, div_factor;
 } orc_opts;
 
@@ -1014,9 +1015,12 @@ enum { ORC_OK = 0, ORC_ENOCONV = -4, ORC_EDIVERGED = -5 };
  * on the centre-sample operator use a geometric hierarchy (Sec. 1).  The
  * residual is measured at the start of each cycle with the operator current
  * then, normalised by the first one (Sec. 6); after an operator change the
- * iteration continues from the carried iterate or from the zero start,
- * whichever has the smaller residual on the new operator; the run stops
- * when every cell is final and the normalised residual is at most tol; the
+ * iteration carries its iterate over (Sec. 5.1-5.3: the smoother continues
+ * on whatever operator is current), or, with op->start = 1, continues from
+ * the carried iterate or from the zero start, whichever has the smaller
+ * residual on the new operator; the run stops
+ * when every cell is final and the normalised residual is at most tol (for
+ * CG the recursion's residual, confirmed with f - A u itself); the
  * stationary iteration aborts when the residual exceeds div_factor times its
  * reference, CG only on a non-finite residual.                             */
 int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, const orc_opts *op, orc_report *rep)
@@ -1105,12 +1109,12 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
         if (op->outer == 0 || restart)
             orc_residual(d, N, g->S[0], u, f, r);
         rk = orc_norm_interior(d, N, r);
-        /* start after an operator change (this implementation's reading; the
-         * paper carries the iterate over): the carried iterate unless its
-         * residual on the new operator exceeds that of the zero start (the
-         * interior set to zero, boundary values kept), in which case the
-         * iteration restarts from the zero start */
-        if (restart && k > 0) {
+        /* start after an operator change.  The paper carries the iterate
+         * over (start = 0: nothing to do).  The optional rule (start = 1)
+         * keeps the carried iterate unless its residual on the new operator
+         * exceeds that of the zero start (the interior set to zero, boundary
+         * values kept), in which case the iteration restarts from there */
+        if (restart && k > 0 && op->start == 1) {
             double *uz = malloc(sizeof(double) * NV), *rz = malloc(sizeof(double) * NV);
             for (int64_t v = 0; v < NV; ++v) uz[v] = is_interior(d, N + 1, v, vi) ? 0.0 : u[v];
             orc_residual(d, N, g->S[0], uz, f, rz);
@@ -1129,9 +1133,19 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
         if (k == 0 || restart) r_ref = rk > r0 ? rk : r0;
         double rel = r0 > 0.0 ? rk / r0 : 0.0;
         if (k < 512) rep->hist[k] = rel;
-        int all_done = 1;
+        int all_done = 1, fresh = restart;
         for (int64_t c = 0; c < nc && all_done; ++c) all_done = done[c];
-        if (all_done && rel <= op->tol) { status = ORC_OK; break; }
+        if (all_done && rel <= op->tol) {
+            /* the stopping rule is on f - A u (Sec. 6); the CG recursion's
+             * residual drifts from it by rounding, so a recursion-based
+             * convergence is confirmed with the residual itself, and if that
+             * is still above the tolerance CG restarts from it */
+            if (op->outer == 0 || restart) { status = ORC_OK; break; }
+            orc_residual(d, N, g->S[0], u, f, r);
+            double rt = orc_norm_interior(d, N, r);
+            if (rt <= op->tol * r0) { rk = rt; status = ORC_OK; break; }
+            fresh = 1;
+        }
         /* the guard watches the stationary iteration; the CG residual norm is
          * not monotone, so CG stops only on a non-finite residual */
         if (op->outer == 0 ? !(rk <= op->div_factor * r_ref) : !isfinite(rk)) { status = ORC_EDIVERGED; break; }
@@ -1149,7 +1163,7 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
             zr += z[v] * r[v];
             zdr += z[v] * (r[v] - rold[v]);
         }
-        double beta = restart ? 0.0 : zdr / zr_old;
+        double beta = fresh ? 0.0 : zdr / zr_old;
         for (int64_t v = 0; v < NV; ++v)
             p[v] = z[v] + beta * p[v];
         orc_residual(d, N, g->S[0], p, zero, Ap); /* Ap = -(A p) on the interior */

@@ -16,6 +16,7 @@ STATIONARY, PCG = 0, 1
 UPFRONT, LAZY = 0, 1
 PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY = 0, 1, 2
 STORE_AUTO, STORE_DECODE, STORE_COPY = 0, 1, 2
+START_CARRY, START_BEST = 0, 1
 EPS_SAMPLES = 6
 HIST = 512
 
@@ -51,7 +52,8 @@ class _SolveOpts(C.Structure):
                 ("s_max", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("max_cycles", C.c_int32), ("coarsest", C.c_int32), ("store_path", C.c_int32),
                 ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
-                ("div_factor", C.c_double), ("tiers", _Tier), ("prov_tol", C.c_double)]
+                ("div_factor", C.c_double), ("tiers", _Tier), ("prov_tol", C.c_double),
+                ("start", C.c_int32), ("pad", C.c_int32)]
 
 
 class _Report(C.Structure):
@@ -142,10 +144,51 @@ def _ptr(t):
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("device tensor expected")
+        raise MgdError(EINVAL, "device tensor expected")
     if not t.is_contiguous():
-        raise ValueError("contiguous tensor expected")
+        raise MgdError(EINVAL, "contiguous tensor expected")
     return t.data_ptr()
+
+
+_DT = {FP64: torch.float64, MIXED: torch.float32}
+
+
+def _buf(t, name, dtype, numel, device=None, optional=False):
+    """Device pointer of a caller buffer after checking what the C ABI cannot:
+    dtype, element count, contiguity, and that it lives on the context's
+    device.  Raises MgdError(EINVAL) before anything is enqueued."""
+    if t is None:
+        if optional:
+            return None
+        raise MgdError(EINVAL, f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise MgdError(EINVAL, f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise MgdError(EINVAL, f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise MgdError(EINVAL, f"{name} must hold {numel} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise MgdError(EINVAL, f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise MgdError(EINVAL, f"{name} must be a device tensor")
+    if device is not None and t.device.index != device:
+        raise MgdError(EINVAL, f"{name} is on cuda:{t.device.index}, the context on cuda:{device}")
+    return t.data_ptr()
+
+
+def _nv(dim, n):
+    return (n + 1) ** dim
+
+
+def _eps_data_count(kind, dim, count):
+    """Doubles a field descriptor's data must hold (None: no data)."""
+    if kind == 3:                      # balls: (c, r) rows
+        return count * (dim + 1)
+    if kind == 4:                      # lattice: (count+1)^d vertex values
+        return (count + 1) ** dim
+    if kind == 5:                      # boxes: (lo, hi, eps) rows
+        return count * (2 * dim + 1)
+    return None
 
 
 def _stream(stream=None):
@@ -189,16 +232,27 @@ class Eps:
     def __init__(self, field, device="cuda"):
         import numpy as np
         data = np.ascontiguousarray(getattr(field, "data", np.zeros(0)), dtype=np.float64)
+        if field.dim not in (2, 3):
+            raise MgdError(EINVAL, f"field dim must be 2 or 3, got {field.dim}")
+        want = _eps_data_count(field.kind, field.dim, field.count)
+        if want is not None and (field.count < 1 or data.size != want):
+            raise MgdError(EINVAL, f"field kind {field.kind} with count {field.count} needs {want} data values, "
+                                   f"got {data.size}")
         self.data = torch.from_numpy(data if data.size else np.zeros(1)).to(device)
         self.s = _Eps(field.kind, field.dim, field.count, 0, field.p0, field.p1, self.data.data_ptr())
         self.dim = field.dim
+        self.n_samples = None
 
     @classmethod
     def samples(cls, dim, samples):
+        """Explicit samples [cells][s^d] (float64, device) for assemble_cells."""
+        if samples.dtype != torch.float64:
+            raise MgdError(EINVAL, f"samples must be torch.float64, got {samples.dtype}")
         obj = cls.__new__(cls)
         obj.data = samples.contiguous()
-        obj.s = _Eps(EPS_SAMPLES, dim, 0, 0, 0.0, 0.0, obj.data.data_ptr())
+        obj.s = _Eps(EPS_SAMPLES, dim, 0, 0, 0.0, 0.0, _ptr(obj.data))
         obj.dim = dim
+        obj.n_samples = obj.data.numel()
         return obj
 
 
@@ -206,9 +260,23 @@ def assemble_cells(ctx, dim, n, s, eps, mode=FP64, cells=None, K_old=None, C_thr
                    want_rel=False, stream=None):
     """Element matrices [count][U] (upper off-diagonal pairs); with K_old also
     the relative change and the below-threshold flags."""
+    if dim not in (2, 3) or mode not in _DT:
+        raise MgdError(EINVAL, "dim must be 2 or 3 and mode FP64 or MIXED")
+    if eps.dim != dim:
+        raise MgdError(EINVAL, "eps dimension differs from dim")
+    ncell = n ** dim
+    if cells is None:
+        count = ncell
+    else:
+        count = int(cells.numel())
+        _buf(cells, "cells", torch.int64, count, ctx.device)
+        if count and (int(cells.min()) < 0 or int(cells.max()) >= ncell):
+            raise MgdError(EINVAL, f"cell ids must lie in [0, {ncell})")
+    if eps.n_samples is not None and eps.n_samples != count * s ** dim:
+        raise MgdError(EINVAL, f"explicit samples must number count * s^d = {count * s ** dim}")
     dev = torch.device("cuda", ctx.device)
-    count = (n ** dim) if cells is None else int(cells.numel())
-    dt = torch.float64 if mode == FP64 else torch.float32
+    dt = _DT[mode]
+    _buf(K_old, "K_old", dt, count * n_pairs(dim), ctx.device, optional=True)
     K = torch.empty((count, n_pairs(dim)), dtype=dt, device=dev)
     rel = torch.empty(count, dtype=torch.float64, device=dev) if (K_old is not None and want_rel) else None
     done = torch.empty(count, dtype=torch.uint8, device=dev) if K_old is not None else None
@@ -219,6 +287,8 @@ def assemble_cells(ctx, dim, n, s, eps, mode=FP64, cells=None, K_old=None, C_thr
 
 def centre_samples(ctx, dim, n, eps, stream=None):
     """FP32 eps at every cell centre [n^d]."""
+    if eps.dim != dim or eps.n_samples is not None:
+        raise MgdError(EINVAL, "centre samples need a field descriptor of dimension dim")
     out = torch.empty(n ** dim, dtype=torch.float32, device=torch.device("cuda", ctx.device))
     ctx.check(lib().mgd_centre_samples(ctx.h, dim, n, C.byref(eps.s), _ptr(out), _stream(stream)))
     return out
@@ -226,8 +296,10 @@ def centre_samples(ctx, dim, n, eps, stream=None):
 
 def gather_stencils(ctx, dim, n, K, k_mode=FP64, s_mode=FP64, stream=None):
     """Upper-half couplings [H][NV] from element matrices of all cells."""
-    dt = torch.float64 if s_mode == FP64 else torch.float32
-    S = torch.empty((n_half(dim), (n + 1) ** dim), dtype=dt, device=K.device)
+    if dim not in (2, 3) or k_mode not in _DT or s_mode not in _DT:
+        raise MgdError(EINVAL, "dim must be 2 or 3 and the modes FP64 or MIXED")
+    _buf(K, "K", _DT[k_mode], n ** dim * n_pairs(dim), ctx.device)
+    S = torch.empty((n_half(dim), (n + 1) ** dim), dtype=_DT[s_mode], device=K.device)
     ctx.check(lib().mgd_gather_stencils(ctx.h, dim, n, _ptr(K), k_mode, _ptr(S), s_mode, _stream(stream)))
     return S
 
@@ -265,10 +337,21 @@ class Hierarchy:
     def vec(self, l=0):
         return torch.zeros(self.nv(l), dtype=self.vdtype, device=torch.device("cuda", self.ctx.device))
 
+    def _level(self, l):
+        if not (0 <= l < self.nlev):
+            raise MgdError(EINVAL, f"level {l} outside [0, {self.nlev})")
+        return l
+
+    def _vec(self, t, name, l, optional=False):
+        return _buf(t, name, self.vdtype, self.nv(l), self.ctx.device, optional)
+
     def set_fine(self, S64, stream=None):
+        _buf(S64, "S", torch.float64, n_half(self.dim) * self.nv(0), self.ctx.device)
         self.ctx.check(lib().mgd_hier_set_fine(self.ctx.h, self.h, _ptr(S64), _stream(stream)))
 
     def compress(self, S32, eps_c, min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=0.0, stream=None):
+        _buf(S32, "S32", torch.float32, n_half(self.dim) * self.nv(0), self.ctx.device)
+        _buf(eps_c, "eps_c", torch.float32, self.n ** self.dim, self.ctx.device)
         pol = _Tier(min_tier, max_tier, tau_abs, tau_rel)
         self.ctx.check(lib().mgd_compress_stencils(self.ctx.h, self.h, _ptr(S32), _ptr(eps_c),
                                                    C.byref(pol), _stream(stream)))
@@ -292,54 +375,84 @@ class Hierarchy:
         return tt, off, pay[:pb]
 
     def level_stencils(self, l, stream=None):
+        self._level(l)
         out = torch.empty((n_half(self.dim), self.nv(l)), dtype=torch.float64,
                           device=torch.device("cuda", self.ctx.device))
         self.ctx.check(lib().mgd_level_stencils(self.ctx.h, self.h, l, _ptr(out), _stream(stream)))
         return out
 
     def level_weights(self, l, stream=None):
+        self._level(l)
         out = torch.empty((1 << self.dim, self.nv(l)), dtype=torch.float64,
                           device=torch.device("cuda", self.ctx.device))
         self.ctx.check(lib().mgd_level_weights(self.ctx.h, self.h, l, _ptr(out), _stream(stream)))
         return out
 
     def smooth(self, l, u, f, sweeps=1, omega=0.6, stream=None):
+        self._level(l)
+        self._vec(u, "u", l)
+        self._vec(f, "f", l)
         self.ctx.check(lib().mgd_smooth(self.ctx.h, self.h, l, _ptr(u), _ptr(f), sweeps, omega, _stream(stream)))
 
     def presmooth(self, l, u, f, u_out, r_out, omega=0.6, stream=None):
         """Two sweeps from u (None: zero) into u_out, then r_out = f - A u_out."""
+        self._level(l)
+        self._vec(u, "u", l, optional=True)
+        for t, nm in ((f, "f"), (u_out, "u_out"), (r_out, "r_out")):
+            self._vec(t, nm, l)
         self.ctx.check(lib().mgd_presmooth(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(u_out), _ptr(r_out),
                                            omega, _stream(stream)))
 
     def presmooth_restrict(self, l, u, f, u_out, fc, omega=0.6, stream=None):
         """Two sweeps from u (None: zero) into u_out, fc = P^T (f - A u_out) on level l+1."""
+        self._level(l)
+        self._level(l + 1)
+        self._vec(u, "u", l, optional=True)
+        self._vec(f, "f", l)
+        self._vec(u_out, "u_out", l)
+        self._vec(fc, "fc", l + 1)
         self.ctx.check(lib().mgd_presmooth_restrict(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(u_out), _ptr(fc),
                                                     omega, _stream(stream)))
 
     def residual(self, l, u, f, r, stream=None):
+        self._level(l)
+        for t, nm in ((u, "u"), (f, "f"), (r, "r")):
+            self._vec(t, nm, l)
         self.ctx.check(lib().mgd_residual(self.ctx.h, self.h, l, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))
 
     def restrict(self, l, r, fc, stream=None):
+        self._level(l)
+        self._level(l + 1)
+        self._vec(r, "r", l)
+        self._vec(fc, "fc", l + 1)
         self.ctx.check(lib().mgd_restrict(self.ctx.h, self.h, l, _ptr(r), _ptr(fc), _stream(stream)))
 
     def prolong_add(self, l, ec, u, stream=None):
+        self._level(l)
+        self._level(l + 1)
+        self._vec(ec, "ec", l + 1)
+        self._vec(u, "u", l)
         self.ctx.check(lib().mgd_prolong_add(self.ctx.h, self.h, l, _ptr(ec), _ptr(u), _stream(stream)))
 
     def vcycle(self, u, f, omega=0.6, nu1=2, nu2=2, stream=None):
+        self._vec(u, "u", 0)
+        self._vec(f, "f", 0)
         o = _CycleOpts(omega, nu1, nu2)
         self.ctx.check(lib().mgd_vcycle(self.ctx.h, self.h, _ptr(u), _ptr(f), C.byref(o), _stream(stream)))
 
     def outer_residual(self, u, f, r, stream=None):
+        for t, nm in ((u, "u"), (f, "f"), (r, "r")):
+            _buf(t, nm, torch.float64, self.nv(0), self.ctx.device)
         self.ctx.check(lib().mgd_outer_residual(self.ctx.h, self.h, _ptr(u), _ptr(f), _ptr(r), _stream(stream)))
 
 
 def solve_opts(precision=FP64, transfer=GEOMETRIC, outer=STATIONARY, schedule=UPFRONT,
                publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6, nu1=2, nu2=2,
                tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0, min_tier=2, max_tier=2,
-               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0):
+               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0, start=START_CARRY):
     return _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
                       max_cycles, coarsest, store_path, C_thr, omega, tol, div_factor,
-                      _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol)
+                      _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol, start, 0)
 
 
 def _report_dict(rc, rep):
@@ -355,8 +468,12 @@ def solve(ctx, dim, n, eps, f, u=None, stream=None, **kw):
     """Full solve (synchronous).  f, u: device float64 [(n+1)^d]; u is the
     initial guess (zero if None) and holds the solution on return.  Keyword
     options as in solve_opts."""
+    if eps.dim != dim or eps.n_samples is not None:
+        raise MgdError(EINVAL, "solve needs a field descriptor of dimension dim")
+    _buf(f, "f", torch.float64, _nv(dim, n), ctx.device)
     if u is None:
         u = torch.zeros_like(f)
+    _buf(u, "u", torch.float64, _nv(dim, n), ctx.device)
     op = solve_opts(**kw)
     rep = _Report()
     rc = ctx.check(lib().mgd_solve(ctx.h, dim, n, C.byref(eps.s), _ptr(f), _ptr(u), C.byref(op),
@@ -385,6 +502,10 @@ class Server:
     def submit(self, dim, n, eps, f, u, stream=None, **kw):
         """Queue a solve; it starts after the work queued so far on `stream`
         (default: the current torch stream), where f and u were written."""
+        if eps.dim != dim or eps.n_samples is not None:
+            raise MgdError(EINVAL, "a request needs a field descriptor of dimension dim")
+        _buf(f, "f", torch.float64, _nv(dim, n), self.ctx.device)
+        _buf(u, "u", torch.float64, _nv(dim, n), self.ctx.device)
         t = C.c_int64()
         op = solve_opts(**kw)
         self.ctx.check(lib().mgd_server_submit(self.h, dim, n, C.byref(eps.s), _ptr(f), _ptr(u),

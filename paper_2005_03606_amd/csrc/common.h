@@ -311,7 +311,9 @@ struct CgScalars {
 };
 constexpr int kHostParts = 1024;
 // residual checks: the squared norm of check k lands in the device scalar
-// s[kChkSlot + (k & 1)] and in the pinned host slot host_part[k & 1]
+// s[kChkSlot + (k & 1)] and in the pinned host slot host_part[k & 1]; slot 2
+// (s[kChkSlot + 2], host_part[2]) takes the true residual that confirms a
+// CG convergence
 constexpr int kChkSlot = 24;
 // s[kRRuSlot]: the carried iterate's squared residual at an operator change
 // (kRRuSlot + 1: scratch); s[kZeroSlot]: 1 when that change restarted from

@@ -1537,8 +1537,9 @@ int check_sum(mgd_hier *h, int nparts, int slot, hipStream_t st)
 {
     if (nparts < 1 || nparts > 1024 || nparts > h->partial_cap)
         return mgd_fail(h->ctx, MGD_EINVAL, "residual check with %d partials", nparts);
+    if (slot < 0 || slot > 2) return mgd_fail(h->ctx, MGD_EINVAL, "residual check slot %d", slot);
     hipLaunchKernelGGL(k_check_sum, dim3(1), dim3(1024), 0, st, (const double *)h->partial, nparts,
-                       h->scal + kChkSlot + (slot & 1), h->host_part_dev + (slot & 1));
+                       h->scal + kChkSlot + slot, h->host_part_dev + slot);
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
 }

@@ -29,6 +29,7 @@ struct SolveState {
     hipEvent_t ev_ready[8] = {};
     hipEvent_t ev_free = nullptr, ev_start = nullptr, ev_final = nullptr;
     hipEvent_t ev_norm[2] = {nullptr, nullptr};  // residual check k completes ev_norm[k & 1]
+    hipEvent_t ev_verify = nullptr;              // the true-residual confirmation completes it
     hipStream_t s_asm = nullptr, stream = nullptr;
     bool own_asm = false;
     size_t bytes = 0;
@@ -45,6 +46,8 @@ struct SolveState {
     double thr = 0.0;   // (tol r_0)^2: squared-norm convergence threshold
     bool lazy = false, pcg = false, ladder_done = false, restart = true, done = false;
     bool parked = false;  // done with the provisional operator, waiting for the pending one
+    bool verifying = false;  // a CG convergence is being confirmed with f - A u
+    bool chk_true[2] = {true, true};  // check k (slot k & 1) measured f - A u, not the CG recursion
     double r0 = 0, rk = 0, r_ref = 0, t0 = 0, t_first = 0, t_loop0 = 0;
 };
 

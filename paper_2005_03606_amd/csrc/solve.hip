@@ -118,7 +118,7 @@ void solve_state_free(SolveState *S)
     dev_free(S->r); dev_free(S->rold); dev_free(S->p[0]); dev_free(S->p[1]); dev_free(S->Ap);
     for (auto &e : S->ev_ready)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {S->ev_free, S->ev_start, S->ev_norm[0], S->ev_norm[1], S->ev_final})
+    for (hipEvent_t e : {S->ev_free, S->ev_start, S->ev_norm[0], S->ev_norm[1], S->ev_final, S->ev_verify})
         if (e) (void)hipEventDestroy(e);
     if (S->own_asm && S->s_asm) (void)hipStreamDestroy(S->s_asm);
     delete S;
@@ -167,7 +167,7 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) CK(MGD_EHIP);
     // the squared residual norms are written by a kernel straight into pinned
     // host memory: the check events release to system scope so the host sees them
-    for (hipEvent_t *e : {&S->ev_norm[0], &S->ev_norm[1]})
+    for (hipEvent_t *e : {&S->ev_norm[0], &S->ev_norm[1], &S->ev_verify})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming | hipEventReleaseToSystem) != hipSuccess) CK(MGD_EHIP);
     if (own_asm) {
         if (hipStreamCreateWithFlags(&S->s_asm, hipStreamNonBlocking) != hipSuccess) CK(MGD_EHIP);
@@ -211,6 +211,7 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
         return mgd_fail(ctx, MGD_EINVAL, "bad publish mode");
     if (op->store_path < MGD_STORE_AUTO || op->store_path > MGD_STORE_COPY)
         return mgd_fail(ctx, MGD_EINVAL, "bad store_path");
+    if (op->start != MGD_START_CARRY && op->start != MGD_START_BEST) return mgd_fail(ctx, MGD_EINVAL, "bad start");
     int sf = op->s_fixed, sm = op->s_max;
     if (sf > 0 && sf != 1 && sf != 2 && sf != 4 && sf != 8 && sf != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_fixed");
     if (sf <= 0 && sm != 1 && sm != 2 && sm != 4 && sm != 8 && sm != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_max");
@@ -233,14 +234,17 @@ static int enqueue_check(SolveState *S, int nparts)
     mgd_ctx *ctx = S->ctx;
     mgd_hier &H = S->H;
     int rc;
-    if (S->restart || !S->pcg || nparts == 0) {
+    const bool true_res = S->restart || !S->pcg || nparts == 0;
+    S->chk_true[S->kq & 1] = true_res;
+    if (true_res) {
         if ((rc = outer_residual(&H, *S->sets[S->cur], S->u, S->f, S->r, &nparts, S->stream))) return rc;
         if (S->pcg && S->restart && (rc = vec_fill_f64(ctx, H.scal + 7, 1, 1.0, S->stream))) return rc;
     }
     const int slot = S->kq & 1;
-    if (S->restart && S->kq > 0) {
-        // an operator change: the carried iterate or the zero start
-        // (the CG direction and product vectors restart too: free as scratch)
+    if (S->restart && S->kq > 0 && S->op.start == MGD_START_BEST) {
+        // an operator change under the optional start rule: the carried
+        // iterate or the zero start (the CG direction and product vectors
+        // restart too: free as scratch)
         if ((rc = restart_pick(&H, *S->sets[S->cur], nparts, slot, S->f, S->u, S->r, S->p[0], S->Ap, S->stream)))
             return rc;
     } else if ((rc = check_sum(&H, nparts, slot, S->stream))) {
@@ -252,6 +256,7 @@ static int enqueue_check(SolveState *S, int nparts)
 }
 
 static int boundary_publish(SolveState *S, bool force_wait);
+static void finish(SolveState *S);
 
 // one preconditioned cycle with the current operator and its residual check;
 // `gated`: queued before the previous check was read, so the update is
@@ -382,6 +387,61 @@ static int await_publish(SolveState *S, bool blocking)
 }
 
 
+// The stopping rule is on f - A u (Sec. 6).  A CG convergence read from the
+// recursion's residual, which drifts from f - A u by rounding, is confirmed
+// with the residual itself (check slot 2); if that is still above the
+// tolerance, CG restarts from it (beta = 0) and the iteration goes on.
+static int verify_finish(SolveState *S, bool blocking)
+{
+    mgd_ctx *ctx = S->ctx;
+    if (blocking) {
+        hipError_t q;
+        while ((q = hipEventQuery(S->ev_verify)) == hipErrorNotReady) {
+        }
+        HIPCHK(ctx, q);
+    } else {
+        hipError_t q = hipEventQuery(S->ev_verify);
+        if (q == hipErrorNotReady) return 2;
+        HIPCHK(ctx, q);
+    }
+    S->verifying = false;
+    const double rr = S->H.host_part[2];
+    if (rr <= S->thr) {
+        S->rk = sqrt(rr);
+        S->status = MGD_OK;
+        finish(S);
+        return 1;
+    }
+    // the recursion converged but f - A u did not: restart CG from the true
+    // residual now in r (and its cycle-type copy); a check queued beyond the
+    // converged one (a gated cycle's) is superseded by the next cycle's
+    int rc;
+    if ((rc = vec_fill_f64(ctx, S->H.scal + 7, 1, 1.0, S->stream))) return rc;
+    S->kq = S->k + 1;
+    S->k++;
+    if (S->ncyc >= S->op.max_cycles) {
+        S->k--;
+        S->rk = sqrt(rr);
+        S->status = MGD_ENOCONV;
+        finish(S);
+        return 1;
+    }
+    if ((rc = enqueue_cycle(S, false))) return rc;
+    return 0;
+}
+
+static int verify_begin(SolveState *S, bool blocking)
+{
+    mgd_hier &H = S->H;
+    int nparts = 0, rc;
+    if ((rc = outer_residual(&H, *S->sets[S->cur], S->u, S->f, S->r, &nparts, S->stream))) return rc;
+    if ((rc = check_sum(&H, nparts, 2, S->stream))) return rc;
+    HIPCHK(S->ctx, hipEventRecord(S->ev_verify, S->stream));
+    S->verifying = true;
+    return verify_finish(S, blocking);
+}
+
+
 int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, const mgd_solve_opts *op,
                 mgd_report *rep, hipStream_t stream)
 {
@@ -410,6 +470,7 @@ int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, c
     S->status = MGD_ENOCONV;
     S->done = false;
     S->parked = false;
+    S->verifying = false;
     S->spec = false;
     S->kq = 0;
     S->thr = 0.0;
@@ -527,6 +588,7 @@ static void finish(SolveState *S)
 int solve_step(SolveState *S, bool blocking)
 {
     if (S->done) return 1;
+    if (S->verifying) return verify_finish(S, blocking);
     if (S->parked) return await_publish(S, blocking);
     mgd_ctx *ctx = S->ctx;
     const mgd_solve_opts &op = S->op;
@@ -575,6 +637,8 @@ int solve_step(SolveState *S, bool blocking)
     }
     if (conv && S->ladder_done) {
         if (S->spec) S->ncyc--;  // the queued cycle made no update
+        S->spec = false;
+        if (!S->chk_true[S->k & 1]) return verify_begin(S, blocking);
         S->status = MGD_OK;
         finish(S);
         return 1;

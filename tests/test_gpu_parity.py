@@ -12,7 +12,7 @@ import torch
 
 import oracle as O
 import workload as W
-from _gpu_util import half_mask, rel_err
+from _gpu_util import assert_hist_close, half_mask, oracle_spread, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -97,9 +97,8 @@ def test_assemble_explicit_samples(ctx):
 def test_assemble_mixed_error_bound(ctx, d, name, s):
     """bf16 hi+lo eps on MFMA with FP32 accumulation: stated error against the
     FP64 oracle <= 2e-4 of the cell's largest entry (bf16 hi+lo keeps 16
-    significand bits of eps: ~2^-17 per sample, plus FP32 sums)."""
-    if d == 3 and s == 16:
-        pytest.skip("3D s=16 covered by the cell-list test")
+    significand bits of eps: ~2^-17 per sample, plus FP32 sums).  3D s = 16
+    takes the three-term split of the G table."""
     fld = (FIELDS_2D if d == 2 else FIELDS_3D)[name]()
     n = 12 if d == 2 else 5
     K, _, _ = P.assemble_cells(ctx, d, n, s, P.Eps(fld), P.MIXED)
@@ -133,6 +132,80 @@ def test_ladder_criterion_matches_oracle(ctx):
         np.testing.assert_allclose(r, rref, rtol=1e-10, atol=1e-13)
         clear = np.abs(rref - 0.01) > 1e-9
         assert (host(done)[clear] == (rref[clear] < 0.01)).all()
+
+
+def test_ladder_criterion_3d_matches_oracle(ctx):
+    d, n = 3, 6
+    fld = W.balls_field(3, 6, 11, r_lo=0.1, r_hi=0.3, eps_in=1e3)
+    Ke = P.Eps(fld)
+    for s in (2, 4, 8):
+        Kold, _, _ = P.assemble_cells(ctx, d, n, s // 2, Ke, P.FP64)
+        K, rel, done = P.assemble_cells(ctx, d, n, s, Ke, P.FP64, K_old=Kold, C_thr=0.01, want_rel=True)
+        A = O.assemble(fld, d, n, s)
+        B = O.assemble(fld, d, n, s // 2)
+        rref = np.abs(A - B).reshape(len(A), -1).max(1) / np.abs(B).reshape(len(B), -1).max(1)
+        r = host(rel)
+        np.testing.assert_allclose(r, rref, rtol=1e-10, atol=1e-15)
+        clear = np.abs(rref - 0.01) > 1e-9
+        assert (host(done)[clear] == (rref[clear] < 0.01)).all()
+        assert (rref < 0.01).any() and (rref >= 0.01).any()
+
+
+def test_ladder_criterion_hand_value_on_gpu(ctx):
+    """The interface cell of the CPU pin (2D, eps 1.02 left of the cell's
+    mid-plane, 1 from it on): rel(2) = 11 |e1 - e2| / (16 e2) = 0.01375 in
+    exact fractions; at C = 0.0137 the cell refines, at 0.0138 it is done."""
+    d, n, i = 2, 4, 1
+    e1, e2 = 1.02, 1.0
+    xm = (i + 0.5) / n
+    fld = W.Field(W.BOXES, d, p0=e1, count=1, data=np.array([xm, -1.0, 2.0, 2.0, e2]))
+    Ke = P.Eps(fld)
+    cells = dev(np.array([i], np.int64), torch.int64)
+    K1, _, _ = P.assemble_cells(ctx, d, n, 1, Ke, P.FP64, cells=cells)
+    for C_thr, want in ((0.0137, 0), (0.0138, 1)):
+        K2, rel, done = P.assemble_cells(ctx, d, n, 2, Ke, P.FP64, cells=cells, K_old=K1, C_thr=C_thr,
+                                         want_rel=True)
+        assert abs(float(host(rel)[0]) - 11.0 * 0.02 / 16.0) < 1e-14
+        assert int(host(done)[0]) == want
+
+
+def _mixed_ladder(ctx, d, n, fld, s_max, C_thr=0.01):
+    """s_final per cell of the mixed ladder as the solver runs it (bf16 hi+lo
+    MFMA rungs, criterion against the previous rung's FP32 matrices)."""
+    Ke = P.Eps(fld)
+    nc = n ** d
+    sf = np.full(nc, s_max)
+    K, _, _ = P.assemble_cells(ctx, d, n, 1, Ke, P.MIXED)
+    open_ = np.ones(nc, bool)
+    s = 2
+    while s <= s_max:
+        Kn, rel, done = P.assemble_cells(ctx, d, n, s, Ke, P.MIXED, K_old=K, C_thr=C_thr, want_rel=True)
+        dn = host(done).astype(bool)
+        newly = open_ & dn
+        sf[newly] = s
+        open_ &= ~dn
+        K = Kn
+        s *= 2
+    return sf
+
+
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
+def test_mixed_ladder_sfinal_disagreements(ctx, d, n):
+    """Reading R5: the mixed ladder (bf16 hi+lo integration) can take another
+    final s than the FP64 oracle only where the oracle's criterion is within
+    the mixed rel error of C; such cells are counted and must have an oracle
+    margin |rel - C| below 1e-3."""
+    fld = W.balls_field(d, 10, 4, r_lo=0.03 if d == 2 else 0.1, r_hi=0.2 if d == 2 else 0.35, eps_in=1e3)
+    s_max = 16 if d == 2 else 8
+    sf = _mixed_ladder(ctx, d, n, fld, s_max)
+    _, sref, relref = O.ladder(fld, d, n, s_max, 0.01)
+    diff = np.nonzero(sf != sref)[0]
+    print(f"{d}D {n}: {len(diff)} of {n ** d} cells take another final s in the mixed ladder")
+    for c in diff:
+        lo = int(min(sf[c], sref[c]))
+        k = int(math.log2(lo)) - 1  # the rung where the two ladders part
+        assert abs(relref[c, k] - 0.01) < 1e-3, (c, sf[c], sref[c], relref[c])
+    assert len(diff) <= max(2, n ** d // 500)
 
 
 # ------------------------------------------------------------ stencils
@@ -474,12 +547,12 @@ def test_solve_fp64_pcg_fused_levels_matches_oracle(ctx):
     fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
     f = W.load_sine(d, n)
     kw = dict(s_fixed=2, tol=1e-10)
-    u_ref, rr = O.solve(fld, d, n, f, transfer=O.BOXMG, outer=O.PCG, **kw)
+    (u_ref, rr), floor, us = oracle_spread(
+        lambda ff: O.solve(fld, d, n, ff, transfer=O.BOXMG, outer=O.PCG, **kw), f)
     u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), transfer=P.BOXMG, outer=P.PCG, **kw)
     assert rep["status"] == 0 and rr["status"] == 0
     assert rep["cycles"] == rr["cycles"]
-    np.testing.assert_allclose(rep["hist"], rr["hist"], rtol=1e-7, atol=1e-13)
-    assert rel_err(host(u), u_ref) < 1e-9
+    _check_solve(rep, rr, host(u), u_ref, floor, us, "pcg256")
 
 
 def _vcycle_rate(h, f, dtype):
@@ -578,58 +651,118 @@ def test_solve_store_paths_bit_identical(ctx, schedule):
 
 
 def test_mixed_vcycle_contracts(ctx):
-    """FP32 cycle on the compressed store: a preconditioner for the FP64
-    outer residual; its contraction must be close to the FP64 cycle's."""
+    """FP32 cycle on the compressed store (FP16 surplus): a preconditioner
+    for the FP64 outer residual, contracting like the oracle's FP64 cycle on
+    the same stencils.  The per-cycle residual ratio is taken over the first
+    three cycles (residual 1 -> ~4e-3), above the FP32 cycle's rounding floor
+    (~1e-5 of r_0 here, where f - A u cancels in FP32), and must be within
+    0.02 of the oracle's."""
     d, n = 2, 32
     fld = W.sine_field(2, 0.9)
     K = O.assemble(fld, d, n, 4)
     S = O.stencils(d, n, K)
     eps_c = np.array([O.element_matrix(fld, d, n, 1, c)[0, 0] / (2.0 / 3.0) for c in range(n * n)], np.float32)
+    f = W.load_const(d, n)
+    ref = O.Hierarchy(d, n, S)
+    u64 = np.zeros_like(f)
+    n64 = [O.norm_interior(d, n, O.residual(d, n, S, u64, f))]
+    for _ in range(3):
+        u64 = ref.vcycle(u64, f)
+        n64.append(O.norm_interior(d, n, O.residual(d, n, S, u64, f)))
+    rate64 = (n64[-1] / n64[0]) ** (1.0 / 3)
     h = P.Hierarchy(ctx, d, n, precision=P.MIXED)
     h.compress(dev(O.to_half(d, S), torch.float32), dev(eps_c, torch.float32), 2, 2, 0.0, 0.0)
     h.coarsen()
-    f = W.load_const(d, n)
     u = torch.zeros(h.nv(), dtype=torch.float32, device="cuda")
     ft = dev(f, torch.float32)
     r = torch.zeros_like(u)
-    norms = []
-    for _ in range(6):
+    h.residual(0, u, ft, r)
+    norms = [float(torch.linalg.norm(r.double()))]
+    for _ in range(3):
         h.vcycle(u, ft)
         h.residual(0, u, ft, r)
         norms.append(float(torch.linalg.norm(r.double())))
-    rate = (norms[-1] / norms[0]) ** (1.0 / 5)
-    assert rate < 0.3, rate
+    rate = (norms[-1] / norms[0]) ** (1.0 / 3)
+    print(f"mixed cycle rate {rate:.4f}, oracle FP64 {rate64:.4f}")
+    assert rate64 < 0.3
+    assert rate <= rate64 + 0.02, (rate, rate64)
 
 
 # ------------------------------------------------------------ solves
+# FP64 solves are compared with the oracle at the size of the oracle's own
+# response to a one-ulp change of the load vector (another summation order
+# makes differences of that size): histories to 1e-7 relative plus 100x that
+# spread at the rounding floor of the late checks, solutions to 100x the
+# spread of the oracle's solution (at least 1e-12).
+U_FACTOR = 100.0
+
+
+def _check_solve(rep, rr, u, u_ref, floor, us, label):
+    assert_hist_close(rep["hist"], rr["hist"], floor, label=label)
+    err = rel_err(u, u_ref)
+    print(f"{label} u: rel err {err:.3e}, oracle one-ulp spread {us:.3e}, ratio {err / us:.1f}")
+    assert err <= max(U_FACTOR * us, 1e-12), (err, us)
+
+
 def test_solve_c1_fp64_matches_oracle(ctx):
     """2D sine eps on 64x64 cells, s = 4, FP64 geometric V(2,2), omega 0.6,
     down to 3x3 vertices, residual reduced by 1e-10."""
     d, n = 2, 64
     fld = W.sine_field(2, 0.9)
     f = W.load_const(d, n)
-    u_ref, rep_ref = O.solve(fld, d, n, f, s_fixed=4, tol=1e-10)
+    (u_ref, rep_ref), floor, us = oracle_spread(lambda ff: O.solve(fld, d, n, ff, s_fixed=4, tol=1e-10), f)
     u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), s_fixed=4, tol=1e-10)
     assert rep["status"] == 0 and rep_ref["status"] == 0
     assert rep["cycles"] == rep_ref["cycles"]
-    # residual histories agree to 1e-8 relative down to the FP64 rounding floor
-    np.testing.assert_allclose(rep["hist"], rep_ref["hist"], rtol=1e-8, atol=1e-13)
-    assert rel_err(host(u), u_ref) < 1e-10
+    _check_solve(rep, rep_ref, host(u), u_ref, floor, us, "c1")
 
 
-def test_solve_lazy_deterministic_matches_oracle_schedule(ctx):
-    d, n = 2, 32
-    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+@pytest.mark.parametrize("start", ["carry", "best"])
+@pytest.mark.parametrize("d,n", [(2, 32), (3, 16)])
+def test_solve_lazy_deterministic_matches_oracle_schedule(ctx, d, n, start):
+    """Lazy schedule, rung k published before cycle k, against the oracle's
+    emulation of the same schedule; the iterate is carried over at each
+    operator change (the paper) or restarted by the optional rule."""
+    fld = W.balls_field(d, 8, 21, r_lo=0.03, r_hi=0.15 if d == 2 else 0.3, eps_in=1e3)
     f = W.load_const(d, n)
-    kw = dict(s_max=16, tol=1e-11)
-    u_ref, rr = O.solve(fld, d, n, f, lazy=True, transfer=O.BOXMG, outer=O.PCG, **kw)
+    kw = dict(s_max=16 if d == 2 else 8, tol=1e-11)
+    st = 0 if start == "carry" else 1
+    (u_ref, rr), floor, us = oracle_spread(
+        lambda ff: O.solve(fld, d, n, ff, lazy=True, transfer=O.BOXMG, outer=O.PCG, start=st, **kw), f)
     u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, publish=P.PUBLISH_DETERMINISTIC,
-                     transfer=P.BOXMG, outer=P.PCG, **kw)
+                     transfer=P.BOXMG, outer=P.PCG, start=st, **kw)
     assert rep["status"] == 0 and rr["status"] == 0
     assert rep["cycles"] == rr["cycles"]
     assert rep["cells_at_s"] == rr["cells_at_s"]
-    np.testing.assert_allclose(rep["hist"], rr["hist"], rtol=1e-7, atol=1e-13)
-    assert rel_err(host(u), u_ref) < 1e-9
+    _check_solve(rep, rr, host(u), u_ref, floor, us, f"lazy{d}d-{start}")
+
+
+@pytest.mark.parametrize("outer", ["stationary", "pcg"])
+@pytest.mark.parametrize("d,n,name", [(3, 16, "balls"), (3, 32, "balls"), (3, 16, "lattice"), (3, 32, "boxes")])
+def test_solve_3d_fp64_matches_oracle(ctx, d, n, name, outer):
+    """3D FP64 up-front solves end to end (ladder to s = 8, BoxMG hierarchy,
+    27-point V(2,2) with the 3D sweep, restriction, prolongation and tail
+    kernels, the outer residual, and for CG the product by recurrence)
+    against the oracle: same cycle count, histories and solution at the
+    oracle's own one-ulp spread."""
+    fld = {"balls": lambda: W.balls_field(3, 8, 3, r_lo=0.1, r_hi=0.4, eps_in=1e3),
+           "lattice": lambda: W.lattice_field(3, 8, 6, sigma=1.0),
+           "boxes": lambda: W.boxes_field(3, 24, 9)}[name]()
+    f = W.load_sine(d, n)
+    oc = O.PCG if outer == "pcg" else O.STATIONARY
+    kw = dict(s_max=8, tol=1e-10, max_cycles=100)
+    (u_ref, rr), floor, us = oracle_spread(lambda ff: O.solve(fld, d, n, ff, transfer=O.BOXMG, outer=oc, **kw), f)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), transfer=P.BOXMG, outer=oc, **kw)
+    assert rep["status"] == 0 and rr["status"] == 0
+    assert rep["cycles"] == rr["cycles"], (rep["cycles"], rr["cycles"])
+    assert rep["cells_at_s"] == rr["cells_at_s"]
+    _check_solve(rep, rr, host(u), u_ref, floor, us, f"3d-{name}{n}-{outer}")
+    # the reported final residual is the true FP64 residual of the solution
+    S = O.stencils(d, n, O.ladder(fld, d, n, 8, 0.01)[0])
+    r = O.residual(d, n, S, host(u), f)
+    rt = O.norm_interior(d, n, r)
+    assert rt <= (1e-10 + 1e-12) * rep["r0"], (rt, rep["r0"])
+    assert abs(rep["r_final"] - rt) <= 1e-12 * rep["r0"], (rep["r_final"], rt)
 
 
 @pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
@@ -683,21 +816,41 @@ def test_divergence_guard_only_for_stationary(ctx, precision):
     assert rp["status"] == P.OK
 
 
-def test_solve_mixed_error_against_fp64_oracle(ctx):
-    """Mixed form (bf16x2 MFMA integration, FP16 surplus store, FP32 cycle,
-    FP64 outer PCG) against the FP64 oracle solution of the same problem:
-    stated bound 2e-3 relative (operator perturbation from the bf16 hi+lo
-    integration and the FP16 deltas)."""
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
+def test_solve_mixed_error_against_fp64_oracle(ctx, d, n):
+    """Mixed form (bf16 hi+lo MFMA integration, FP16 surplus store, FP32
+    cycle, FP64 outer PCG) against the FP64 oracle's solution of the same
+    problem at a fixed s = 8, so that only precision differs: the error
+    comes from the bf16 hi+lo integration (~2^-17 relative per sample) and
+    the FP16 surplus (half an FP16 ulp of the scaled delta), amplified by the
+    operator's conditioning.  MEASURE-ME"""
+    fld = W.balls_field(d, 10, 4, r_lo=0.03 if d == 2 else 0.1, r_hi=0.2 if d == 2 else 0.35, eps_in=1e3)
+    f = W.load_sine(d, n)
+    u_ref, rr = O.solve(fld, d, n, f, s_fixed=8, tol=1e-12, transfer=O.BOXMG, outer=O.PCG)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), precision=P.MIXED, s_fixed=8,
+                     tol=1e-10, transfer=P.BOXMG, outer=P.PCG)
+    assert rep["status"] == 0
+    assert rep["r_final"] <= 1e-10 * rep["r0"]
+    err = rel_err(host(u), u_ref)
+    print(f"mixed vs FP64 oracle, {d}D {n}: {err:.3e}")
+    assert err < 5e-6, err
+
+
+def test_solve_mixed_lazy_error_against_fp64_oracle(ctx):
+    """The mixed lazy solve against the oracle's FP64 up-front solution: the
+    error adds the cells whose mixed ladder ends at another s (reading R5,
+    counted in test_mixed_ladder_sfinal_disagreements); MEASURE-ME"""
     d, n = 2, 64
     fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
     f = W.load_sine(d, n)
-    u_ref, rr = O.solve(fld, d, n, f, s_max=8, tol=1e-11, transfer=O.BOXMG, outer=O.PCG)
+    u_ref, rr = O.solve(fld, d, n, f, s_max=8, tol=1e-12, transfer=O.BOXMG, outer=O.PCG)
     u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), precision=P.MIXED, schedule=P.LAZY, s_max=8,
                      tol=1e-10, transfer=P.BOXMG, outer=P.PCG)
     assert rep["status"] == 0
-    assert rep["hist"][-1] <= 1e-10
+    assert rep["r_final"] <= 1e-10 * rep["r0"]
     err = rel_err(host(u), u_ref)
-    assert err < 2e-3, err
+    print(f"mixed lazy vs FP64 oracle: {err:.3e}")
+    assert err < 5e-5, err
 
 
 def test_solve_single_level_and_odd_sizes(ctx):

@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 import workload as W
+from _gpu_util import half_mask
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -283,6 +284,72 @@ def test_ladder_keeps_new_matrix_and_caps_at_smax():
     assert (sf == 8).any() and (sf == 2).any()
 
 
+def _interface_cell_field(d, n, i, e_left, e_right):
+    """Cell i of row 0 split at its mid-plane x = (i + 1/2) h: e_left below,
+    e_right from the plane on (the centre sample sits on the plane, so the
+    centre-sample matrix is e_right times the unit matrix)."""
+    xm = (i + 0.5) / n
+    row = [xm] + [-1.0] * (d - 1) + [2.0] * d + [e_right]
+    return W.Field(W.BOXES, d, p0=e_left, count=1, data=np.array(row))
+
+
+def test_ladder_criterion_hand_value():
+    """Sec. 5.2 criterion rel = |K_new - K_old|_max / |K_old|_max, refine while
+    rel >= C.  On the 2D interface cell (eps = e1 left of the mid-plane, e2
+    from it on) the rungs are, in exact fractions from the 1D integrals over
+    the half intervals (int (1-x)^2 = 7/24, int x(1-x) = 1/12, int x^2 = 1/24
+    on [0,1/2]):
+      K(1) = e2 Kref, |K(1)|_max = 2/3 e2 (the diagonal);
+      K(2) = e1 K_left + e2 K_right, K_left[0][0] = 11/24 the largest entry;
+      K(2) - K(1) = (e1 - e2) K_left, so rel(2) = |e1 - e2| (11/24)/(2/3 e2)
+                  = 11 |e1 - e2| / (16 e2);
+      K(4) = K(2) (even s resolve the plane), so rel(4) = 0.
+    With e1 = 1.02, e2 = 1: rel(2) = 0.01375, while the same difference
+    relative to the NEW matrix (max entry (11 e1 + 5 e2)/24) is
+    0.22/16.22 = 0.013564.  C = 0.0137 lies between: the paper's old-matrix
+    normalisation refines to s = 4, the new-matrix one would stop at s = 2.
+    At C = rel(2) exactly the inequality rel >= C refines (a <= test would
+    stop).  The kept matrix is the newest one (K(4))."""
+    d, n, i = 2, 4, 1
+    e1, e2 = 1.02, 1.0
+    fld = _interface_cell_field(d, n, i, e1, e2)
+    rel2 = 11.0 * abs(e1 - e2) / (16.0 * e2)
+    K, rel = np.zeros(16), np.zeros(4)
+    sf = O.lib().orc_ladder_cell(O._FieldRef(fld).ptr, d, n, i, 16, 0.0137, K, rel)
+    assert abs(rel[0] - rel2) < 1e-14
+    assert rel[1] < 1e-14
+    assert sf == 4
+    # kept matrix: e1 K_left + e2 K_right from the hand fractions (row 0)
+    row0 = np.array([11 * e1 + 5 * e2, -2 * (e1 + e2), -5 * e1 + e2, -4 * (e1 + e2)]) / 24.0
+    np.testing.assert_allclose(K.reshape(4, 4)[0], row0, rtol=0, atol=1e-15)
+    # just above rel(2): stops at s = 2
+    sf = O.lib().orc_ladder_cell(O._FieldRef(fld).ptr, d, n, i, 16, 0.0138, K, rel)
+    assert sf == 2
+    # the tie rel == C refines
+    c_tie = float(rel[0])
+    sf = O.lib().orc_ladder_cell(O._FieldRef(fld).ptr, d, n, i, 16, c_tie, K, rel)
+    assert sf == 4
+    sf = O.lib().orc_ladder_cell(O._FieldRef(fld).ptr, d, n, i, 16, np.nextafter(c_tie, 1.0), K, rel)
+    assert sf == 2
+
+
+def test_ladder_criterion_hand_value_3d():
+    """The same interface cell in 3D: K_left[0][0] = h (1/18 + 7/72 + 7/72)
+    = h/4 is the largest entry of K(2) - K(1) = (e1 - e2) K_left, and
+    |K(1)|_max = e2 h/3, so rel(2) = 3 |e1 - e2| / (4 e2).  With e1 = 0.5,
+    e2 = 1 that is 0.375; relative to the new matrix (max entry
+    h (e1/4 + e2/12)) it would be 0.6."""
+    d, n, i = 3, 4, 2
+    e1, e2 = 0.5, 1.0
+    fld = _interface_cell_field(d, n, i, e1, e2)
+    K, rel = np.zeros(64), np.zeros(4)
+    sf = O.lib().orc_ladder_cell(O._FieldRef(fld).ptr, d, n, i, 8, 0.5, K, rel)
+    assert abs(rel[0] - 0.375) < 1e-14
+    assert sf == 2
+    sf = O.lib().orc_ladder_cell(O._FieldRef(fld).ptr, d, n, i, 8, float(rel[0]), K, rel)
+    assert sf == 4 and rel[1] < 1e-14
+
+
 # ------------------------------------------------------------------ stencils
 @pytest.mark.parametrize("d,n", [(2, 4), (3, 3)])
 def test_stencils_are_rows_of_scatter_assembled_matrix(d, n):
@@ -507,25 +574,9 @@ def test_lazy_schedule_reaches_the_upfront_operator():
         assert np.abs(u[inner] - ue).max() < 1e-8 * np.abs(ue).max()
 
 
-def test_lazy_restart_takes_the_better_start():
-    """After an operator change the iteration continues from the carried
-    iterate or from the zero start (interior zeroed, boundary values kept),
-    whichever has the smaller residual on the new operator.  With u0 = 0 and a
-    zero boundary the zero start's residual is |f| = r_0: no check after a
-    publish exceeds 1, and a check where the zero start was taken reads
-    exactly 1.  That the rule has something to decide is checked apart: one
-    CG step on the centre-sample operator (built here from the oracle's
-    pieces) leaves a residual on the s = 2 operator far above |f|."""
-    d, n = 2, 32
-    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
-    f = W.load_sine(d, n)
-    kw = dict(s_max=16, tol=1e-10, transfer=O.BOXMG, outer=O.PCG)
-    u, rep = O.solve(fld, d, n, f, lazy=True, **kw)
-    h = rep["hist"]
-    assert rep["status"] == O.OK
-    assert all(h[k] <= 1.0 for k in range(1, 5))
-    assert h[1] == 1.0
-    # first cycle on the centre-sample operator, then the s = 2 operator's residual
+def _one_cg_step_on_centre_operator(d, n, fld, f):
+    """The iterate after one preconditioned CG step on the centre-sample
+    operator, built here from the oracle's pieces and dense algebra."""
     inner = _interior(d, n)
     S1 = O.stencils(d, n, O.assemble(fld, d, n, 1))
     H1 = O.Hierarchy(d, n, S1, transfer=O.BOXMG)
@@ -533,6 +584,69 @@ def test_lazy_restart_takes_the_better_start():
     Az = O.dense_matrix(d, n, S1) @ z[inner]
     u1 = np.zeros_like(f)
     u1[inner] = (z[inner] @ f[inner]) / (z[inner] @ Az) * z[inner]
+    return u1
+
+
+def test_lazy_start_carries_the_iterate_over():
+    """Default start after an operator change (Sec. 5.1-5.3): the iteration
+    continues from the carried iterate.  Deterministic schedule, CG outer,
+    centre-sample operator on a geometric hierarchy: cycle 0 is one CG step
+    on the centre-sample operator, then rung 1 (s = 2) is published, and the
+    residual of check 1 is the carried iterate's residual on the s = 2
+    operator, which is reproduced here from the oracle's pieces (one CG step
+    with the geometric provisional hierarchy) and lies far above r_0 for 1e3
+    inclusions."""
+    d, n = 2, 32
+    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=16, tol=1e-10, transfer=O.BOXMG, outer=O.PCG)
+    u, rep = O.solve(fld, d, n, f, lazy=True, start=0, **kw)
+    assert rep["status"] == O.OK
+    h = rep["hist"]
+    inner = _interior(d, n)
+    # cycle 0 on the provisional operator with its geometric hierarchy
+    S1 = O.stencils(d, n, O.assemble(fld, d, n, 1))
+    Hg = O.Hierarchy(d, n, S1)
+    ec = np.array([O.eps_at(fld, [((c % n) + 0.5) / n, ((c // n) + 0.5) / n]) for c in range(n * n)])
+    Hg.set_geometric(S1, ec)
+    z = Hg.vcycle(np.zeros_like(f), f)
+    Az = O.dense_matrix(d, n, S1) @ z[inner]
+    u1 = np.zeros_like(f)
+    u1[inner] = (z[inner] @ f[inner]) / (z[inner] @ Az) * z[inner]
+    # rung 1 published (every cell holds its s = 2 matrix): the carried
+    # iterate's residual on the s = 2 operator
+    S2 = O.stencils(d, n, O.assemble(fld, d, n, 2))
+    r2 = O.residual(d, n, S2, u1, f)
+    r0 = np.linalg.norm(f[inner])
+    assert abs(h[1] - np.linalg.norm(r2[inner]) / r0) < 1e-10 * h[1]
+    assert h[1] > 10.0
+    # the same run converges to the final operator's solution
+    K, sf, _ = O.ladder(fld, d, n, 16, 0.01)
+    A = O.dense_matrix(d, n, O.stencils(d, n, K))
+    ue = np.linalg.solve(A, f[inner])
+    assert np.abs(u[inner] - ue).max() < 1e-8 * np.abs(ue).max()
+
+
+def test_lazy_restart_rule_takes_the_better_start():
+    """The optional start rule (start = 1): after an operator change the
+    iteration continues from the carried iterate or from the zero start
+    (interior zeroed, boundary values kept), whichever has the smaller
+    residual on the new operator.  With u0 = 0 and a zero boundary the zero
+    start's residual is |f| = r_0: no check after a publish exceeds 1, and a
+    check where the zero start was taken reads exactly 1.  That the rule has
+    something to decide is checked apart: one CG step on the centre-sample
+    operator leaves a residual on the s = 2 operator far above |f|."""
+    d, n = 2, 32
+    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=16, tol=1e-10, transfer=O.BOXMG, outer=O.PCG, start=1)
+    u, rep = O.solve(fld, d, n, f, lazy=True, **kw)
+    h = rep["hist"]
+    assert rep["status"] == O.OK
+    assert all(h[k] <= 1.0 for k in range(1, 5))
+    assert h[1] == 1.0
+    inner = _interior(d, n)
+    u1 = _one_cg_step_on_centre_operator(d, n, fld, f)
     S2 = O.stencils(d, n, O.assemble(fld, d, n, 2))
     r2 = O.residual(d, n, S2, u1, f)
     assert np.linalg.norm(r2[inner]) > 10.0 * np.linalg.norm(f[inner])
@@ -624,6 +738,61 @@ def test_boxmg_weights_preserve_constants():
         np.testing.assert_allclose(A, A.T, atol=1e-12 * np.abs(A).max())
 
 
+def _ulp_perturb(a, rng):
+    return a + rng.choice([-1.0, 1.0], size=a.shape) * np.spacing(np.abs(a)) * (a != 0)
+
+
+def _boxmg_chain(d, n, S, rng=None):
+    """Weights and Galerkin products level by level from the oracle's pieces;
+    with rng, every level's weights and product are moved by one ulp (random
+    sign per entry) before the next level is built: the rounding of a
+    different but equally valid summation order, injected at every level."""
+    levels, weights, nl = [S], [], n
+    while nl % 2 == 0 and nl // 2 >= 2:
+        Pw = O.transfer_weights(d, nl, levels[-1], O.BOXMG)
+        if rng is not None:
+            Pw = _ulp_perturb(Pw, rng)
+        Sc = O.galerkin(d, nl, levels[-1], Pw)
+        if rng is not None:
+            Sc = _ulp_perturb(Sc, rng)
+        levels.append(Sc)
+        weights.append(Pw)
+        nl //= 2
+    return levels, weights
+
+
+def test_boxmg_chain_amplifies_rounding():
+    """Condition of a BoxMG Galerkin chain on a 1e3-contrast operator (3D,
+    32^3 cells, six balls): one-ulp changes injected into every level's
+    weights and product, i.e. rounding differences of the size any other
+    summation order makes, move the deepest level by far more than one ulp
+    (its weights divide by collapsed diagonals, and each level feeds the
+    next).  Measured: up to 7.7e-13
+    relative on the deepest (2^3) level, 2.1e-13 on its weights, against
+    ~1.7e-15 on the first coarse level.  A whole hierarchy
+    computed by another correct implementation is therefore compared at
+    1e-11 (level by level, from the same fine operator, the bound stays
+    1e-12).  Couplings with an interior endpoint are compared (those between
+    two boundary vertices never act)."""
+    d, n = 3, 32
+    fld = W.balls_field(d, 6, 8, r_lo=0.05, r_hi=0.3, eps_in=1e3)
+    S = O.stencils(d, n, O.assemble(fld, d, n, 4))
+    ref, wref = _boxmg_chain(d, n, S)
+    rng = np.random.default_rng(3)
+    m1, mdeep = half_mask(d, n // 2), half_mask(d, n >> (len(ref) - 1))
+    deep = first = wdeep = 0.0
+    for _ in range(3):
+        lev, wts = _boxmg_chain(d, n, S, rng)
+        a, b = O.to_half(d, ref[-1]), O.to_half(d, lev[-1])
+        deep = max(deep, np.abs(a - b)[mdeep].max() / np.abs(a[mdeep]).max())
+        a1, b1 = O.to_half(d, ref[1]), O.to_half(d, lev[1])
+        first = max(first, np.abs(a1 - b1)[m1].max() / np.abs(a1[m1]).max())
+        wdeep = max(wdeep, np.abs(wref[-1] - wts[-1]).max())
+    assert first < 1e-14
+    assert 1e-13 < deep < 1e-11, deep
+    assert 1e-14 < wdeep < 1e-12, wdeep
+
+
 def test_boxmg_galerkin_equals_dense_ptap_with_its_weights():
     d, n = 2, 8
     fld = W.balls_field(d, 5, 2, r_lo=0.1, r_hi=0.3, eps_in=100.0)
@@ -668,6 +837,27 @@ def test_pcg_outer_reaches_dense_solution_in_fewer_cycles():
     assert rp["cycles"] < rs["cycles"]
     for u in (us, up):
         assert np.abs(u[inner] - ue).max() < 1e-7 * np.abs(ue).max()
+
+
+def test_cg_stop_is_confirmed_with_the_true_residual():
+    """The stopping rule is on f - A u (Sec. 6).  CG's recursive residual
+    drifts from it by rounding; the reported final residual is f - A u of
+    the returned solution, computed here with the dense matrix, and it is
+    within the tolerance.  The two FP64 evaluations of f - A u (stencils and
+    dense rows) differ by rounding of order 1e-16 |A| |u| per entry, so they
+    are compared to 1e-12 r_0."""
+    d, n = 2, 32
+    fld = W.balls_field(2, 8, 21, r_lo=0.03, r_hi=0.15, eps_in=1e3)
+    f = W.load_sine(d, n)
+    for tol in (1e-8, 1e-10):
+        u, rep = O.solve(fld, d, n, f, s_max=8, tol=tol, transfer=O.BOXMG, outer=O.PCG)
+        assert rep["status"] == O.OK
+        K, _, _ = O.ladder(fld, d, n, 8, 0.01)
+        A = O.dense_matrix(d, n, O.stencils(d, n, K))
+        inner = _interior(d, n)
+        rt = np.linalg.norm(f[inner] - A @ u[inner])
+        assert abs(rep["r_final"] - rt) <= 1e-12 * rep["r0"]
+        assert rt <= tol * rep["r0"] * (1 + 1e-6)
 
 
 def test_divergence_guard():
