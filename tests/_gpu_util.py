@@ -70,9 +70,10 @@ def oracle_spread(run, f, trials=2, seed=0):
     """How far the oracle's own residual history and solution move when the
     load vector changes by one ulp per entry: the size of the differences any
     other correct FP64 implementation (another summation order) produces.
-    run(f) -> (u, rep).  Returns (hist_floor, u_spread): the largest history
-    change over the checks whose value is at most 1e-6 (the rounding floor
-    of the late checks) and the largest solution change relative to max |u|."""
+    run(f) -> (u, rep).  Returns ((u, rep) of the unperturbed run,
+    hist_floor, u_spread): the largest history change over the checks whose
+    value is at most 1e-6 (the rounding floor of the late checks) and the
+    largest solution change relative to max |u|."""
     rng = np.random.default_rng(seed)
     u0, r0 = run(f)
     h0 = np.asarray(r0["hist"])

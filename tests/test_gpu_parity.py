@@ -145,7 +145,9 @@ def test_ladder_criterion_3d_matches_oracle(ctx):
         B = O.assemble(fld, d, n, s // 2)
         rref = np.abs(A - B).reshape(len(A), -1).max(1) / np.abs(B).reshape(len(B), -1).max(1)
         r = host(rel)
-        np.testing.assert_allclose(r, rref, rtol=1e-10, atol=1e-15)
+        # cells of constant eps change only by the rounding of the two sums:
+        # there both sides' rel is noise of a few ulps
+        np.testing.assert_allclose(r, rref, rtol=1e-10, atol=1e-14)
         clear = np.abs(rref - 0.01) > 1e-9
         assert (host(done)[clear] == (rref[clear] < 0.01)).all()
         assert (rref < 0.01).any() and (rref >= 0.01).any()
@@ -542,11 +544,14 @@ def test_vcycles_fp64_fused_levels_match_oracle(ctx, transfer, n):
 
 def test_solve_fp64_pcg_fused_levels_matches_oracle(ctx):
     """PCG outer iteration whose V-cycle runs the fused finest-level kernels
-    (dot products formed inside the post-smoothing pass)."""
+    (dot products formed inside the post-smoothing pass).  Tolerance 1e-9:
+    on this 1e3-contrast operator FP64 evaluates f - A u only to about
+    1e-10 r_0 (the oracle's own true residual stalls there while its CG
+    recursion goes on falling), so 1e-10 is not attainable."""
     d, n = 2, 256
     fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
     f = W.load_sine(d, n)
-    kw = dict(s_fixed=2, tol=1e-10)
+    kw = dict(s_fixed=2, tol=1e-9)
     (u_ref, rr), floor, us = oracle_spread(
         lambda ff: O.solve(fld, d, n, ff, transfer=O.BOXMG, outer=O.PCG, **kw), f)
     u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), transfer=P.BOXMG, outer=P.PCG, **kw)
@@ -691,14 +696,17 @@ def test_mixed_vcycle_contracts(ctx):
 # ------------------------------------------------------------ solves
 # FP64 solves are compared with the oracle at the size of the oracle's own
 # response to a one-ulp change of the load vector (another summation order
-# makes differences of that size): histories to 1e-7 relative plus 100x that
-# spread at the rounding floor of the late checks, solutions to 100x the
-# spread of the oracle's solution (at least 1e-12).
+# makes differences of that size): histories to 1e-7 relative plus 10x that
+# spread at the rounding floor of the late checks (measured: up to 2x),
+# solutions to 100x the spread of the oracle's solution, at least 1e-12
+# (measured: up to 72x on 3D 32^3 balls with 20 stationary cycles, each
+# cycle adding rounding of its own where the perturbation enters once).
 U_FACTOR = 100.0
+H_FACTOR = 10.0
 
 
 def _check_solve(rep, rr, u, u_ref, floor, us, label):
-    assert_hist_close(rep["hist"], rr["hist"], floor, label=label)
+    assert_hist_close(rep["hist"], rr["hist"], floor, factor=H_FACTOR, label=label)
     err = rel_err(u, u_ref)
     print(f"{label} u: rel err {err:.3e}, oracle one-ulp spread {us:.3e}, ratio {err / us:.1f}")
     assert err <= max(U_FACTOR * us, 1e-12), (err, us)
@@ -823,7 +831,8 @@ def test_solve_mixed_error_against_fp64_oracle(ctx, d, n):
     problem at a fixed s = 8, so that only precision differs: the error
     comes from the bf16 hi+lo integration (~2^-17 relative per sample) and
     the FP16 surplus (half an FP16 ulp of the scaled delta), amplified by the
-    operator's conditioning.  MEASURE-ME"""
+    operator's conditioning.  Measured 2D 64^2: 1.0e-4, 3D 16^3: 2.9e-4;
+    bounds 3e-4 and 1e-3."""
     fld = W.balls_field(d, 10, 4, r_lo=0.03 if d == 2 else 0.1, r_hi=0.2 if d == 2 else 0.35, eps_in=1e3)
     f = W.load_sine(d, n)
     u_ref, rr = O.solve(fld, d, n, f, s_fixed=8, tol=1e-12, transfer=O.BOXMG, outer=O.PCG)
@@ -833,13 +842,14 @@ def test_solve_mixed_error_against_fp64_oracle(ctx, d, n):
     assert rep["r_final"] <= 1e-10 * rep["r0"]
     err = rel_err(host(u), u_ref)
     print(f"mixed vs FP64 oracle, {d}D {n}: {err:.3e}")
-    assert err < 5e-6, err
+    assert err < (3e-4 if d == 2 else 1e-3), err
 
 
 def test_solve_mixed_lazy_error_against_fp64_oracle(ctx):
     """The mixed lazy solve against the oracle's FP64 up-front solution: the
     error adds the cells whose mixed ladder ends at another s (reading R5,
-    counted in test_mixed_ladder_sfinal_disagreements); MEASURE-ME"""
+    counted in test_mixed_ladder_sfinal_disagreements: none here); measured
+    7.8e-6, bound 3e-5."""
     d, n = 2, 64
     fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
     f = W.load_sine(d, n)
@@ -850,7 +860,7 @@ def test_solve_mixed_lazy_error_against_fp64_oracle(ctx):
     assert rep["r_final"] <= 1e-10 * rep["r0"]
     err = rel_err(host(u), u_ref)
     print(f"mixed lazy vs FP64 oracle: {err:.3e}")
-    assert err < 5e-5, err
+    assert err < 3e-5, err
 
 
 def test_solve_single_level_and_odd_sizes(ctx):
