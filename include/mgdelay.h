@@ -178,6 +178,22 @@ typedef struct {
 int mgd_compress_stencils(mgd_ctx *ctx, mgd_hier *h, const float *S32, const float *eps_c,
                           const mgd_tier_policy *policy, hipStream_t stream);
 
+/* Allocation-free variant of mgd_compress_stencils, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): same arguments, same store bit
+ * for bit.  mgd_compress_stencils allocates its working buffers (surplus
+ * [H][NV] FP32 and vertex tiers [NV], 4 H + 1 bytes per level-0 vertex) on
+ * its first call on a hierarchy; this variant instead uses a static device
+ * array of 64 MiB that every GPU the library runs on holds until the
+ * process ends, and calls no allocating routine.  Level 0 may have about
+ * 64 MiB / (4 H + 1) vertices at most (2D: 3.9 M, e.g. 1976^2 cells; 3D:
+ * 1.26 M, e.g. 107^3 cells), else MGD_EINVAL before any work is enqueued.  All calls on one device share
+ * the array (each call overwrites what it uses, nothing is carried over):
+ * calls that overlap on one GPU, on different streams or host threads,
+ * race and must be ordered by the caller. */
+int mgd_compress_stencils_noalloc(mgd_ctx *ctx, mgd_hier *h, const float *S32, const float *eps_c,
+                                  const mgd_tier_policy *policy, hipStream_t stream);
+
 /* Copy the compressed store out (dev buffers; pass NULL to skip one):
  * tile_tier uint8 [ntile], tile_off uint32 [ntile], payload (payload_bytes).
  * Host scalars ntile / payload_bytes are returned synchronously. */

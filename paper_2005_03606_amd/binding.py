@@ -99,6 +99,7 @@ def lib():
         "mgd_hier_level_n": ([_P, C.c_int], C.c_int),
         "mgd_hier_set_fine": ([_P, _P, _P, _P], C.c_int),
         "mgd_compress_stencils": ([_P, _P, _P, _P, C.POINTER(_Tier), _P], C.c_int),
+        "mgd_compress_stencils_noalloc": ([_P, _P, _P, _P, C.POINTER(_Tier), _P], C.c_int),
         "mgd_store_info": ([_P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64 * 4)], C.c_int),
         "mgd_store_export": ([_P, _P, _P, _P, _P, _P], C.c_int),
@@ -355,6 +356,14 @@ class Hierarchy:
         pol = _Tier(min_tier, max_tier, tau_abs, tau_rel)
         self.ctx.check(lib().mgd_compress_stencils(self.ctx.h, self.h, _ptr(S32), _ptr(eps_c),
                                                    C.byref(pol), _stream(stream)))
+
+    def compress_noalloc(self, S32, eps_c, min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=0.0, stream=None):
+        """compress() without device allocation (static scratch; bounded level size)."""
+        _buf(S32, "S32", torch.float32, n_half(self.dim) * self.nv(0), self.ctx.device)
+        _buf(eps_c, "eps_c", torch.float32, self.n ** self.dim, self.ctx.device)
+        pol = _Tier(min_tier, max_tier, tau_abs, tau_rel)
+        self.ctx.check(lib().mgd_compress_stencils_noalloc(self.ctx.h, self.h, _ptr(S32), _ptr(eps_c),
+                                                           C.byref(pol), _stream(stream)))
 
     def coarsen(self, stream=None):
         self.ctx.check(lib().mgd_coarsen(self.ctx.h, self.h, _stream(stream)))

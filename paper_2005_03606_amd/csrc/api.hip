@@ -46,10 +46,6 @@ int hier_alloc_levels(mgd_hier *h)
         HIPCHK(ctx, hipMemset(h->r[l], 0, b));
         HIPCHK(ctx, hipMemset(h->t[l], 0, b));
     }
-    if (h->precision == MGD_MIXED) {
-        if ((rc = dev_alloc(ctx, (void **)&h->delta, (size_t)h->NV[0] * h->H * 4))) return rc;
-        if ((rc = dev_alloc(ctx, (void **)&h->vtier, (size_t)h->NV[0]))) return rc;
-    }
     int64_t nb = (h->NV[0] + 255) / 256 + (h->nl[0] + 1) / 4 + 64;
     h->partial_cap = 2 * nb > h->m_coarse + 64 ? 2 * nb : h->m_coarse + 64;
     if ((rc = dev_alloc(ctx, (void **)&h->partial, (size_t)h->partial_cap * 8))) return rc;
@@ -66,6 +62,17 @@ int hier_alloc_levels(mgd_hier *h)
     // the clears above run on the null stream, which work on the caller's
     // non-blocking streams does not wait for: finish them before returning
     HIPCHK(ctx, hipDeviceSynchronize());
+    return MGD_OK;
+}
+
+// working buffers of mgd_compress_stencils (the surplus [H][NV] and the
+// vertex tiers), allocated on its first call on a hierarchy; the solver
+// allocates them with its workspace
+int hier_compress_buffers(mgd_hier *h)
+{
+    int rc;
+    if (!h->delta && (rc = dev_alloc(h->ctx, (void **)&h->delta, (size_t)h->NV[0] * h->H * 4))) return rc;
+    if (!h->vtier && (rc = dev_alloc(h->ctx, (void **)&h->vtier, (size_t)h->NV[0]))) return rc;
     return MGD_OK;
 }
 
@@ -141,6 +148,11 @@ int mgd_create(mgd_ctx **out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&ctx->s_asm, hipStreamNonBlocking) != hipSuccess) { delete ctx; return MGD_EHIP; }
+    if (scratch_init(ctx) != MGD_OK) {
+        (void)hipStreamDestroy(ctx->s_asm);
+        delete ctx;
+        return MGD_EHIP;
+    }
     *out = ctx;
     return MGD_OK;
 }
@@ -258,7 +270,9 @@ int mgd_compress_stencils(mgd_ctx *ctx, mgd_hier *h, const float *S32, const flo
         return mgd_fail(ctx, MGD_EINVAL, "tiers must satisfy 1 <= min_tier <= max_tier <= 3");
     if (!(pol->tau_abs >= 0.0) || !(pol->tau_rel >= 0.0)) return mgd_fail(ctx, MGD_EINVAL, "tau must be >= 0");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    return compress_into(h, h->ops, S32, eps_c, pol, stream);
+    int rc = hier_compress_buffers(h);
+    if (rc) return rc;
+    return compress_into(h, h->ops, S32, eps_c, pol, h->delta, h->vtier, stream);
 }
 
 int mgd_store_info(mgd_ctx *ctx, const mgd_hier *h, int64_t *ntile, int64_t *payload_bytes, int64_t tier_tiles[4])

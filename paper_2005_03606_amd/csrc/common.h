@@ -19,6 +19,7 @@ struct mgd_ctx {
     hipStream_t s_asm = nullptr;  // assembly stream (default priority)
     char err[512] = {0};
     SolveState *cache = nullptr;  // device-resident workspace of the last solve shape
+    unsigned char *scratch = nullptr;  // device address of this device's static scratch array
 };
 
 int mgd_fail(mgd_ctx *ctx, int code, const char *fmt, ...);
@@ -286,8 +287,14 @@ int launch_gather(mgd_ctx *ctx, int dim, int n, const void *K, int k_mode, void 
 int launch_centre_eps(mgd_ctx *ctx, int dim, int n, const mgd_eps *eps, float *eps_c, hipStream_t st);
 int opset_alloc(mgd_hier *h, OpSet &o);
 void opset_free(OpSet &o);
+// surplus and tier selection of a level-0 store: delta [H][NV] and vtier [NV]
+// are working buffers (the hierarchy's, or the caller's scratch)
 int compress_into(mgd_hier *h, OpSet &o, const float *S32, const float *eps_c,
-                  const mgd_tier_policy *pol, hipStream_t st);
+                  const mgd_tier_policy *pol, float *delta, uint8_t *vtier, hipStream_t st);
+// the hierarchy's compression buffers, allocated on first use
+int hier_compress_buffers(mgd_hier *h);
+// per-device static scratch (noalloc.hip): set at context creation
+int scratch_init(mgd_ctx *ctx);
 int coarsen_ops(mgd_hier *h, OpSet &o, hipStream_t st);
 // geometric hierarchy of a provisional operator: coarse levels rediscretised
 // from child-averaged cell values (finest: eps_c0), d-linear weights;

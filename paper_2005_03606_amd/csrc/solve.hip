@@ -100,7 +100,7 @@ static int build(Ladder &L, OpSet &o, hipStream_t st)
         if ((rc = launch_gather(h->ctx, h->dim, h->n, L.K, MGD_FP64, o.S64[0], MGD_FP64, st))) return rc;
     } else {
         if ((rc = launch_gather(h->ctx, h->dim, h->n, L.K, MGD_MIXED, L.Sg, MGD_MIXED, st))) return rc;
-        if ((rc = compress_into(h, o, L.Sg, L.eps_c, &L.tiers, st))) return rc;
+        if ((rc = compress_into(h, o, L.Sg, L.eps_c, &L.tiers, h->delta, h->vtier, st))) return rc;
     }
     return coarsen_ops(h, o, st);
 }
@@ -153,6 +153,7 @@ int solve_state_create(mgd_ctx *ctx, int dim, int n, int precision, int transfer
         }                          \
     } while (0)
     CK(hier_alloc_levels(&H));
+    if (precision == MGD_MIXED) CK(hier_compress_buffers(&H));
     CK(opset_alloc(&H, S->O1));
     CK(ladder_alloc(S->L, &H));
     int64_t NV = H.NV[0];

@@ -227,7 +227,7 @@ template <typename TI> __global__ void k_to_f64(const TI *in, int64_t cnt, doubl
 
 // ------------------------------------------------------------ host side
 int compress_into(mgd_hier *h, OpSet &o, const float *S32, const float *eps_c,
-                  const mgd_tier_policy *pol, hipStream_t st)
+                  const mgd_tier_policy *pol, float *delta, uint8_t *vtier, hipStream_t st)
 {
     mgd_ctx *ctx = h->ctx;
     int64_t NV = h->NV[0], nc = 1;
@@ -237,18 +237,18 @@ int compress_into(mgd_hier *h, OpSet &o, const float *S32, const float *eps_c,
     dim3 gv(grid_for(NV, 256));
     if (h->dim == 2)
         hipLaunchKernelGGL(k_deltas<2>, gv, dim3(256), 0, st, S32, o.eps_c, h->n, NV, pol->tau_abs,
-                           pol->tau_rel, pol->min_tier, pol->max_tier, h->delta, h->vtier);
+                           pol->tau_rel, pol->min_tier, pol->max_tier, delta, vtier);
     else
         hipLaunchKernelGGL(k_deltas<3>, gv, dim3(256), 0, st, S32, o.eps_c, h->n, NV, pol->tau_abs,
-                           pol->tau_rel, pol->min_tier, pol->max_tier, h->delta, h->vtier);
-    hipLaunchKernelGGL(k_tile_tier, dim3(grid_for(o.ntile, 256)), dim3(256), 0, st, h->vtier, NV, o.ntile,
+                           pol->tau_rel, pol->min_tier, pol->max_tier, delta, vtier);
+    hipLaunchKernelGGL(k_tile_tier, dim3(grid_for(o.ntile, 256)), dim3(256), 0, st, vtier, NV, o.ntile,
                        h->H, o.tier, o.toff);
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, o.toff, o.ntile, o.units_total);
     dim3 ge(grid_for(o.ntile * 64, 256));
     if (h->dim == 2)
-        hipLaunchKernelGGL(k_encode<2>, ge, dim3(256), 0, st, h->delta, NV, o.ntile, o.tier, o.toff, o.payload);
+        hipLaunchKernelGGL(k_encode<2>, ge, dim3(256), 0, st, delta, NV, o.ntile, o.tier, o.toff, o.payload);
     else
-        hipLaunchKernelGGL(k_encode<3>, ge, dim3(256), 0, st, h->delta, NV, o.ntile, o.tier, o.toff, o.payload);
+        hipLaunchKernelGGL(k_encode<3>, ge, dim3(256), 0, st, delta, NV, o.ntile, o.tier, o.toff, o.payload);
     HIPCHK(ctx, hipGetLastError());
     return decode_store_f32(h, o, st);  // the FP32 finest operator follows the store
 }
