@@ -53,6 +53,7 @@ enum { MGD_UPFRONT = 0, MGD_LAZY = 1 };        /* assembly schedule */
 enum { MGD_PUBLISH_ASYNC = 0, MGD_PUBLISH_DETERMINISTIC = 1, MGD_PUBLISH_EVERY = 2 };
 enum { MGD_STORE_AUTO = 0, MGD_STORE_DECODE = 1, MGD_STORE_COPY = 2 }; /* finest-level source */
 enum { MGD_START_CARRY = 0, MGD_START_BEST = 1 }; /* iterate after an operator change */
+enum { MGD_CYCLE_V = 0, MGD_CYCLE_ADAFAC_PI = 1, MGD_CYCLE_ADAFAC_JAC = 2 }; /* correction cycle */
 
 typedef struct mgd_ctx mgd_ctx;   /* per-device context: streams, scratch */
 typedef struct mgd_hier mgd_hier; /* device-resident multigrid hierarchy */
@@ -290,6 +291,14 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * carried iterate unless its residual on the new operator exceeds that of
  * the zero start (interior set to zero, boundary values kept), and then
  * continues from the zero start (decided on the device).
+ * cycle: the correction applied per outer iteration.  MGD_CYCLE_V is the
+ * multiplicative V(nu1,nu2); MGD_CYCLE_ADAFAC_PI and MGD_CYCLE_ADAFAC_JAC are
+ * the additive adaFAC-x cycle of Sec. 4.1 eq. (mg:adaFAC-x): the residual
+ * restricted to every level, each level's damped Jacobi update minus an
+ * auxiliary coarse step (PI: injection and P; Jac: the prolongation smoothed
+ * by one damped Jacobi step and its transpose), exact coarsest solve, the
+ * updates summed through the prolongations.  The additive cycles need
+ * outer = MGD_STATIONARY (adaFAC-PI is not symmetric).
  * f (dev double [NV]) is the load vector; u (dev double [NV]) is the initial
  * guess on entry and the solution on return. */
 typedef struct {
@@ -299,7 +308,7 @@ typedef struct {
     double C, omega, tol, div_factor;
     mgd_tier_policy tiers;
     double prov_tol;
-    int32_t start, pad;
+    int32_t start, cycle;
 } mgd_solve_opts;
 
 #define MGD_HIST 512

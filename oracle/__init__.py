@@ -47,7 +47,7 @@ class Opts(C.Structure):
     _fields_ = [("s_fixed", C.c_int32), ("s_max", C.c_int32), ("lazy", C.c_int32),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("coarsest", C.c_int32),
                 ("max_cycles", C.c_int32), ("transfer", C.c_int32),
-                ("outer", C.c_int32), ("start", C.c_int32),
+                ("outer", C.c_int32), ("start", C.c_int32), ("cycle", C.c_int32), ("pad", C.c_int32),
                 ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
                 ("div_factor", C.c_double)]
 
@@ -120,6 +120,7 @@ def lib():
         L.orc_mg_level_stencils.restype = C.POINTER(C.c_double)
         L.orc_mg_destroy.argtypes = [C.c_void_p]
         L.orc_mg_vcycle.argtypes = [C.c_void_p, _D, _D, C.c_double, C.c_int, C.c_int]
+        L.orc_mg_adafac.argtypes = [C.c_void_p, _D, _D, C.c_double, C.c_int]
         L.orc_norm_interior.argtypes = [C.c_int, C.c_int, _D]
         L.orc_norm_interior.restype = C.c_double
         L.orc_solve.argtypes = [fp, C.c_int, C.c_int, _D, _D, C.POINTER(Opts), C.POINTER(Report)]
@@ -335,6 +336,12 @@ class Hierarchy:
         lib().orc_mg_set_geometric(self.h, np.ascontiguousarray(S0, dtype=np.float64).ravel(),
                                    np.ascontiguousarray(eps_c0, dtype=np.float64).ravel())
 
+    def adafac(self, u, f, omega=0.6, variant=1):
+        """One additive adaFAC cycle (variant 1: PI, 2: Jac) from u."""
+        u = np.array(u, dtype=np.float64, copy=True)
+        lib().orc_mg_adafac(self.h, u, np.ascontiguousarray(f, dtype=np.float64), omega, variant)
+        return u
+
     def vcycle(self, u, f, omega=0.6, nu1=2, nu2=2):
         u = np.array(u, dtype=np.float64, copy=True)
         lib().orc_mg_vcycle(self.h, u, np.ascontiguousarray(f, dtype=np.float64), omega, nu1, nu2)
@@ -343,13 +350,14 @@ class Hierarchy:
 
 def solve(fld, d, n, f, u0=None, s_fixed=0, s_max=16, lazy=False, C_thr=0.01, omega=0.6,
           nu1=2, nu2=2, coarsest=2, tol=1e-10, max_cycles=200, div_factor=100.0,
-          transfer=GEOMETRIC, outer=0, start=0):
+          transfer=GEOMETRIC, outer=0, start=0, cycle=0):
     """start: after an operator change 0 carries the iterate over (the
     paper), 1 takes the carried iterate or the zero start, whichever has the
-    smaller residual on the new operator."""
+    smaller residual on the new operator.  cycle: 0 multiplicative V(nu1,nu2),
+    1 additive adaFAC-PI, 2 adaFAC-Jac (stationary outer iteration)."""
     r = _FieldRef(fld)
     u = np.zeros(nvert(d, n)) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
-    op = Opts(s_fixed, s_max, int(lazy), nu1, nu2, coarsest, max_cycles, transfer, outer, start,
+    op = Opts(s_fixed, s_max, int(lazy), nu1, nu2, coarsest, max_cycles, transfer, outer, start, cycle, 0,
               C_thr, omega, tol, div_factor)
     rep = Report()
     st = lib().orc_solve(r.ptr, d, n, np.ascontiguousarray(f, dtype=np.float64), u,
@@ -424,6 +432,64 @@ def ladder_cells(fld, d, n, cells, s_max, C_thr):
         Ks.append(K.reshape(nl, nl))
         ss.append(s)
     return np.array(Ks), np.array(ss)
+
+
+def _paper_sigs(L):
+    if getattr(L, "_paper_set", False):
+        return
+    U8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+    fp = C.POINTER(_Field)
+    L.orc_ladder_cell_inc.argtypes = [fp, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_double, _D, _D]
+    L.orc_ladder_cell_inc.restype = C.c_int
+    L.orc_p3_encode.argtypes = [C.c_double, C.c_int, U8]
+    L.orc_p3_decode.argtypes = [U8, C.c_int]
+    L.orc_p3_decode.restype = C.c_double
+    L.orc_p3_choose.argtypes = [_D, C.c_int, C.c_double]
+    L.orc_p3_choose.restype = C.c_int
+    L.orc_paper_table.argtypes = [fp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _D]
+    L._paper_set = True
+
+
+def ladder_cell_inc(fld, d, n, cell, n_max, C_thr):
+    """The paper's n -> n + 1 ladder of one cell: (K_final, n_final, rel)."""
+    L = lib()
+    _paper_sigs(L)
+    K = np.zeros((1 << d) ** 2)
+    rel = np.full(max(n_max - 1, 1), np.nan)
+    s = L.orc_ladder_cell_inc(_FieldRef(fld).ptr, d, n, int(cell), n_max, C_thr, K, rel)
+    return K.reshape(1 << d, 1 << d), s, rel
+
+
+def p3_encode(x, p):
+    L = lib()
+    _paper_sigs(L)
+    out = np.zeros(8, np.uint8)
+    L.orc_p3_encode(float(x), int(p), out)
+    return out[:p].copy()
+
+
+def p3_decode(b, p):
+    L = lib()
+    _paper_sigs(L)
+    buf = np.zeros(8, np.uint8)
+    buf[:p] = b
+    return L.orc_p3_decode(buf, int(p))
+
+
+def p3_choose(surplus, tau):
+    L = lib()
+    _paper_sigs(L)
+    a = np.ascontiguousarray(surplus, dtype=np.float64).ravel()
+    return L.orc_p3_choose(a, a.size, tau)
+
+
+def paper_table(fld, d, n, C_thr, tau, cycles):
+    """Per cycle (max n, mean n, compression) of the paper's ladder and format."""
+    L = lib()
+    _paper_sigs(L)
+    out = np.zeros(3 * cycles)
+    L.orc_paper_table(_FieldRef(fld).ptr, d, n, C_thr, tau, cycles, out)
+    return out.reshape(cycles, 3)
 
 
 def pairs(d):

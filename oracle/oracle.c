@@ -266,6 +266,146 @@ void orc_ladder(const orc_field *f, int d, int N, int s_max, double C, double *K
                                      rel ? rel + c * 4 : NULL);
 }
 
+static int64_t npow(int n, int d);
+
+/* The paper's own ladder (Sec. 5.2) as its memory-footprint table applies
+ * it (Sec. 6.3): a cell goes from n to n + 1 samples per axis while the
+ * element matrix changes by C or more (relative to the old matrix, max
+ * norm); once a step changes it by less than C the cell keeps the matrix it
+ * had (the table's smooth case stores nothing beyond the n = 1 matrix);
+ * n_max ends it.  Returns the final n; rel[k] is the change at the step
+ * n = k + 1 -> k + 2.                                                       */
+int orc_ladder_cell_inc(const orc_field *f, int d, int N, int64_t c, int n_max, double C, double *K, double *rel)
+{
+    int nl = 1 << d, nn = nl * nl;
+    double Kn[64];
+    orc_element_matrix(f, d, N, 1, c, K);
+    int s = 1;
+    for (int m = 2; m <= n_max; ++m) {
+        orc_element_matrix(f, d, N, m, c, Kn);
+        double diff[64];
+        for (int i = 0; i < nn; ++i)
+            diff[i] = Kn[i] - K[i];
+        double r = maxabs(diff, nn) / maxabs(K, nn);
+        if (rel) rel[m - 2] = r;
+        if (r < C)
+            break;
+        memcpy(K, Kn, sizeof(double) * nn);
+        s = m;
+    }
+    return s;
+}
+
+/* ----------------------------------------- the paper's truncated format */
+/* Sec. 5.5: a datum in p bytes (2 <= p < 8) holds a sign bit, the leading
+ * m = 8 (p - 1) - 1 bits of the IEEE double's 52-bit fraction (truncated,
+ * the leading 1 implied) and one byte with the unbiased exponent as a
+ * signed char, clamped to [-128, 127]; p = 8 is the double itself.  Zero
+ * has no exponent: it is kept exact here (exponent byte -128, fraction 0,
+ * and a decoder that maps that pattern to 0).                              */
+void orc_p3_encode(double x, int p, uint8_t *out)
+{
+    if (p >= 8) { memcpy(out, &x, 8); return; }
+    uint64_t b;
+    memcpy(&b, &x, 8);
+    int sign = (int)(b >> 63);
+    int eb = (int)((b >> 52) & 0x7ff);
+    uint64_t frac = b & ((1ull << 52) - 1);
+    int e = eb - 1023;
+    if (x == 0.0) { e = -128; frac = 0; }
+    if (e < -128) e = -128;
+    if (e > 127) e = 127;
+    int m = 8 * (p - 1) - 1;
+    uint64_t mt = frac >> (52 - m);                     /* truncation */
+    uint64_t word = ((uint64_t)sign << m) | mt;         /* p - 1 bytes */
+    for (int k = 0; k < p - 1; ++k) out[k] = (uint8_t)(word >> (8 * k));
+    out[p - 1] = (uint8_t)(int8_t)e;
+}
+
+double orc_p3_decode(const uint8_t *in, int p)
+{
+    if (p >= 8) { double x; memcpy(&x, in, 8); return x; }
+    int m = 8 * (p - 1) - 1;
+    uint64_t word = 0;
+    for (int k = 0; k < p - 1; ++k) word |= (uint64_t)in[k] << (8 * k);
+    int sign = (int)(word >> m) & 1;
+    uint64_t mt = word & ((1ull << m) - 1);
+    int e = (int8_t)in[p - 1];
+    if (e == -128 && mt == 0) return sign ? -0.0 : 0.0;
+    double v = ldexp(1.0 + ldexp((double)mt, -m), e);
+    return sign ? -v : v;
+}
+
+/* bytes per entry for one cell's surplus (K - K(1)), Sec. 5.5: 0 (only the
+ * marker) when the surplus' Frobenius norm is below tau, else the fewest
+ * bytes p in 2..8 whose truncation error stays within tau in every entry  */
+int orc_p3_choose(const double *surplus, int nn, double tau)
+{
+    double fro = 0.0;
+    for (int i = 0; i < nn; ++i) fro += surplus[i] * surplus[i];
+    if (sqrt(fro) < tau) return 0;
+    for (int p = 2; p < 8; ++p) {
+        double err = 0.0;
+        uint8_t buf[8];
+        for (int i = 0; i < nn; ++i) {
+            orc_p3_encode(surplus[i], p, buf);
+            double dd = fabs(orc_p3_decode(buf, p) - surplus[i]);
+            if (dd > err) err = dd;
+        }
+        if (err <= tau) return p;
+    }
+    return 8;
+}
+
+/* Table memory-footprint of Sec. 6.3 for the paper's ladder, published one
+ * rung per cycle: in cycle k (k = 2 .. cycles) every unfinished cell tries
+ * n = k and keeps it unless it changed the matrix by less than C (then the
+ * cell is done with n = k - 1); out[k-1] = {max n, mean n, compression},
+ * compression =
+ * 2^d 2^d 8 bytes per cell over (1 marker byte + 2^d 2^d p bytes of its
+ * surplus over the n = 1 matrix) summed over the cells.                   */
+void orc_paper_table(const orc_field *f, int d, int N, double C, double tau, int cycles, double *out)
+{
+    int nl = 1 << d, nn = nl * nl;
+    int64_t nc = npow(N, d);
+    double *K = malloc(sizeof(double) * nc * nn), *K1 = malloc(sizeof(double) * nc * nn);
+    int *n = malloc(sizeof(int) * nc);
+    uint8_t *done = malloc(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        orc_element_matrix(f, d, N, 1, c, K1 + c * nn);
+        memcpy(K + c * nn, K1 + c * nn, sizeof(double) * nn);
+        n[c] = 1;
+        done[c] = 0;
+    }
+    for (int k = 1; k <= cycles; ++k) {
+        if (k >= 2)
+            for (int64_t c = 0; c < nc; ++c) {
+                if (done[c]) continue;
+                double Kn[64], diff[64];
+                orc_element_matrix(f, d, N, k, c, Kn);
+                for (int i = 0; i < nn; ++i) diff[i] = Kn[i] - K[c * nn + i];
+                double r = maxabs(diff, nn) / maxabs(K + c * nn, nn);
+                if (r < C) { done[c] = 1; continue; }  /* keeps K(k - 1) */
+                memcpy(K + c * nn, Kn, sizeof(double) * nn);
+                n[c] = k;
+            }
+        int nmax = 0;
+        double nsum = 0.0, bytes = 0.0;
+        for (int64_t c = 0; c < nc; ++c) {
+            double sur[64];
+            for (int i = 0; i < nn; ++i) sur[i] = K[c * nn + i] - K1[c * nn + i];
+            int p = orc_p3_choose(sur, nn, tau);
+            bytes += 1.0 + (double)nn * p;
+            if (n[c] > nmax) nmax = n[c];
+            nsum += n[c];
+        }
+        out[3 * (k - 1)] = nmax;
+        out[3 * (k - 1) + 1] = nsum / nc;
+        out[3 * (k - 1) + 2] = (double)nc * nn * 8.0 / bytes;
+    }
+    free(K); free(K1); free(n); free(done);
+}
+
 /* ------------------------------------------------------------ stencils */
 static int64_t npow(int n, int d)
 {
@@ -972,6 +1112,85 @@ void orc_mg_vcycle(orc_mg *g, double *u, const double *f, double omega, int nu1,
     memcpy(u, g->u[0], sizeof(double) * NV);
 }
 
+/* ------------------------------------------------- additive adaFAC-x cycle */
+/* Sec. 4.1, eq. (mg:adaFAC-x), written as a correction scheme on the same
+ * hierarchy: the fine residual r_0 = f - A_0 u is restricted to every level
+ * (r_l = R r_{l-1}); every level l above the coarsest computes its update
+ * at once from r_l alone,
+ *     e_l = S_l r_l - P~ S_{l+1} R~ r_l,     S_l = omega diag(A_l)^{-1},
+ * the second term an auxiliary coarse step that damps the update by what the
+ * concurrently running coarser levels will add; the coarsest level solves
+ * exactly; the updates are summed through the prolongations,
+ * u += sum_l P_0 .. P_{l-1} e_l.
+ * variant 1 (adaFAC-PI): R~ = injection (the fine value at the coarse
+ *   vertex), P~ = P;
+ * variant 2 (adaFAC-Jac): P~ = (I - S_l A_l) P, the prolongation smoothed
+ *   by one damped Jacobi step, and R~ = P~^T.                               */
+static void level_diag_scale(int d, int n, const double *S, const double *r, double omega, double *out)
+{
+    int64_t NV = npow(n + 1, d);
+    int vi[3], c = nst(d) / 2;
+    for (int64_t v = 0; v < NV; ++v)
+        out[v] = is_interior(d, n + 1, v, vi) ? omega * r[v] / S[(size_t)v * nst(d) + c] : 0.0;
+}
+
+void orc_mg_adafac(orc_mg *g, double *u, const double *f, double omega, int variant)
+{
+    int d = g->d, L = g->nlev;
+    int64_t NV0 = npow(g->n[0] + 1, d);
+    /* residuals of every level: g->r[l] */
+    orc_residual(d, g->n[0], g->S[0], u, f, g->r[0]);
+    for (int l = 1; l < L; ++l)
+        orc_restrict(d, g->n[l - 1], g->Pw[l - 1], g->r[l - 1], g->r[l]);
+    /* level updates: g->u[l] */
+    for (int l = 0; l < L - 1; ++l) {
+        int n = g->n[l], nc = g->n[l + 1];
+        int64_t NV = npow(n + 1, d), NVc = npow(nc + 1, d);
+        double *e = g->u[l], *a = g->f[l + 1], *t = g->t[l];
+        level_diag_scale(d, n, g->S[l], g->r[l], omega, e);          /* S_l r_l */
+        if (variant == 1) {
+            /* R~ r_l: the fine residual at each interior coarse vertex */
+            int Vi[3];
+            for (int64_t V = 0; V < NVc; ++V) {
+                if (!is_interior(d, nc + 1, V, Vi)) { a[V] = 0.0; continue; }
+                int wi[3];
+                for (int m = 0; m < d; ++m) wi[m] = 2 * Vi[m];
+                a[V] = g->r[l][vid(d, n + 1, wi)];
+            }
+            level_diag_scale(d, nc, g->S[l + 1], a, omega, a);       /* S_{l+1} R~ r_l */
+            for (int64_t V = 0; V < NVc; ++V) a[V] = -a[V];
+            orc_prolong_add(d, n, g->Pw[l], a, e);                    /* e -= P a */
+        } else {
+            /* R~ r = P^T (I - A D^{-1} omega) r */
+            double *y = malloc(sizeof(double) * NV), *w = malloc(sizeof(double) * NV);
+            level_diag_scale(d, n, g->S[l], g->r[l], omega, y);      /* y = S_l r */
+            orc_residual(d, n, g->S[l], y, g->r[l], w);               /* w = r - A y */
+            orc_restrict(d, n, g->Pw[l], w, a);                       /* a = R w */
+            level_diag_scale(d, nc, g->S[l + 1], a, omega, a);       /* a = S_{l+1} R~ r */
+            /* P~ a = (I - S_l A_l) P a */
+            memset(t, 0, sizeof(double) * NV);
+            orc_prolong_add(d, n, g->Pw[l], a, t);                    /* t = P a */
+            memset(y, 0, sizeof(double) * NV);
+            orc_residual(d, n, g->S[l], t, y, w);                     /* w = -A t */
+            level_diag_scale(d, n, g->S[l], w, omega, y);            /* y = -S_l A t */
+            int vi[3];
+            for (int64_t v = 0; v < NV; ++v)
+                if (is_interior(d, n + 1, v, vi)) e[v] -= t[v] + y[v];
+            free(y);
+            free(w);
+        }
+    }
+    /* coarsest level: exact solve of A_{L-1} e = r_{L-1} */
+    memcpy(g->f[L - 1], g->r[L - 1], sizeof(double) * npow(g->n[L - 1] + 1, d));
+    coarse_solve(g, L - 1);
+    /* u += sum_l P_0 .. P_{l-1} e_l, summed from the coarsest level up */
+    for (int l = L - 2; l >= 0; --l)
+        orc_prolong_add(d, g->n[l], g->Pw[l], g->u[l + 1], g->u[l]);
+    int vi[3];
+    for (int64_t v = 0; v < NV0; ++v)
+        if (is_interior(d, g->n[0] + 1, v, vi)) u[v] += g->u[0][v];
+}
+
 double orc_norm_interior(int d, int n, const double *r)
 {
     int64_t NV = npow(n + 1, d);
@@ -994,6 +1213,9 @@ typedef struct {
     int32_t outer;      /* 0 stationary (u += V r), 1 conjugate gradients with V as preconditioner */
     int32_t start;      /* after an operator change: 0 carry the iterate over (Sec. 5.1-5.3),
                            1 the carried iterate or the zero start, whichever has the smaller residual */
+    int32_t cycle;      /* 0 multiplicative V(nu1,nu2); 1 additive adaFAC-PI, 2 adaFAC-Jac (one cycle
+                           per iteration, stationary outer iteration only) */
+    int32_t pad;
     double C, omega, tol, div_factor;
 } orc_opts;
 
@@ -1151,7 +1373,8 @@ int orc_solve(const orc_field *fld, int d, int N, const double *f, double *u, co
         if (op->outer == 0 ? !(rk <= op->div_factor * r_ref) : !isfinite(rk)) { status = ORC_EDIVERGED; break; }
         if (k == op->max_cycles) break;
         if (op->outer == 0) {
-            orc_mg_vcycle(g, u, f, op->omega, op->nu1, op->nu2);
+            if (op->cycle == 0) orc_mg_vcycle(g, u, f, op->omega, op->nu1, op->nu2);
+            else orc_mg_adafac(g, u, f, op->omega, op->cycle);
             restart = 0;
             continue;
         }

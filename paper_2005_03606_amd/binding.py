@@ -17,6 +17,7 @@ UPFRONT, LAZY = 0, 1
 PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY = 0, 1, 2
 STORE_AUTO, STORE_DECODE, STORE_COPY = 0, 1, 2
 START_CARRY, START_BEST = 0, 1
+CYCLE_V, CYCLE_ADAFAC_PI, CYCLE_ADAFAC_JAC = 0, 1, 2
 EPS_SAMPLES = 6
 HIST = 512
 
@@ -53,7 +54,7 @@ class _SolveOpts(C.Structure):
                 ("max_cycles", C.c_int32), ("coarsest", C.c_int32), ("store_path", C.c_int32),
                 ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
                 ("div_factor", C.c_double), ("tiers", _Tier), ("prov_tol", C.c_double),
-                ("start", C.c_int32), ("pad", C.c_int32)]
+                ("start", C.c_int32), ("cycle", C.c_int32)]
 
 
 class _Report(C.Structure):
@@ -458,10 +459,10 @@ class Hierarchy:
 def solve_opts(precision=FP64, transfer=GEOMETRIC, outer=STATIONARY, schedule=UPFRONT,
                publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6, nu1=2, nu2=2,
                tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0, min_tier=2, max_tier=2,
-               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0, start=START_CARRY):
+               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0, start=START_CARRY, cycle=CYCLE_V):
     return _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
                       max_cycles, coarsest, store_path, C_thr, omega, tol, div_factor,
-                      _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol, start, 0)
+                      _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol, start, cycle)
 
 
 def _report_dict(rc, rep):

@@ -358,6 +358,9 @@ int vcycle_ops(mgd_hier *h, const OpSet &o, void *u, const void *f, double omega
                bool zero_guess, hipStream_t st, const Lev2Dots *dots = nullptr, void **result = nullptr,
                bool *dots_done = nullptr);
 bool lev2_ok(const mgd_hier *h, int l, int nu1, int nu2);
+// one additive adaFAC-x correction *result = B rhs (adafac.hip)
+int adafac_ops(mgd_hier *h, const OpSet &o, const void *rhs, double omega, int variant, void **result,
+               hipStream_t st);
 int lev2_pre(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *r_out,
              double omega, hipStream_t st);
 int lev2_prer(mgd_hier *h, const OpSet &o, int l, const void *u, const void *f, void *u_out, void *fc, double omega,

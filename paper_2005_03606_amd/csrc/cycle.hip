@@ -93,6 +93,93 @@ __global__ __launch_bounds__(256) void k_sweep(Op A, int n, const T *u, const T 
     }
 }
 
+// ---- 3D sweep and residual on the compressed finest store (mixed form).
+// A vertex's 26 couplings all lie in the 2 x 2 x 2 cells around it: the
+// centre-sample base of the coupling to v + o sums the samples of the cells
+// holding both (at most two with a nonzero unit coupling, so the order of
+// the sum does not matter), times k(o) h; the surplus of an upper slot sits
+// in v's tile, that of a lower slot in the tile of v - o.  Each coupling is
+// base + surplus in FP64, rounded once to FP32: the values of the store's
+// FP32 decode, applied in the same order as apply_row, so the results agree
+// bit for bit with the sweep that reads the decode.  Cells of a tier-0 tile
+// thus cost their centre samples only (4 bytes per cell instead of 52 per
+// vertex): the operator is re-evaluated from eps_c on the fly.
+__device__ inline void store3_couplings(const StoreView &sv, const Grid<3> &g, int64_t v, const int *x,
+                                        float *own, float *low)
+{
+#pragma clang fp contract(off)
+    const int n = g.n;
+    double e[8];
+    bool ok[8];
+#pragma unroll
+    for (int B = 0; B < 8; ++B) {
+        const int c0 = x[0] - (B & 1), c1 = x[1] - ((B >> 1) & 1), c2 = x[2] - (B >> 2);
+        ok[B] = c0 >= 0 && c0 < n && c1 >= 0 && c1 < n && c2 >= 0 && c2 < n;
+        e[B] = ok[B] ? (double)sv.eps_c[(int64_t)c0 + (int64_t)n * (c1 + (int64_t)n * c2)] : 0.0;
+    }
+    const double hp = 1.0 / (double)n;
+#pragma unroll
+    for (int j = 0; j < 13; ++j) {
+        const int o0 = half_off(3, j, 0), o1 = half_off(3, j, 1), o2 = half_off(3, j, 2);
+        const int nz = (o0 != 0) + (o1 != 0) + (o2 != 0);
+        // cells holding v and v + o (own) / v and v - o (low)
+        double so = 0.0, sl = 0.0;
+#pragma unroll
+        for (int B = 7; B >= 0; --B) {
+            const int b0 = B & 1, b1 = (B >> 1) & 1, b2 = B >> 2;
+            const bool sh_o = (unsigned)(b0 + o0) <= 1u && (unsigned)(b1 + o1) <= 1u && (unsigned)(b2 + o2) <= 1u;
+            const bool sh_l = (unsigned)(b0 - o0) <= 1u && (unsigned)(b1 - o1) <= 1u && (unsigned)(b2 - o2) <= 1u;
+            if (ok[B] && sh_o) so = so + e[B];
+            if (ok[B] && sh_l) sl = sl + e[B];
+        }
+        const double k = kref_unit(3, nz);
+        const int64_t lin = half_lin(3, j, g.nv);
+        own[j] = (float)((so * k) * hp + (double)sv.delta(v, j, 13));
+        low[j] = (float)((sl * k) * hp + (double)sv.delta(v - lin, j, 13));
+    }
+}
+
+// MODE 0: Jacobi sweep, MODE 1: residual (as k_sweep<3, ..., float>)
+template <int MODE, bool ZERO>
+__global__ __launch_bounds__(256) void k_sweep3_store(StoreView sv, int n, const float *u, const float *f, float *out,
+                                                     float omega)
+{
+    Grid<3> g(n);
+    int64_t v = block_index<3>() * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3];
+    g.coords(v, x);
+    if (!g.interior(x)) {
+        out[v] = 0.0f;
+        return;
+    }
+    float own[13], low[13];
+    store3_couplings(sv, g, v, x, own, low);
+    float Au, Dv;
+    if (ZERO) {
+        float dsum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 13; ++j) dsum += own[j] + low[j];
+        Dv = -dsum;
+        Au = 0.0f;
+    } else {
+        float acc = 0.0f, dsum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 13; ++j) {
+            const int64_t lin = half_lin(3, j, g.nv);
+            acc += own[j] * u[v + lin];
+            dsum += own[j];
+            acc += low[j] * u[v - lin];
+            dsum += low[j];
+        }
+        Dv = -dsum;
+        Au = Dv * u[v] + acc;
+    }
+    const float r = f[v] - Au;
+    if (MODE == 0) out[v] = (ZERO ? 0.0f : u[v]) + omega * r / Dv;
+    else out[v] = r;
+}
+
 __device__ inline double pw1c(int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; }
 
 template <int D, typename T, typename TW>
@@ -413,6 +500,16 @@ static inline void stage2_tiles(int n, int &ntx, int &nt)
 int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
 StoreView store_view(const mgd_hier *h, const OpSet &o);
 
+// the 3D mixed finest level decodes the compressed store per vertex only when
+// asked to (MGD_STORE_DECODE); by default it reads the FP32 decode (same
+// values, same results bit for bit), which is faster: the per-vertex decode
+// re-evaluates 26 couplings in FP64 for every vertex of every pass
+static bool store3_decode(const mgd_hier *h)
+{
+    if (h->dim != 3 || h->precision != MGD_MIXED) return false;
+    return h->store_path == MGD_STORE_DECODE;
+}
+
 template <int D, typename T>
 static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *f, T *out, double omega, int mode,
                    bool zero_guess, double *partial, hipStream_t st)
@@ -433,6 +530,17 @@ static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *
         if (mode == 1) hipLaunchKernelGGL((k_stage2<float, ST_RESID>), g2, dim3(256), 0, st, sa);
         else if (zero_guess) hipLaunchKernelGGL((k_stage2<float, ST_SWEEP0>), g2, dim3(256), 0, st, sa);
         else hipLaunchKernelGGL((k_stage2<float, ST_SWEEP>), g2, dim3(256), 0, st, sa);
+        HIPCHK(h->ctx, hipGetLastError());
+        return MGD_OK;
+    }
+    if (D == 3 && h->precision == MGD_MIXED && level == 0 && store3_decode(h) && !partial) {
+        // the mixed finest level streamed from HBM: decode the store per vertex
+        const StoreView sv = store_view(h, o);
+        const float *uf = (const float *)u, *ff = (const float *)f;
+        float *of = (float *)out;
+        if (mode == 1) hipLaunchKernelGGL((k_sweep3_store<1, false>), gr, dim3(256), 0, st, sv, n, uf, ff, of, (float)omega);
+        else if (zero_guess) hipLaunchKernelGGL((k_sweep3_store<0, true>), gr, dim3(256), 0, st, sv, n, uf, ff, of, (float)omega);
+        else hipLaunchKernelGGL((k_sweep3_store<0, false>), gr, dim3(256), 0, st, sv, n, uf, ff, of, (float)omega);
         HIPCHK(h->ctx, hipGetLastError());
         return MGD_OK;
     }
@@ -1464,6 +1572,51 @@ int pcg_dots(mgd_hier *h, const void *z, const double *r, const double *rold, hi
     return MGD_OK;
 }
 
+// k_p_matvec_rec on the 3D mixed finest store: the couplings decoded per
+// vertex as in k_sweep3_store (the same values as the FP32 decode, applied
+// in the same order, so the same bits)
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_p_matvec_rec_store(StoreView sv, int n, const TZ *z, const double *pold,
+                                                            double *pnew, double *Ap, CgScalars c, double *partial)
+{
+    __shared__ double red[256];
+    Grid<3> g(n);
+    const double zr = sum_partials(c.p1, c.n1, red), zdr = sum_partials(c.p1 + c.n1, c.n1, red);
+    const double beta = c.s[7] != 0.0 ? 0.0 : zdr / c.s[c.zr_old];
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[c.zr_new] = zr;
+    double prod = 0.0;
+    for (int64_t v = block_index<3>() * blockDim.x + threadIdx.x; v < g.NV; v += (int64_t)gridDim.x * blockDim.x) {
+        int x[3] = {0, 0, 0};
+        g.coords(v, x);
+        const double zv = (double)z[v];
+        const double pv = beta != 0.0 ? zv + beta * pold[v] : zv;
+        pnew[v] = pv;
+        if (g.interior(x)) {
+            float own[13], low[13];
+            store3_couplings(sv, g, v, x, own, low);
+            double acc = 0.0, dsum = 0.0;
+#pragma unroll
+            for (int j = 0; j < 13; ++j) {
+                const int64_t lin = half_lin(3, j, g.nv);
+                const double a = own[j];
+                acc += a * (double)z[v + lin];
+                dsum += a;
+                const double b = low[j];
+                acc += b * (double)z[v - lin];
+                dsum += b;
+            }
+            const double az = -dsum * zv + acc;
+            const double apv = beta != 0.0 ? az + beta * Ap[v] : az;
+            Ap[v] = apv;
+            prod += pv * apv;
+        } else {
+            Ap[v] = 0.0;
+        }
+    }
+    double sum = block_sum<256>(prod, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
 template <int D, typename TZ>
 static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *pold, double *pnew, double *Ap,
                         const CgScalars &c, hipStream_t st)
@@ -1475,6 +1628,9 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
         if (h->precision == MGD_FP64)
             hipLaunchKernelGGL((k_p_matvec_rec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
                                OpHalf<double>{o.S64[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
+        else if (store3_decode(h))
+            hipLaunchKernelGGL((k_p_matvec_rec_store<TZ>), dim3(grid), dim3(256), 0, st, store_view(h, o), h->n, z,
+                               pold, pnew, Ap, c, h->partial2);
         else
             hipLaunchKernelGGL((k_p_matvec_rec<D, OpHalf<float>, TZ>), dim3(grid), dim3(256), 0, st,
                                OpHalf<float>{o.S32[0], h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);

@@ -213,6 +213,9 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
     if (op->store_path < MGD_STORE_AUTO || op->store_path > MGD_STORE_COPY)
         return mgd_fail(ctx, MGD_EINVAL, "bad store_path");
     if (op->start != MGD_START_CARRY && op->start != MGD_START_BEST) return mgd_fail(ctx, MGD_EINVAL, "bad start");
+    if (op->cycle < MGD_CYCLE_V || op->cycle > MGD_CYCLE_ADAFAC_JAC) return mgd_fail(ctx, MGD_EINVAL, "bad cycle");
+    if (op->cycle != MGD_CYCLE_V && op->outer != MGD_STATIONARY)
+        return mgd_fail(ctx, MGD_EINVAL, "the additive adaFAC cycles need the stationary outer iteration");
     int sf = op->s_fixed, sm = op->s_max;
     if (sf > 0 && sf != 1 && sf != 2 && sf != 4 && sf != 8 && sf != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_fixed");
     if (sf <= 0 && sm != 1 && sm != 2 && sm != 4 && sm != 8 && sm != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_max");
@@ -276,9 +279,12 @@ static int enqueue_cycle(SolveState *S, bool gated)
     bool dots_done = false;
     int nparts = 0;
     Lev2Dots dots{S->r, S->rold, H.scal};
-    if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st, S->pcg ? &dots : nullptr, &z,
-                         &dots_done)))
+    if (op.cycle != MGD_CYCLE_V) {
+        if ((rc = adafac_ops(&H, O, rhs, op.omega, op.cycle, &z, st))) return rc;
+    } else if ((rc = vcycle_ops(&H, O, H.u[0], rhs, op.omega, op.nu1, op.nu2, true, st, S->pcg ? &dots : nullptr,
+                                &z, &dots_done))) {
         return rc;
+    }
     if (!S->pcg) {
         if ((rc = vec_add_cycle(&H, S->u, z, st))) return rc;
     } else {

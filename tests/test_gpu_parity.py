@@ -636,13 +636,55 @@ def test_store_paths_bit_identical(ctx, transfer, n):
         assert np.array_equal(a, b), k
 
 
+@pytest.mark.parametrize("n", [24, 72])
+def test_store_paths_bit_identical_3d(ctx, n):
+    """3D mixed finest level: the sweep that decodes the compressed store per
+    vertex (tier-0 couplings re-evaluated from the centre samples, FP8 / FP16
+    / FP32 surplus decoded) and the sweep that reads the store's FP32 decode
+    apply the same values in the same order: sweeps from zero and from a
+    given iterate, residuals and V-cycles agree bit for bit."""
+    d = 3
+    fld = W.balls_field(3, 10, 4, r_lo=0.08, r_hi=0.3, eps_in=1e3)
+    K, _, _ = P.assemble_cells(ctx, d, n, 4, P.Eps(fld), P.MIXED)
+    S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
+    eps_c = P.centre_samples(ctx, d, n, P.Eps(fld))
+    rng = np.random.default_rng(22)
+    inner = W.interior_mask(d, n)
+    f = dev(rng.standard_normal(inner.size) * inner, torch.float32)
+    u = dev(rng.standard_normal(inner.size) * inner, torch.float32)
+    outs = {}
+    for sp in (P.STORE_DECODE, P.STORE_COPY):
+        h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG, store_path=sp)
+        h.compress(S32, eps_c, 1, 3, 0.0, 1e-5)
+        h.coarsen()
+        tiers = h.store_info()[2]
+        res = []
+        for start in (None, u):
+            uo, ro = torch.zeros_like(f), torch.zeros_like(f)
+            h.presmooth(0, start, f, uo, ro)  # two sweeps (the first from zero) and the residual
+            res += [uo, ro]
+        z = u.clone()
+        h.smooth(0, z, f, sweeps=3)
+        res.append(z)
+        z = u.clone()
+        for _ in range(2):
+            h.vcycle(z, f)
+        res.append(z)
+        outs[sp] = [host(t) for t in res]
+        h.close()
+    assert sum(1 for t in tiers if t > 0) >= 3, tiers
+    for k, (a, b) in enumerate(zip(outs[P.STORE_DECODE], outs[P.STORE_COPY])):
+        assert np.array_equal(a, b), k
+
+
 @pytest.mark.parametrize("schedule", ["upfront", "lazy"])
-def test_solve_store_paths_bit_identical(ctx, schedule):
-    """A mixed PCG solve (fused pre and post halves with the dot partials,
-    fused CG product) gives the same history and solution bit for bit with
-    the finest operator decoded from the store or read as its FP32 decode."""
-    d, n = 2, 96
-    fld = W.balls_field(2, 10, 4, r_lo=0.03, r_hi=0.2, eps_in=1e3)
+@pytest.mark.parametrize("d,n", [(2, 96), (3, 24)])
+def test_solve_store_paths_bit_identical(ctx, schedule, d, n):
+    """A mixed PCG solve (2D: fused pre and post halves with the dot
+    partials, fused CG product; 3D: store-decoding sweeps and CG product)
+    gives the same history and solution bit for bit with the finest operator
+    decoded from the store or read as its FP32 decode."""
+    fld = W.balls_field(d, 10, 4, r_lo=0.03 if d == 2 else 0.08, r_hi=0.2 if d == 2 else 0.3, eps_in=1e3)
     f = dev(W.load_sine(d, n))
     kw = dict(s_max=8, tol=1e-9, transfer=P.BOXMG, outer=P.PCG, precision=P.MIXED, min_tier=1, max_tier=3,
               tau_rel=1e-6, schedule=P.UPFRONT if schedule == "upfront" else P.LAZY,
@@ -1020,3 +1062,43 @@ def test_repeated_solves_reuse_workspace_bitwise(ctx):
     kw = dict(s_max=8, tol=1e-9, transfer=P.BOXMG, outer=P.PCG, precision=P.MIXED)
     outs = [P.solve(ctx, d, n, P.Eps(fld), f, schedule=P.UPFRONT, **kw)[0] for _ in range(2)]
     assert torch.equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------ adaFAC-x
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("d,n,name,transfer", [(2, 64, "sine", 0), (2, 64, "sine", 1), (2, 32, "balls", 1)])
+def test_adafac_solve_matches_oracle(ctx, variant, d, n, name, transfer):
+    """Stationary iteration with the additive adaFAC-x correction (Sec. 4.1;
+    1: adaFAC-PI in two launches over all levels, 2: adaFAC-Jac) against the
+    oracle's: same cycle count, histories and solution at the oracle's
+    one-ulp spread.  2D: the oracle measures adaFAC-PI at 0.52-0.62 per
+    cycle and adaFAC-Jac at 0.93-0.95 here (tolerances 1e-10 and 1e-8); in
+    3D with omega = 0.6 both diverge on the balls material."""
+    fld = W.sine_field(d, 0.9) if name == "sine" else W.balls_field(d, 8, 3, r_lo=0.1, r_hi=0.3, eps_in=1e3)
+    f = W.load_sine(d, n)
+    kw = dict(s_fixed=4, tol=1e-10 if variant == 1 else 1e-8, max_cycles=500)
+    (u_ref, rr), floor, us = oracle_spread(
+        lambda ff: O.solve(fld, d, n, ff, transfer=transfer, cycle=variant, **kw), f)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), transfer=transfer, cycle=variant, **kw)
+    assert rr["status"] == 0, rr["status"]
+    assert rep["status"] == 0 and rep["cycles"] == rr["cycles"], (rep["cycles"], rr["cycles"])
+    _check_solve(rep, rr, host(u), u_ref, floor, us, f"adafac{variant}-{d}d-{name}{n}")
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_adafac_mixed_solve_error(ctx, variant):
+    """The mixed form with the adaFAC correction (FP32 cycle on the store's
+    decode, FP64 outer residual) reaches the tolerance on the operator it
+    solves; its distance to the FP64 oracle's solution is stated (FP16
+    surplus store, same bound as the V-cycle's)."""
+    d, n = 2, 64
+    fld = W.sine_field(2, 0.9)
+    f = W.load_sine(d, n)
+    u_ref, rr = O.solve(fld, d, n, f, s_fixed=4, tol=1e-12, transfer=O.BOXMG, outer=O.PCG)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), precision=P.MIXED, s_fixed=4, tol=1e-8, transfer=P.BOXMG,
+                     cycle=variant, max_cycles=500)
+    assert rep["status"] == 0, rep["status"]
+    assert rep["r_final"] <= 1e-8 * rep["r0"]
+    err = rel_err(host(u), u_ref)
+    print(f"adafac{variant} mixed vs FP64 oracle: {err:.3e} in {rep['cycles']} cycles")
+    assert err < 3e-4, err
