@@ -43,12 +43,13 @@ WORKLOAD = ("3D 512^3 Q1 cells (27-point stencils), eps=1 + 512 seeded boxes (si
 TIERS_C5 = dict(min_tier=1, max_tier=3, tau_abs=0.0, tau_rel=1e-6)
 TIERS_FP16 = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
 FORMS = ("mixed_lazy", "mixed_lazy_parked", "mixed_upfront", "fp64_upfront")
-# the roofline kernel: one damped-Jacobi sweep of the 3D mixed finest level,
-# decoding the compressed store per vertex; its traffic record (counter runs
-# of `bench.py --kernels-only`) is valid only for the source it was taken on
-SWEEP_KERNEL = "k_sweep3_store<0, false>"
+# the roofline kernel: one damped-Jacobi sweep of the 3D mixed finest level
+# as the solve runs it (the FP32 decode of the store, four vertices per
+# thread); its traffic record (counter runs of `bench.py --kernels-only`) is
+# valid only for the source it was taken on
+SWEEP_KERNEL = "k_sweep3x4<float, 0, false>"
 KERNEL_SOURCES = ("paper_2005_03606_amd/csrc/cycle.hip", "paper_2005_03606_amd/csrc/common.h")
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep3_store_boxes512_traffic.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep3x4_boxes512_traffic.md")
 
 
 def parse():
@@ -194,16 +195,18 @@ def recorded_traffic(n):
 
 def sweep_roofline(P, W, n, sweeps):
     """One damped-Jacobi sweep of the mixed finest level of the headline
-    workload (3D 512^3 boxes, the final operator of the adaptive ladder in
-    the dynamic-tier store), the kernel that moves most of the mixed cycle's
-    bytes: the couplings of a tier-0 tile are re-evaluated from the centre
-    samples, stored surplus is decoded per vertex.  Timed with HIP events on
-    the stream the kernels run on, same kernel and launch shape as in the
-    solve.
+    workload (3D 512^3 boxes, the final operator of the adaptive ladder), the
+    kernel that moves most of the mixed cycle's bytes, with the solve's
+    operator source and launch shape: the FP32 decode of the compressed
+    store, four vertices per thread.  Timed with HIP events on the stream the
+    kernels run on.
 
     Algorithmic bytes per launch (one stencil pass over every vertex): the
-    store (payload of the FP8 / FP16 / FP32 tiles + tier byte and offset per
-    64-vertex tile + FP32 centre sample per cell) + FP32 u in, f in, u out."""
+    13 FP32 couplings of the half stencil (52 B) + FP32 u in, f in, u out
+    (12 B) per vertex.  `store_form_frac` prices the same time against the
+    bytes of the compressed store itself (payload + tier byte and offset per
+    64-vertex tile + FP32 centre sample per cell), the least any sweep of
+    this operator must read."""
     import torch
     d = 3
     ctx = P.Context(0)
@@ -212,14 +215,14 @@ def sweep_roofline(P, W, n, sweeps):
     S32 = P.gather_stencils(ctx, d, n, K, P.MIXED, P.MIXED)
     del K
     eps_c = P.centre_samples(ctx, d, n, eps)
-    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG, store_path=P.STORE_DECODE)
+    h = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
     h.compress(S32, eps_c, **TIERS_C5)
     del S32
     torch.cuda.empty_cache()
     ntile, payload, tier_tiles = h.store_info()
     NV = (n + 1) ** d
-    stencil_bytes = payload + 5 * ntile + 4 * n ** d
-    pass_bytes = stencil_bytes + 12 * NV
+    pass_bytes = 64 * NV
+    store_pass_bytes = payload + 5 * ntile + 4 * n ** d + 12 * NV
     inner = torch.from_numpy(W.interior_mask(d, n)).cuda()
     f32 = inner.to(torch.float32)
     u32 = torch.zeros_like(f32)
@@ -240,9 +243,11 @@ def sweep_roofline(P, W, n, sweeps):
     achieved = pass_bytes / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(n),
-            "kernel": SWEEP_KERNEL, "bytes_per_launch": int(pass_bytes),
-            "bytes_per_dof": round(pass_bytes / NV, 3), "avg_launch_us": round(avg_ms * 1e3, 2),
-            "launches_timed": 2 * calls, "store_tiers_0_fp8_fp16_fp32": tier_tiles,
+            "kernel": SWEEP_KERNEL, "bytes_per_launch": int(pass_bytes), "bytes_per_dof": 64,
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": 2 * calls,
+            "store_form_bytes_per_launch": int(store_pass_bytes),
+            "store_form_frac": round(store_pass_bytes / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "store_tiers_0_fp8_fp16_fp32": tier_tiles,
             "workload": f"finest level of the headline workload ({n}^3 cells), final ladder operator"}
 
 

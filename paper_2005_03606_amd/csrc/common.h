@@ -76,6 +76,41 @@ template <int D> __device__ inline int64_t block_index()
     return D == 3 ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
 }
 
+// 3D work items of four consecutive vertices of a grid row, x0 = 1 + 4c
+// .. x0 + 3, on grids with n % 4 == 0: a row's vertices 1..n are then
+// exactly n/4 items (vertex 0 goes with the row's first item; vertex n, on
+// the boundary, is its last item's fourth).  The items go to the XCDs by
+// slabs of rows: the blocks b with b mod 8 == k take the k-th eighth of the
+// y range, plane after plane, so the plane below an item was read by the
+// same XCD shortly before and its L2 still holds it (a slab plane of a
+// 512^3 grid is 64 x 513 vertices; a whole plane would not fit).  Item i of
+// XCD k: c = i mod T, then the slab's row, then the plane.
+__host__ __device__ constexpr bool items4_fit(int D, int n) { return D == 3 && n % 4 == 0 && n >= 4 && n <= 4096; }
+
+__device__ inline bool items4_at(int n, uint32_t i, uint32_t k, uint32_t &x0, uint32_t &y, uint32_t &z)
+{
+    const uint32_t nv = (uint32_t)n + 1u, T = (uint32_t)n >> 2;
+    const uint32_t base = nv >> 3, rem = nv & 7u;
+    const uint32_t rows = base + (k < rem ? 1u : 0u), y0 = k * base + (k < rem ? k : rem);
+    if (i >= T * rows * nv) return false;
+    const uint32_t t = i / T;
+    x0 = 1u + 4u * (i - t * T);
+    z = t / rows;
+    y = y0 + (t - z * rows);
+    return true;
+}
+
+// blocks of 256 threads for one item per thread (a multiple of 8)
+static inline unsigned items4_blocks(int n)
+{
+    const int64_t nv = n + 1, rows_max = nv / 8 + (nv % 8 != 0);
+    return (unsigned)(8 * (((int64_t)(n / 4) * rows_max * nv + 255) / 256));
+}
+
+template <typename T> __device__ inline void ldv4(const T *p, T *o) { __builtin_memcpy(o, p, 4 * sizeof(T)); }
+template <typename T> __device__ inline void ldv2(const T *p, T *o) { __builtin_memcpy(o, p, 2 * sizeof(T)); }
+template <typename T> __device__ inline void stv4(T *p, const T *o) { __builtin_memcpy(p, o, 4 * sizeof(T)); }
+
 template <int D> struct Grid {
     int n;      // cells per axis
     int64_t nv; // vertices per axis

@@ -1095,3 +1095,101 @@ def test_level_compression_respects_tolerance():
                     assert abs(got - float(delta)) <= abs(float(delta)) * 2.0 ** -11 + 2.0 ** (int(e8[v]) - 127 - 24)
         if tmin == 1:
             assert (tt == 0).any()  # cells away from the balls store nothing
+
+
+# ------------------------------------------- paper mode: n -> n + 1, p3 bytes
+def test_p3_format_hand_bytes():
+    """Sec. 5.5 format with p = 2: sign bit, 7 truncated fraction bits, one
+    signed-char exponent byte.  -3 = -1.5 * 2^1: fraction .1000000, so the
+    first byte is 1 (sign) 1000000 = 0xC0 and the exponent byte is 1.
+    1/3 = 1.0101010 01.. * 2^-2 keeps .0101010 = 42/128: the decoded value is
+    (1 + 42/128) / 4 = 0.33203125 and the exponent byte is -2 = 0xFE."""
+    assert list(O.p3_encode(-3.0, 2)) == [0xC0, 0x01]
+    assert O.p3_decode(O.p3_encode(-3.0, 2), 2) == -3.0
+    assert list(O.p3_encode(1.0 / 3.0, 2)) == [0x2A, 0xFE]
+    assert O.p3_decode(O.p3_encode(1.0 / 3.0, 2), 2) == 0.33203125
+    # p = 3: fifteen fraction bits of 1/3 are 010101010101010 = 0x2AAA
+    assert list(O.p3_encode(1.0 / 3.0, 3)) == [0xAA, 0x2A, 0xFE]
+    assert O.p3_decode(O.p3_encode(1.0 / 3.0, 3), 3) == (1 + 0x2AAA / 2**15) / 4
+
+
+def test_p3_format_truncates_toward_zero_within_one_ulp():
+    rng = np.random.default_rng(7)
+    xs = rng.standard_normal(400) * np.exp(rng.uniform(-30, 30, 400))
+    for p in range(2, 8):
+        m = 8 * (p - 1) - 1
+        for x in xs:
+            y = O.p3_decode(O.p3_encode(x, p), p)
+            e = math.frexp(abs(x))[1] - 1          # x = 1.f * 2^e
+            assert math.copysign(1.0, y) == math.copysign(1.0, x)
+            assert abs(y) <= abs(x)                # truncation, never rounding up
+            assert abs(x) - abs(y) < 2.0 ** (e - m)
+            if p == 7:                              # 47 bits: one float64 step away
+                assert abs(x - y) <= abs(x) * 2.0 ** -47
+
+
+def test_p3_format_zero_double_and_exponent_clamp():
+    for p in range(2, 8):
+        assert O.p3_decode(O.p3_encode(0.0, p), p) == 0.0
+    x = 0.123456789012345
+    assert O.p3_decode(O.p3_encode(x, 8), 8) == x     # p = 8 is the double itself
+    b = O.p3_encode(2.0 ** 200, 3)
+    assert b[-1] == 0x7F                               # exponent clamped to 127
+    b = O.p3_encode(2.0 ** -300, 3)
+    assert b[-1] == 0x80                               # ... and to -128
+
+
+def test_p3_choose_picks_fewest_bytes_within_tau():
+    """p3 = 0 when the surplus' Frobenius norm is below tau; else the fewest
+    bytes whose truncation keeps every entry within tau.  For 1/3 the p = 2
+    error is 1/3 - 0.33203125 = 1.3e-3, the p = 3 error is below 2^-17."""
+    assert O.p3_choose(np.full(16, 1e-10), 1e-8) == 0          # norm 4e-10
+    assert O.p3_choose(np.full(16, 1e-8), 1e-8) != 0           # norm 4e-8
+    s = np.zeros(16)
+    s[5] = 1.0 / 3.0
+    assert O.p3_choose(s, 2e-3) == 2
+    assert O.p3_choose(s, 1e-3) == 3
+    assert O.p3_choose(s, 1e-20) == 8                          # beyond 47 bits
+
+
+def test_paper_ladder_keeps_the_older_matrix_on_convergence():
+    """n -> n + 1 ladder: a cell stops at the first n whose successor n + 1
+    changed the matrix by less than C and keeps K(n), not K(n + 1)."""
+    fld = W.balls_field(2, 6, 11, r_lo=0.05, r_hi=0.2)
+    N, n_max, C = 8, 6, 0.01
+    stops = set()
+    for c in range(N * N):
+        K, s, rel = O.ladder_cell_inc(fld, 2, N, c, n_max, C)
+        np.testing.assert_array_equal(K, O.element_matrix(fld, 2, N, s, c).reshape(4, 4))
+        for j in range(s - 1):                 # n = j + 2 against n = j + 1
+            assert rel[j] >= C
+        if s < n_max:
+            assert rel[s - 1] < C
+        stops.add(s)
+    assert 1 in stops and len(stops) > 1
+
+
+def test_paper_table_theta1_row_exact():
+    """Table memory-footprint, theta = 1 columns, every cycle: no cell ever
+    leaves n = 1 and every surplus encodes as the one-byte marker, so the
+    compression is 2^d 2^d 8 / 1 = 128 exactly."""
+    rows = _golden("table_memory_footprint.txt")
+    t = O.paper_table(W.theta_field(2, 1.0), 2, 27, 0.01, 1e-8, len(rows))
+    for k, r in enumerate(rows):
+        assert int(r[1]) == t[k, 0]
+        assert float(r[2]) == round(t[k, 1], 2)
+        assert float(r[3]) == round(t[k, 2], 2)
+
+
+def test_paper_table_theta16_is_localised():
+    """Table memory-footprint, theta = 16, qualitatively: some cell moves past
+    n = 1 in cycle 2 while the mean n stays near 1 and the compression stays
+    between 64 and the marker-only 128 (the paper prints 118).  The exact
+    figures depend on the grid the sample points fall on (1/27 here against
+    the paper's spacetree), so only these properties are pinned."""
+    t = O.paper_table(W.theta_field(2, 16.0), 2, 27, 0.01, 1e-8, 4)
+    assert t[0, 0] == 1 and t[0, 2] == 128.0
+    assert t[1, 0] >= 2
+    assert (np.diff(t[:, 1]) >= 0).all()               # mean n never falls
+    assert (t[1:, 1] < 1.05).all()
+    assert ((t[1:, 2] > 64) & (t[1:, 2] < 128)).all()
