@@ -277,20 +277,36 @@ def integration_rates(P, W, ctx, n3=512, ncells=1 << 20):
 
 
 def kernels_only(args):
-    """Counter runs: the roofline sweep at the workload size, then a plain
-    device copy of known size (calibration of the traffic counters)."""
+    """Counter runs: the roofline sweep at the workload size, a plain device
+    copy of known size (calibration of the traffic counters), then one bf16
+    hi+lo MFMA integration launch per s = 4, 8, 16 over the first 2^20 cells
+    of the headline grid (matrix-core counters)."""
     import torch
     import paper_2005_03606_amd as P
     import workload as W
     r = sweep_roofline(P, W, args.n, args.sweeps)
-    nbytes = 256 << 20
+    nbytes = 2 << 30
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(4):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"sweep": r, "copy_bytes_each_way": nbytes, "copies": 4,
-                      "source_sha16": source_sha16()}), flush=True)
+    del a, b
+    ctx = P.Context(0)
+    eps = P.Eps(W.config_field(4))
+    ncells = 1 << 20
+    cells = torch.arange(ncells, dtype=torch.int64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    mfma = {}
+    for s in (4, 8, 16):
+        ev[0].record()
+        P.assemble_cells(ctx, 3, args.n, s, eps, P.MIXED, cells=cells)
+        ev[1].record()
+        torch.cuda.synchronize()
+        mfma[f"s{s}_ms"] = round(ev[0].elapsed_time(ev[1]), 3)
+    ctx.close()
+    print(json.dumps({"sweep": r, "copy_bytes_each_way": nbytes, "copies": 4, "mfma_launches": mfma,
+                      "mfma_cells": ncells, "source_sha16": source_sha16()}), flush=True)
 
 
 # ---------------------------------------------------------------- serving

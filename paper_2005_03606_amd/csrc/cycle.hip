@@ -1692,123 +1692,6 @@ __global__ __launch_bounds__(256) void k_p_matvec_rec_store(StoreView sv, int n,
     if (threadIdx.x == 0) partial[blockIdx.x] = sum;
 }
 
-// ---- the 3D CG product (R29 recurrence) in items of four vertices (n % 4
-// == 0), as k_sweep3x4: 4-wide loads of the couplings, six-value segments
-// of the nine z rows, 4-wide FP64 p_old / A p_old in and p_new / A p out.
-// The couplings come from the stored half stencils (Cpl4Half) or from the
-// compressed store decoded per vertex (Cpl4Store, the same values as its
-// FP32 decode); both walk the same items in the same order per thread, so
-// their partial sums of p.Ap, and with them the solves, are the same bits.
-template <typename T> struct Cpl4Half {
-    const T *S;
-    size_t NV;
-    struct Loc {};
-    __device__ inline void prep(Loc &, int, size_t, uint32_t, uint32_t, uint32_t) const {}
-    __device__ inline void get(const Loc &, int j, size_t v, ptrdiff_t lin, double *A, double *B) const
-    {
-        T a[4], b[4];
-        ldv4(S + (size_t)j * NV + v, a);
-        ldv4(S + (size_t)j * NV + v - lin, b);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { A[i] = (double)a[i]; B[i] = (double)b[i]; }
-    }
-};
-
-struct Cpl4Store {
-    StoreView sv;
-    struct Loc { float own[4][13], low[4][13]; };
-    __device__ inline void prep(Loc &l, int n, size_t v, uint32_t x0, uint32_t y, uint32_t z) const
-    {
-        const Grid<3> g(n);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x[3] = {(int)x0 + i, (int)y, (int)z};
-            if (x[0] < n) store3_couplings(sv, g, (int64_t)v + i, x, l.own[i], l.low[i]);
-            else
-                for (int j = 0; j < 13; ++j) l.own[i][j] = l.low[i][j] = 0.0f;
-        }
-    }
-    __device__ inline void get(const Loc &l, int j, size_t, ptrdiff_t, double *A, double *B) const
-    {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { A[i] = (double)l.own[i][j]; B[i] = (double)l.low[i][j]; }
-    }
-};
-
-template <class Cpl, typename TZ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_p_matvec3x4(Cpl cp, int n, const TZ *__restrict__ z,
-                                                     const double *__restrict__ pold, double *__restrict__ pnew,
-                                                     double *__restrict__ Ap, CgScalars c, double *partial)
-{
-    __shared__ double red[256];
-    const double zr = sum_partials(c.p1, c.n1, red), zdr = sum_partials(c.p1 + c.n1, c.n1, red);
-    const double beta = c.s[7] != 0.0 ? 0.0 : zdr / c.s[c.zr_old];
-    if (blockIdx.x == 0 && threadIdx.x == 0) c.s[c.zr_new] = zr;
-    const size_t nv = (size_t)n + 1;
-    const uint32_t k = blockIdx.x & 7u, stride = (gridDim.x >> 3) * 256u;
-    double prod = 0.0;
-    uint32_t x0, y, zz;
-    for (uint32_t it = (blockIdx.x >> 3) * 256u + threadIdx.x; items4_at(n, it, k, x0, y, zz); it += stride) {
-        const size_t v = x0 + nv * (y + nv * zz);
-        if (x0 == 1) {
-            const double z0 = (double)z[v - 1];
-            pnew[v - 1] = beta != 0.0 ? z0 + beta * pold[v - 1] : z0;
-            Ap[v - 1] = 0.0;
-        }
-        double pv[4], apv[4] = {0.0, 0.0, 0.0, 0.0};
-        if (y != 0 && zz != 0 && y != (uint32_t)n && zz != (uint32_t)n) {
-            TZ Z[9][6];
-#pragma unroll
-            for (int r = 0; r < 9; ++r) {
-                const TZ *p = z + v - 1 + (ptrdiff_t)(r % 3 - 1) * (ptrdiff_t)nv + (ptrdiff_t)(r / 3 - 1) * (ptrdiff_t)(nv * nv);
-                ldv4(p, Z[r]);
-                if (x0 + 3 < (uint32_t)n) ldv2(p + 4, Z[r] + 4);  // past the row's end on its last item
-                else { Z[r][4] = p[4]; Z[r][5] = (TZ)0; }
-            }
-            double po[4] = {0.0, 0.0, 0.0, 0.0}, ao[4] = {0.0, 0.0, 0.0, 0.0};
-            if (beta != 0.0) { ldv4(pold + v, po); ldv4(Ap + v, ao); }
-            typename Cpl::Loc loc;
-            cp.prep(loc, n, v, x0, y, zz);
-            double acc[4] = {0.0, 0.0, 0.0, 0.0}, dsum[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int j = 0; j < 13; ++j) {
-                const int ox = half_off(3, j, 0), oy = half_off(3, j, 1), oz = half_off(3, j, 2);
-                const ptrdiff_t lin = ox + (ptrdiff_t)oy * (ptrdiff_t)nv + (ptrdiff_t)oz * (ptrdiff_t)(nv * nv);
-                double A[4], B[4];
-                cp.get(loc, j, v, lin, A, B);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    acc[i] += A[i] * (double)Z[(oy + 1) + 3 * (oz + 1)][1 + ox + i];
-                    dsum[i] += A[i];
-                    acc[i] += B[i] * (double)Z[(1 - oy) + 3 * (1 - oz)][1 - ox + i];
-                    dsum[i] += B[i];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double zv = (double)Z[4][1 + i];
-                pv[i] = beta != 0.0 ? zv + beta * po[i] : zv;
-                if (x0 + i < (uint32_t)n) {
-                    const double az = -dsum[i] * zv + acc[i];
-                    apv[i] = beta != 0.0 ? az + beta * ao[i] : az;
-                    prod += pv[i] * apv[i];
-                }
-            }
-        } else {
-            TZ zb[4];
-            ldv4(z + v, zb);
-            double po[4] = {0.0, 0.0, 0.0, 0.0};
-            if (beta != 0.0) ldv4(pold + v, po);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) pv[i] = beta != 0.0 ? (double)zb[i] + beta * po[i] : (double)zb[i];
-        }
-        stv4(pnew + v, pv);
-        stv4(Ap + v, apv);
-    }
-    double sum = block_sum<256>(prod, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
-}
-
 template <int D, typename TZ>
 static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *pold, double *pnew, double *Ap,
                         const CgScalars &c, hipStream_t st)
@@ -1816,22 +1699,6 @@ static int pcg_matvec_t(mgd_hier *h, const OpSet &o, const TZ *z, const double *
     // more blocks than the other reducing kernels: each thread's rows gather
     // 27 neighbours, and the product needs the occupancy to hide that latency
     const unsigned grid = (unsigned)std::min<int64_t>({grid_for(h->NV[0], 256), (int64_t)kPmvBlocks, h->partial_cap});
-    if (items4_fit(D, h->n)) {
-        // a multiple of 8 blocks (each XCD strides over its own items)
-        const unsigned g4 = std::max(8u, std::min(grid, items4_blocks(h->n)) & ~7u);
-        if (h->precision == MGD_FP64)
-            hipLaunchKernelGGL((k_p_matvec3x4<Cpl4Half<double>, TZ>), dim3(g4), dim3(256), 0, st,
-                               Cpl4Half<double>{o.S64[0], (size_t)h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
-        else if (store3_decode(h))
-            hipLaunchKernelGGL((k_p_matvec3x4<Cpl4Store, TZ>), dim3(g4), dim3(256), 0, st,
-                               Cpl4Store{store_view(h, o)}, h->n, z, pold, pnew, Ap, c, h->partial2);
-        else
-            hipLaunchKernelGGL((k_p_matvec3x4<Cpl4Half<float>, TZ>), dim3(g4), dim3(256), 0, st,
-                               Cpl4Half<float>{o.S32[0], (size_t)h->NV[0]}, h->n, z, pold, pnew, Ap, c, h->partial2);
-        HIPCHK(h->ctx, hipGetLastError());
-        h->p2_n = g4;
-        return MGD_OK;
-    }
     if (D == 3) {
         if (h->precision == MGD_FP64)
             hipLaunchKernelGGL((k_p_matvec_rec<D, OpHalf<double>, TZ>), dim3(grid), dim3(256), 0, st,
