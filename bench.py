@@ -309,6 +309,41 @@ def kernels_only(args):
                       "mfma_cells": ncells, "source_sha16": source_sha16()}), flush=True)
 
 
+# ------------------------------------------------------------ paper mode
+def paper_mode_table(P, W, ctx, n=243, cycles=10, C_thr=0.01, tau=1e-8):
+    """Table memory-footprint (Sec. 6.3) in the paper's own mode on the GPU:
+    the n -> n + 1 ladder keeping the older matrix, p3-byte surplus format,
+    theta = 1 / 16 / 64 on a 2D grid of h = 1/n; per cycle (max n, mean n,
+    compression) and the time of the whole table (ladder steps + encoding)."""
+    import numpy as np
+    import torch
+    d = 2
+    out = {"grid": f"2D {n}^2 cells (h = 1/{n}), C = {C_thr}, tau = {tau}, {cycles} cycles"}
+    nn = (1 << d) ** 2
+    for theta in (1.0, 16.0, 64.0):
+        eps = P.Eps(W.theta_field(d, theta))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K1, _, _ = P.assemble_cells(ctx, d, n, 1, eps, P.FP64)
+        K = K1.clone()
+        ncell = n ** d
+        nfin = torch.ones(ncell, dtype=torch.int64, device="cuda")
+        cells = torch.arange(ncell, dtype=torch.int64, device="cuda")
+        rows = []
+        for k in range(1, cycles + 1):
+            if k >= 2 and cells.numel():
+                _, done = P.ladder_step_keep(ctx, d, n, k, eps, K, cells=cells, C_thr=C_thr)
+                cells = cells[done == 0]
+                nfin[cells] = k
+            p3, _ = P.p3_encode(ctx, d, K, K1, tau)
+            nb = int((1 + nn * p3.to(torch.int64)).sum())
+            rows.append([int(nfin.max()), round(float(nfin.double().mean()), 4), round(ncell * nn * 8.0 / nb, 2)])
+        torch.cuda.synchronize()
+        out[f"theta_{int(theta)}"] = {"rows_max_n_mean_n_compression": rows,
+                                      "ms": round((time.perf_counter() - t0) * 1e3, 2)}
+    return out
+
+
 # ---------------------------------------------------------------- serving
 def serving_bench(P, W, count, slots):
     """Serving replay: mixed 2D/3D requests with Gaussian-field materials,
@@ -418,6 +453,8 @@ def main():
     ctx = P.Context(0)
     log("integration rates")
     comps["cell_integrations_per_s"] = integration_rates(P, W, ctx)
+    log("paper mode")
+    comps["paper_mode_memory_footprint"] = paper_mode_table(P, W, ctx)
     ctx.close()
     if args.n2d > 0:
         m = args.n2d

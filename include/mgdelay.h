@@ -113,6 +113,41 @@ int mgd_assemble_cells(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s,
                        int32_t mode, void *K_out, const void *K_old, double C,
                        double *rel_out, uint8_t *done_out, hipStream_t stream);
 
+/* (1p) The paper's own ladder step, n -> n + 1 (Sec. 5.2, with the older
+ * matrix kept on convergence: the reading under which Table
+ * memory-footprint's theta = 1 row stays at n = 1): for each listed cell c,
+ * the element matrix with s^d samples (FP64, any s in 1..16) is compared
+ * with the row K[c], which holds the cell's matrix with (s - 1)^d samples;
+ * rel = ||K_new - K[c]||_max / ||K[c]||_max over the full 2^d x 2^d
+ * matrices.  rel < C: the cell is done and K[c] keeps the older matrix;
+ * else K[c] becomes K_new.  K (dev double [n^d][U], rows by cell id) is
+ * read and written in place; cells (dev int64 [count], or NULL for all n^d
+ * in order); rel_out (dev double [count], may be NULL); done_out (dev uint8
+ * [count], may be NULL) gets 1 for done.  eps: any field kind but
+ * explicit samples.  Errors: MGD_EINVAL for s outside 1..16 or a bad grid,
+ * field or count. */
+int mgd_ladder_step_keep(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s, const int64_t *cells,
+                         int64_t count, const mgd_eps *eps, double *K, double C, double *rel_out,
+                         uint8_t *done_out, hipStream_t stream);
+
+/* (1q) The paper's flexible-precision format of the hierarchical surplus
+ * (Sec. 5.5), cell by cell: E = K - K1 as a full 2^d x 2^d matrix (off the
+ * diagonal from the stored pairs, E[a][b] = E[b][a] = K[p] - K1[p]; on it
+ * minus the sum of its row's off-diagonal entries, taken in ascending
+ * column order, as rows of a stiffness matrix sum to zero).  p3 = 0 when
+ * the Frobenius norm of E (squares summed row by row) is below tau; else
+ * the fewest bytes p in 2..7 whose encoding keeps every entry within tau of
+ * it, or 8 (the double itself).  A p-byte datum (2 <= p <= 7): p - 1 bytes,
+ * little-endian, holding the sign in the top bit and the leading
+ * 8 (p - 1) - 1 bits of the IEEE fraction (truncated), then one byte with
+ * the unbiased exponent as a signed char clamped to [-128, 127]; zero is
+ * exponent -128 with a zero fraction.  K, K1: dev double [count][U];
+ * p3_out: dev uint8 [count]; bytes_out: dev uint8 [count][2^d 2^d 8], of
+ * which a cell's first 2^d 2^d p3 bytes (entries row by row) are written.
+ * Errors: MGD_EINVAL for a bad dim, count or tau, or a NULL buffer. */
+int mgd_p3_encode(mgd_ctx *ctx, int32_t dim, const double *K, const double *K1, int64_t count, double tau,
+                  uint8_t *p3_out, uint8_t *bytes_out, hipStream_t stream);
+
 /* Centre samples eps(x_c) of all n^d cells as FP32 (eps_c_out dev float
  * [n^d]): the s = 1 integration of Sec. 5.2 and the base of the
  * hierarchical surplus (Sec. 5.5) that mgd_compress_stencils subtracts. */

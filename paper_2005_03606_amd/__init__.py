@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     PUBLISH_ASYNC, PUBLISH_DETERMINISTIC, PUBLISH_EVERY, STORE_AUTO, STORE_DECODE, STORE_COPY,
     START_CARRY, START_BEST, CYCLE_V, CYCLE_ADAFAC_PI, CYCLE_ADAFAC_JAC,
     MgdError, Context, Eps, Hierarchy,
-    assemble_cells, centre_samples, gather_stencils, solve, solve_opts, solve_footprint, Server,
+    assemble_cells, ladder_step_keep, p3_encode, centre_samples, gather_stencils, solve, solve_opts,
+    solve_footprint, Server,
     n_half, n_pairs, lib, library_path,
 )

@@ -92,6 +92,9 @@ def lib():
         "mgd_version": ([], C.c_char_p),
         "mgd_assemble_cells": ([_P, _I, _I, _I, _P, C.c_int64, C.POINTER(_Eps), _I, _P, _P,
                                 C.c_double, _P, _P, _P], C.c_int),
+        "mgd_ladder_step_keep": ([_P, _I, _I, _I, _P, C.c_int64, C.POINTER(_Eps), _P, C.c_double, _P, _P, _P],
+                                 C.c_int),
+        "mgd_p3_encode": ([_P, _I, _P, _P, C.c_int64, C.c_double, _P, _P, _P], C.c_int),
         "mgd_gather_stencils": ([_P, _I, _I, _P, _I, _P, _I, _P], C.c_int),
         "mgd_centre_samples": ([_P, _I, _I, C.POINTER(_Eps), _P, _P], C.c_int),
         "mgd_hier_create": ([_P, C.POINTER(_HierDesc), C.POINTER(_P)], C.c_int),
@@ -285,6 +288,51 @@ def assemble_cells(ctx, dim, n, s, eps, mode=FP64, cells=None, K_old=None, C_thr
     ctx.check(lib().mgd_assemble_cells(ctx.h, dim, n, s, _ptr(cells), count, C.byref(eps.s), mode,
                                        _ptr(K), _ptr(K_old), C_thr, _ptr(rel), _ptr(done), _stream(stream)))
     return K, rel, done
+
+
+def ladder_step_keep(ctx, dim, n, s, eps, K, cells=None, C_thr=0.01, want_rel=False, stream=None):
+    """The paper's n -> n + 1 step at s samples per axis (FP64): K (device
+    float64 [n^d][U], rows by cell, holding the (s-1)^d-sample matrices of
+    the listed cells) keeps a cell's row when it changed by less than C_thr,
+    else takes the new matrix.  Returns (rel, done) over the listed cells."""
+    if dim not in (2, 3):
+        raise MgdError(EINVAL, "dim must be 2 or 3")
+    if eps.dim != dim or eps.n_samples is not None:
+        raise MgdError(EINVAL, "the ladder step needs a field descriptor of dimension dim")
+    ncell = n ** dim
+    if cells is None:
+        count = ncell
+    else:
+        count = int(cells.numel())
+        _buf(cells, "cells", torch.int64, count, ctx.device)
+        if count and (int(cells.min()) < 0 or int(cells.max()) >= ncell):
+            raise MgdError(EINVAL, f"cell ids must lie in [0, {ncell})")
+    _buf(K, "K", torch.float64, ncell * n_pairs(dim), ctx.device)
+    dev = torch.device("cuda", ctx.device)
+    rel = torch.empty(count, dtype=torch.float64, device=dev) if want_rel else None
+    done = torch.empty(count, dtype=torch.uint8, device=dev)
+    ctx.check(lib().mgd_ladder_step_keep(ctx.h, dim, n, s, _ptr(cells), count, C.byref(eps.s), _ptr(K), C_thr,
+                                         _ptr(rel), _ptr(done), _stream(stream)))
+    return rel, done
+
+
+def p3_encode(ctx, dim, K, K1, tau, stream=None):
+    """The paper's p3-byte format of the surplus K - K1 (device float64
+    [count][U] each), cell by cell: (p3 [count] uint8, bytes [count][2^d 2^d 8]
+    uint8, of which a cell's first 2^d 2^d p3 bytes are its entries)."""
+    if dim not in (2, 3):
+        raise MgdError(EINVAL, "dim must be 2 or 3")
+    U = n_pairs(dim)
+    count = int(K.numel()) // U if K is not None else 0
+    _buf(K, "K", torch.float64, count * U, ctx.device)
+    _buf(K1, "K1", torch.float64, count * U, ctx.device)
+    dev = torch.device("cuda", ctx.device)
+    nn = (1 << dim) ** 2
+    p3 = torch.empty(count, dtype=torch.uint8, device=dev)
+    out = torch.zeros((count, nn * 8), dtype=torch.uint8, device=dev)
+    ctx.check(lib().mgd_p3_encode(ctx.h, dim, _ptr(K), _ptr(K1), count, float(tau), _ptr(p3), _ptr(out),
+                                  _stream(stream)))
+    return p3, out
 
 
 def centre_samples(ctx, dim, n, eps, stream=None):

@@ -190,6 +190,39 @@ int mgd_assemble_cells(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s, const in
                            nullptr, stream);
 }
 
+int mgd_ladder_step_keep(mgd_ctx *ctx, int32_t dim, int32_t n, int32_t s, const int64_t *cells, int64_t count,
+                         const mgd_eps *eps, double *K, double C, double *rel_out, uint8_t *done_out,
+                         hipStream_t stream)
+{
+    if (!ctx) return MGD_EINVAL;
+    int rc;
+    if ((rc = check_grid(ctx, dim, n)) || (rc = check_eps(ctx, eps, dim, false))) return rc;
+    if (s < 1 || s > 16) return mgd_fail(ctx, MGD_EINVAL, "s must be in 1..16 (got %d)", s);
+    int64_t ncell = ipow(n, dim);
+    if (count == 0) return MGD_OK;
+    if (!cells && count != ncell) return mgd_fail(ctx, MGD_EINVAL, "cells == NULL needs count == n^d");
+    if (count < 0 || count > ncell) return mgd_fail(ctx, MGD_EINVAL, "bad count %lld", (long long)count);
+    if (!K) return mgd_fail(ctx, MGD_EINVAL, "K is NULL");
+    if (!(C >= 0.0)) return mgd_fail(ctx, MGD_EINVAL, "C must be >= 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    // rows by cell id, read and rewritten in place by the lane that owns the cell
+    return launch_assemble(ctx, dim, n, s, cells, count, eps, MGD_FP64, K, K, 1, C, rel_out, done_out, nullptr,
+                           stream, 1);
+}
+
+int mgd_p3_encode(mgd_ctx *ctx, int32_t dim, const double *K, const double *K1, int64_t count, double tau,
+                  uint8_t *p3_out, uint8_t *bytes_out, hipStream_t stream)
+{
+    if (!ctx) return MGD_EINVAL;
+    if (dim != 2 && dim != 3) return mgd_fail(ctx, MGD_EINVAL, "dim must be 2 or 3 (got %d)", dim);
+    if (count < 0) return mgd_fail(ctx, MGD_EINVAL, "bad count %lld", (long long)count);
+    if (!(tau >= 0.0)) return mgd_fail(ctx, MGD_EINVAL, "tau must be >= 0");
+    if (count == 0) return MGD_OK;
+    if (!K || !K1 || !p3_out || !bytes_out) return mgd_fail(ctx, MGD_EINVAL, "NULL buffer");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return launch_p3_encode(ctx, dim, K, K1, count, tau, p3_out, bytes_out, stream);
+}
+
 int mgd_centre_samples(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, float *eps_c_out,
                        hipStream_t stream)
 {

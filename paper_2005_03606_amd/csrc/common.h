@@ -313,7 +313,10 @@ void dev_free(void *p);
 int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, int64_t count,
                     const mgd_eps *eps, int mode, void *K_out, const void *K_old, int k_by_cell,
                     double C, double *rel_out, uint8_t *done_out, const int64_t *count_dev,
-                    hipStream_t st);
+                    hipStream_t st, int keep_old = 0);
+// the paper's p3-byte format of element-matrix surpluses (paper.hip)
+int launch_p3_encode(mgd_ctx *ctx, int dim, const double *K, const double *K1, int64_t count, double tau,
+                     uint8_t *p3_out, uint8_t *bytes_out, hipStream_t st);
 int launch_compact_open(mgd_ctx *ctx, const uint8_t *done, const int64_t *cells_in, const int64_t *count_dev,
                         int64_t count_bound, int32_t *block_tmp, int64_t *cells_out, int64_t *count_out,
                         hipStream_t st);

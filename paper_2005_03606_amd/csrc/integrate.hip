@@ -329,6 +329,7 @@ struct AsmArgs {
     double C;
     double *rel_out;
     uint8_t *done_out;
+    int keep_old;              // rel < C: leave the row with K_old (K_out == K_old, in place)
 };
 
 __device__ inline int64_t asm_count(const AsmArgs &a) { return a.count_dev ? *a.count_dev : a.count; }
@@ -405,6 +406,7 @@ __device__ inline void store_and_check(const AsmArgs &a, int64_t i, int64_t cell
         double rel = ladder_rel<D, T>(K, old);
         if (a.rel_out) a.rel_out[i] = rel;
         if (a.done_out) a.done_out[i] = rel < a.C ? 1 : 0;
+        if (a.keep_old && rel < a.C) return;
     }
     T *Ko = (T *)a.K_out + row * U;
     for (int p = 0; p < U; ++p) Ko[p] = K[p];
@@ -869,10 +871,11 @@ static int get_gtable(mgd_ctx *ctx, int D, int s, GTable **out)
 int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, int64_t count,
                     const mgd_eps *eps, int mode, void *K_out, const void *K_old, int k_by_cell,
                     double C, double *rel_out, uint8_t *done_out, const int64_t *count_dev,
-                    hipStream_t st)
+                    hipStream_t st, int keep_old)
 {
     if (count <= 0) return MGD_OK;
     AsmArgs a;
+    a.keep_old = keep_old;
     a.n = n; a.s = s; a.count = count; a.count_dev = count_dev; a.cells = cells;
     a.eps.kind = eps->kind; a.eps.dim = eps->dim; a.eps.count = eps->count;
     a.eps.p0 = eps->p0; a.eps.p1 = eps->p1; a.eps.data = eps->data;
