@@ -290,6 +290,7 @@ int mgd_hier_set_fine(mgd_ctx *ctx, mgd_hier *h, const double *S, hipStream_t st
 {
     if (!ctx || !h || !S) return MGD_EINVAL;
     if (h->precision != MGD_FP64) return mgd_fail(ctx, MGD_EINVAL, "set_fine needs an FP64 hierarchy");
+    h->ops.dz_ok = 0;
     HIPCHK(ctx, hipMemcpyAsync(h->ops.S64[0], S, (size_t)h->NV[0] * h->H * 8, hipMemcpyDeviceToDevice, stream));
     return MGD_OK;
 }

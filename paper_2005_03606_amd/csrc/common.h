@@ -269,6 +269,13 @@ struct OpSet {           // operators of every level (one version)
     float *eps_c = nullptr;
     uint32_t *units_total = nullptr;  // device scalar: payload size in 64-byte units
     int64_t ntile = 0, payload_cap_units = 0;
+    // 3D: the diagonal of every level's operator in the order of the
+    // zero-start sweep (minus the sum over half slots of own + mirrored
+    // coupling), per vertex; bit l of dz_ok says level l's is current.  Every
+    // writer of a level's couplings clears dz_ok; the first zero-start sweep
+    // after that recomputes it (one pass over the couplings per operator)
+    void *Dz[MGD_MAXLEV] = {};
+    mutable uint32_t dz_ok = 0;
     double *chol = nullptr;  // dense Cholesky factor of the coarsest interior matrix
     double *cinv = nullptr;  // its inverse, for coarse grids of at most kCinvMax unknowns
 };

@@ -646,6 +646,67 @@ static int sweep(mgd_hier *h, const OpSet &o, int level, const void *u, const vo
     return sweep_t<3, float>(h, o, level, (const float *)u, (const float *)f, (float *)out, omega, mode, zero_guess, partial, st);
 }
 
+// ---- the 3D zero-start sweep from the stored diagonal.  From u = 0 a
+// damped-Jacobi sweep is u_1 = omega f / D: only the diagonal of the
+// operator enters, so with D kept per level (Dz, computed once per operator
+// by k_diag_zero with the zero-start sweep's own sum order) the pass reads
+// 8 bytes per vertex instead of the whole stencil.  Same values as the
+// stencil kernels' zero-start mode, bit for bit.
+template <typename T> __global__ __launch_bounds__(256) void k_diag_zero(const T *__restrict__ S, int n, T *__restrict__ Dz)
+{
+    Grid<3> g(n);
+    const int64_t v = block_index<3>() * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3];
+    g.coords(v, x);
+    T d = (T)1;
+    if (g.interior(x)) {
+        T dsum = (T)0;
+        for (int j = 0; j < 13; ++j) {
+            const int64_t lin = half_lin(3, j, g.nv);
+            dsum += S[(int64_t)j * g.NV + v] + S[(int64_t)j * g.NV + v - lin];
+        }
+        d = -dsum;
+    }
+    Dz[v] = d;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_sweep_d(const T *__restrict__ Dz, int n, const T *__restrict__ f,
+                                                     T *__restrict__ out, T omega)
+{
+    Grid<3> g(n);
+    const int64_t v = block_index<3>() * blockDim.x + threadIdx.x;
+    if (v >= g.NV) return;
+    int x[3];
+    g.coords(v, x);
+    out[v] = g.interior(x) ? (T)0 + omega * (f[v] - (T)0) / Dz[v] : (T)0;
+}
+
+template <typename T>
+static int zero_sweep_t(mgd_hier *h, const OpSet &o, int level, const T *f, T *out, double omega, hipStream_t st)
+{
+    const int n = h->nl[level];
+    const dim3 gr(grid_for(h->NV[level], 256));
+    T *Dz = (T *)o.Dz[level];
+    if (!(o.dz_ok >> level & 1u)) {
+        const T *S = h->precision == MGD_FP64 ? (const T *)o.S64[level] : (const T *)o.S32[level];
+        hipLaunchKernelGGL((k_diag_zero<T>), gr, dim3(256), 0, st, S, n, Dz);
+        HIPCHK(h->ctx, hipGetLastError());
+        o.dz_ok |= 1u << level;
+    }
+    hipLaunchKernelGGL((k_zero_sweep_d<T>), gr, dim3(256), 0, st, Dz, n, f, out, (T)omega);
+    HIPCHK(h->ctx, hipGetLastError());
+    return MGD_OK;
+}
+
+// the 3D zero-start sweep takes the stored diagonal except on the
+// store-decoding finest level (whose kernels read the store only)
+static bool zero_sweep_by_diag(const mgd_hier *h, const OpSet &o, int level)
+{
+    return h->dim == 3 && o.Dz[level] && !(h->precision == MGD_MIXED && level == 0 && store3_decode(h));
+}
+
 int cycle_smooth(mgd_hier *h, const OpSet &o, int level, void *u, const void *f, void *tmp, int sweeps,
                  double omega, bool zero_guess, hipStream_t st)
 {
@@ -653,7 +714,13 @@ int cycle_smooth(mgd_hier *h, const OpSet &o, int level, void *u, const void *f,
     for (int k = 0; k < sweeps; ++k) {
         const void *src = (k % 2 == 0) ? u : tmp;
         void *dst = (k % 2 == 0) ? tmp : u;
-        int rc = sweep(h, o, level, src, f, dst, omega, 0, zero_guess && k == 0, nullptr, st);
+        int rc;
+        if (zero_guess && k == 0 && zero_sweep_by_diag(h, o, level))
+            rc = h->precision == MGD_FP64
+                     ? zero_sweep_t<double>(h, o, level, (const double *)f, (double *)dst, omega, st)
+                     : zero_sweep_t<float>(h, o, level, (const float *)f, (float *)dst, omega, st);
+        else
+            rc = sweep(h, o, level, src, f, dst, omega, 0, zero_guess && k == 0, nullptr, st);
         if (rc) return rc;
     }
     if (sweeps % 2 == 1)

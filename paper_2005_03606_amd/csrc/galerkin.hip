@@ -574,6 +574,7 @@ static void galerkin_launch(const HalfRow<D, T> &A, const T *W, int nf, int64_t 
 // the store, kept current by every change of the store)
 template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *const *S, hipStream_t st)
 {
+    o.dz_ok = 0;
     mgd_ctx *ctx = h->ctx;
     for (int l = 0; l + 1 < h->nlev; ++l) {
         HalfRow<D, T> A{S[l], h->NV[l], (int64_t)h->nl[l] + 1};
@@ -651,6 +652,7 @@ template <int D, typename T> __global__ void k_geo_weights_t(int n, T *W)
 template <int D, typename T>
 static int coarsen_geometric_t(mgd_hier *h, OpSet &o, T *const *S, const float *eps_c0, float *scratch, hipStream_t st)
 {
+    o.dz_ok = 0;
     // cell values of level l in scratch, alternating between two halves
     int64_t nc1 = 1;
     for (int m = 0; m < D; ++m) nc1 *= h->nl[0] / 2;

@@ -96,6 +96,7 @@ static int build(Ladder &L, OpSet &o, hipStream_t st)
 {
     mgd_hier *h = L.h;
     int rc;
+    o.dz_ok = 0;
     if (h->precision == MGD_FP64) {
         if ((rc = launch_gather(h->ctx, h->dim, h->n, L.K, MGD_FP64, o.S64[0], MGD_FP64, st))) return rc;
     } else {
@@ -514,6 +515,7 @@ int solve_begin(SolveState *S, const mgd_eps *eps, const double *f, double *u, c
         // (FP64: the gather; mixed: the centre-sample base needs none) and
         // runs beside the provisional coarsening
         mgd_hier *h = L.h;
+        S->H.ops.dz_ok = 0;
         if (h->precision == MGD_FP64)
             rc = launch_gather(ctx, h->dim, h->n, L.K, MGD_FP64, S->H.ops.S64[0], MGD_FP64, stream);
         else
@@ -726,6 +728,7 @@ size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest
         int64_t NV = ipow(nl[l] + 1, dim);
         ops += (size_t)NV * H * vb;
         if (transfer == MGD_BOXMG && l + 1 < nlev) ops += (size_t)NV * nlw * vb;
+        if (dim == 3) ops += (size_t)NV * vb;  // zero-start diagonal
         vec += 4 * (size_t)NV * vb;
     }
     if (precision == MGD_MIXED) {

@@ -279,6 +279,7 @@ StoreView store_view(const mgd_hier *h, const OpSet &o)
 // kernels, the 3D outer operator); kept current with every change of the store
 int decode_store_f32(mgd_hier *h, OpSet &o, hipStream_t st)
 {
+    o.dz_ok = 0;
     StoreView sv = store_view(h, o);
     dim3 gv(grid_for(h->NV[0], 256));
     if (h->dim == 2) hipLaunchKernelGGL((k_decode_store<2, float>), gv, dim3(256), 0, st, sv, h->n, o.S32[0]);
@@ -320,7 +321,9 @@ int opset_alloc(mgd_hier *h, OpSet &o)
         }
         if (h->transfer == MGD_BOXMG && l + 1 < h->nlev)
             if ((rc = dev_alloc(ctx, &o.W[l], (size_t)h->NV[l] * nlw * h->vec_bytes()))) return rc;
+        if (h->dim == 3 && (rc = dev_alloc(ctx, &o.Dz[l], (size_t)h->NV[l] * h->vec_bytes()))) return rc;
     }
+    o.dz_ok = 0;
     if (h->precision == MGD_MIXED) {
         int64_t nc = 1;
         for (int m = 0; m < h->dim; ++m) nc *= h->n;
@@ -344,8 +347,8 @@ int opset_alloc(mgd_hier *h, OpSet &o)
 void opset_free(OpSet &o)
 {
     for (int l = 0; l < MGD_MAXLEV; ++l) {
-        dev_free(o.S64[l]); dev_free(o.S32[l]); dev_free(o.W[l]);
-        o.S64[l] = nullptr; o.S32[l] = nullptr; o.W[l] = nullptr;
+        dev_free(o.S64[l]); dev_free(o.S32[l]); dev_free(o.W[l]); dev_free(o.Dz[l]);
+        o.S64[l] = nullptr; o.S32[l] = nullptr; o.W[l] = nullptr; o.Dz[l] = nullptr;
     }
     dev_free(o.tier); dev_free(o.toff); dev_free(o.payload); dev_free(o.eps_c);
     dev_free(o.units_total); dev_free(o.chol); dev_free(o.cinv);
