@@ -230,6 +230,14 @@ int mgd_compress_stencils(mgd_ctx *ctx, mgd_hier *h, const float *S32, const flo
 int mgd_compress_stencils_noalloc(mgd_ctx *ctx, mgd_hier *h, const float *S32, const float *eps_c,
                                   const mgd_tier_policy *policy, hipStream_t stream);
 
+/* Transfer weights of a 3D BoxMG hierarchy level (coarsened): the number of
+ * 64-vertex tiles of the level and of those whose operator-dependent
+ * prolongation equals the d-linear one in every structurally nonzero weight
+ * (hierarchical surplus P - P_geo = 0, Sec. 5.5); the restriction and
+ * prolongation read no weights there.  Synchronous.  MGD_EINVAL for a 2D or
+ * geometric hierarchy or a level without a coarser one. */
+int mgd_weight_tiles(mgd_ctx *ctx, const mgd_hier *h, int32_t level, int64_t *ntile, int64_t *geo_tiles);
+
 /* Copy the compressed store out (dev buffers; pass NULL to skip one):
  * tile_tier uint8 [ntile], tile_off uint32 [ntile], payload (payload_bytes).
  * Host scalars ntile / payload_bytes are returned synchronously. */

@@ -107,6 +107,7 @@ def lib():
         "mgd_store_info": ([_P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64 * 4)], C.c_int),
         "mgd_store_export": ([_P, _P, _P, _P, _P, _P], C.c_int),
+        "mgd_weight_tiles": ([_P, _P, _I, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
         "mgd_coarsen": ([_P, _P, _P], C.c_int),
         "mgd_level_stencils": ([_P, _P, C.c_int, _P, _P], C.c_int),
         "mgd_level_weights": ([_P, _P, C.c_int, _P, _P], C.c_int),
@@ -421,6 +422,12 @@ class Hierarchy:
         nt, pb, tiers = C.c_int64(), C.c_int64(), (C.c_int64 * 4)()
         self.ctx.check(lib().mgd_store_info(self.ctx.h, self.h, C.byref(nt), C.byref(pb), C.byref(tiers)))
         return nt.value, pb.value, list(tiers)
+
+    def weight_tiles(self, level):
+        """(tiles, tiles whose BoxMG prolongation is d-linear) of a 3D BoxMG level."""
+        nt, geo = C.c_int64(), C.c_int64()
+        self.ctx.check(lib().mgd_weight_tiles(self.ctx.h, self.h, level, C.byref(nt), C.byref(geo)))
+        return nt.value, geo.value
 
     def store_export(self, stream=None):
         nt, pb, _ = self.store_info()

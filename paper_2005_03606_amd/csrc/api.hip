@@ -309,6 +309,23 @@ int mgd_compress_stencils(mgd_ctx *ctx, mgd_hier *h, const float *S32, const flo
     return compress_into(h, h->ops, S32, eps_c, pol, h->delta, h->vtier, stream);
 }
 
+int mgd_weight_tiles(mgd_ctx *ctx, const mgd_hier *h, int32_t level, int64_t *ntile, int64_t *geo_tiles)
+{
+    if (!ctx || !h || !ntile || !geo_tiles) return MGD_EINVAL;
+    if (h->dim != 3 || h->transfer != MGD_BOXMG) return mgd_fail(ctx, MGD_EINVAL, "weight tiles need a 3D BoxMG hierarchy");
+    if (level < 0 || level + 1 >= h->nlev) return mgd_fail(ctx, MGD_EINVAL, "level %d has no coarser level", level);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t nt = (h->NV[level] + 63) / 64;
+    std::vector<uint8_t> f((size_t)nt);
+    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, hipMemcpy(f.data(), h->ops.wgeo[level], (size_t)nt, hipMemcpyDeviceToHost));
+    int64_t g = 0;
+    for (uint8_t b : f) g += b != 0;
+    *ntile = nt;
+    *geo_tiles = g;
+    return MGD_OK;
+}
+
 int mgd_store_info(mgd_ctx *ctx, const mgd_hier *h, int64_t *ntile, int64_t *payload_bytes, int64_t tier_tiles[4])
 {
     if (!ctx || !h) return MGD_EINVAL;

@@ -276,6 +276,11 @@ struct OpSet {           // operators of every level (one version)
     // after that recomputes it (one pass over the couplings per operator)
     void *Dz[MGD_MAXLEV] = {};
     mutable uint32_t dz_ok = 0;
+    // 3D BoxMG: per 64-vertex tile of level l, 1 where every structurally
+    // nonzero weight of W[l] equals the d-linear one (the hierarchical
+    // surplus P - P_geo of Sec. 5.5 is zero there), so the transfers take the
+    // d-linear value instead of reading the tile's weights
+    uint8_t *wgeo[MGD_MAXLEV] = {};
     double *chol = nullptr;  // dense Cholesky factor of the coarsest interior matrix
     double *cinv = nullptr;  // its inverse, for coarse grids of at most kCinvMax unknowns
 };

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_restrict2(const T *W, int nf, const T *
 // in the box of 2X + d is B_m = 1 where d_m = -1, else 0, fixed at compile
 // time; the terms of R = P^T in the order of the fine offsets (x fastest)
 template <typename T, bool GEO>
-__global__ __launch_bounds__(256) void k_restrict3(const T *W, int nf, const T *r, T *fc)
+__global__ __launch_bounds__(256) void k_restrict3(const T *W, const uint8_t *wgeo, int nf, const T *r, T *fc)
 {
     const int nc = nf / 2;
     const int64_t nvc = nc + 1, NVc = nvc * nvc * nvc, nvf = nf + 1, NVf = nvf * nvf * nvf;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_restrict3(const T *W, int nf, const T *
         const int B = (d0 < 0 ? 1 : 0) | (d1 < 0 ? 2 : 0) | (d2 < 0 ? 4 : 0);
         const int64_t v = c0 + d0 + nvf * (d1 + nvf * d2);
         T w;
-        if (GEO) w = (T)((d0 ? 0.5 : 1.0) * (d1 ? 0.5 : 1.0) * (d2 ? 0.5 : 1.0));
+        if (GEO || (wgeo && wgeo[v >> 6])) w = (T)((d0 ? 0.5 : 1.0) * (d1 ? 0.5 : 1.0) * (d2 ? 0.5 : 1.0));
         else w = W[(int64_t)B * NVf + v];
         s += w * r[v];
     }
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_restrict3(const T *W, int nf, const T *
 // ascending B as k_prolong, so the same bits; the 8 corner values are loaded
 // once for the 8 children.
 template <typename T, bool GEO>
-__global__ __launch_bounds__(256) void k_prolong3(const T *W, int nf, const T *ec, T *u)
+__global__ __launch_bounds__(256) void k_prolong3(const T *W, const uint8_t *wgeo, int nf, const T *ec, T *u)
 {
     const int nc = nf / 2;
     const int64_t nvc = nc + 1, NVc = nvc * nvc * nvc, nvf = nf + 1, NVf = nvf * nvf * nvf;
@@ -377,12 +377,13 @@ __global__ __launch_bounds__(256) void k_prolong3(const T *W, int nf, const T *e
         const int x0 = 2 * X0 + (b & 1), x1 = 2 * X1 + ((b >> 1) & 1), x2 = 2 * X2 + (b >> 2);
         if (x0 < 1 || x0 > nf - 1 || x1 < 1 || x1 > nf - 1 || x2 < 1 || x2 > nf - 1) continue;
         const int64_t v = x0 + nvf * (x1 + nvf * (int64_t)x2);
+        const bool geo = GEO || (wgeo && wgeo[v >> 6]);
         T acc = (T)0;
 #pragma unroll
         for (int B = 0; B < 8; ++B) {
             if (B & ~b) continue;  // compile time after unrolling
             T w;
-            if (GEO) w = (T)((b & 1 ? 0.5 : 1.0) * ((b >> 1) & 1 ? 0.5 : 1.0) * ((b >> 2) & 1 ? 0.5 : 1.0));
+            if (geo) w = (T)((b & 1 ? 0.5 : 1.0) * ((b >> 1) & 1 ? 0.5 : 1.0) * ((b >> 2) & 1 ? 0.5 : 1.0));
             else w = W[(int64_t)B * NVf + v];
             if (w != (T)0) acc += w * e[B];
         }
@@ -742,14 +743,14 @@ int cycle_restrict(mgd_hier *h, const OpSet &o, int level, const void *r, void *
         const double *W = box ? (const double *)o.W[level] : nullptr;
         if (h->dim == 2 && W) hipLaunchKernelGGL((k_restrict2<double, false>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
         else if (h->dim == 2) hipLaunchKernelGGL((k_restrict2<double, true>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
-        else if (W) hipLaunchKernelGGL((k_restrict3<double, false>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
-        else hipLaunchKernelGGL((k_restrict3<double, true>), gr, dim3(256), 0, st, W, nf, (const double *)r, (double *)fc);
+        else if (W) hipLaunchKernelGGL((k_restrict3<double, false>), gr, dim3(256), 0, st, W, o.wgeo[level], nf, (const double *)r, (double *)fc);
+        else hipLaunchKernelGGL((k_restrict3<double, true>), gr, dim3(256), 0, st, W, nullptr, nf, (const double *)r, (double *)fc);
     } else {
         const float *W = box ? (const float *)o.W[level] : nullptr;
         if (h->dim == 2 && W) hipLaunchKernelGGL((k_restrict2<float, false>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
         else if (h->dim == 2) hipLaunchKernelGGL((k_restrict2<float, true>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
-        else if (W) hipLaunchKernelGGL((k_restrict3<float, false>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
-        else hipLaunchKernelGGL((k_restrict3<float, true>), gr, dim3(256), 0, st, W, nf, (const float *)r, (float *)fc);
+        else if (W) hipLaunchKernelGGL((k_restrict3<float, false>), gr, dim3(256), 0, st, W, o.wgeo[level], nf, (const float *)r, (float *)fc);
+        else hipLaunchKernelGGL((k_restrict3<float, true>), gr, dim3(256), 0, st, W, nullptr, nf, (const float *)r, (float *)fc);
     }
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;
@@ -763,13 +764,13 @@ int cycle_prolong(mgd_hier *h, const OpSet &o, int level, const void *ec, void *
     if (h->precision == MGD_FP64) {
         const double *W = box ? (const double *)o.W[level] : nullptr;
         if (h->dim == 2) hipLaunchKernelGGL((k_prolong<2, double>), gr, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
-        else if (W) hipLaunchKernelGGL((k_prolong3<double, false>), gc3, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
-        else hipLaunchKernelGGL((k_prolong3<double, true>), gc3, dim3(256), 0, st, W, nf, (const double *)ec, (double *)u);
+        else if (W) hipLaunchKernelGGL((k_prolong3<double, false>), gc3, dim3(256), 0, st, W, o.wgeo[level], nf, (const double *)ec, (double *)u);
+        else hipLaunchKernelGGL((k_prolong3<double, true>), gc3, dim3(256), 0, st, W, nullptr, nf, (const double *)ec, (double *)u);
     } else {
         const float *W = box ? (const float *)o.W[level] : nullptr;
         if (h->dim == 2) hipLaunchKernelGGL((k_prolong<2, float>), gr, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
-        else if (W) hipLaunchKernelGGL((k_prolong3<float, false>), gc3, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
-        else hipLaunchKernelGGL((k_prolong3<float, true>), gc3, dim3(256), 0, st, W, nf, (const float *)ec, (float *)u);
+        else if (W) hipLaunchKernelGGL((k_prolong3<float, false>), gc3, dim3(256), 0, st, W, o.wgeo[level], nf, (const float *)ec, (float *)u);
+        else hipLaunchKernelGGL((k_prolong3<float, true>), gc3, dim3(256), 0, st, W, nullptr, nf, (const float *)ec, (float *)u);
     }
     HIPCHK(h->ctx, hipGetLastError());
     return MGD_OK;

@@ -572,6 +572,36 @@ static void galerkin_launch(const HalfRow<D, T> &A, const T *W, int nf, int64_t 
 // weights, Galerkin products and the coarsest matrix in FP64 arithmetic; the
 // mixed form stores the levels in FP32 (its finest level: the FP32 decode of
 // the store, kept current by every change of the store)
+// one wavefront per 64-vertex tile of W (3D): 1 if every structurally
+// nonzero weight of the tile's vertices equals the d-linear weight
+template <typename T> __global__ __launch_bounds__(256) void k_wgeo_tiles(const T *W, int n, uint8_t *flags)
+{
+    Grid<3> g(n);
+    const int64_t ntile = (g.NV + 63) / 64;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= ntile) return;
+    const int64_t v = t * 64 + (threadIdx.x & 63);
+    bool geo = true;
+    if (v < g.NV) {
+        int x[3];
+        g.coords(v, x);
+        double w[8];
+        geo_weights<3, double>(x, w);
+        const int odd = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
+        for (int B = 0; B < 8; ++B)
+            if (!(B & ~odd) && W[(int64_t)B * g.NV + v] != (T)w[B]) geo = false;
+    }
+    const bool all = __all(geo);
+    if ((threadIdx.x & 63) == 0) flags[t] = all ? 1 : 0;
+}
+
+template <typename T> static void wgeo_launch(const T *W, int n, int64_t NV, uint8_t *flags, hipStream_t st)
+{
+    if (!flags) return;
+    const int64_t ntile = (NV + 63) / 64;
+    hipLaunchKernelGGL((k_wgeo_tiles<T>), dim3(grid_for(ntile, 4)), dim3(256), 0, st, W, n, flags);
+}
+
 template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *const *S, hipStream_t st)
 {
     o.dz_ok = 0;
@@ -579,7 +609,10 @@ template <int D, typename T> static int coarsen_t(mgd_hier *h, OpSet &o, T *cons
     for (int l = 0; l + 1 < h->nlev; ++l) {
         HalfRow<D, T> A{S[l], h->NV[l], (int64_t)h->nl[l] + 1};
         T *W = (T *)o.W[l];
-        if (h->transfer == MGD_BOXMG) weights_launch<D, T>(A, h->nl[l], h->NV[l], W, st);
+        if (h->transfer == MGD_BOXMG) {
+            weights_launch<D, T>(A, h->nl[l], h->NV[l], W, st);
+            if (D == 3) wgeo_launch<T>(W, h->nl[l], h->NV[l], o.wgeo[l], st);
+        }
         galerkin_launch<D, T>(A, (const T *)(h->transfer == MGD_BOXMG ? W : nullptr), h->nl[l], h->NV[l + 1],
                               S[l + 1], st);
     }
@@ -664,9 +697,11 @@ static int coarsen_geometric_t(mgd_hier *h, OpSet &o, T *const *S, const float *
         hipLaunchKernelGGL(k_avg_children<D>, dim3(grid_for(ncl, 256)), dim3(256), 0, st, ef, h->nl[l - 1], ec);
         hipLaunchKernelGGL((k_base_stencils<D, T>), dim3(grid_for(h->NV[l], 256)), dim3(256), 0, st,
                            (const float *)ec, h->nl[l], S[l]);
-        if (h->transfer == MGD_BOXMG)
+        if (h->transfer == MGD_BOXMG) {
             hipLaunchKernelGGL((k_geo_weights_t<D, T>), dim3(grid_for(h->NV[l - 1], 256)), dim3(256), 0, st,
                                h->nl[l - 1], (T *)o.W[l - 1]);
+            if (D == 3) wgeo_launch<T>((const T *)o.W[l - 1], h->nl[l - 1], h->NV[l - 1], o.wgeo[l - 1], st);
+        }
         ef = ec;
     }
     int lc = h->nlev - 1;

@@ -729,6 +729,7 @@ size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest
         ops += (size_t)NV * H * vb;
         if (transfer == MGD_BOXMG && l + 1 < nlev) ops += (size_t)NV * nlw * vb;
         if (dim == 3) ops += (size_t)NV * vb;  // zero-start diagonal
+        if (dim == 3 && transfer == MGD_BOXMG && l + 1 < nlev) ops += (size_t)(NV + 63) / 64;  // d-linear tile flags
         vec += 4 * (size_t)NV * vb;
     }
     if (precision == MGD_MIXED) {

@@ -322,6 +322,9 @@ int opset_alloc(mgd_hier *h, OpSet &o)
         if (h->transfer == MGD_BOXMG && l + 1 < h->nlev)
             if ((rc = dev_alloc(ctx, &o.W[l], (size_t)h->NV[l] * nlw * h->vec_bytes()))) return rc;
         if (h->dim == 3 && (rc = dev_alloc(ctx, &o.Dz[l], (size_t)h->NV[l] * h->vec_bytes()))) return rc;
+        if (h->dim == 3 && h->transfer == MGD_BOXMG && l + 1 < h->nlev &&
+            (rc = dev_alloc(ctx, (void **)&o.wgeo[l], (size_t)(h->NV[l] + 63) / 64)))
+            return rc;
     }
     o.dz_ok = 0;
     if (h->precision == MGD_MIXED) {
@@ -347,8 +350,8 @@ int opset_alloc(mgd_hier *h, OpSet &o)
 void opset_free(OpSet &o)
 {
     for (int l = 0; l < MGD_MAXLEV; ++l) {
-        dev_free(o.S64[l]); dev_free(o.S32[l]); dev_free(o.W[l]); dev_free(o.Dz[l]);
-        o.S64[l] = nullptr; o.S32[l] = nullptr; o.W[l] = nullptr; o.Dz[l] = nullptr;
+        dev_free(o.S64[l]); dev_free(o.S32[l]); dev_free(o.W[l]); dev_free(o.Dz[l]); dev_free(o.wgeo[l]);
+        o.S64[l] = nullptr; o.S32[l] = nullptr; o.W[l] = nullptr; o.Dz[l] = nullptr; o.wgeo[l] = nullptr;
     }
     dev_free(o.tier); dev_free(o.toff); dev_free(o.payload); dev_free(o.eps_c);
     dev_free(o.units_total); dev_free(o.chol); dev_free(o.cinv);

@@ -408,6 +408,60 @@ def test_cycle_pieces_fp64(ctx, d, n):
     assert rel_err(host(uu), O.prolong_add(d, n, ec, u, Pw)) < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_transfers_skip_dlinear_weight_tiles(ctx, precision):
+    """3D BoxMG at 16^3 with one ball of 1e3 in a corner: the tiles far from
+    it have the d-linear prolongation (P - P_geo = 0), the tiles at it do
+    not, and restriction and prolongation, which take the d-linear value on
+    the flagged tiles instead of reading the weights, still equal the
+    oracle's with the weights the hierarchy reports; a constant material
+    flags every tile."""
+    d, n = 3, 16
+    fld = W.balls_field(d, 1, 3, r_lo=0.15, r_hi=0.15, eps_in=1e3)
+    fld.data[:3] = 0.2  # the ball's centre
+    S = O.stencils(d, n, O.assemble(fld, d, n, 4))
+    prec = P.FP64 if precision == "fp64" else P.MIXED
+    h = P.Hierarchy(ctx, d, n, precision=prec, transfer=P.BOXMG)
+    if prec == P.FP64:
+        h.set_fine(dev(O.to_half(d, S)))
+        h.coarsen()
+    else:
+        S32 = dev(O.to_half(d, S), torch.float32)
+        eps_c = dev(np.full(n ** d, 1.0), torch.float32)
+        h.compress(S32, eps_c, min_tier=3, max_tier=3, tau_abs=0.0, tau_rel=0.0)
+        h.coarsen()
+    nt, geo = h.weight_tiles(0)
+    assert nt == (17 ** 3 + 63) // 64
+    # FP64 weights of a uniform region are d-linear only up to rounding (the
+    # oracle's: 9 of 77 tiles exactly); FP32 ones round to it (58 of 77)
+    assert geo < nt and (prec == P.FP64 or geo > nt // 2), (geo, nt)
+    Pw = host(h.level_weights(0)).T
+    tdt = torch.float64 if prec == P.FP64 else torch.float32
+    rng = np.random.default_rng(9)
+    inner = W.interior_mask(d, n)
+    r = rng.standard_normal(inner.size) * inner
+    fc = torch.zeros(h.nv(1), dtype=tdt, device="cuda")
+    h.restrict(0, dev(r, tdt), fc)
+    rr = host(dev(r, tdt)).astype(np.float64)
+    bar = 1e-12 if prec == P.FP64 else 1e-6
+    assert rel_err(host(fc).astype(np.float64), O.restrict(d, n, rr, Pw)) < bar
+    ec = rng.standard_normal(h.nv(1)) * W.interior_mask(d, n // 2)
+    u = rng.standard_normal(inner.size) * inner
+    uu = dev(u, tdt)
+    h.prolong_add(0, dev(ec, tdt), uu)
+    ecd = host(dev(ec, tdt)).astype(np.float64)
+    ud = host(dev(u, tdt)).astype(np.float64)
+    assert rel_err(host(uu).astype(np.float64), O.prolong_add(d, n, ecd, ud, Pw)) < bar
+    hc = P.Hierarchy(ctx, d, n, precision=P.MIXED, transfer=P.BOXMG)
+    Sc = O.stencils(d, n, O.assemble(W.const_field(d, 2.0), d, n, 1))
+    hc.compress(dev(O.to_half(d, Sc), torch.float32), dev(np.full(n ** d, 2.0), torch.float32),
+                min_tier=3, max_tier=3, tau_abs=0.0, tau_rel=0.0)
+    hc.coarsen()
+    assert hc.weight_tiles(0) == (nt, nt)
+    with pytest.raises(P.MgdError):
+        hc.weight_tiles(h.nlev - 1)
+
+
 @pytest.mark.parametrize("transfer", [0, 1])
 @pytest.mark.parametrize("d,n", [(2, 32), (2, 24), (3, 8)])
 def test_vcycles_fp64_match_oracle(ctx, transfer, d, n):
