@@ -1120,14 +1120,17 @@ def test_repeated_solves_reuse_workspace_bitwise(ctx):
 
 # ------------------------------------------------------------ adaFAC-x
 @pytest.mark.parametrize("variant", [1, 2])
-@pytest.mark.parametrize("d,n,name,transfer", [(2, 64, "sine", 0), (2, 64, "sine", 1), (2, 32, "balls", 1)])
+@pytest.mark.parametrize("d,n,name,transfer", [(2, 64, "sine", 0), (2, 64, "sine", 1), (2, 32, "balls", 1),
+                                               (3, 16, "sine", 0), (3, 16, "sine", 1)])
 def test_adafac_solve_matches_oracle(ctx, variant, d, n, name, transfer):
     """Stationary iteration with the additive adaFAC-x correction (Sec. 4.1;
     1: adaFAC-PI in two launches over all levels, 2: adaFAC-Jac) against the
     oracle's: same cycle count, histories and solution at the oracle's
     one-ulp spread.  2D: the oracle measures adaFAC-PI at 0.52-0.62 per
-    cycle and adaFAC-Jac at 0.93-0.95 here (tolerances 1e-10 and 1e-8); in
-    3D with omega = 0.6 both diverge on the balls material."""
+    cycle and adaFAC-Jac at 0.93-0.95 here (tolerances 1e-10 and 1e-8); 3D
+    sine 16^3: 37 and 76-82 cycles (the unit 3D operator's rates: 0.67 and
+    0.70 at 8^3); on the 3D balls material (1e3) with omega = 0.6 both
+    diverge, on the oracle too."""
     fld = W.sine_field(d, 0.9) if name == "sine" else W.balls_field(d, 8, 3, r_lo=0.1, r_hi=0.3, eps_in=1e3)
     f = W.load_sine(d, n)
     kw = dict(s_fixed=4, tol=1e-10 if variant == 1 else 1e-8, max_cycles=500)
