@@ -17,8 +17,10 @@ on provisional ones, and with the plain FP64 form assembled up front.  Inputs
 
 Components: the same comparison on the 2D 1024^2 balls workload and on the
 3D 256^3 Gaussian-field workload, cell integrations per second by s, the
-serving replay (2048 requests), and the roofline of the mixed finest-level
-sweep at 512^3.
+serving replay (2048 requests), the roofline of the mixed finest-level
+sweep at 512^3, the additive adaFAC-PI / adaFAC-Jac cycles against V(2,2)
+on a 3D 256^3 sine material, and the paper's own ladder and byte format
+(memory-footprint table) on a 2D 243^2 grid.
 
 Prints one JSON line.  `value` is the mixed-lazy form's fine-grid V-cycle
 throughput over the whole solve: (n-1)^3 DoF x V-cycles / time-to-solution.
@@ -309,6 +311,33 @@ def kernels_only(args):
                       "mfma_cells": ncells, "source_sha16": source_sha16()}), flush=True)
 
 
+# --------------------------------------------------------------- adaFAC
+def adafac_component(P, W, ctx, n=256, tol=1e-8):
+    """The additive adaFAC-PI / adaFAC-Jac corrections against the
+    multiplicative V(2,2) one, each inside the stationary FP64 outer
+    iteration, 3D n^3 sine material (eps = 1 + 0.9 sin 2 pi x sin 2 pi y
+    sin 2 pi z), BoxMG transfers, s = 4 up front: time to tol and cycles, in
+    the FP64 and the mixed form (FP16 surplus store)."""
+    import torch
+    d = 3
+    eps = P.Eps(W.sine_field(d, 0.9))
+    f = torch.from_numpy(W.load_sine(d, n)).cuda()
+    out = {"workload": f"3D {n}^3 sine material, s = 4 up front, BoxMG, stationary outer iteration to {tol}"}
+    for prec, pname in ((P.FP64, "fp64"), (P.MIXED, "mixed")):
+        for cyc, cname in ((P.CYCLE_V, "vcycle"), (P.CYCLE_ADAFAC_PI, "adafac_pi"), (P.CYCLE_ADAFAC_JAC, "adafac_jac")):
+            kw = dict(precision=prec, transfer=P.BOXMG, outer=P.STATIONARY, s_fixed=4, tol=tol, max_cycles=400,
+                      cycle=cyc, **TIERS_FP16)
+            P.solve(ctx, d, n, eps, f, torch.zeros_like(f), **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = P.solve(ctx, d, n, eps, f, torch.zeros_like(f), **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            out[f"{pname}_{cname}"] = {"ms": round(ms, 2), "cycles": rep["cycles"], "status": rep["status"],
+                                       "ms_per_cycle": round(rep["t_cycles_ms"] / max(rep["cycles"], 1), 3)}
+    return out
+
+
 # ------------------------------------------------------------ paper mode
 def paper_mode_table(P, W, ctx, n=243, cycles=10, C_thr=0.01, tau=1e-8):
     """Table memory-footprint (Sec. 6.3) in the paper's own mode on the GPU:
@@ -455,6 +484,8 @@ def main():
     comps["cell_integrations_per_s"] = integration_rates(P, W, ctx)
     log("paper mode")
     comps["paper_mode_memory_footprint"] = paper_mode_table(P, W, ctx)
+    log("adafac")
+    comps["adafac"] = adafac_component(P, W, ctx)
     ctx.close()
     if args.n2d > 0:
         m = args.n2d

@@ -1163,13 +1163,14 @@ def test_adafac_solve_matches_oracle(ctx, variant, d, n, name, transfer):
 
 
 @pytest.mark.parametrize("variant", [1, 2])
-def test_adafac_mixed_solve_error(ctx, variant):
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 32)])
+def test_adafac_mixed_solve_error(ctx, variant, d, n):
     """The mixed form with the adaFAC correction (FP32 cycle on the store's
     decode, FP64 outer residual) reaches the tolerance on the operator it
-    solves; its distance to the FP64 oracle's solution is stated (FP16
-    surplus store, same bound as the V-cycle's)."""
-    d, n = 2, 64
-    fld = W.sine_field(2, 0.9)
+    solves; its distance to the FP64 oracle's solution (FP16 surplus store)
+    measured 1.4e-7 (2D 64^2) and 5.8e-7 (3D 32^3) for both variants; the
+    bound is about ten times that."""
+    fld = W.sine_field(d, 0.9)
     f = W.load_sine(d, n)
     u_ref, rr = O.solve(fld, d, n, f, s_fixed=4, tol=1e-12, transfer=O.BOXMG, outer=O.PCG)
     u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), precision=P.MIXED, s_fixed=4, tol=1e-8, transfer=P.BOXMG,
@@ -1178,7 +1179,7 @@ def test_adafac_mixed_solve_error(ctx, variant):
     assert rep["r_final"] <= 1e-8 * rep["r0"]
     err = rel_err(host(u), u_ref)
     print(f"adafac{variant} mixed vs FP64 oracle: {err:.3e} in {rep['cycles']} cycles")
-    assert err < 3e-4, err
+    assert err < 5e-6, err
 
 
 # ------------------------------------------------------------ headline size, sampled
