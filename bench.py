@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512, help="cells per axis of the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=16, help="grid of the oracle's sample of the same material")
+    ap.add_argument("--cpu-n", type=int, default=20, help="grid of the oracle's sample of the same material")
     ap.add_argument("--sweeps", type=int, default=40, help="timed launches of the roofline kernel")
     ap.add_argument("--serve-requests", type=int, default=2048,
                     help="requests in the serving replay (0 skips it)")
