@@ -843,6 +843,28 @@ def test_solve_lazy_deterministic_matches_oracle_schedule(ctx, d, n, start):
     _check_solve(rep, rr, host(u), u_ref, floor, us, f"lazy{d}d-{start}")
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("d,n", [(2, 32), (3, 16)])
+def test_solve_lazy_adafac_matches_oracle_schedule(ctx, d, n, variant):
+    """The paper's own combination, the additive adaFAC-x correction on
+    operators that change under it (Sec. 4.1, Sec. 5.1): lazy schedule with
+    rung k published before cycle k, the iterate carried over, stationary
+    outer iteration, against the oracle's emulation: same cycle count,
+    histories and solution at the oracle's one-ulp spread.  Log-normal
+    lattice materials (the oracle: PI 40 / 38 cycles, Jac 238 / 103)."""
+    fld = W.lattice_field(2, 12, 4, sigma=1.0) if d == 2 else W.lattice_field(3, 5, 6, sigma=1.0)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=16 if d == 2 else 8, tol=1e-10 if variant == 1 else 1e-8, max_cycles=500)
+    (u_ref, rr), floor, us = oracle_spread(
+        lambda ff: O.solve(fld, d, n, ff, lazy=True, transfer=O.BOXMG, outer=O.STATIONARY, cycle=variant, **kw), f)
+    u, rep = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, publish=P.PUBLISH_DETERMINISTIC,
+                     transfer=P.BOXMG, outer=P.STATIONARY, cycle=variant, **kw)
+    assert rep["status"] == 0 and rr["status"] == 0
+    assert rep["cycles"] == rr["cycles"], (rep["cycles"], rr["cycles"])
+    assert rep["cells_at_s"] == rr["cells_at_s"]
+    _check_solve(rep, rr, host(u), u_ref, floor, us, f"lazy-adafac{variant}-{d}d")
+
+
 @pytest.mark.parametrize("outer", ["stationary", "pcg"])
 @pytest.mark.parametrize("d,n,name", [(3, 16, "balls"), (3, 32, "balls"), (3, 16, "lattice"), (3, 32, "boxes")])
 def test_solve_3d_fp64_matches_oracle(ctx, d, n, name, outer):
