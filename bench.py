@@ -46,12 +46,16 @@ TIERS_C5 = dict(min_tier=1, max_tier=3, tau_abs=0.0, tau_rel=1e-6)
 TIERS_FP16 = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
 FORMS = ("mixed_lazy", "mixed_lazy_parked", "mixed_upfront", "fp64_upfront")
 # the roofline kernel: one damped-Jacobi sweep of the 3D mixed finest level
-# as the solve runs it (the FP32 decode of the store, four vertices per
-# thread); its traffic record (counter runs of `bench.py --kernels-only`) is
-# valid only for the source it was taken on
-SWEEP_KERNEL = "k_sweep3x4<float, 0, false>"
+# as the solve runs it (four vertices per thread; items whose coupling
+# sources are all tier-0 tiles re-evaluate their couplings from the centre
+# samples, the others read the store's FP32 decode); its traffic record
+# (counter runs of `bench.py --kernels-only`) is valid only for the source it
+# was taken on
+SWEEP_KERNEL = "k_sweep3x4h<0>"
 KERNEL_SOURCES = ("paper_2005_03606_amd/csrc/cycle.hip", "paper_2005_03606_amd/csrc/common.h")
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep3x4_boxes512_traffic.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep3x4h_boxes512_traffic.md")
+# half-stencil offsets of a 27-point stencil (the 13 upper neighbours)
+HALF3 = [((i % 3) - 1, (i // 3) % 3 - 1, i // 9 - 1) for i in range(14, 27)]
 
 
 def parse():
@@ -195,20 +199,51 @@ def recorded_traffic(n):
     return int(m.group(2))
 
 
+def tier0_items(tier, n):
+    """Items of four finest-level vertices (x0 = 1 + 4c on interior rows)
+    whose coupling sources all lie in tier-0 tiles (own couplings: the tiles
+    of v and v + 3; mirrored ones: those of v - o and v - o + 3 for every half
+    slot o), i.e. the items whose couplings the default 3D sweep re-evaluates
+    from the centre samples.  Counted on the device from the exported tile
+    tiers, 32 planes at a time."""
+    import torch
+    nv, T = n + 1, n // 4
+    t0 = tier == 0
+    dev = tier.device
+    c = torch.arange(T, device=dev, dtype=torch.int64)
+    y = torch.arange(1, n, device=dev, dtype=torch.int64)
+    row = (1 + 4 * c)[None, :] + nv * y[:, None]
+    count = 0
+    for z0 in range(1, n, 32):
+        z = torch.arange(z0, min(z0 + 32, n), device=dev, dtype=torch.int64)
+        v = row[None] + nv * nv * z[:, None, None]
+        ok = t0[v >> 6] & t0[(v + 3) >> 6]
+        for ox, oy, oz in HALF3:
+            w = v - (ox + oy * nv + oz * nv * nv)
+            ok &= t0[w >> 6] & t0[(w + 3) >> 6]
+        count += int(ok.sum())
+    return count
+
+
 def sweep_roofline(P, W, n, sweeps):
     """One damped-Jacobi sweep of the mixed finest level of the headline
     workload (3D 512^3 boxes, the final operator of the adaptive ladder), the
     kernel that moves most of the mixed cycle's bytes, with the solve's
-    operator source and launch shape: the FP32 decode of the compressed
-    store, four vertices per thread.  Timed with HIP events on the stream the
-    kernels run on.
+    operator source and launch shape: four vertices per thread; an item whose
+    coupling sources all lie in tier-0 tiles re-evaluates its couplings from
+    its 5 x 2 x 2 cells' centre samples, every other item reads the store's
+    FP32 decode.  Timed with HIP events on the stream the kernels run on.
 
-    Algorithmic bytes per launch (one stencil pass over every vertex): the
-    13 FP32 couplings of the half stencil (52 B) + FP32 u in, f in, u out
-    (12 B) per vertex.  `store_form_frac` prices the same time against the
-    bytes of the compressed store itself (payload + tier byte and offset per
-    64-vertex tile + FP32 centre sample per cell), the least any sweep of
-    this operator must read."""
+    Algorithmic bytes per launch: FP32 u in, f in, u out (12 B per vertex),
+    the 13 FP32 couplings of the half stencil and their mirrored ones for
+    every vertex of a decode-reading item (208 B per item: each slot read as
+    its own vertex's and as its neighbour's), each tier-0 item's cells once
+    (16 B: four cells per item), and the item flags (1 B per item).
+    `decode_form_frac` prices the same time at the 64 B per vertex of a sweep
+    that reads the decode everywhere (the work this pass replaces);
+    `store_form_frac` at the compressed store's own bytes (payload + tier byte
+    and offset per 64-vertex tile + FP32 centre sample per cell), the least
+    any sweep of this operator must read."""
     import torch
     d = 3
     ctx = P.Context(0)
@@ -222,8 +257,13 @@ def sweep_roofline(P, W, n, sweeps):
     del S32
     torch.cuda.empty_cache()
     ntile, payload, tier_tiles = h.store_info()
+    tier = h.store_export()[0]
     NV = (n + 1) ** d
-    pass_bytes = 64 * NV
+    items, items_inner = (n // 4) * (n + 1) ** 2, (n // 4) * (n - 1) ** 2
+    t0 = tier0_items(tier, n)
+    del tier
+    pass_bytes = 12 * NV + 208 * (items_inner - t0) + 16 * t0 + items
+    decode_pass_bytes = 64 * NV
     store_pass_bytes = payload + 5 * ntile + 4 * n ** d + 12 * NV
     inner = torch.from_numpy(W.interior_mask(d, n)).cuda()
     f32 = inner.to(torch.float32)
@@ -243,12 +283,14 @@ def sweep_roofline(P, W, n, sweeps):
     ctx.close()
     torch.cuda.empty_cache()
     achieved = pass_bytes / (avg_ms / 1e3) / 1e9
+    frac = lambda b: round(b / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(n),
-            "kernel": SWEEP_KERNEL, "bytes_per_launch": int(pass_bytes), "bytes_per_dof": 64,
+            "kernel": SWEEP_KERNEL, "bytes_per_launch": int(pass_bytes),
+            "bytes_per_dof": round(pass_bytes / NV, 2), "tier0_items": t0, "items": items_inner,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": 2 * calls,
-            "store_form_bytes_per_launch": int(store_pass_bytes),
-            "store_form_frac": round(store_pass_bytes / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "decode_form_bytes_per_launch": int(decode_pass_bytes), "decode_form_frac": frac(decode_pass_bytes),
+            "store_form_bytes_per_launch": int(store_pass_bytes), "store_form_frac": frac(store_pass_bytes),
             "store_tiers_0_fp8_fp16_fp32": tier_tiles,
             "workload": f"finest level of the headline workload ({n}^3 cells), final ladder operator"}
 

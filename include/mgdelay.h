@@ -169,13 +169,18 @@ int mgd_gather_stencils(mgd_ctx *ctx, int32_t dim, int32_t n, const void *K, int
  * to FP32: the mixed operator), coarse levels are FP32 half stencils, cycle
  * vectors are FP32.
  * Levels: n_0 = n, halved while even and n/2 >= coarsest (>= 2).
- * store_path (MGD_MIXED, 2D V(2,2) fused level kernels and the CG product):
- * MGD_STORE_DECODE decodes the compressed store in every pass,
- * MGD_STORE_COPY reads the FP32 decode; both apply the same operator values
- * and give the same results bit for bit.  MGD_STORE_AUTO (0) decodes the
- * store when the finest level has at least 2^22 vertices (streamed from HBM,
- * where the store's fewer bytes set the pace) and reads the FP32 decode on
- * smaller levels (cache-resident between passes, bound by arithmetic).
+ * store_path (MGD_MIXED, the finest level's sweeps, residuals and CG
+ * product): MGD_STORE_DECODE decodes the compressed store in every pass,
+ * MGD_STORE_COPY reads the FP32 decode.  MGD_STORE_AUTO (0): in 2D it decodes
+ * the store when the finest level has at least 2^22 vertices (streamed from
+ * HBM, where the store's fewer bytes set the pace) and reads the FP32 decode
+ * on smaller levels (cache-resident between passes, bound by arithmetic); in
+ * 3D with n % 4 == 0 the sweeps and residuals re-evaluate the couplings of
+ * every four-vertex item whose coupling sources all lie in tier-0 tiles
+ * (surplus 0, Sec. 5.5) from the cells' centre samples and read the FP32
+ * decode for the other items, and the CG product reads the FP32 decode.
+ * Every choice applies the same operator values in the same order and gives
+ * the same results bit for bit.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t dim, n, precision, transfer, coarsest, store_path;

@@ -276,6 +276,11 @@ struct OpSet {           // operators of every level (one version)
     // after that recomputes it (one pass over the couplings per operator)
     void *Dz[MGD_MAXLEV] = {};
     mutable uint32_t dz_ok = 0;
+    // 3D mixed, n % 4 == 0: per item of four finest-level vertices, 1 when
+    // all its coupling sources lie in tier-0 tiles (k_item_mask); current
+    // while bit kImaskOk of dz_ok is set, so every writer of the finest
+    // operator invalidates it together with the diagonals
+    uint8_t *imask = nullptr;
     // 3D BoxMG: per 64-vertex tile of level l, 1 where every structurally
     // nonzero weight of W[l] equals the d-linear one (the hierarchical
     // surplus P - P_geo of Sec. 5.5 is zero there), so the transfers take the
@@ -285,6 +290,7 @@ struct OpSet {           // operators of every level (one version)
     double *cinv = nullptr;  // its inverse, for coarse grids of at most kCinvMax unknowns
 };
 constexpr int64_t kCinvMax = 128;
+constexpr uint32_t kImaskOk = 1u << 31;  // above every level bit (MGD_MAXLEV < 31)
 
 struct mgd_hier {
     mgd_ctx *ctx = nullptr;

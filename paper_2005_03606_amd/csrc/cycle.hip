@@ -159,6 +159,140 @@ __global__ __launch_bounds__(256) void k_sweep3x4(const T *__restrict__ S, int n
     stv4(out + v, o);
 }
 
+// ---- 3D mixed finest level in items of four, the default path.  The FP32
+// decode streams 52 bytes of couplings per vertex, yet in a tier-0 tile (no
+// stored surplus, Sec. 5.5) every coupling is the centre-sample base alone:
+// a function of the 2 x 2 x 2 cells around the vertex, whose samples cost
+// 4 bytes per cell.  k_item_mask marks with 1 each item (natural order
+// c + T (y + nv z), x0 = 1 + 4c) whose coupling sources all lie in tier-0
+// tiles: its own couplings (tiles of v and v + 3) and the mirrored ones of
+// every half slot j (tiles of v - o_j and v - o_j + 3).  Boundary rows get 0.
+__global__ __launch_bounds__(256) void k_item_mask(const uint8_t *__restrict__ tier, int n, uint8_t *__restrict__ im)
+{
+    const int64_t nv = (int64_t)n + 1, T = n >> 2;
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= T * nv * nv) return;
+    const int64_t t = id / T, c = id - t * T, y = t % nv, z = t / nv;
+    bool all = false;
+    if (y != 0 && z != 0 && y != n && z != n) {
+        const int64_t v = 1 + 4 * c + nv * (y + nv * z);
+        auto base = [&](int64_t w) { return tier[w >> 6] == 0 && tier[(w + 3) >> 6] == 0; };
+        all = base(v);
+        for (int j = 0; j < 13; ++j) all = all && base(v - half_lin(3, j, nv));
+    }
+    im[id] = all ? 1 : 0;
+}
+
+// Centre-sample coupling (surplus 0) between vertex x0 + i of an item and
+// its neighbour at a face or body diagonal offset o, from the item's cells
+// e[cz][cy][cx] = eps_c(x0 - 1 + cx, y - 1 + cy, z - 1 + cz): the samples of
+// the cells holding both vertices (descending B, as the decode sums them),
+// times k(o), times h, rounded once to FP32 -- the decode's value, up to the
+// sign of a zero (the decode adds the zero surplus, turning -0 into +0),
+// which no sum below can see: every accumulator starts at +0, and a sum of
+// FP32 values that starts at +0 never becomes -0, so adding +0 or -0 leaves
+// it unchanged.
+__device__ inline float base_item(const float (&e)[2][2][5], int i, int o0, int o1, int o2, double hp)
+{
+#pragma clang fp contract(off)
+    double sum = 0.0;
+#pragma unroll
+    for (int B = 7; B >= 0; --B) {
+        const int b0 = B & 1, b1 = (B >> 1) & 1, b2 = B >> 2;
+        if ((unsigned)(b0 + o0) <= 1u && (unsigned)(b1 + o1) <= 1u && (unsigned)(b2 + o2) <= 1u)
+            sum = sum + (double)e[1 - b2][1 - b1][i + 1 - b0];
+    }
+    return (float)((sum * (-1.0 / 12.0)) * hp);
+}
+
+// k_sweep3x4<float, MODE, false> on the mixed finest level, with the
+// couplings of a tier-0 item re-evaluated from eps_c (its 5 x 2 x 2 cells, 20
+// floats instead of 104 couplings) and those of every other item read from
+// the decode S.  Each vertex takes the same values in the same order as in
+// k_sweep3x4 (vertex by vertex instead of slot by slot: the four vertices'
+// sums are independent), so the results are the same bits (for finite
+// iterates: the skipped zero couplings would turn an infinite u into NaN).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sweep3x4h(const float *__restrict__ S, const uint8_t *__restrict__ im,
+                                                   const float *__restrict__ eps_c, int n, const float *__restrict__ u,
+                                                   const float *__restrict__ f, float *__restrict__ out, float omega)
+{
+    uint32_t x0, y, z;
+    if (!items4_at(n, (blockIdx.x >> 3) * 256u + threadIdx.x, blockIdx.x & 7u, x0, y, z)) return;
+    const size_t nv = (size_t)n + 1, NV = nv * nv * nv;
+    const size_t v = x0 + nv * (y + nv * z);
+    if (x0 == 1) out[v - 1] = 0.0f;
+    float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (y != 0 && z != 0 && y != (uint32_t)n && z != (uint32_t)n) {
+        const bool tier0 = im[(x0 >> 2) + (size_t)(n >> 2) * (y + nv * z)] != 0;
+        float U[9][6];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const float *p = u + v - 1 + (ptrdiff_t)(r % 3 - 1) * (ptrdiff_t)nv + (ptrdiff_t)(r / 3 - 1) * (ptrdiff_t)(nv * nv);
+            ldv4(p, U[r]);
+            if (x0 + 3 < (uint32_t)n) ldv2(p + 4, U[r] + 4);
+            else { U[r][4] = p[4]; U[r][5] = 0.0f; }
+        }
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (tier0) {
+            float e[2][2][5];
+#pragma unroll
+            for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                    const float *row = eps_c + (x0 - 1) + (size_t)n * ((y - 1 + cy) + (size_t)n * (z - 1 + cz));
+                    ldv4(row, e[cz][cy]);
+                    // cell x0 + 3 exists unless vertex x0 + 3 = n, a boundary vertex
+                    e[cz][cy][4] = x0 + 3 < (uint32_t)n ? row[4] : 0.0f;
+                }
+            const double hp = 1.0 / (double)n;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 13; ++j) {
+                    const int ox = half_off(3, j, 0), oy = half_off(3, j, 1), oz = half_off(3, j, 2);
+                    // couplings along one axis are k = 0 times the samples:
+                    // zeros, which leave both sums unchanged for a finite
+                    // iterate (see base_item)
+                    if ((ox != 0) + (oy != 0) + (oz != 0) == 1) continue;
+                    const float a = base_item(e, i, ox, oy, oz, hp), b = base_item(e, i, -ox, -oy, -oz, hp);
+                    acc[i] += a * U[(oy + 1) + 3 * (oz + 1)][1 + ox + i];
+                    dsum[i] += a;
+                    acc[i] += b * U[(1 - oy) + 3 * (1 - oz)][1 - ox + i];
+                    dsum[i] += b;
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 13; ++j) {
+                const int ox = half_off(3, j, 0), oy = half_off(3, j, 1), oz = half_off(3, j, 2);
+                const ptrdiff_t lin = ox + (ptrdiff_t)oy * (ptrdiff_t)nv + (ptrdiff_t)oz * (ptrdiff_t)(nv * nv);
+                const float *Sj = S + (size_t)j * NV;
+                float A[4], B[4];
+                ldv4(Sj + v, A);
+                ldv4(Sj + v - lin, B);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    acc[i] += A[i] * U[(oy + 1) + 3 * (oz + 1)][1 + ox + i];
+                    dsum[i] += A[i];
+                    acc[i] += B[i] * U[(1 - oy) + 3 * (1 - oz)][1 - ox + i];
+                    dsum[i] += B[i];
+                }
+            }
+        }
+        float F[4];
+        ldv4(f + v, F);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float Dv = -dsum[i];
+            const float Au = Dv * U[4][1 + i] + acc[i];
+            const float r = F[i] - Au;
+            o[i] = MODE == 1 ? r : U[4][1 + i] + omega * r / Dv;
+        }
+        if (x0 + 3 == (uint32_t)n) o[3] = 0.0f;
+    }
+    stv4(out + v, o);
+}
+
 // ---- 3D sweep and residual on the compressed finest store (mixed form).
 // A vertex's 26 couplings all lie in the 2 x 2 x 2 cells around it: the
 // centre-sample base of the coupling to v + o sums the samples of the cells
@@ -568,13 +702,27 @@ int store_set_base(mgd_hier *h, OpSet &o, const float *eps_c, hipStream_t st);
 StoreView store_view(const mgd_hier *h, const OpSet &o);
 
 // the 3D mixed finest level decodes the compressed store per vertex only when
-// asked to (MGD_STORE_DECODE); by default it reads the FP32 decode (same
-// values, same results bit for bit), which is faster: the per-vertex decode
-// re-evaluates 26 couplings in FP64 for every vertex of every pass
+// asked to (MGD_STORE_DECODE): the per-vertex decode re-evaluates 26
+// couplings in FP64 for every vertex of every pass and looks up the tiles of
+// its mirrored couplings one by one.  MGD_STORE_COPY reads the FP32 decode;
+// by default (MGD_STORE_AUTO) the sweeps and residuals re-evaluate only
+// items whose sources are all tier 0, sharing the work across the item
+// (k_sweep3x4h).  Same values, same results bit for bit
 static bool store3_decode(const mgd_hier *h)
 {
     if (h->dim != 3 || h->precision != MGD_MIXED) return false;
     return h->store_path == MGD_STORE_DECODE;
+}
+
+// the tier-0 item mask of the finest level, rebuilt after every change of
+// the operator (one pass over the tile tiers)
+static void ensure_imask(mgd_hier *h, const OpSet &o, hipStream_t st)
+{
+    if (o.dz_ok & kImaskOk) return;
+    const int n = h->n;
+    const int64_t items = (int64_t)(n / 4) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_item_mask, dim3(grid_for(items, 256)), dim3(256), 0, st, o.tier, n, o.imask);
+    o.dz_ok |= kImaskOk;
 }
 
 template <int D, typename T>
@@ -608,6 +756,21 @@ static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *
         if (mode == 1) hipLaunchKernelGGL((k_sweep3_store<1, false>), gr, dim3(256), 0, st, sv, n, uf, ff, of, (float)omega);
         else if (zero_guess) hipLaunchKernelGGL((k_sweep3_store<0, true>), gr, dim3(256), 0, st, sv, n, uf, ff, of, (float)omega);
         else hipLaunchKernelGGL((k_sweep3_store<0, false>), gr, dim3(256), 0, st, sv, n, uf, ff, of, (float)omega);
+        HIPCHK(h->ctx, hipGetLastError());
+        return MGD_OK;
+    }
+    if (D == 3 && h->precision == MGD_MIXED && level == 0 && h->store_path == MGD_STORE_AUTO && o.imask &&
+        !zero_guess && !partial) {
+        // the default: tier-0 sources re-evaluated from eps_c, the rest read
+        // from the FP32 decode
+        ensure_imask(h, o, st);
+        const dim3 g4(items4_blocks(n));
+        const float *uf = (const float *)u, *ff = (const float *)f;
+        float *of = (float *)out;
+        if (mode == 1)
+            hipLaunchKernelGGL((k_sweep3x4h<1>), g4, dim3(256), 0, st, o.S32[0], o.imask, o.eps_c, n, uf, ff, of, (float)omega);
+        else
+            hipLaunchKernelGGL((k_sweep3x4h<0>), g4, dim3(256), 0, st, o.S32[0], o.imask, o.eps_c, n, uf, ff, of, (float)omega);
         HIPCHK(h->ctx, hipGetLastError());
         return MGD_OK;
     }

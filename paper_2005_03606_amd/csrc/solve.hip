@@ -735,6 +735,7 @@ size_t solve_footprint(int dim, int n, int precision, int transfer, int coarsest
     if (precision == MGD_MIXED) {
         int64_t ntile = (NV0 + 63) / 64;
         ops += (size_t)ntile * 5 + (size_t)ntile * (64 + 256 * H) + (size_t)ncell * 4 + 64;
+        if (dim == 3 && items4_fit(3, n)) ops += (size_t)(n / 4) * (n + 1) * (n + 1);  // tier-0 item mask
     }
     ops += (size_t)(m > 0 ? m * m : 1) * 8;
     if (m <= kCinvMax) ops += (size_t)(m > 0 ? m * m : 1) * 8;

@@ -337,6 +337,9 @@ int opset_alloc(mgd_hier *h, OpSet &o)
         if ((rc = dev_alloc(ctx, (void **)&o.payload, (size_t)o.payload_cap_units * 64))) return rc;
         if ((rc = dev_alloc(ctx, (void **)&o.eps_c, nc * 4))) return rc;
         if ((rc = dev_alloc(ctx, (void **)&o.units_total, 64))) return rc;
+        if (h->dim == 3 && items4_fit(3, h->n) &&
+            (rc = dev_alloc(ctx, (void **)&o.imask, (size_t)(h->n / 4) * h->NV[0] / (h->n + 1))))
+            return rc;
         HIPCHK(ctx, hipMemset(o.tier, 0, o.ntile));
         HIPCHK(ctx, hipMemset(o.toff, 0, o.ntile * 4));
         HIPCHK(ctx, hipMemset(o.units_total, 0, 4));
@@ -354,6 +357,6 @@ void opset_free(OpSet &o)
         o.S64[l] = nullptr; o.S32[l] = nullptr; o.W[l] = nullptr; o.Dz[l] = nullptr; o.wgeo[l] = nullptr;
     }
     dev_free(o.tier); dev_free(o.toff); dev_free(o.payload); dev_free(o.eps_c);
-    dev_free(o.units_total); dev_free(o.chol); dev_free(o.cinv);
+    dev_free(o.units_total); dev_free(o.chol); dev_free(o.cinv); dev_free(o.imask);
     o = OpSet();
 }
