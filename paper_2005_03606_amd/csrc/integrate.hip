@@ -356,6 +356,88 @@ __device__ inline double sample_coord(int ci, int q, int s, int n)
     return ((double)ci + ((double)q + 0.5) * (1.0 / (double)s)) / (double)n;
 }
 
+// ---- boxes on a cell's sample lattice.  sample_coord is monotone in the
+// sample index (each step rounds a monotone function), so the samples of a
+// cell that pass a box's test on axis m (x >= lower face, x < upper face)
+// form an index range [lo, hi), found once per cell by bisection with that
+// same test.  A box whose range is empty on some axis holds none of the
+// cell's samples; the others keep the descriptor's order, and painting a
+// sample compares small integers: the same box wins as in eps_eval, so eps
+// is the same value.
+constexpr int kCellBoxes = 8;
+template <typename T> struct CellBoxes {
+    int count;                 // boxes kept; -1: more than kCellBoxes reach the cell
+    T val[kCellBoxes];         // eps inside the box, rounded as eps_eval rounds it
+    // XMASK: lo_y | hi_y << 5 | lo_z << 10 | hi_z << 15 | x mask of the lane's
+    // 8 samples << 20; else lo_x | hi_x << 5 | lo_y << 10 | hi_y << 15 |
+    // lo_z << 20 | hi_z << 25
+    uint32_t rng[kCellBoxes];
+};
+
+// smallest q in [0, s] whose sample coordinate is >= t
+__device__ inline int first_sample_at_least(int ci, int s, int n, double t)
+{
+    int lo = 0, hi = s;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sample_coord(ci, mid, s, n) >= t) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// the boxes of `rows` that hold samples of cell ci (s <= 16); with XMASK the
+// lane's 8 samples have x indices (qx0 + e) mod s
+template <int D, typename T, bool XMASK>
+__device__ inline void cell_boxes(const int *ci, int s, int n, int qx0, const double *rows, int count,
+                                  CellBoxes<T> &cb)
+{
+    double first[3], last[3];
+    for (int m = 0; m < D; ++m) {
+        first[m] = sample_coord(ci[m], 0, s, n);
+        last[m] = sample_coord(ci[m], s - 1, s, n);
+    }
+    cb.count = 0;
+    for (int b = 0; b < count; ++b) {
+        const double *row = rows + (size_t)b * (2 * D + 1);
+        bool reach = true;
+        for (int m = 0; m < D; ++m) reach = reach && row[D + m] > first[m] && row[m] <= last[m];
+        if (!reach) continue;
+        int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+        bool empty = false;
+        for (int m = 0; m < D; ++m) {
+            lo[m] = first_sample_at_least(ci[m], s, n, row[m]);
+            hi[m] = first_sample_at_least(ci[m], s, n, row[D + m]);
+            empty = empty || lo[m] >= hi[m];
+        }
+        if (empty) continue;
+        if (cb.count == kCellBoxes) {
+            cb.count = -1;
+            return;
+        }
+        uint32_t r;
+        if (XMASK) {
+            uint32_t xm = 0;
+            for (int e = 0; e < 8; ++e) {
+                const int qx = (qx0 + e) & (s - 1);
+                if (qx >= lo[0] && qx < hi[0]) xm |= 1u << e;
+            }
+            r = (uint32_t)lo[1] | (uint32_t)hi[1] << 5 | (uint32_t)lo[2] << 10 | (uint32_t)hi[2] << 15 | xm << 20;
+        } else {
+            r = (uint32_t)lo[0] | (uint32_t)hi[0] << 5 | (uint32_t)lo[1] << 10 | (uint32_t)hi[1] << 15 |
+                (uint32_t)lo[2] << 20 | (uint32_t)hi[2] << 25;
+        }
+        const T v = (T)row[2 * D];
+#pragma unroll
+        for (int k = 0; k < kCellBoxes; ++k)
+            if (k == cb.count) {
+                cb.val[k] = v;
+                cb.rng[k] = r;
+            }
+        ++cb.count;
+    }
+}
+
 // M_q(a,b) over the q-th of s sub-intervals: index 0 = (0,0), 1 = (0,1), 2 = (1,1)
 __device__ inline void moments64(int s, int q, double *M)
 {
@@ -439,6 +521,22 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
         build_candidates<D>(a.eps, n, valid, ci, ci, cand, &rows, &nrows);
         EpsCell<D, double> ecell;
         eps_cell_prepare<D, double>(a.eps, n, valid, ci, ecell);
+        // boxes from s = 8 on: painted from the cell's index ranges unless a
+        // lane's cell in the wave is reached by more than kCellBoxes boxes
+        CellBoxes<double> cbx;
+        cbx.count = 0;
+        bool fastbox = false;
+        int kmax = 0;
+        if (EK == MGD_EPS_BOXES && s >= 8) {
+            if (valid) cell_boxes<D, double, false>(ci, s, n, 0, rows, nrows, cbx);
+            int c = cbx.count, over = cbx.count < 0 ? 1 : 0;
+            for (int off = 32; off > 0; off >>= 1) {
+                c = max(c, __shfl_xor(c, off));
+                over = max(over, __shfl_xor(over, off));
+            }
+            fastbox = over == 0;
+            kmax = c;
+        }
         int nlines = (D == 2) ? s : s * s;
         int64_t nq = (int64_t)nlines * s;
         // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
@@ -456,6 +554,18 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
                 double x[3];
                 x[1] = sample_coord(ci[1], qy, s, n);
                 if (D == 3) x[2] = sample_coord(ci[2], qz, s, n);
+                // the kept boxes whose y and z ranges hold this line
+                uint32_t yzm = 0;
+                if (EK == MGD_EPS_BOXES && fastbox) {
+#pragma unroll
+                    for (int k = 0; k < kCellBoxes; ++k) {
+                        if (k >= kmax) break;
+                        const uint32_t r = cbx.rng[k];
+                        if (k < cbx.count && (uint32_t)qy >= (r >> 10 & 31u) && (uint32_t)qy < (r >> 15 & 31u) &&
+                            (uint32_t)qz >= (r >> 20 & 31u) && (uint32_t)qz < (r >> 25 & 31u))
+                            yzm |= 1u << k;
+                    }
+                }
                 // a lattice cell inside one lattice cell: along the x-line
                 // p0 g = ga + t_x gb (FP64), one exp per sample
                 const bool latl = EK == MGD_EPS_LATTICE && ecell.ok;
@@ -480,6 +590,15 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
                         e = a.samples[i * nq + q];
                     } else if (latl) {
                         e = exp(ga + (sample_coord(ci[0], qx, s, n) * a.eps.count - ecell.base[0]) * gb);
+                    } else if (EK == MGD_EPS_BOXES && fastbox) {
+                        e = a.eps.p0;
+#pragma unroll
+                        for (int k = 0; k < kCellBoxes; ++k) {
+                            if (k >= kmax) break;
+                            const uint32_t r = cbx.rng[k];
+                            if ((yzm >> k & 1u) && (uint32_t)qx >= (r & 31u) && (uint32_t)qx < (r >> 5 & 31u))
+                                e = cbx.val[k];
+                        }
                     } else {
                         x[0] = sample_coord(ci[0], qx, s, n);
                         e = eps_eval_cell<D, double, EK>(a.eps, ecell, x, rows, nrows);
@@ -612,6 +731,25 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
         if (WL) build_candidates_wave<D>(a.eps, n, valid, ci, wrows[wave], &rows, &nrows);
         EpsCell<D, float> ecell;
         eps_cell_prepare<D, float>(a.eps, n, valid, ci, ecell);
+        // boxes from s = 8 on (below, preparing a cell's ranges costs about
+        // what the per-sample test does): the wave paints from the ranges
+        // unless a lane's cell is reached by more than kCellBoxes boxes
+        CellBoxes<float> cbx;
+        cbx.count = 0;
+        bool fastbox = false;
+        int kmax = 0;
+        uint32_t yzm = 0;
+        const float bg = (float)a.eps.p0;
+        if (EK == MGD_EPS_BOXES && s >= 8) {
+            if (valid) cell_boxes<D, float, true>(ci, s, n, kg * 8, rows, nrows, cbx);
+            int c = cbx.count, over = cbx.count < 0 ? 1 : 0;
+            for (int off = 32; off > 0; off >>= 1) {
+                c = max(c, __shfl_xor(c, off));
+                over = max(over, __shfl_xor(over, off));
+            }
+            fastbox = over == 0;
+            kmax = c;
+        }
         // sample q = ch 32 + kg 8 + e has x-index q mod s = (kg 8 + e) mod s
         // for every chunk (s divides 32): the lane's eight x coordinates are
         // computed once; y and z only when q / s changes
@@ -646,6 +784,29 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
                 if (valid && q < nq) {
                     if (kind == MGD_EPS_SAMPLES) {
                         ev = (float)a.samples[i * nq + q];
+                    } else if (EK == MGD_EPS_BOXES && fastbox) {
+                        const int qr = q >> ls;
+                        if (qr != qr_last) {
+                            // the kept boxes whose y and z ranges hold this sample row
+                            const uint32_t qy = (uint32_t)(qr & (s - 1)), qz = D == 3 ? (uint32_t)(qr >> ls) : 0u;
+                            yzm = 0;
+#pragma unroll
+                            for (int k = 0; k < kCellBoxes; ++k) {
+                                if (k >= kmax) break;
+                                const uint32_t r = cbx.rng[k];
+                                if (k < cbx.count && qy >= (r & 31u) && qy < (r >> 5 & 31u) && qz >= (r >> 10 & 31u) &&
+                                    qz < (r >> 15 & 31u))
+                                    yzm |= 1u << k;
+                            }
+                            qr_last = qr;
+                        }
+                        float v = bg;
+#pragma unroll
+                        for (int k = 0; k < kCellBoxes; ++k) {
+                            if (k >= kmax) break;
+                            if ((yzm >> k & 1u) && (cbx.rng[k] >> (20 + e) & 1u)) v = cbx.val[k];
+                        }
+                        ev = v;
                     } else {
                         const int qr = q >> ls;
                         if (qr != qr_last) {
@@ -904,11 +1065,14 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         if (stride) hipLaunchKernelGGL((k_integrate64<DD, GG, true, TO, EK>), dim3(grid), dim3(256), 0, st, a); \
         else hipLaunchKernelGGL((k_integrate64<DD, GG, false, TO, EK>), dim3(grid), dim3(256), 0, st, a);       \
     } while (0)
-        // lattice and ball fields: instantiations without the other kinds' code
+        // lattice, ball and box fields: instantiations without the other kinds'
+        // code (boxes from s = 8 on, where painting from index ranges pays for
+        // the registers it takes)
 #define L64T(DD, GG, TO)                                                                 \
     do {                                                                                 \
         if (a.eps.kind == MGD_EPS_LATTICE) L64K(DD, GG, TO, MGD_EPS_LATTICE);           \
         else if (a.eps.kind == MGD_EPS_BALLS) L64K(DD, GG, TO, MGD_EPS_BALLS);          \
+        else if (a.eps.kind == MGD_EPS_BOXES && s >= 8) L64K(DD, GG, TO, MGD_EPS_BOXES); \
         else L64K(DD, GG, TO, -1);                                                       \
     } while (0)
 #define L64(DD, GG)                                  \
@@ -940,12 +1104,14 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
             hipLaunchKernelGGL((k_integrate_mfma<DD, NT, NTERM, TPW, false, EK>), dim3(grid), dim3(256), 0, st,  \
                                a, T->dev, T->nchunks, (float)inv_den);                                           \
     } while (0)
-        // lattice and ball fields get instantiations without the other kinds'
-        // code (the unrolled sample loop then fits the instruction cache)
+        // lattice, ball and box fields get instantiations without the other
+        // kinds' code (the unrolled sample loop then fits the instruction
+        // cache; boxes paint from per-cell index ranges, from s = 8 on)
 #define LM(DD, NT, NTERM, TPW)                                                                  \
     do {                                                                                        \
         if (a.eps.kind == MGD_EPS_LATTICE) LMK(DD, NT, NTERM, TPW, MGD_EPS_LATTICE);           \
         else if (a.eps.kind == MGD_EPS_BALLS) LMK(DD, NT, NTERM, TPW, MGD_EPS_BALLS);          \
+        else if (a.eps.kind == MGD_EPS_BOXES && s >= 8) LMK(DD, NT, NTERM, TPW, MGD_EPS_BOXES); \
         else LMK(DD, NT, NTERM, TPW, -1);                                                       \
     } while (0)
         if (dim == 2) {

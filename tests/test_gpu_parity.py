@@ -92,6 +92,68 @@ def test_assemble_explicit_samples(ctx):
     assert rel_err(host(K), ref) < 1e-13
 
 
+def _oracle_cell_samples(fld, d, n, s, cells):
+    """eps of the oracle at every sample point x_q = (c + (q + 1/2)/s)/n of
+    the given cells, q ascending (x fastest)."""
+    ref = O._FieldRef(fld)
+    out = np.zeros((len(cells), s ** d))
+    for k, c in enumerate(cells):
+        ci = [(c // n ** m) % n for m in range(d)]
+        for q in range(s ** d):
+            qm = [(q // s ** m) % s for m in range(d)]
+            x = np.array([(ci[m] + (qm[m] + 0.5) / s) / n for m in range(d)])
+            out[k, q] = O.lib().orc_eps(ref.ptr, x)
+    return out
+
+
+def _boxes_reaching(fld, d, n, s, cells):
+    """Per cell, the number of boxes that hold at least one of its samples."""
+    rows = np.asarray(fld.data).reshape(fld.count, 2 * d + 1)
+    out = []
+    for c in cells:
+        ci = [(c // n ** m) % n for m in range(d)]
+        hit = np.ones(len(rows), bool)
+        for m in range(d):
+            xs = (ci[m] + (np.arange(s) + 0.5) / s) / n
+            inside = (xs[None, :] >= rows[:, m:m + 1]) & (xs[None, :] < rows[:, d + m:d + m + 1])
+            hit &= inside.any(1)
+        out.append(int(hit.sum()))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("mode", ["mixed", "fp64"])
+@pytest.mark.parametrize("s", [8, 16])
+@pytest.mark.parametrize("d,many", [(2, False), (2, True), (3, False), (3, True)])
+def test_assemble_boxes_equals_explicit_samples(ctx, d, s, many, mode):
+    """Box fields in the integration (bf16 hi+lo MFMA and FP64) paint a
+    cell's samples from per-cell index ranges of its boxes (s >= 8).  The
+    element matrices equal, bit for bit, those assembled from the oracle's
+    eps at the same sample points passed as explicit samples, so every sample
+    took the same box.  `many`: large overlapping boxes, some cells reached by
+    more than eight (their waves take the per-sample test), the others
+    painted from ranges."""
+    n = 6 if d == 3 else 12
+    if d == 3:
+        fld = (W.boxes_field(3, 50, 50, side_lo=0.2, side_hi=0.5) if many
+               else W.boxes_field(3, 14, 40, side_lo=0.05, side_hi=0.3))
+    else:
+        fld = (W.boxes_field(2, 30, 56, side_lo=0.2, side_hi=0.5) if many
+               else W.boxes_field(2, 10, 43, side_lo=0.05, side_hi=0.3))
+    cells = np.arange(0, 64, 2, dtype=np.int64)  # two waves of 16 cells
+    reach = _boxes_reaching(fld, d, n, s, cells)
+    if many:
+        # the first wave at the limit of eight boxes per cell, the second past it
+        assert reach[:16].max() == 8 and reach[16:].max() > 8, reach
+    else:
+        assert 2 <= reach.max() <= 8, reach
+    samp = _oracle_cell_samples(fld, d, n, s, cells)
+    cd = dev(cells, torch.int64)
+    pm = P.MIXED if mode == "mixed" else P.FP64
+    Kf, _, _ = P.assemble_cells(ctx, d, n, s, P.Eps(fld), pm, cells=cd)
+    Ks, _, _ = P.assemble_cells(ctx, d, n, s, P.Eps.samples(d, dev(samp)), pm, cells=cd)
+    assert torch.equal(Kf, Ks)
+
+
 @pytest.mark.parametrize("d,name", [(2, "sine"), (2, "balls"), (2, "lattice"), (3, "lattice"), (3, "balls")])
 @pytest.mark.parametrize("s", [2, 8, 16])
 def test_assemble_mixed_error_bound(ctx, d, name, s):
