@@ -438,6 +438,60 @@ __device__ inline void cell_boxes(const int *ci, int s, int n, int qx0, const do
     }
 }
 
+// ---- boxes at small s (2 and 4 samples per axis, FP64 kernel): the boxes
+// of the candidate list that can hold one of the cell's samples (upper face
+// above its first sample and lower face at most its last one, per axis), at
+// most kCellCand in descriptor order; each sample then takes eps_eval's test
+// against those alone, so the same box wins.  count -1: more reach the cell,
+// and the whole list is tested.  (In the MFMA kernel the registers it takes
+// cost a wave per SIMD at s = 4, more than it saves.)
+constexpr int kCellCand = 4;
+struct CellCand {
+    int count;
+    int idx[kCellCand];
+};
+
+template <int D>
+__device__ inline void cell_candidates(const int *ci, int s, int n, const double *rows, int count, CellCand &cc)
+{
+    double first[3], last[3];
+    for (int m = 0; m < D; ++m) {
+        first[m] = sample_coord(ci[m], 0, s, n);
+        last[m] = sample_coord(ci[m], s - 1, s, n);
+    }
+    cc.count = 0;
+    for (int b = 0; b < count; ++b) {
+        const double *row = rows + (size_t)b * (2 * D + 1);
+        bool reach = true;
+        for (int m = 0; m < D; ++m) reach = reach && row[D + m] > first[m] && row[m] <= last[m];
+        if (!reach) continue;
+        if (cc.count == kCellCand) {
+            cc.count = -1;
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < kCellCand; ++k)
+            if (k == cc.count) cc.idx[k] = b;
+        ++cc.count;
+    }
+}
+
+// eps_eval's box case over the prefiltered rows
+template <int D, typename T>
+__device__ inline T eps_boxes_cand(const EpsDev &e, const double *x, const double *rows, const CellCand &cc)
+{
+    double v = e.p0;
+#pragma unroll
+    for (int k = 0; k < kCellCand; ++k) {
+        if (k >= cc.count) break;
+        const double *row = rows + (size_t)cc.idx[k] * (2 * D + 1);
+        bool in = true;
+        for (int m = 0; m < D; ++m) in = in && x[m] >= row[m] && x[m] < row[D + m];
+        if (in) v = row[2 * D];
+    }
+    return (T)v;
+}
+
 // M_q(a,b) over the q-th of s sub-intervals: index 0 = (0,0), 1 = (0,1), 2 = (1,1)
 __device__ inline void moments64(int s, int q, double *M)
 {
@@ -537,6 +591,11 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
             fastbox = over == 0;
             kmax = c;
         }
+        // the generic instantiation at s = 2 and 4 on a box field
+        CellCand cand4;
+        cand4.count = -1;
+        const bool boxcand = EK < 0 && a.eps.kind == MGD_EPS_BOXES && s >= 2 && s <= 4;
+        if (boxcand && valid) cell_candidates<D>(ci, s, n, rows, nrows, cand4);
         int nlines = (D == 2) ? s : s * s;
         int64_t nq = (int64_t)nlines * s;
         // accumulators: T1[ty][tz] = sum eps My Mz, T2[tx][tz] = sum eps Mx Mz,
@@ -601,7 +660,8 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
                         }
                     } else {
                         x[0] = sample_coord(ci[0], qx, s, n);
-                        e = eps_eval_cell<D, double, EK>(a.eps, ecell, x, rows, nrows);
+                        e = boxcand && cand4.count >= 0 ? eps_boxes_cand<D, double>(a.eps, x, rows, cand4)
+                                                        : eps_eval_cell<D, double, EK>(a.eps, ecell, x, rows, nrows);
                     }
                     double Mx[3];
                     moments64(s, qx, Mx);
