@@ -262,6 +262,7 @@ def sweep_roofline(P, W, n, sweeps):
     items, items_inner = (n // 4) * (n + 1) ** 2, (n // 4) * (n - 1) ** 2
     t0 = tier0_items(tier, n)
     del tier
+    t0_lib = h.tier0_items()[1]  # the library's own count (equal by construction)
     pass_bytes = 12 * NV + 208 * (items_inner - t0) + 16 * t0 + items
     decode_pass_bytes = 64 * NV
     store_pass_bytes = payload + 5 * ntile + 4 * n ** d + 12 * NV
@@ -287,7 +288,8 @@ def sweep_roofline(P, W, n, sweeps):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(n),
             "kernel": SWEEP_KERNEL, "bytes_per_launch": int(pass_bytes),
-            "bytes_per_dof": round(pass_bytes / NV, 2), "tier0_items": t0, "items": items_inner,
+            "bytes_per_dof": round(pass_bytes / NV, 2), "tier0_items": t0, "tier0_items_library": t0_lib,
+            "items": items_inner,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": 2 * calls,
             "decode_form_bytes_per_launch": int(decode_pass_bytes), "decode_form_frac": frac(decode_pass_bytes),
             "store_form_bytes_per_launch": int(store_pass_bytes), "store_form_frac": frac(store_pass_bytes),

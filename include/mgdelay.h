@@ -243,6 +243,15 @@ int mgd_compress_stencils_noalloc(mgd_ctx *ctx, mgd_hier *h, const float *S32, c
  * geometric hierarchy or a level without a coarser one. */
 int mgd_weight_tiles(mgd_ctx *ctx, const mgd_hier *h, int32_t level, int64_t *ntile, int64_t *geo_tiles);
 
+/* Items of the finest level of a 3D mixed hierarchy as the default sweep
+ * takes them (four consecutive vertices of a grid row, x0 = 1 + 4c; n % 4
+ * == 0) and how many of them re-evaluate their couplings from the centre
+ * samples (Sec. 5.5: every coupling source in a tier-0 tile, i.e. no stored
+ * surplus).  Built from the current store on `stream`; synchronous.  0 and 0
+ * when n % 4 != 0 (the sweep then reads the decode for every vertex).
+ * MGD_EINVAL for a 2D or FP64 hierarchy. */
+int mgd_tier0_items(mgd_ctx *ctx, mgd_hier *h, int64_t *items, int64_t *tier0, hipStream_t stream);
+
 /* Copy the compressed store out (dev buffers; pass NULL to skip one):
  * tile_tier uint8 [ntile], tile_off uint32 [ntile], payload (payload_bytes).
  * Host scalars ntile / payload_bytes are returned synchronously. */

@@ -108,6 +108,7 @@ def lib():
                             C.POINTER(C.c_int64 * 4)], C.c_int),
         "mgd_store_export": ([_P, _P, _P, _P, _P, _P], C.c_int),
         "mgd_weight_tiles": ([_P, _P, _I, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+        "mgd_tier0_items": ([_P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _P], C.c_int),
         "mgd_coarsen": ([_P, _P, _P], C.c_int),
         "mgd_level_stencils": ([_P, _P, C.c_int, _P, _P], C.c_int),
         "mgd_level_weights": ([_P, _P, C.c_int, _P, _P], C.c_int),
@@ -428,6 +429,13 @@ class Hierarchy:
         nt, geo = C.c_int64(), C.c_int64()
         self.ctx.check(lib().mgd_weight_tiles(self.ctx.h, self.h, level, C.byref(nt), C.byref(geo)))
         return nt.value, geo.value
+
+    def tier0_items(self, stream=None):
+        """(items, items re-evaluated from the centre samples) of the default
+        3D sweep on the finest level."""
+        it, t0 = C.c_int64(), C.c_int64()
+        self.ctx.check(lib().mgd_tier0_items(self.ctx.h, self.h, C.byref(it), C.byref(t0), _stream(stream)))
+        return it.value, t0.value
 
     def store_export(self, stream=None):
         nt, pb, _ = self.store_info()

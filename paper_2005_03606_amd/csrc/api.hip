@@ -309,6 +309,15 @@ int mgd_compress_stencils(mgd_ctx *ctx, mgd_hier *h, const float *S32, const flo
     return compress_into(h, h->ops, S32, eps_c, pol, h->delta, h->vtier, stream);
 }
 
+int mgd_tier0_items(mgd_ctx *ctx, mgd_hier *h, int64_t *items, int64_t *tier0, hipStream_t stream)
+{
+    if (!ctx || !h || !items || !tier0) return MGD_EINVAL;
+    if (h->dim != 3 || h->precision != MGD_MIXED)
+        return mgd_fail(ctx, MGD_EINVAL, "tier-0 items exist for a 3D mixed hierarchy only");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return item_mask_count(h, items, tier0, stream);
+}
+
 int mgd_weight_tiles(mgd_ctx *ctx, const mgd_hier *h, int32_t level, int64_t *ntile, int64_t *geo_tiles)
 {
     if (!ctx || !h || !ntile || !geo_tiles) return MGD_EINVAL;

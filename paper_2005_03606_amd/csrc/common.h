@@ -335,6 +335,8 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
 // the paper's p3-byte format of element-matrix surpluses (paper.hip)
 int launch_p3_encode(mgd_ctx *ctx, int dim, const double *K, const double *K1, int64_t count, double tau,
                      uint8_t *p3_out, uint8_t *bytes_out, hipStream_t st);
+// finest-level items of the default 3D sweep and its tier-0 ones (cycle.hip)
+int item_mask_count(mgd_hier *h, int64_t *items, int64_t *tier0, hipStream_t st);
 int launch_compact_open(mgd_ctx *ctx, const uint8_t *done, const int64_t *cells_in, const int64_t *count_dev,
                         int64_t count_bound, int32_t *block_tmp, int64_t *cells_out, int64_t *count_out,
                         hipStream_t st);

@@ -5,6 +5,7 @@
 // and the vector kernels of the outer iteration, with deterministic
 // (fixed-order) reductions.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -723,6 +724,27 @@ static void ensure_imask(mgd_hier *h, const OpSet &o, hipStream_t st)
     const int64_t items = (int64_t)(n / 4) * (n + 1) * (n + 1);
     hipLaunchKernelGGL(k_item_mask, dim3(grid_for(items, 256)), dim3(256), 0, st, o.tier, n, o.imask);
     o.dz_ok |= kImaskOk;
+}
+
+// items of the finest level and those the default 3D sweep re-evaluates
+// from the centre samples (synchronous; 0 and 0 where that path is absent)
+int item_mask_count(mgd_hier *h, int64_t *items, int64_t *tier0, hipStream_t st)
+{
+    *items = 0;
+    *tier0 = 0;
+    if (h->dim != 3 || h->precision != MGD_MIXED || !h->ops.imask) return MGD_OK;
+    const int n = h->n;
+    const int64_t cnt = (int64_t)(n / 4) * (n + 1) * (n + 1);
+    ensure_imask(h, h->ops, st);
+    HIPCHK(h->ctx, hipGetLastError());
+    std::vector<uint8_t> m((size_t)cnt);
+    HIPCHK(h->ctx, hipStreamSynchronize(st));
+    HIPCHK(h->ctx, hipMemcpy(m.data(), h->ops.imask, (size_t)cnt, hipMemcpyDeviceToHost));
+    int64_t c = 0;
+    for (uint8_t b : m) c += b != 0;
+    *items = cnt;
+    *tier0 = c;
+    return MGD_OK;
 }
 
 template <int D, typename T>

@@ -800,6 +800,8 @@ def test_store_paths_bit_identical_3d(ctx, n):
         h.coarsen()
         tiers = h.store_info()[2]
         t0, nitem = tier0_items(host(h.store_export()[0]), n)
+        # the library's own item flags (built on first use) against the definition
+        assert h.tier0_items() == ((n // 4) * (n + 1) ** 2, t0)
         res = []
         for start in (None, u):
             uo, ro = torch.zeros_like(f), torch.zeros_like(f)
@@ -818,6 +820,10 @@ def test_store_paths_bit_identical_3d(ctx, n):
     # the default path re-evaluates some items and reads the decode for others
     print("tier-0 items", t0, "of", nitem)
     assert 0 < t0 < nitem, (t0, nitem)
+    h2 = P.Hierarchy(ctx, 2, 16, precision=P.MIXED, transfer=P.BOXMG)
+    with pytest.raises(P.MgdError):
+        h2.tier0_items()
+    h2.close()
     for sp in (P.STORE_DECODE, P.STORE_AUTO):
         for k, (a, b) in enumerate(zip(outs[sp], outs[P.STORE_COPY])):
             assert np.array_equal(a, b), (sp, k)
