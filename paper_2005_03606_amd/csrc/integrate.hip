@@ -446,6 +446,10 @@ __device__ inline void cell_boxes(const int *ci, int s, int n, int qx0, const do
 // and the whole list is tested.  (In the MFMA kernel the registers it takes
 // cost a wave per SIMD at s = 4, more than it saves.)
 constexpr int kCellCand = 4;
+// instantiation code of the FP64 kernel for box fields at s <= 4: box
+// evaluation only (no other field kind's code or registers) with the
+// per-cell candidates below
+constexpr int kBoxesSmall = 64;
 struct CellCand {
     int count;
     int idx[kCellCand];
@@ -559,6 +563,7 @@ __device__ inline void store_and_check(const AsmArgs &a, int64_t i, int64_t cell
 template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bounds__(256) void k_integrate64(AsmArgs a)
 {
     __shared__ CandLDS cand;
+    constexpr int EKF = EK == kBoxesSmall ? MGD_EPS_BOXES : EK;  // the field kind evaluated
     const int64_t cnt = asm_count(a);
     for (int64_t blk = blockIdx.x;; blk += gridDim.x) {
         if (blk * (int64_t)blockDim.x / G >= cnt) return;  // uniform, before any barrier
@@ -574,7 +579,7 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
         int nrows;
         build_candidates<D>(a.eps, n, valid, ci, ci, cand, &rows, &nrows);
         EpsCell<D, double> ecell;
-        eps_cell_prepare<D, double>(a.eps, n, valid, ci, ecell);
+        if (EKF < 0 || EKF == MGD_EPS_LATTICE) eps_cell_prepare<D, double>(a.eps, n, valid, ci, ecell);
         // boxes from s = 8 on: painted from the cell's index ranges unless a
         // lane's cell in the wave is reached by more than kCellBoxes boxes
         CellBoxes<double> cbx;
@@ -594,7 +599,7 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
         // the generic instantiation at s = 2 and 4 on a box field
         CellCand cand4;
         cand4.count = -1;
-        const bool boxcand = EK < 0 && a.eps.kind == MGD_EPS_BOXES && s >= 2 && s <= 4;
+        const bool boxcand = (EK < 0 || EK == kBoxesSmall) && a.eps.kind == MGD_EPS_BOXES && s >= 2 && s <= 4;
         if (boxcand && valid) cell_candidates<D>(ci, s, n, rows, nrows, cand4);
         int nlines = (D == 2) ? s : s * s;
         int64_t nq = (int64_t)nlines * s;
@@ -644,7 +649,7 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
                 }
                 for (int qx = 0; qx < s; ++qx) {
                     double e;
-                    if ((EK >= 0 ? EK : a.eps.kind) == MGD_EPS_SAMPLES) {
+                    if ((EKF >= 0 ? EKF : a.eps.kind) == MGD_EPS_SAMPLES) {
                         int64_t q = qx + (int64_t)s * line;
                         e = a.samples[i * nq + q];
                     } else if (latl) {
@@ -661,7 +666,7 @@ template <int D, int G, bool STRIDE, typename TO, int EK> __global__ __launch_bo
                     } else {
                         x[0] = sample_coord(ci[0], qx, s, n);
                         e = boxcand && cand4.count >= 0 ? eps_boxes_cand<D, double>(a.eps, x, rows, cand4)
-                                                        : eps_eval_cell<D, double, EK>(a.eps, ecell, x, rows, nrows);
+                                                        : eps_eval_cell<D, double, EKF>(a.eps, ecell, x, rows, nrows);
                     }
                     double Mx[3];
                     moments64(s, qx, Mx);
@@ -1133,6 +1138,7 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         if (a.eps.kind == MGD_EPS_LATTICE) L64K(DD, GG, TO, MGD_EPS_LATTICE);           \
         else if (a.eps.kind == MGD_EPS_BALLS) L64K(DD, GG, TO, MGD_EPS_BALLS);          \
         else if (a.eps.kind == MGD_EPS_BOXES && s >= 8) L64K(DD, GG, TO, MGD_EPS_BOXES); \
+        else if (a.eps.kind == MGD_EPS_BOXES) L64K(DD, GG, TO, kBoxesSmall);            \
         else L64K(DD, GG, TO, -1);                                                       \
     } while (0)
 #define L64(DD, GG)                                  \
