@@ -446,8 +446,8 @@ __device__ inline void cell_boxes(const int *ci, int s, int n, int qx0, const do
 // and the whole list is tested.  (In the MFMA kernel the registers it takes
 // cost a wave per SIMD at s = 4, more than it saves.)
 constexpr int kCellCand = 4;
-// instantiation code of the FP64 kernel for box fields at s <= 4: box
-// evaluation only (no other field kind's code or registers) with the
+// instantiation code for box fields below s = 8: box evaluation only (no
+// other field kind's code or registers); in the FP64 kernel with the
 // per-cell candidates below
 constexpr int kBoxesSmall = 64;
 struct CellCand {
@@ -758,6 +758,7 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
                                                     float (*ko)[16][n_pairs(D) + 1], CandLDS &cand,
                                                     double (*wrows)[kWaveCand * 7])
 {
+    constexpr int EKF = EK == kBoxesSmall ? MGD_EPS_BOXES : EK;  // the field kind evaluated
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int row = lane & 15, kg = lane >> 4;
     const int64_t blk0 = blk * (64 * TPW);
@@ -795,7 +796,7 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
         cell_coords<D>(cell, n, ci);
         if (WL) build_candidates_wave<D>(a.eps, n, valid, ci, wrows[wave], &rows, &nrows);
         EpsCell<D, float> ecell;
-        eps_cell_prepare<D, float>(a.eps, n, valid, ci, ecell);
+        if (EKF < 0 || EKF == MGD_EPS_LATTICE) eps_cell_prepare<D, float>(a.eps, n, valid, ci, ecell);
         // boxes from s = 8 on (below, preparing a cell's ranges costs about
         // what the per-sample test does): the wave paints from the ranges
         // unless a lane's cell is reached by more than kCellBoxes boxes
@@ -828,7 +829,7 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
         // with g trilinear in the corner values, so along the lane's x-line
         // (y and z fixed) p0 g log2(e) = ga + t_x gb, and a sample costs one
         // FMA and one exp2; ga and gb change with y and z only
-        const int kind = EK >= 0 ? EK : a.eps.kind;
+        const int kind = EKF >= 0 ? EKF : a.eps.kind;
         const bool lat = kind == MGD_EPS_LATTICE && ecell.ok;
         const float kexp = (float)(a.eps.p0 * 1.4426950408889634);
         float txl[8], ga = 0.0f, gb = 0.0f;
@@ -898,7 +899,7 @@ __device__ __forceinline__ void integrate_mfma_tile(const AsmArgs &a, const uint
                             ev = __builtin_amdgcn_exp2f(ga + txl[e] * gb);
                         } else {
                             const double x[3] = {xq[e], xy, xz};
-                            ev = eps_eval_cell<D, float, EK>(a.eps, ecell, x, rows, nrows);
+                            ev = eps_eval_cell<D, float, EKF>(a.eps, ecell, x, rows, nrows);
                         }
                     }
                 }
@@ -1178,6 +1179,7 @@ int launch_assemble(mgd_ctx *ctx, int dim, int n, int s, const int64_t *cells, i
         if (a.eps.kind == MGD_EPS_LATTICE) LMK(DD, NT, NTERM, TPW, MGD_EPS_LATTICE);           \
         else if (a.eps.kind == MGD_EPS_BALLS) LMK(DD, NT, NTERM, TPW, MGD_EPS_BALLS);          \
         else if (a.eps.kind == MGD_EPS_BOXES && s >= 8) LMK(DD, NT, NTERM, TPW, MGD_EPS_BOXES); \
+        else if (a.eps.kind == MGD_EPS_BOXES) LMK(DD, NT, NTERM, TPW, kBoxesSmall);            \
         else LMK(DD, NT, NTERM, TPW, -1);                                                       \
     } while (0)
         if (dim == 2) {
