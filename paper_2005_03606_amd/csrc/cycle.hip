@@ -114,15 +114,29 @@ __global__ __launch_bounds__(256) void k_sweep3x4(const T *__restrict__ S, int n
     if (y != 0 && z != 0 && y != (uint32_t)n && z != (uint32_t)n) {
         T U[9][6];
         if (!ZERO) {
+            // x0 + 4 lies past the row's end on its last item (the last row
+            // of the array has nothing after it); vertex n, the one that
+            // would use it, is a boundary vertex.  In FP32 that item reads
+            // its pair one place lower and zeroes the missing value, so no
+            // load sits behind a branch and all of them issue together (80
+            // -> 64 VGPRs); the FP64 kernel keeps the branch: with the same
+            // change its 3D solves took 5-7 % longer
+            const bool last = x0 + 3 >= (uint32_t)n;
 #pragma unroll
             for (int r = 0; r < 9; ++r) {
                 const T *p = u + v - 1 + (ptrdiff_t)(r % 3 - 1) * (ptrdiff_t)nv + (ptrdiff_t)(r / 3 - 1) * (ptrdiff_t)(nv * nv);
                 ldv4(p, U[r]);
-                // x0 + 4 lies past the row's end on its last item (the last
-                // row of the array has nothing after it); vertex n, the one
-                // that would use it, is a boundary vertex
-                if (x0 + 3 < (uint32_t)n) ldv2(p + 4, U[r] + 4);
-                else { U[r][4] = p[4]; U[r][5] = (T)0; }
+                if constexpr (sizeof(T) == 4) {
+                    T t[2];
+                    ldv2(p + (last ? 3 : 4), t);
+                    U[r][4] = last ? t[1] : t[0];
+                    U[r][5] = last ? (T)0 : t[1];
+                } else if (!last) {
+                    ldv2(p + 4, U[r] + 4);
+                } else {
+                    U[r][4] = p[4];
+                    U[r][5] = (T)0;
+                }
             }
         }
         T acc[4] = {(T)0, (T)0, (T)0, (T)0}, dsum[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -215,8 +229,9 @@ __device__ inline float base_item(const float (&e)[2][2][5], int i, int o0, int 
 // iterates: the skipped zero couplings would turn an infinite u into NaN).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sweep3x4h(const float *__restrict__ S, const uint8_t *__restrict__ im,
-                                                   const float *__restrict__ eps_c, int n, const float *__restrict__ u,
-                                                   const float *__restrict__ f, float *__restrict__ out, float omega)
+                                                   const float *__restrict__ eps_c, int n, double hp,
+                                                   const float *__restrict__ u, const float *__restrict__ f,
+                                                   float *__restrict__ out, float omega)
 {
     uint32_t x0, y, z;
     if (!items4_at(n, (blockIdx.x >> 3) * 256u + threadIdx.x, blockIdx.x & 7u, x0, y, z)) return;
@@ -226,27 +241,44 @@ __global__ __launch_bounds__(256) void k_sweep3x4h(const float *__restrict__ S, 
     float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (y != 0 && z != 0 && y != (uint32_t)n && z != (uint32_t)n) {
         const bool tier0 = im[(x0 >> 2) + (size_t)(n >> 2) * (y + nv * z)] != 0;
+        // every load below the flag is issued without a branch, so that one
+        // wait covers the iterate, the load and (for a tier-0 item) the
+        // samples: on the item that ends a row (vertex x0 + 3 = n, a boundary
+        // vertex) the two values past x0 + 2 are read one place lower, where
+        // they stay inside the row, and the one that does not exist is zeroed
+        const bool last = x0 + 3 >= (uint32_t)n;
         float U[9][6];
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
             const float *p = u + v - 1 + (ptrdiff_t)(r % 3 - 1) * (ptrdiff_t)nv + (ptrdiff_t)(r / 3 - 1) * (ptrdiff_t)(nv * nv);
             ldv4(p, U[r]);
-            if (x0 + 3 < (uint32_t)n) ldv2(p + 4, U[r] + 4);
-            else { U[r][4] = p[4]; U[r][5] = 0.0f; }
+            float t[2];
+            ldv2(p + (last ? 3 : 4), t);
+            U[r][4] = last ? t[1] : t[0];
+            U[r][5] = last ? 0.0f : t[1];
         }
+        float F[4];
+        ldv4(f + v, F);
+        // the item's cell samples are loaded for every item, beside the
+        // iterate: a tier-0 item then waits for one round of loads, and the
+        // 20 floats of another item are mostly cache hits of its neighbours.
+        // The empty asm uses them here, so that the compiler cannot move the
+        // loads into the tier-0 branch behind the wait for the flag.
+        float e[2][2][5];
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+                const float *row = eps_c + (x0 - 1) + (size_t)n * ((y - 1 + cy) + (size_t)n * (z - 1 + cz));
+                ldv4(row, e[cz][cy]);
+                // cell x0 + 3 exists unless vertex x0 + 3 = n
+                const float e4 = row[last ? 3 : 4];
+                e[cz][cy][4] = last ? 0.0f : e4;
+                asm volatile("" ::"v"(e[cz][cy][0]), "v"(e[cz][cy][1]), "v"(e[cz][cy][2]), "v"(e[cz][cy][3]),
+                             "v"(e[cz][cy][4]));
+            }
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (tier0) {
-            float e[2][2][5];
-#pragma unroll
-            for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-                for (int cy = 0; cy < 2; ++cy) {
-                    const float *row = eps_c + (x0 - 1) + (size_t)n * ((y - 1 + cy) + (size_t)n * (z - 1 + cz));
-                    ldv4(row, e[cz][cy]);
-                    // cell x0 + 3 exists unless vertex x0 + 3 = n, a boundary vertex
-                    e[cz][cy][4] = x0 + 3 < (uint32_t)n ? row[4] : 0.0f;
-                }
-            const double hp = 1.0 / (double)n;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -280,8 +312,6 @@ __global__ __launch_bounds__(256) void k_sweep3x4h(const float *__restrict__ S, 
                 }
             }
         }
-        float F[4];
-        ldv4(f + v, F);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float Dv = -dsum[i];
@@ -789,10 +819,13 @@ static int sweep_t(mgd_hier *h, const OpSet &o, int level, const T *u, const T *
         const dim3 g4(items4_blocks(n));
         const float *uf = (const float *)u, *ff = (const float *)f;
         float *of = (float *)out;
+        const double hp = 1.0 / (double)n;
         if (mode == 1)
-            hipLaunchKernelGGL((k_sweep3x4h<1>), g4, dim3(256), 0, st, o.S32[0], o.imask, o.eps_c, n, uf, ff, of, (float)omega);
+            hipLaunchKernelGGL((k_sweep3x4h<1>), g4, dim3(256), 0, st, o.S32[0], o.imask, o.eps_c, n, hp, uf, ff, of,
+                               (float)omega);
         else
-            hipLaunchKernelGGL((k_sweep3x4h<0>), g4, dim3(256), 0, st, o.S32[0], o.imask, o.eps_c, n, uf, ff, of, (float)omega);
+            hipLaunchKernelGGL((k_sweep3x4h<0>), g4, dim3(256), 0, st, o.S32[0], o.imask, o.eps_c, n, hp, uf, ff, of,
+                               (float)omega);
         HIPCHK(h->ctx, hipGetLastError());
         return MGD_OK;
     }
