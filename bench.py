@@ -44,7 +44,7 @@ WORKLOAD = ("3D 512^3 Q1 cells (27-point stencils), eps=1 + 512 seeded boxes (si
             "outer CG to 1e-8; mixed-lazy vs FP64-up-front")
 TIERS_C5 = dict(min_tier=1, max_tier=3, tau_abs=0.0, tau_rel=1e-6)
 TIERS_FP16 = dict(min_tier=2, max_tier=2, tau_abs=0.0, tau_rel=1e-7)
-FORMS = ("mixed_lazy", "mixed_lazy_parked", "mixed_upfront", "fp64_upfront")
+FORMS = ("mixed_lazy", "mixed_lazy_guarded", "mixed_lazy_parked", "mixed_upfront", "fp64_upfront")
 # the roofline kernel: one damped-Jacobi sweep of the 3D mixed finest level
 # as the solve runs it (four vertices per thread; items whose coupling
 # sources are all tier-0 tiles re-evaluate their couplings from the centre
@@ -87,6 +87,8 @@ def solve_forms(P, W, d, n, fld, tiers, steps, warmup, s_max=16, main=None):
     - mixed_lazy: the paper's schedule, cycling on the provisional operator
       while the ladder runs on the assembly stream (the iterate carried over
       at the publish);
+    - mixed_lazy_guarded: the same schedule with the growth guard 2 (cycles
+      on a provisional operator stop once they have doubled the residual);
     - mixed_lazy_parked: the same lazy assembly with the provisional target
       1 (no cycles on a provisional operator: the assembly has the GPU);
     - mixed_upfront and fp64_upfront: every cell's ladder first.
@@ -98,6 +100,7 @@ def solve_forms(P, W, d, n, fld, tiers, steps, warmup, s_max=16, main=None):
     f = torch.from_numpy(f_host).cuda()
     base = dict(transfer=P.BOXMG, outer=P.PCG, s_max=s_max, tol=1e-8, max_cycles=600)
     kws = {"mixed_lazy": dict(base, precision=P.MIXED, schedule=P.LAZY, **tiers),
+           "mixed_lazy_guarded": dict(base, precision=P.MIXED, schedule=P.LAZY, prov_growth=2.0, **tiers),
            "mixed_lazy_parked": dict(base, precision=P.MIXED, schedule=P.LAZY, prov_tol=1.0, **tiers),
            "mixed_upfront": dict(base, precision=P.MIXED, schedule=P.UPFRONT, **tiers),
            "fp64_upfront": dict(base, precision=P.FP64, schedule=P.UPFRONT)}

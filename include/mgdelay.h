@@ -342,6 +342,14 @@ int mgd_outer_residual(mgd_ctx *ctx, mgd_hier *h, const double *u, const double 
  * waits for the pending operator, leaving the device to the assembly stream
  * (a provisional operator's solution is no closer to the final one than the
  * operator is to the final operator); 0 cycles on until the publish.
+ * prov_growth (same modes): once the residual on a provisional operator
+ * exceeds prov_growth times the residual at the last operator change, the
+ * solver likewise stops cycling on it and waits for the pending operator:
+ * cycles that raise the residual only take compute units from the assembly
+ * (a contrast the provisional operator's coarse levels cannot follow makes
+ * its cycles diverge); the iterate is carried over as usual.  0 (the
+ * default) keeps cycling; a value above 1 leaves room for the CG residual's
+ * transients.
  * store_path: as for a hierarchy (MGD_MIXED).
  * start: the iterate after an operator change.  MGD_START_CARRY (0, the
  * paper's schedule, Sec. 5.1-5.3) carries it over; MGD_START_BEST keeps the
@@ -366,6 +374,7 @@ typedef struct {
     mgd_tier_policy tiers;
     double prov_tol;
     int32_t start, cycle;
+    double prov_growth;
 } mgd_solve_opts;
 
 #define MGD_HIST 512

@@ -54,7 +54,7 @@ class _SolveOpts(C.Structure):
                 ("max_cycles", C.c_int32), ("coarsest", C.c_int32), ("store_path", C.c_int32),
                 ("C", C.c_double), ("omega", C.c_double), ("tol", C.c_double),
                 ("div_factor", C.c_double), ("tiers", _Tier), ("prov_tol", C.c_double),
-                ("start", C.c_int32), ("cycle", C.c_int32)]
+                ("start", C.c_int32), ("cycle", C.c_int32), ("prov_growth", C.c_double)]
 
 
 class _Report(C.Structure):
@@ -522,10 +522,11 @@ class Hierarchy:
 def solve_opts(precision=FP64, transfer=GEOMETRIC, outer=STATIONARY, schedule=UPFRONT,
                publish=PUBLISH_ASYNC, s_fixed=0, s_max=16, C_thr=0.01, omega=0.6, nu1=2, nu2=2,
                tol=1e-8, max_cycles=200, coarsest=2, div_factor=100.0, min_tier=2, max_tier=2,
-               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0, start=START_CARRY, cycle=CYCLE_V):
+               tau_abs=0.0, tau_rel=0.0, prov_tol=0.0, store_path=0, start=START_CARRY, cycle=CYCLE_V,
+               prov_growth=0.0):
     return _SolveOpts(precision, transfer, outer, schedule, publish, s_fixed, s_max, nu1, nu2,
                       max_cycles, coarsest, store_path, C_thr, omega, tol, div_factor,
-                      _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol, start, cycle)
+                      _Tier(min_tier, max_tier, tau_abs, tau_rel), prov_tol, start, cycle, prov_growth)
 
 
 def _report_dict(rc, rep):

@@ -221,7 +221,7 @@ int solve_validate(mgd_ctx *ctx, int32_t dim, int32_t n, const mgd_eps *eps, con
     if (sf > 0 && sf != 1 && sf != 2 && sf != 4 && sf != 8 && sf != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_fixed");
     if (sf <= 0 && sm != 1 && sm != 2 && sm != 4 && sm != 8 && sm != 16) return mgd_fail(ctx, MGD_EINVAL, "bad s_max");
     if (op->nu1 < 0 || op->nu2 < 0 || op->max_cycles < 0 || !(op->tol >= 0.0) || !(op->div_factor > 0.0) ||
-        !(op->prov_tol >= 0.0))
+        !(op->prov_tol >= 0.0) || !(op->prov_growth >= 0.0))
         return mgd_fail(ctx, MGD_EINVAL, "bad cycle options");
     if (op->precision == MGD_MIXED &&
         (op->tiers.min_tier < 1 || op->tiers.max_tier > 3 || op->tiers.min_tier > op->tiers.max_tier ||
@@ -653,11 +653,13 @@ int solve_step(SolveState *S, bool blocking)
         return 1;
     }
     // on a provisional operator, the asynchronous modes stop cycling once the
-    // tolerance (starvation guard) or the provisional target is met, wait for
+    // tolerance (starvation guard) or the provisional target is met, or once
+    // the cycles have raised the residual past the growth bound, wait for
     // the pending operator and publish it at once; the deterministic mode
     // keeps its schedule
     if (!S->ladder_done && S->publish_mode != MGD_PUBLISH_DETERMINISTIC &&
-        (conv || (op.prov_tol > 0.0 && S->rk <= op.prov_tol * S->r_ref)))
+        (conv || (op.prov_tol > 0.0 && S->rk <= op.prov_tol * S->r_ref) ||
+         (op.prov_growth > 0.0 && S->rk > op.prov_growth * S->r_ref)))
         return await_publish(S, blocking);
     S->k++;
     if (S->spec) {  // the next cycle and its check are queued already

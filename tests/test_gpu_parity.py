@@ -1046,6 +1046,35 @@ def test_solve_lazy_provisional_target_equals_upfront(ctx, d, n, publish, prov_t
         assert abs(r2["cycles"] - r1["cycles"]) <= 1
 
 
+@pytest.mark.parametrize("growth", [0.5, 2.0])
+def test_solve_lazy_growth_guard_equals_upfront(ctx, growth):
+    """The growth guard of the asynchronous lazy schedule on the high-contrast
+    box material (3D, 32^3, eps in [1e-4, 1e4], mixed, tiers 1-3): the solve
+    reaches the up-front schedule's operator and solution.  A bound below 1
+    holds at the first check already (the residual equals its reference
+    there), so the solver parks at once, as with a provisional target of 1:
+    the first checks all see the zero initial guess and the cycle count is
+    the up-front one within one."""
+    d, n = 3, 32
+    fld = W.boxes_field(3, 64, W.SEED_BASE + 4)
+    f = W.load_sine(d, n)
+    kw = dict(s_max=16, tol=1e-8, transfer=P.BOXMG, outer=P.PCG, precision=P.MIXED, min_tier=1, max_tier=3,
+              tau_rel=1e-6)
+    u1, r1 = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.UPFRONT, **kw)
+    u2, r2 = P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, publish=P.PUBLISH_ASYNC, prov_growth=growth,
+                     **kw)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r1["cells_at_s"] == r2["cells_at_s"]
+    assert r2["r_final"] <= 1e-8 * r2["r0"]
+    assert rel_err(host(u2), host(u1)) < 1e-6
+    if growth < 1.0:
+        assert r2["publishes"] == 1
+        assert r2["hist"][:2] == [1.0, 1.0]
+        assert abs(r2["cycles"] - r1["cycles"]) <= 1
+    with pytest.raises(P.MgdError):
+        P.solve(ctx, d, n, P.Eps(fld), dev(f), schedule=P.LAZY, prov_growth=-1.0, **kw)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_divergence_guard_only_for_stationary(ctx, precision):
     d, n = 2, 32
