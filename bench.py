@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--n3d", type=int, default=256, help="3D Gaussian-field component (0 skips)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline sweep and a calibration copy (for counter runs)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only one mixed up-front solve of the headline workload and a calibration copy "
+                         "(for counter runs over a whole cycle)")
     return ap.parse_args()
 
 
@@ -358,6 +361,31 @@ def kernels_only(args):
                       "mfma_cells": ncells, "source_sha16": source_sha16()}), flush=True)
 
 
+def solve_only(args):
+    """Counter runs over whole cycles: one mixed up-front solve of the
+    headline workload (the solve's own kernels, every level), then four
+    2 GiB device copies for the calibration of the traffic counters."""
+    import torch
+    import paper_2005_03606_amd as P
+    import workload as W
+    d, n = 3, args.n
+    ctx = P.Context(0)
+    f = torch.from_numpy(W.load_sine(d, n)).cuda()
+    u, r = P.solve(ctx, d, n, P.Eps(W.config_field(4)), f, torch.zeros_like(f), transfer=P.BOXMG, outer=P.PCG,
+                   s_max=16, tol=1e-8, max_cycles=600, precision=P.MIXED, schedule=P.UPFRONT, **TIERS_C5)
+    ctx.close()
+    del u, f
+    torch.cuda.empty_cache()
+    nbytes = 2 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"solve_status": r["status"], "cycles": r["cycles"], "copy_bytes_each_way": nbytes, "copies": 4,
+                      "source_sha16": source_sha16()}), flush=True)
+
+
 # --------------------------------------------------------------- adaFAC
 def adafac_component(P, W, ctx, n=256, tol=1e-8):
     """The additive adaFAC-PI / adaFAC-Jac corrections against the
@@ -507,6 +535,8 @@ def main():
         sys.exit(2)
     if args.kernels_only:
         return kernels_only(args)
+    if args.solve_only:
+        return solve_only(args)
     import torch
 
     import paper_2005_03606_amd as P
